@@ -1,0 +1,27 @@
+"""FP64 CPU oracle for Wannier-Fourier interpolation of the electron-phonon
+vertex and the imaginary electron self-energy (EPW method, Ponce et al.,
+arXiv:1604.03525).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
+link this package: it exists so that tests, the smoke check and the CPU
+baseline leg of the benchmark can compare the HIP library against a plain,
+slow, obviously correct evaluation of the definitions.  It shares no code with
+the HIP path; both sides only consume the seeded inputs of
+``paper_1604_03525_amd.inputs``.
+
+Modules
+-------
+lattice     Wigner-Seitz vectors and degeneracies, Gamma-centred grids,
+            the k+q index map (integer arithmetic).
+interp      Fourier interpolation R -> k of H, D and g; eigensolves;
+            rotation of g into the band/mode basis (Sec. 3 Eq. (2) and
+            Sec. 4; the interpolation itself is only cited by the paper).
+selfenergy  Fermi/Bose occupations, Gaussian delta, Im Sigma_nk of
+            Sec. 3 Eq. (8), degenerate averaging (Sec. 10.4).
+torch_ref   The same forward in plain torch CPU float64, differentiated by
+            autograd: the reference gradient for the hand-written adjoint.
+
+Parity status: every function here is pinned by tests/test_oracle_*.py
+against closed forms, brute-force sums, round trips or invariants, except
+where its docstring says "parity unpinned".
+"""
