@@ -1,0 +1,173 @@
+"""Throughput of the interpolation + Im Sigma hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+Workload: the realistic fcc system (2 atoms, 8 Wannier bands, 6 modes,
+6^3 coarse grid -> 279 Wigner-Seitz vectors each for electrons and phonons,
+fine 20^3 k x 20^3 q = 6.4e7 k.q pairs, T = 300 K, sigma = 20 meV, mu at
+mid-gap + 0.1 eV), synthetic seeded inputs resident in HBM before the timed
+region.  A step is one epw_imsigma call over all pairs: phases, every
+eigensolve, both contractions, both rotations and the reduction.
+
+The headline value is the float64 forward; the float32 (and, where built,
+split-bf16) forward and the backward are reported alongside.  One JSON line
+goes to stdout.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "k·q pairs/sec for interp+Im Σ_nk (FP64 vs FP32/split-BF16) and backward, 1 GPU"
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "split_bf16": 2500.0}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def setup(device):
+    from paper_1604_03525_amd import epw
+    from paper_1604_03525_amd import inputs as I
+    m = I.realistic_model()
+    R, nd = epw.epw_ws_vectors(m.metric, m.coarse)
+    HR, DR, gR = I.realistic_arrays(R, R)
+    k = epw.epw_grid_points(m.kgrid)
+    kq = epw.epw_kq_index(m.kgrid, m.qgrid)
+    sysd = epw.System(R, nd, R, nd, HR, DR, gR, device)
+    pts = epw.Points(k, k, kq, device=device)
+    return m, sysd, pts, (R, nd, HR, DR, gR, k)
+
+
+def fused_flops(nk, nq, ne, nm, nb):
+    """Algorithmic flops of the dominant kernel over all its launches:
+    the R_e -> k contraction (8 flops per complex multiply-add) plus the
+    two n_b x n_b rotations per (k, q, nu)."""
+    return 8.0 * nk * nq * ne * nm * nb * nb + 16.0 * nk * nq * nm * nb ** 3
+
+
+def timed(fn, steps, warmup, torch):
+    from paper_1604_03525_amd import epw
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    epw.epw_timing_enable(True)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        fn()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    stages = {}
+    for name, sid in (("eigh", 0), ("gemm_rp", 1), ("moderot", 2), ("fused", 3), ("backward", 4)):
+        ms, n = epw.epw_timing_read(sid)
+        stages[name] = (ms, n)
+    epw.epw_timing_enable(False)
+    return dt, stages
+
+
+def cpu_baseline(host, model, seconds_target=15.0):
+    """The FP64 oracle on a bounded sample: a few k points against all q."""
+    import numpy as np
+    from threadpoolctl import threadpool_info
+    from oracle import selfenergy
+    R, nd, HR, DR, gR, k = host
+    threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    nk_s = 0
+    t0 = time.perf_counter()
+    rng = np.random.default_rng(0)
+    idx = rng.choice(len(k), 64, replace=False)
+    while time.perf_counter() - t0 < seconds_target and nk_s < 64:
+        selfenergy.imsigma(HR, R, nd, DR, R, nd, gR, k[idx[nk_s:nk_s + 1]], k, model.T, model.mu,
+                           model.sigma)
+        nk_s += 1
+    dt = time.perf_counter() - t0
+    pairs = nk_s * len(k)
+    return {"value": pairs / dt, "unit": "k·q pairs/s", "cores": int(threads), "kind": "oracle",
+            "sample": "%d k points x all %d q of the same workload (%.1f s, FP64 NumPy)" % (nk_s, len(k), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--variants", default="fp32,split_bf16,backward")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(the q-sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1604_03525_amd import epw
+    if not torch.cuda.is_available():
+        print("bench.py needs a HIP device", file=sys.stderr)
+        sys.exit(2)
+    dev = torch.device("cuda:0")
+    model, sysd, pts, host = setup(dev)
+    nk, nq = pts.k.shape[0], pts.q.shape[0]
+    ne, nm, nb = sysd.Re.shape[0], sysd.nm, sysd.nb
+    pairs = nk * nq
+    ws = epw.Workspace(dev)
+
+    def run(dtype):
+        par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma, dtype=dtype)
+        out = torch.empty((nk, nb), dtype=torch.float64, device=dev)
+        return lambda: epw.epw_imsigma(sysd, pts, par, out=out, workspace=ws)
+
+    log("bench: fp64 forward, %d steps after %d warmup" % (args.steps, args.warmup))
+    dt, st = timed(run("fp64"), args.steps, args.warmup, torch)
+    ms_step = 1e3 * dt / args.steps
+    value = pairs * args.steps / dt
+    fms, fn = st["fused"]
+    flops = fused_flops(nk, nq, ne, nm, nb) * args.steps
+    achieved = flops / (fms * 1e-3) / 1e12 if fms > 0 else None
+    result = {
+        "metric": METRIC, "value": value, "unit": "k·q pairs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded random fcc model, see paper_1604_03525_amd/inputs.py)",
+        "config": {"workload": "fcc 2 atoms, nb=8, nm=6, WS 279+279, 20^3 k x 20^3 q grid, "
+                               "T=300 K, sigma=20 meV, FP64 forward",
+                   "nk": nk, "nq": nq, "pairs": pairs, "nb": nb, "nm": nm, "nRe": ne,
+                   "parallelism": "1 GPU"},
+        "roofline": {"bound": "mfma", "kernel": "fused_k_kernel (R_e->k contraction + rotation + reduction)",
+                     "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                     "frac": (achieved / PEAK_TFLOPS["fp64"]) if achieved else None, "traffic": None,
+                     "launches": fn, "avg_launch_ms": fms / fn if fn else None},
+        "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
+    }
+    variants = {}
+    for var in [v for v in args.variants.split(",") if v]:
+        try:
+            if var in ("fp32", "split_bf16"):
+                log("bench: %s forward" % var)
+                dtv, stv = timed(run(var), args.steps, args.warmup, torch)
+                fmsv, fnv = stv["fused"]
+                ach = flops / (fmsv * 1e-3) / 1e12 if fmsv > 0 else None
+                variants[var] = {"value": pairs * args.steps / dtv, "ms_per_step": 1e3 * dtv / args.steps,
+                                 "speedup_vs_fp64": (pairs * args.steps / dtv) / value,
+                                 "fused_tflops": ach, "fused_frac_of_peak": ach / PEAK_TFLOPS[var] if ach else None}
+            elif var == "backward":
+                log("bench: fp64 backward")
+                par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
+                w = torch.rand((nk, nb), dtype=torch.float64, device=dev)
+                dtb, _ = timed(lambda: epw.epw_imsigma_backward(sysd, pts, par, w, workspace=ws),
+                               args.steps, args.warmup, torch)
+                variants[var] = {"value": pairs * args.steps / dtb, "ms_per_step": 1e3 * dtb / args.steps}
+        except epw.EpwError as e:
+            variants[var] = {"unavailable": str(e)}
+    result["variants"] = variants
+    if not args.no_cpu_baseline:
+        log("bench: cpu baseline (oracle sample)")
+        result["cpu_baseline"] = cpu_baseline(host, model)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

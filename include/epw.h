@@ -1,0 +1,254 @@
+/*
+ * epw.h - C ABI of libepw: Wannier-Fourier interpolation of electrons,
+ * phonons and the electron-phonon vertex onto fine k/q points, and the
+ * imaginary electron self-energy (linewidth) of the EPW method
+ * (Ponce, Margine, Verdi, Giustino, arXiv:1604.03525), for AMD MI355X
+ * (gfx950).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ *  - Array arguments marked "device" are HIP device pointers owned by the
+ *    caller; "host" arrays live in host memory.  The library never frees
+ *    or retains a pointer after the call returns.
+ *  - Arrays are C-contiguous (row-major).  Complex numbers are interleaved
+ *    (re, im) pairs of double ("c128").
+ *  - Device calls are enqueued on the caller's stream (a hipStream_t passed
+ *    as void*, NULL = the default stream) and return before the work ends.
+ *  - Every call returns an int status: EPW_OK (0) or a negative code; the
+ *    message of the last failure on the calling thread is returned by
+ *    epw_last_error().  Argument checks happen before anything is enqueued,
+ *    so a failed call leaves outputs untouched.
+ *  - The library allocates no device memory.  Calls that need scratch take
+ *    a caller-allocated device workspace (ws, ws_bytes); its size comes
+ *    from epw_workspace_size().  Concurrent calls must use distinct
+ *    workspaces.
+ *  - Units: energies in eV, temperature in K, hbar = 1.  Points are in
+ *    fractional (reciprocal-lattice) coordinates, real-space vectors in
+ *    integer lattice coordinates.
+ *  - Interpolation convention (the paper cites it, Sec. 1 and Sec. 8 step
+ *    (iii), without printing it): X(p) = sum_R exp(+2 pi i p.R) X(R)/ndeg(R)
+ *    over the Wigner-Seitz vectors R with degeneracy weights ndeg.
+ */
+#ifndef EPW_H
+#define EPW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define EPW_OK        0
+#define EPW_EINVAL   -1   /* NULL pointer or invalid scalar parameter            */
+#define EPW_ESHAPE   -2   /* unsupported or inconsistent sizes                   */
+#define EPW_EDTYPE   -3   /* unknown precision selector                          */
+#define EPW_ENOMEM   -5   /* workspace (or host capacity) too small              */
+#define EPW_EHIP     -6   /* the HIP runtime reported an error                   */
+
+/* ---- precision of the contractions and rotations ----
+ * Eigensolves, phase arguments k.R, occupations and the degenerate-subspace
+ * logic are float64 in every mode. */
+#define EPW_FP64        0   /* complex float64 on MFMA                              */
+#define EPW_FP32        1   /* complex float32 on MFMA, float32 accumulation        */
+#define EPW_SPLIT_BF16  2   /* x = hi + lo in bfloat16, three products per real
+                               product on MFMA, float32 accumulation               */
+
+/* ---- size limits ---- */
+#define EPW_MAX_NB  16      /* Wannier bands                                        */
+#define EPW_MAX_NM  16      /* phonon modes (3 x atoms)                             */
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* epw_last_error(void);
+
+/* Library version, 100*major + minor. */
+int epw_version(void);
+
+/* ======================================================================
+ * Host-side integer steps (no GPU involved, bit-exact)
+ * ====================================================================== */
+
+/* Wigner-Seitz vectors of the ncell[0] x ncell[1] x ncell[2] supercell
+ * (the real-space support of the interpolation; Sec. 1, Sec. 8 step (ii)).
+ *  metric  host [9]  integer metric G_ab = a_a.a_b of the primitive vectors
+ *                    (any common positive scale), row-major, positive definite
+ *  ncell   host [3]  supercell size N_a >= 1 (the coarse k/q grid)
+ *  R       host [cap][3] out: vectors n with |n|_G <= |n - T|_G for every
+ *                    supercell vector T = (N1 t1, N2 t2, N3 t3), t in {-2..2}^3,
+ *                    lexicographically ascending
+ *  ndeg    host [cap] out: number of T attaining equality (T = 0 included)
+ *  cap     capacity of R and ndeg; *count receives the number of vectors.
+ * Errors: EPW_EINVAL (NULL, N_a < 1, metric not positive definite),
+ *         EPW_ENOMEM (cap < count; *count is still set). */
+int epw_ws_vectors(const int64_t metric[9], const int32_t ncell[3],
+                   int32_t* R, int32_t* ndeg, int32_t cap, int32_t* count);
+
+/* Gamma-centred grid n[0] x n[1] x n[2] (Sec. 8, Sec. 10.2): point
+ * i = (i1*n1 + i2)*n2 + i3 gets (i1/n0, i2/n1, i3/n2).
+ *  out host [n0*n1*n2][3] double.  Errors: EPW_EINVAL. */
+int epw_grid_points(const int32_t n[3], double* out);
+
+/* Index of k+q (folded into [0,1)^3) in the k grid for Gamma-centred grids
+ * with kgrid[a] a multiple of qgrid[a]:
+ *  out host [Nk][Nq] int32, k and q in the C order of epw_grid_points.
+ * Errors: EPW_EINVAL (NULL), EPW_ESHAPE (incommensurate grids). */
+int epw_kq_index(const int32_t kgrid[3], const int32_t qgrid[3], int32_t* out);
+
+/* ======================================================================
+ * Device steps
+ * ====================================================================== */
+
+/* Electron bands at arbitrary points: H(k) = sum_R exp(2 pi i k.R) H(R)/ndeg,
+ * Hermitised, diagonalised in float64 (Jacobi) -> eps ascending, U columns.
+ * (The paper obtains the rotation matrices U_k at arbitrary k from the
+ * interpolated Hamiltonian: Sec. 4, after the overlap formula.)
+ *  nb              bands, 1..EPW_MAX_NB
+ *  nR, R, ndeg     device [nR][3] int32, [nR] int32 (WS set, ndeg >= 1)
+ *  HR              device [nR][nb][nb] c128
+ *  nk, kfrac       device [nk][3] double
+ *  eps             device [nk][nb] double out
+ *  U               device [nk][nb][nb] c128 out (U[k][i][n]: orbital i of band n)
+ * Errors: EPW_EINVAL, EPW_ESHAPE, EPW_EHIP. */
+int epw_interp_bands(int nb, int nR, const int32_t* R, const int32_t* ndeg,
+                     const void* HR, int nk, const double* kfrac,
+                     double* eps, void* U, void* stream);
+
+/* Phonons at arbitrary points: D(q) = sum_R exp(2 pi i q.R) D(R)/ndeg with
+ * the masses folded into D (Sec. 3, after Eq. (2)), Hermitised and
+ * diagonalised in float64; omega = sign(l) sqrt|l| per eigenvalue l.
+ *  nm              modes, 1..EPW_MAX_NM
+ *  DR              device [nR][nm][nm] double (real force constants / masses)
+ *  omega           device [nq][nm] double out (ascending)
+ *  evec            device [nq][nm][nm] c128 out (columns)
+ * Errors: EPW_EINVAL, EPW_ESHAPE, EPW_EHIP. */
+int epw_interp_phonons(int nm, int nR, const int32_t* R, const int32_t* ndeg,
+                       const double* DR, int nq, const double* qfrac,
+                       double* omega, void* evec, void* stream);
+
+/* Real-space system shared by the vertex and self-energy calls. */
+typedef struct {
+    int32_t nb;            /* Wannier bands (1..EPW_MAX_NB)                      */
+    int32_t nm;            /* phonon modes = 3 x atoms (1..EPW_MAX_NM)           */
+    int32_t nRe;           /* electron WS vectors                                */
+    int32_t nRp;           /* phonon WS vectors                                  */
+    const int32_t* Re;     /* device [nRe][3]                                    */
+    const int32_t* ndeg_e; /* device [nRe]                                       */
+    const int32_t* Rp;     /* device [nRp][3]                                    */
+    const int32_t* ndeg_p; /* device [nRp]                                       */
+    const void* HR;        /* device [nRe][nb][nb] c128                          */
+    const double* DR;      /* device [nRp][nm][nm] double; may be NULL when
+                              phonon states are given in epw_points              */
+    const void* gR;        /* device [nRe][nRp][nm][nb][nb] c128: g_{ka}(R_e,R_p),
+                              row index = Wannier function on the k+q side      */
+} epw_system;
+
+/* Fine points. */
+typedef struct {
+    int32_t nk;            /* number of k points                                 */
+    int32_t nq;            /* number of q points                                 */
+    const double* kfrac;   /* device [nk][3]                                     */
+    const double* qfrac;   /* device [nq][3]                                     */
+    const int32_t* kq;     /* device [nk][nq]: index in the k set of the point
+                              equal to k+q modulo a reciprocal lattice vector
+                              (grid runs), or NULL: the k+q states are then
+                              interpolated and diagonalised for every pair       */
+    const double* omega;   /* device [nq][nm] or NULL: given phonon frequencies  */
+    const void* evec;      /* device [nq][nm][nm] c128 or NULL: given modes.  When
+                              both are set, DR is not used.                      */
+} epw_points;
+
+/* Physical and numerical parameters of Eq. (8). */
+typedef struct {
+    double T;              /* temperature (K), >= 0                              */
+    double mu;             /* chemical potential = Fermi level (eV)              */
+    double sigma;          /* Gaussian width (eV), > 0: delta(x) ->
+                              exp(-x^2/sigma^2)/(sigma sqrt(pi))                  */
+    double omega_cut;      /* modes with omega < omega_cut contribute 0 (eV)      */
+    double deg_tol;        /* bands closer than this are averaged (eV), >= 0     */
+    double nq_norm;        /* N_q of the BZ mean (1/N_q) sum_q; 0 -> nq          */
+    int32_t dtype;         /* EPW_FP64 / EPW_FP32 / EPW_SPLIT_BF16               */
+    int32_t chunk_q;       /* q points per chunk (0 = choose from the workspace) */
+    int32_t accumulate;    /* 0: overwrite the output, 1: add to it              */
+    int32_t reserved;
+} epw_params;
+
+/* Electron-phonon vertex in the band/mode basis (Sec. 3 Eq. (2)):
+ *   g_mn,nu(k,q) = [U_{k+q}^dag (sum_ka g_ka(k,q) e_ka,nu(q)) U_k]_mn / sqrt(2 omega_q,nu)
+ *   g_ka(k,q)   = sum_{R_e,R_p} exp(2 pi i (k.R_e + q.R_p)) g_ka(R_e,R_p)/(ndeg_e ndeg_p)
+ * materialised for every pair (meant for small sizes and tests); modes with
+ * omega < par->omega_cut are set to 0.  Only par->dtype and par->omega_cut
+ * are read.
+ *  gkq  device [nk][nq][nm][nb][nb] c128 out
+ * The band-basis vertex depends on the eigenvector gauge; gauge-invariant
+ * combinations (sums of |g|^2 over degenerate states) are what compare
+ * between implementations.
+ * Errors: EPW_EINVAL, EPW_ESHAPE, EPW_EDTYPE, EPW_ENOMEM, EPW_EHIP. */
+int epw_interp_g(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                 void* gkq, void* ws, size_t ws_bytes, void* stream);
+
+/* Imaginary electron self-energy on shell, Sec. 3 Eq. (8):
+ *   Im Sigma_nk = (pi/N_q) sum_q sum_m,nu |g_mn,nu(k,q)|^2
+ *       { [n_q,nu + f_m,k+q] delta(eps_nk - eps_m,k+q + omega_q,nu)
+ *       + [n_q,nu + 1 - f_m,k+q] delta(eps_nk - eps_m,k+q - omega_q,nu) }
+ * with n the Bose and f the Fermi-Dirac function at T, then averaged over
+ * bands degenerate within deg_tol.  The scattering rate of the Sec. 10.2
+ * example is 2 Im Sigma.
+ *  imsig  device [nk][nb] double out (overwritten or accumulated)
+ * Errors: EPW_EINVAL, EPW_ESHAPE, EPW_EDTYPE, EPW_ENOMEM, EPW_EHIP. */
+int epw_imsigma(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                double* imsig, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of L = sum_nk w_nk Im Sigma_nk (the forward of epw_imsigma) with
+ * respect to g(R_e,R_p), H(R_e) and omega_q,nu.  Complex gradients are
+ * dL/dRe + i dL/dIm; H(k) is the Hermitised sum, so every entry of H(R) is
+ * an independent complex parameter; dL/domega is taken at fixed e_q (through
+ * the Bose factor, the Gaussians and 1/sqrt(2 omega)) and is 0 for cut
+ * modes.  The rotated vertex is recomputed, not stored.
+ *  w       device [nk][nb] double
+ *  dgR     device [nRe][nRp][nm][nb][nb] c128 out (NULL to skip)
+ *  dHR     device [nRe][nb][nb] c128 out (NULL to skip; grid runs only)
+ *  domega  device [nq][nm] double out (NULL to skip)
+ * Outputs are overwritten (par->accumulate = 1 adds instead).
+ * Errors: as epw_imsigma. */
+int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                         const double* w, void* dgR, void* dHR, double* domega,
+                         void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace bytes for the call `which` (EPW_WS_INTERP_G, EPW_WS_IMSIGMA,
+ * EPW_WS_IMSIGMA_BACKWARD) with these sizes and parameters; device pointers
+ * inside sys/pts are not dereferenced and may be NULL.  Returns 0 and sets
+ * the error message on invalid arguments. */
+#define EPW_WS_INTERP_G          1
+#define EPW_WS_IMSIGMA           2
+#define EPW_WS_IMSIGMA_BACKWARD  3
+size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
+                          const epw_params* par);
+
+/* ======================================================================
+ * Stage timing (diagnostics)
+ * ====================================================================== */
+
+/* When enabled, every launch of the kernels of a stage is bracketed by a
+ * pair of HIP events recorded on the launch's own stream.  The library's
+ * only process-wide state; guarded by a mutex.  Stages: */
+#define EPW_STAGE_EIGH      0   /* interpolation + eigensolve of H(k), D(q)      */
+#define EPW_STAGE_GEMM_RP   1   /* R_p -> q contraction                          */
+#define EPW_STAGE_MODEROT   2   /* mode rotation and 1/sqrt(2 omega)             */
+#define EPW_STAGE_FUSED     3   /* R_e -> k contraction + rotation + reduction   */
+#define EPW_STAGE_BACKWARD  4   /* adjoint kernels                               */
+#define EPW_NUM_STAGES      5
+
+/* enable != 0 starts recording (and discards earlier records); 0 stops. */
+int epw_timing_enable(int enable);
+
+/* Waits for the recorded events of `stage`, returns the summed duration in
+ * milliseconds and the number of launches, and discards those records.
+ * Errors: EPW_EINVAL (bad stage or NULL), EPW_EHIP. */
+int epw_timing_read(int stage, double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPW_H */

@@ -1,0 +1,116 @@
+"""ctypes view of libepw (include/epw.h): structs, prototypes, loader.
+
+The shared library is built in-tree by paper_1604_03525_amd.build; loading
+fails loudly when it is missing, there is no fallback path.
+"""
+import ctypes
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libepw.so")
+
+EPW_OK = 0
+EPW_EINVAL = -1
+EPW_ESHAPE = -2
+EPW_EDTYPE = -3
+EPW_ENOMEM = -5
+EPW_EHIP = -6
+
+EPW_FP64 = 0
+EPW_FP32 = 1
+EPW_SPLIT_BF16 = 2
+
+EPW_WS_INTERP_G = 1
+EPW_WS_IMSIGMA = 2
+EPW_WS_IMSIGMA_BACKWARD = 3
+
+EPW_STAGE_EIGH = 0
+EPW_STAGE_GEMM_RP = 1
+EPW_STAGE_MODEROT = 2
+EPW_STAGE_FUSED = 3
+EPW_STAGE_BACKWARD = 4
+
+EPW_MAX_NB = 16
+EPW_MAX_NM = 16
+
+_vp = ctypes.c_void_p
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class EpwSystem(ctypes.Structure):
+    _fields_ = [("nb", ctypes.c_int32), ("nm", ctypes.c_int32),
+                ("nRe", ctypes.c_int32), ("nRp", ctypes.c_int32),
+                ("Re", _vp), ("ndeg_e", _vp), ("Rp", _vp), ("ndeg_p", _vp),
+                ("HR", _vp), ("DR", _vp), ("gR", _vp)]
+
+
+class EpwPoints(ctypes.Structure):
+    _fields_ = [("nk", ctypes.c_int32), ("nq", ctypes.c_int32),
+                ("kfrac", _vp), ("qfrac", _vp), ("kq", _vp),
+                ("omega", _vp), ("evec", _vp)]
+
+
+class EpwParams(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_double), ("mu", ctypes.c_double), ("sigma", ctypes.c_double),
+                ("omega_cut", ctypes.c_double), ("deg_tol", ctypes.c_double),
+                ("nq_norm", ctypes.c_double), ("dtype", ctypes.c_int32),
+                ("chunk_q", ctypes.c_int32), ("accumulate", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+# name -> (restype, argtypes); every symbol include/epw.h declares
+PROTOTYPES = {
+    "epw_last_error": (ctypes.c_char_p, []),
+    "epw_version": (ctypes.c_int, []),
+    "epw_ws_vectors": (ctypes.c_int, [_i64p, _i32p, _i32p, _i32p, ctypes.c_int32, _i32p]),
+    "epw_grid_points": (ctypes.c_int, [_i32p, _dp]),
+    "epw_kq_index": (ctypes.c_int, [_i32p, _i32p, _i32p]),
+    "epw_interp_bands": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int,
+                                        _vp, _vp, _vp, _vp]),
+    "epw_interp_phonons": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, ctypes.c_int,
+                                          _vp, _vp, _vp, _vp]),
+    "epw_interp_g": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
+                                    ctypes.POINTER(EpwParams), _vp, _vp, ctypes.c_size_t, _vp]),
+    "epw_imsigma": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
+                                   ctypes.POINTER(EpwParams), _vp, _vp, ctypes.c_size_t, _vp]),
+    "epw_imsigma_backward": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
+                                            ctypes.POINTER(EpwParams), _vp, _vp, _vp, _vp, _vp,
+                                            ctypes.c_size_t, _vp]),
+    "epw_timing_enable": (ctypes.c_int, [ctypes.c_int]),
+    "epw_timing_read": (ctypes.c_int, [ctypes.c_int, _dp, _i64p]),
+    "epw_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(EpwSystem),
+                                             ctypes.POINTER(EpwPoints), ctypes.POINTER(EpwParams)]),
+}
+
+_LIB = None
+
+
+class EpwError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libepw error %d: %s" % (code, msg))
+        self.code = code
+
+
+def load():
+    """Load libepw.so (once).  Raises if it has not been built."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libepw.so not found at %s: build it with "
+                           "`python -m paper_1604_03525_amd.build`" % LIB_PATH)
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in PROTOTYPES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def check(rc):
+    if rc != EPW_OK:
+        msg = load().epw_last_error()
+        raise EpwError(rc, msg.decode() if msg else "")
+    return rc

@@ -1,0 +1,326 @@
+// C ABI entry points: argument checks, workspace layout and the order of
+// kernel launches for each call.  All device work goes to the caller's
+// stream; nothing here blocks on the device.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "epw_internal.h"
+#include "kernels.h"
+
+namespace epw {
+namespace {
+
+constexpr int SLICE_CUS = 256;          // column-slice count is sized for 256 CUs
+constexpr size_t AUTO_CHUNK_BYTES = (size_t)4 << 30;
+
+size_t cbytes(Prec p) { return p == Prec::F64 ? 16 : 8; }
+
+int check_common(const epw_system* s, const epw_points* p, const epw_params* par, const char* fn) {
+    if (!s || !p || !par) return fail(EPW_EINVAL, "%s: NULL argument", fn);
+    if (s->nb < 1 || s->nb > EPW_MAX_NB) return fail(EPW_ESHAPE, "%s: nb = %d not in 1..%d", fn, s->nb, EPW_MAX_NB);
+    if (s->nm < 1 || s->nm > EPW_MAX_NM) return fail(EPW_ESHAPE, "%s: nm = %d not in 1..%d", fn, s->nm, EPW_MAX_NM);
+    if (s->nRe < 1 || s->nRp < 1) return fail(EPW_ESHAPE, "%s: empty WS set", fn);
+    if (s->nRe > (1 << 20) || s->nRp > (1 << 20)) return fail(EPW_ESHAPE, "%s: WS set too large", fn);
+    if (p->nk < 0 || p->nq < 0) return fail(EPW_ESHAPE, "%s: negative point count", fn);
+    if (par->dtype != EPW_FP64 && par->dtype != EPW_FP32 && par->dtype != EPW_SPLIT_BF16)
+        return fail(EPW_EDTYPE, "%s: unknown dtype %d", fn, par->dtype);
+    if (!(par->sigma > 0.0) || !std::isfinite(par->sigma)) return fail(EPW_EINVAL, "%s: sigma must be > 0", fn);
+    if (!(par->T >= 0.0) || !std::isfinite(par->T)) return fail(EPW_EINVAL, "%s: T must be >= 0", fn);
+    if (!std::isfinite(par->mu)) return fail(EPW_EINVAL, "%s: mu not finite", fn);
+    if (!(par->deg_tol >= 0.0)) return fail(EPW_EINVAL, "%s: deg_tol must be >= 0", fn);
+    if (!(par->nq_norm >= 0.0)) return fail(EPW_EINVAL, "%s: nq_norm must be >= 0", fn);
+    if (!std::isfinite(par->omega_cut)) return fail(EPW_EINVAL, "%s: omega_cut not finite", fn);
+    if (par->chunk_q < 0) return fail(EPW_EINVAL, "%s: chunk_q < 0", fn);
+    const bool given = p->omega && p->evec;
+    if ((p->omega != nullptr) != (p->evec != nullptr))
+        return fail(EPW_EINVAL, "%s: omega and evec must be given together", fn);
+    if (p->nk > 0 && p->nq > 0) {
+        if (!s->Re || !s->ndeg_e || !s->Rp || !s->ndeg_p || !s->HR || !s->gR)
+            return fail(EPW_EINVAL, "%s: NULL pointer in epw_system", fn);
+        if (!given && !s->DR) return fail(EPW_EINVAL, "%s: DR is NULL and no phonon states given", fn);
+        if (!p->kfrac || !p->qfrac) return fail(EPW_EINVAL, "%s: NULL point array", fn);
+        if (!p->kq) return fail(EPW_ESHAPE, "%s: k+q states off the k set (kq = NULL) are not supported", fn);
+    }
+    return EPW_OK;
+}
+
+struct Layout {
+    Prec prec;
+    int nbp, Q, nchunks, S;
+    // fixed tables
+    double* eps = nullptr;
+    void* U = nullptr;
+    double* ftab = nullptr;
+    void* phi_k = nullptr;
+    void* gR_t = nullptr;
+    // per chunk
+    double* omega_c = nullptr;
+    void* evec_c = nullptr;
+    double* sc = nullptr;
+    double* nbose = nullptr;
+    void* phi_q = nullptr;
+    void* gq = nullptr;
+    void* Bnu = nullptr;
+    double* part = nullptr;
+};
+
+int tiles_n_for(int qc, int nm, int nbp) {
+    const long ncols = (long)qc * nm * nbp * nbp;
+    const int BN = nbp * nbp >= 64 ? nbp * nbp : 64;
+    return (int)((ncols + BN - 1) / BN);
+}
+
+// Carve the workspace (or count its size when A.dry).
+void plan(const epw_system* s, const epw_points* p, const epw_params* par, bool store, Arena& A, Layout& L) {
+    L.prec = (Prec)par->dtype;
+    L.nbp = pow2_at_least(s->nb);
+    const size_t cb = cbytes(L.prec);
+    const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
+    const bool given = p->omega && p->evec;
+    // chunk size
+    const size_t per_q = cb * ((size_t)ne * nm * nb * nb + (size_t)ne * nm * L.nbp * L.nbp + np_) +
+                         (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm;
+    long Q = par->chunk_q > 0 ? par->chunk_q : (long)(AUTO_CHUNK_BYTES / per_q);
+    if (Q < 1) Q = 1;
+    if (Q > nq) Q = nq > 0 ? nq : 1;
+    L.Q = (int)Q;
+    L.nchunks = nq > 0 ? (int)((nq + Q - 1) / Q) : 0;
+    L.S = store ? 0 : fused_slices(nk, L.nbp, tiles_n_for(L.Q, nm, L.nbp), SLICE_CUS);
+    L.eps = (double*)A.take(8 * (size_t)nk * nb);
+    L.U = A.take(16 * (size_t)nk * nb * nb);
+    L.ftab = (double*)A.take(8 * (size_t)nk * nb);
+    L.phi_k = A.take(cb * (size_t)nk * ne);
+    if (L.prec != Prec::F64) L.gR_t = A.take(cb * (size_t)ne * np_ * nm * nb * nb);
+    if (!given) {
+        L.omega_c = (double*)A.take(8 * (size_t)L.Q * nm);
+        L.evec_c = A.take(16 * (size_t)L.Q * nm * nm);
+    }
+    L.sc = (double*)A.take(8 * (size_t)L.Q * nm);
+    L.nbose = (double*)A.take(8 * (size_t)L.Q * nm);
+    L.phi_q = A.take(cb * (size_t)L.Q * np_);
+    L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
+    L.Bnu = A.take(cb * (size_t)ne * L.Q * nm * L.nbp * L.nbp);
+    if (!store) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
+}
+
+// Shared forward pipeline: store mode writes g_mn,nu(k,q) to gkq,
+// otherwise Im Sigma goes to imsig.
+void run_forward(const epw_system* s, const epw_points* p, const epw_params* par, Layout& L,
+                 double* imsig, void* gkq, hipStream_t st) {
+    const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
+    const Prec prec = L.prec;
+    const bool given = p->omega && p->evec;
+    // electrons on the k set (the k+q states are members of the k set)
+    {
+        StageTimer t(EPW_STAGE_EIGH, st);
+        launch_interp_eigh(false, false, nb, ne, s->Re, s->ndeg_e, (const double*)s->HR, nk, p->kfrac,
+                           L.eps, L.U, st);
+    }
+    launch_fermi_table((size_t)nk * nb, L.eps, par->mu, par->T, L.ftab, st);
+    launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_k, st);
+    const void* gsrc = s->gR;
+    if (prec == Prec::F32) {
+        launch_c128_to_c64((size_t)ne * np_ * nm * nb * nb, s->gR, L.gR_t, st);
+        gsrc = L.gR_t;
+    }
+    const double nqn = par->nq_norm > 0.0 ? par->nq_norm : (double)nq;
+    const double scale = M_PI / (nqn * par->sigma * std::sqrt(M_PI));
+    for (int c = 0; c < L.nchunks; ++c) {
+        const int q0 = c * L.Q;
+        const int qc = (q0 + L.Q <= nq) ? L.Q : nq - q0;
+        const double* om;
+        const void* ev;
+        if (given) {
+            om = p->omega + (size_t)q0 * nm;
+            ev = (const char*)p->evec + 16 * (size_t)q0 * nm * nm;
+        } else {
+            StageTimer t(EPW_STAGE_EIGH, st);
+            launch_interp_eigh(true, true, nm, np_, s->Rp, s->ndeg_p, s->DR, qc, p->qfrac + 3 * (size_t)q0,
+                               L.omega_c, L.evec_c, st);
+            om = L.omega_c;
+            ev = L.evec_c;
+        }
+        launch_phonon_factors(qc, nm, om, par->omega_cut, par->T, L.sc, L.nbose, st);
+        launch_phase_table(prec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
+        {
+            StageTimer t(EPW_STAGE_GEMM_RP, st);
+            launch_gemm_rp(prec, qc, ne, np_, nm * nb * nb, L.phi_q, np_, gsrc, L.gq, st);
+        }
+        {
+            StageTimer t(EPW_STAGE_MODEROT, st);
+            launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st);
+        }
+        FusedArgs a;
+        a.nk = nk;
+        a.ne = ne;
+        a.nb = nb;
+        a.nbp = L.nbp;
+        a.nm = nm;
+        a.qc = qc;
+        a.q0 = q0;
+        a.nq_total = nq;
+        a.phi_k = L.phi_k;
+        a.ldk = ne;
+        a.B = L.Bnu;
+        a.eps = L.eps;
+        a.U = L.U;
+        a.ftab = L.ftab;
+        a.kq = p->kq;
+        a.omega = om;
+        a.nbose = L.nbose;
+        a.sc = L.sc;
+        a.sigma = par->sigma;
+        a.part = L.part;
+        a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp), SLICE_CUS);
+        a.gkq = gkq;
+        {
+            StageTimer t(EPW_STAGE_FUSED, st);
+            launch_fused_k(prec, a, SLICE_CUS, st);
+        }
+        if (!gkq)
+            launch_reduce_partials(nk, nb, a.S, L.part, scale, (c > 0 || par->accumulate) ? 1 : 0, imsig, st);
+    }
+    if (!gkq) {
+        if (L.nchunks == 0 && !par->accumulate && nk > 0)
+            EPW_HIP(hipMemsetAsync(imsig, 0, 8 * (size_t)nk * nb, st));
+        launch_degenerate_average(nk, nb, L.eps, par->deg_tol, imsig, st);
+    }
+}
+
+template <class F>
+int guarded(const char* fn, F body) {
+    try {
+        return body();
+    } catch (const HipFailure& e) {
+        return fail(EPW_EHIP, "%s: HIP error %d (%s) in %s at %s:%d", fn, e.code,
+                    hipGetErrorString((hipError_t)e.code), e.call, e.file, e.line);
+    } catch (...) {
+        return fail(EPW_EINVAL, "%s: unexpected host exception", fn);
+    }
+}
+
+}  // namespace
+}  // namespace epw
+
+using namespace epw;
+
+extern "C" int epw_interp_bands(int nb, int nR, const int32_t* R, const int32_t* ndeg, const void* HR,
+                                int nk, const double* kfrac, double* eps, void* U, void* stream) {
+    clear_error();
+    if (nb < 1 || nb > EPW_MAX_NB) return fail(EPW_ESHAPE, "epw_interp_bands: nb = %d not in 1..%d", nb, EPW_MAX_NB);
+    if (nR < 1 || nk < 0) return fail(EPW_ESHAPE, "epw_interp_bands: nR = %d, nk = %d", nR, nk);
+    if (nk == 0) return EPW_OK;
+    if (!R || !ndeg || !HR || !kfrac || !eps || !U) return fail(EPW_EINVAL, "epw_interp_bands: NULL argument");
+    return guarded("epw_interp_bands", [&]() {
+        launch_interp_eigh(false, false, nb, nR, R, ndeg, (const double*)HR, nk, kfrac, eps, U,
+                           (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_interp_phonons(int nm, int nR, const int32_t* R, const int32_t* ndeg, const double* DR,
+                                  int nq, const double* qfrac, double* omega, void* evec, void* stream) {
+    clear_error();
+    if (nm < 1 || nm > EPW_MAX_NM) return fail(EPW_ESHAPE, "epw_interp_phonons: nm = %d not in 1..%d", nm, EPW_MAX_NM);
+    if (nR < 1 || nq < 0) return fail(EPW_ESHAPE, "epw_interp_phonons: nR = %d, nq = %d", nR, nq);
+    if (nq == 0) return EPW_OK;
+    if (!R || !ndeg || !DR || !qfrac || !omega || !evec) return fail(EPW_EINVAL, "epw_interp_phonons: NULL argument");
+    return guarded("epw_interp_phonons", [&]() {
+        launch_interp_eigh(true, true, nm, nR, R, ndeg, DR, nq, qfrac, omega, evec, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
+                                     const epw_params* par) {
+    clear_error();
+    if (which != EPW_WS_INTERP_G && which != EPW_WS_IMSIGMA && which != EPW_WS_IMSIGMA_BACKWARD) {
+        fail(EPW_EINVAL, "epw_workspace_size: unknown call id %d", which);
+        return 0;
+    }
+    if (!sys || !pts || !par) {
+        fail(EPW_EINVAL, "epw_workspace_size: NULL argument");
+        return 0;
+    }
+    epw_points p = *pts;
+    epw_system s = *sys;
+    // sizes only: pretend pointers are present so the shape checks run
+    static const int32_t dummy_i = 0;
+    static const double dummy_d = 0.0;
+    if (!p.kq) p.kq = &dummy_i;
+    if (!p.kfrac) p.kfrac = &dummy_d;
+    if (!p.qfrac) p.qfrac = &dummy_d;
+    if (!s.Re) s.Re = &dummy_i;
+    if (!s.Rp) s.Rp = &dummy_i;
+    if (!s.ndeg_e) s.ndeg_e = &dummy_i;
+    if (!s.ndeg_p) s.ndeg_p = &dummy_i;
+    if (!s.HR) s.HR = &dummy_d;
+    if (!s.gR) s.gR = &dummy_d;
+    if (!s.DR && !(p.omega && p.evec)) s.DR = &dummy_d;
+    if (check_common(&s, &p, par, "epw_workspace_size") != EPW_OK) return 0;
+    Arena A;
+    A.dry = true;
+    Layout L;
+    plan(&s, &p, par, which == EPW_WS_INTERP_G, A, L);
+    return A.used + 256;
+}
+
+extern "C" int epw_interp_g(const epw_system* sys, const epw_points* pts, const epw_params* par, void* gkq,
+                            void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    int rc = check_common(sys, pts, par, "epw_interp_g");
+    if (rc != EPW_OK) return rc;
+    if (pts->nk == 0 || pts->nq == 0) return EPW_OK;
+    if (!gkq) return fail(EPW_EINVAL, "epw_interp_g: NULL output");
+    if (par->dtype == EPW_SPLIT_BF16) return fail(EPW_EDTYPE, "epw_interp_g: split-bf16 not available yet");
+    Arena dry;
+    dry.dry = true;
+    Layout L;
+    plan(sys, pts, par, true, dry, L);
+    if (!ws || ws_bytes < dry.used + 256)
+        return fail(EPW_ENOMEM, "epw_interp_g: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
+    return guarded("epw_interp_g", [&]() {
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        plan(sys, pts, par, true, A, L);
+        run_forward(sys, pts, par, L, nullptr, gkq, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_imsigma(const epw_system* sys, const epw_points* pts, const epw_params* par, double* imsig,
+                           void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    int rc = check_common(sys, pts, par, "epw_imsigma");
+    if (rc != EPW_OK) return rc;
+    if (pts->nk == 0) return EPW_OK;
+    if (!imsig) return fail(EPW_EINVAL, "epw_imsigma: NULL output");
+    if (par->dtype == EPW_SPLIT_BF16) return fail(EPW_EDTYPE, "epw_imsigma: split-bf16 not available yet");
+    Arena dry;
+    dry.dry = true;
+    Layout L;
+    plan(sys, pts, par, false, dry, L);
+    if (!ws || ws_bytes < dry.used + 256)
+        return fail(EPW_ENOMEM, "epw_imsigma: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
+    return guarded("epw_imsigma", [&]() {
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        plan(sys, pts, par, false, A, L);
+        run_forward(sys, pts, par, L, imsig, nullptr, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                                    const double* w, void* dgR, void* dHR, double* domega, void* ws,
+                                    size_t ws_bytes, void* stream) {
+    clear_error();
+    int rc = check_common(sys, pts, par, "epw_imsigma_backward");
+    if (rc != EPW_OK) return rc;
+    (void)w; (void)dgR; (void)dHR; (void)domega; (void)ws; (void)ws_bytes; (void)stream;
+    return fail(EPW_ESHAPE, "epw_imsigma_backward: not available yet");
+}

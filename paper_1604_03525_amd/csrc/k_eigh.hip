@@ -1,0 +1,282 @@
+// Interpolation of small Hermitian matrices (H(k), D(q)) from real space and
+// their float64 eigendecomposition, one wavefront per point.
+//
+// X(p) = sum_R exp(2 pi i p.R) X(R)/ndeg(R): the phases of a block of R
+// vectors are staged in LDS; lanes split the (entry, R) work, partial sums
+// are reduced in a fixed order (bit-reproducible).  The matrix is then
+// Hermitised and diagonalised by the cyclic complex Jacobi method with the
+// round-robin (tournament) ordering: every round applies n/2 disjoint plane
+// rotations at once, columns then rows, so the LDS updates of one round
+// never collide.  Jacobi is used because it reaches full float64 accuracy
+// for eigenvalues and eigenvectors at these sizes (n <= 16) and maps onto a
+// single wave without serial Householder steps.
+#include <hip/hip_runtime.h>
+
+#include "epw_internal.h"
+#include "kernels.h"
+
+namespace epw {
+namespace {
+
+constexpr int MAXN = 16;
+constexpr int LDA = MAXN + 1;     // padded leading dimension in LDS
+constexpr int RBLK = 256;         // R vectors staged per pass
+constexpr int MAX_SWEEPS = 24;
+
+__device__ inline double2 cmul(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+__device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
+    const int m = n2 - 1;
+    const int a = (r + i) % m;
+    const int b = (i == 0) ? m : (r - i + m) % m;
+    p = a < b ? a : b;
+    q = a < b ? b : a;
+}
+
+// REAL_IN: X(R) is real (dynamical matrix); else complex interleaved.
+// SQRT_OUT: write omega = sign(l) sqrt|l| instead of the eigenvalue l.
+// pts_a/pts_b: point p is pts_a[ia] (+ pts_b[ib] when pair mode is used).
+template <bool REAL_IN, bool SQRT_OUT>
+__global__ __launch_bounds__(64) void interp_eigh_kernel(
+    int n, int nR, const int32_t* __restrict__ R, const int32_t* __restrict__ ndeg,
+    const double* __restrict__ XR, int np, const double* __restrict__ pts,
+    double* __restrict__ evals, double2* __restrict__ evecs)
+{
+    __shared__ double2 A[MAXN + 1][LDA];
+    __shared__ double2 V[MAXN + 1][LDA];
+    __shared__ double2 ph[RBLK];
+    __shared__ double2 red[64];
+    __shared__ double rot[MAXN / 2][4];
+    __shared__ int rpq[MAXN / 2][2];
+    __shared__ double sred[64];
+
+    const int lane = threadIdx.x;
+    const int p = blockIdx.x;
+    if (p >= np) return;
+    const double k0 = pts[3 * (size_t)p + 0];
+    const double k1 = pts[3 * (size_t)p + 1];
+    const double k2 = pts[3 * (size_t)p + 2];
+    const int E = n * n;
+    const int P = (E >= 64) ? 1 : 64 / E;          // R partitions per entry
+    const int EPL = (E + 63) / 64;                   // entries per lane when P == 1
+
+    double2 acc[4];
+    for (int j = 0; j < 4; ++j) acc[j] = make_double2(0.0, 0.0);
+
+    for (int r0 = 0; r0 < nR; r0 += RBLK) {
+        const int cnt = min(RBLK, nR - r0);
+        __syncthreads();
+        for (int r = lane; r < cnt; r += 64) {
+            const int idx = r0 + r;
+            double x = k0 * (double)R[3 * idx] + k1 * (double)R[3 * idx + 1] +
+                       k2 * (double)R[3 * idx + 2];
+            x -= rint(x);
+            double s, c;
+            sincospi(2.0 * x, &s, &c);
+            const double w = 1.0 / (double)ndeg[idx];
+            ph[r] = make_double2(c * w, s * w);
+        }
+        __syncthreads();
+        if (P > 1) {
+            const int e = lane % E, part = lane / E;
+            if (part < P) {
+                for (int r = part; r < cnt; r += P) {
+                    const double2 f = ph[r];
+                    if (REAL_IN) {
+                        const double x = XR[(size_t)(r0 + r) * E + e];
+                        acc[0].x += f.x * x;
+                        acc[0].y += f.y * x;
+                    } else {
+                        const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
+                        const double2 t = cmul(f, x);
+                        acc[0].x += t.x;
+                        acc[0].y += t.y;
+                    }
+                }
+            }
+        } else {
+            for (int j = 0; j < EPL; ++j) {
+                const int e = lane + 64 * j;
+                if (e >= E) break;
+                for (int r = 0; r < cnt; ++r) {
+                    const double2 f = ph[r];
+                    if (REAL_IN) {
+                        const double x = XR[(size_t)(r0 + r) * E + e];
+                        acc[j].x += f.x * x;
+                        acc[j].y += f.y * x;
+                    } else {
+                        const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
+                        const double2 t = cmul(f, x);
+                        acc[j].x += t.x;
+                        acc[j].y += t.y;
+                    }
+                }
+            }
+        }
+    }
+    // raw interpolated matrix -> V (scratch)
+    if (P > 1) {
+        red[lane] = acc[0];
+        __syncthreads();
+        if (lane < E) {
+            double2 s = make_double2(0.0, 0.0);
+            for (int part = 0; part < P; ++part) {
+                s.x += red[lane + E * part].x;
+                s.y += red[lane + E * part].y;
+            }
+            V[lane / n][lane % n] = s;
+        }
+    } else {
+        for (int j = 0; j < EPL; ++j) {
+            const int e = lane + 64 * j;
+            if (e < E) V[e / n][e % n] = acc[j];
+        }
+    }
+    __syncthreads();
+    // Hermitise into A; V <- identity; padding row/column of zeros
+    const int n2 = n + (n & 1);
+    for (int e = lane; e < n2 * n2; e += 64) {
+        const int i = e / n2, j = e % n2;
+        double2 a = make_double2(0.0, 0.0);
+        if (i < n && j < n) {
+            const double2 x = V[i][j], y = V[j][i];
+            a = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+        }
+        A[i][j] = a;
+    }
+    __syncthreads();
+    for (int e = lane; e < n2 * n2; e += 64) {
+        const int i = e / n2, j = e % n2;
+        V[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    }
+    __syncthreads();
+
+    const int npair = n2 / 2;
+    for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+        // convergence: off-diagonal mass against the whole matrix
+        double off = 0.0, dia = 0.0;
+        for (int e = lane; e < n * n; e += 64) {
+            const int i = e / n, j = e % n;
+            const double2 a = A[i][j];
+            const double m2 = a.x * a.x + a.y * a.y;
+            if (i == j) dia += m2; else off += m2;
+        }
+        sred[lane] = off;
+        red[lane].x = dia;
+        __syncthreads();
+        if (lane == 0) {
+            double so = 0.0, sd = 0.0;
+            for (int l = 0; l < 64; ++l) { so += sred[l]; sd += red[l].x; }
+            sred[0] = (so <= 1e-30 * (so + sd)) ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        const bool done = sred[0] != 0.0;
+        __syncthreads();
+        if (done) break;
+        for (int r = 0; r < n2 - 1; ++r) {
+            if (lane < npair) {
+                int pp, qq;
+                rr_pair(n2, r, lane, pp, qq);
+                double c = 1.0, s = 0.0, cph = 1.0, sph = 0.0;
+                if (qq < n) {
+                    const double app = A[pp][pp].x, aqq = A[qq][qq].x;
+                    const double2 b = A[pp][qq];
+                    const double ab = hypot(b.x, b.y);
+                    if (ab > 0.0) {
+                        cph = b.x / ab;
+                        sph = b.y / ab;
+                        const double tau = (aqq - app) / (2.0 * ab);
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
+                        c = 1.0 / sqrt(1.0 + t * t);
+                        s = t * c;
+                    }
+                } else {
+                    qq = -1;   // inactive (dummy index)
+                }
+                rot[lane][0] = c;
+                rot[lane][1] = s;
+                rot[lane][2] = cph;
+                rot[lane][3] = sph;
+                rpq[lane][0] = pp;
+                rpq[lane][1] = qq;
+            }
+            __syncthreads();
+            // columns of A and V: col_p' = c col_p - s e^{-i phi} col_q,
+            //                     col_q' = s col_p + c e^{-i phi} col_q
+            for (int item = lane; item < 2 * npair * n; item += 64) {
+                const int which = item / (npair * n);
+                const int rem = item % (npair * n);
+                const int pr = rem / n, i = rem % n;
+                const int pp = rpq[pr][0], qq = rpq[pr][1];
+                if (qq < 0) continue;
+                const double c = rot[pr][0], s = rot[pr][1];
+                const double2 emi = make_double2(rot[pr][2], -rot[pr][3]);
+                double2 (*M)[LDA] = which ? V : A;
+                const double2 xp = M[i][pp];
+                const double2 w = cmul(M[i][qq], emi);
+                M[i][pp] = make_double2(c * xp.x - s * w.x, c * xp.y - s * w.y);
+                M[i][qq] = make_double2(s * xp.x + c * w.x, s * xp.y + c * w.y);
+            }
+            __syncthreads();
+            // rows of A: row_p' = c row_p - s e^{i phi} row_q, row_q' = s row_p + c e^{i phi} row_q
+            for (int item = lane; item < npair * n; item += 64) {
+                const int pr = item / n, j = item % n;
+                const int pp = rpq[pr][0], qq = rpq[pr][1];
+                if (qq < 0) continue;
+                const double c = rot[pr][0], s = rot[pr][1];
+                const double2 epi = make_double2(rot[pr][2], rot[pr][3]);
+                const double2 xp = A[pp][j];
+                const double2 w = cmul(A[qq][j], epi);
+                A[pp][j] = make_double2(c * xp.x - s * w.x, c * xp.y - s * w.y);
+                A[qq][j] = make_double2(s * xp.x + c * w.x, s * xp.y + c * w.y);
+            }
+            __syncthreads();
+            if (lane < npair && rpq[lane][1] >= 0) {
+                const int pp = rpq[lane][0], qq = rpq[lane][1];
+                A[pp][qq] = make_double2(0.0, 0.0);
+                A[qq][pp] = make_double2(0.0, 0.0);
+                A[pp][pp].y = 0.0;
+                A[qq][qq].y = 0.0;
+            }
+            __syncthreads();
+        }
+    }
+    // ascending order with a stable rank; eigenvector i is column i of V
+    if (lane < n) {
+        const double li = A[lane][lane].x;
+        int rank = 0;
+        for (int j = 0; j < n; ++j) {
+            const double lj = A[j][j].x;
+            rank += (lj < li) || (lj == li && j < lane);
+        }
+        double out = li;
+        if (SQRT_OUT) out = (li < 0.0 ? -1.0 : 1.0) * sqrt(fabs(li));
+        evals[(size_t)p * n + rank] = out;
+        for (int row = 0; row < n; ++row)
+            evecs[((size_t)p * n + row) * n + rank] = V[row][lane];
+    }
+}
+
+}  // namespace
+
+void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_t* R,
+                        const int32_t* ndeg, const double* XR, int np, const double* pts,
+                        double* evals, void* evecs, hipStream_t stream)
+{
+    if (np <= 0) return;
+    dim3 grid(np), block(64);
+    double2* ev = reinterpret_cast<double2*>(evecs);
+    if (real_in && sqrt_out)
+        interp_eigh_kernel<true, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, evals, ev);
+    else if (real_in)
+        interp_eigh_kernel<true, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, evals, ev);
+    else if (sqrt_out)
+        interp_eigh_kernel<false, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, evals, ev);
+    else
+        interp_eigh_kernel<false, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, evals, ev);
+    launch_check("interp_eigh_kernel");
+}
+
+}  // namespace epw

@@ -1,0 +1,235 @@
+"""Python binding of libepw with the same call names as include/epw.h.
+
+Argument marshalling only: host integer steps take and return NumPy arrays;
+device steps take torch tensors on a HIP device (torch provides the memory
+and the current stream) and every arithmetic step runs in libepw's kernels.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import (EPW_FP32, EPW_FP64, EPW_SPLIT_BF16, EPW_WS_IMSIGMA,  # noqa: F401
+                   EPW_WS_IMSIGMA_BACKWARD, EPW_WS_INTERP_G, EpwError)
+
+DTYPES = {"fp64": EPW_FP64, "fp32": EPW_FP32, "split_bf16": EPW_SPLIT_BF16}
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _dev(t, dtype, device):
+    """Contiguous device tensor of the given dtype (no copy when already so)."""
+    if isinstance(t, np.ndarray):
+        t = torch.from_numpy(np.ascontiguousarray(t))
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+# ------------------------------------------------------------------ host steps
+
+def epw_ws_vectors(metric, ncell):
+    """Wigner-Seitz vectors and degeneracies (host, exact)."""
+    lib = _lib.load()
+    m = np.ascontiguousarray(np.asarray(metric, dtype=np.int64).reshape(9))
+    n = np.ascontiguousarray(np.asarray(ncell, dtype=np.int32).reshape(3))
+    count = ctypes.c_int32(0)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    rc = lib.epw_ws_vectors(m.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n.ctypes.data_as(i32p),
+                            None, None, 0, ctypes.byref(count))
+    if rc not in (_lib.EPW_OK, _lib.EPW_ENOMEM):
+        _lib.check(rc)
+    R = np.zeros((count.value, 3), dtype=np.int32)
+    nd = np.zeros(count.value, dtype=np.int32)
+    _lib.check(lib.epw_ws_vectors(m.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n.ctypes.data_as(i32p),
+                                  R.ctypes.data_as(i32p), nd.ctypes.data_as(i32p), count.value,
+                                  ctypes.byref(count)))
+    return R, nd
+
+
+def epw_grid_points(n):
+    lib = _lib.load()
+    nn = np.ascontiguousarray(np.asarray(n, dtype=np.int32).reshape(3))
+    out = np.zeros((int(np.prod(nn)), 3), dtype=np.float64)
+    _lib.check(lib.epw_grid_points(nn.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                   out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def epw_kq_index(kgrid, qgrid):
+    lib = _lib.load()
+    kg = np.ascontiguousarray(np.asarray(kgrid, dtype=np.int32).reshape(3))
+    qg = np.ascontiguousarray(np.asarray(qgrid, dtype=np.int32).reshape(3))
+    out = np.zeros((int(np.prod(kg)), int(np.prod(qg))), dtype=np.int32)
+    i32p = ctypes.POINTER(ctypes.c_int32)
+    _lib.check(lib.epw_kq_index(kg.ctypes.data_as(i32p), qg.ctypes.data_as(i32p), out.ctypes.data_as(i32p)))
+    return out
+
+
+# ---------------------------------------------------------------- device steps
+
+def epw_interp_bands(HR, R, ndeg, kfrac):
+    """(eps [nk][nb] float64, U [nk][nb][nb] complex128) on the device of HR."""
+    lib = _lib.load()
+    dev = HR.device
+    HR = _dev(HR, torch.complex128, dev)
+    R = _dev(R, torch.int32, dev)
+    ndeg = _dev(ndeg, torch.int32, dev)
+    k = _dev(kfrac, torch.float64, dev)
+    nb, nk = HR.shape[-1], k.shape[0]
+    eps = torch.empty((nk, nb), dtype=torch.float64, device=dev)
+    U = torch.empty((nk, nb, nb), dtype=torch.complex128, device=dev)
+    _lib.check(lib.epw_interp_bands(nb, R.shape[0], _ptr(R), _ptr(ndeg), _ptr(HR), nk, _ptr(k),
+                                    _ptr(eps), _ptr(U), _stream(dev)))
+    return eps, U
+
+
+def epw_interp_phonons(DR, R, ndeg, qfrac):
+    """(omega [nq][nm] float64, evec [nq][nm][nm] complex128)."""
+    lib = _lib.load()
+    dev = DR.device
+    DR = _dev(DR, torch.float64, dev)
+    R = _dev(R, torch.int32, dev)
+    ndeg = _dev(ndeg, torch.int32, dev)
+    q = _dev(qfrac, torch.float64, dev)
+    nm, nq = DR.shape[-1], q.shape[0]
+    om = torch.empty((nq, nm), dtype=torch.float64, device=dev)
+    ev = torch.empty((nq, nm, nm), dtype=torch.complex128, device=dev)
+    _lib.check(lib.epw_interp_phonons(nm, R.shape[0], _ptr(R), _ptr(ndeg), _ptr(DR), nq, _ptr(q),
+                                      _ptr(om), _ptr(ev), _stream(dev)))
+    return om, ev
+
+
+class System:
+    """Device-resident real-space system: WS sets, H(R_e), D(R_p), g(R_e,R_p)."""
+
+    def __init__(self, Re, ndeg_e, Rp, ndeg_p, HR, DR, gR, device="cuda"):
+        self.device = torch.device(device)
+        d = self.device
+        self.Re = _dev(Re, torch.int32, d)
+        self.ndeg_e = _dev(ndeg_e, torch.int32, d)
+        self.Rp = _dev(Rp, torch.int32, d)
+        self.ndeg_p = _dev(ndeg_p, torch.int32, d)
+        self.HR = _dev(HR, torch.complex128, d)
+        self.DR = None if DR is None else _dev(DR, torch.float64, d)
+        self.gR = _dev(gR, torch.complex128, d)
+        self.nb = self.HR.shape[-1]
+        self.nm = self.gR.shape[2]
+
+    def c_struct(self):
+        return _lib.EpwSystem(self.nb, self.nm, self.Re.shape[0], self.Rp.shape[0],
+                              _ptr(self.Re), _ptr(self.ndeg_e), _ptr(self.Rp), _ptr(self.ndeg_p),
+                              _ptr(self.HR), _ptr(self.DR), _ptr(self.gR))
+
+
+class Points:
+    """Device-resident fine points: k set, q set, optional k+q map and
+    optional given phonon states."""
+
+    def __init__(self, kfrac, qfrac, kq=None, omega=None, evec=None, device="cuda"):
+        d = torch.device(device)
+        self.k = _dev(kfrac, torch.float64, d)
+        self.q = _dev(qfrac, torch.float64, d)
+        self.kq = None if kq is None else _dev(kq, torch.int32, d)
+        self.omega = None if omega is None else _dev(omega, torch.float64, d)
+        self.evec = None if evec is None else _dev(evec, torch.complex128, d)
+
+    def c_struct(self):
+        return _lib.EpwPoints(self.k.shape[0], self.q.shape[0], _ptr(self.k), _ptr(self.q),
+                              _ptr(self.kq), _ptr(self.omega), _ptr(self.evec))
+
+
+def make_params(T=300.0, mu=0.0, sigma=0.05, omega_cut=1e-3, deg_tol=1e-6, nq_norm=0.0,
+                dtype="fp64", chunk_q=0, accumulate=False):
+    return _lib.EpwParams(float(T), float(mu), float(sigma), float(omega_cut), float(deg_tol),
+                          float(nq_norm), DTYPES[dtype] if isinstance(dtype, str) else int(dtype),
+                          int(chunk_q), int(bool(accumulate)), 0)
+
+
+def epw_workspace_size(which, system, points, params):
+    lib = _lib.load()
+    s, p = system.c_struct(), points.c_struct()
+    n = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p), ctypes.byref(params))
+    if n == 0:
+        msg = lib.epw_last_error()
+        raise EpwError(_lib.EPW_EINVAL, msg.decode() if msg else "")
+    return int(n)
+
+
+class Workspace:
+    """Grow-only device workspace reused across calls on one stream."""
+
+    def __init__(self, device="cuda"):
+        self.device = torch.device(device)
+        self.buf = None
+
+    def get(self, nbytes):
+        if self.buf is None or self.buf.numel() < nbytes:
+            self.buf = None
+            self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        return self.buf
+
+
+def epw_interp_g(system, points, params, workspace=None):
+    """g_mn,nu(k,q) [nk][nq][nm][nb][nb] complex128 (materialised)."""
+    lib = _lib.load()
+    ws = workspace or Workspace(system.device)
+    nbytes = epw_workspace_size(EPW_WS_INTERP_G, system, points, params)
+    buf = ws.get(nbytes)
+    nk, nq = points.k.shape[0], points.q.shape[0]
+    out = torch.empty((nk, nq, system.nm, system.nb, system.nb), dtype=torch.complex128,
+                      device=system.device)
+    s, p = system.c_struct(), points.c_struct()
+    _lib.check(lib.epw_interp_g(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), _ptr(out),
+                                _ptr(buf), buf.numel(), _stream(system.device)))
+    return out
+
+
+def epw_imsigma(system, points, params, out=None, workspace=None):
+    """Im Sigma_nk [nk][nb] float64 (Sec. 3 Eq. (8))."""
+    lib = _lib.load()
+    ws = workspace or Workspace(system.device)
+    nbytes = epw_workspace_size(EPW_WS_IMSIGMA, system, points, params)
+    buf = ws.get(nbytes)
+    if out is None:
+        out = torch.empty((points.k.shape[0], system.nb), dtype=torch.float64, device=system.device)
+    s, p = system.c_struct(), points.c_struct()
+    _lib.check(lib.epw_imsigma(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), _ptr(out),
+                               _ptr(buf), buf.numel(), _stream(system.device)))
+    return out
+
+
+def epw_imsigma_backward(system, points, params, w, want=("gR", "HR", "omega"), workspace=None):
+    """(dL/dgR, dL/dHR, dL/domega) for L = sum w Im Sigma."""
+    lib = _lib.load()
+    ws = workspace or Workspace(system.device)
+    nbytes = epw_workspace_size(EPW_WS_IMSIGMA_BACKWARD, system, points, params)
+    buf = ws.get(nbytes)
+    d = system.device
+    w = _dev(w, torch.float64, d)
+    dg = torch.empty_like(system.gR) if "gR" in want else None
+    dh = torch.empty_like(system.HR) if "HR" in want else None
+    nq, nm = points.q.shape[0], system.nm
+    dom = torch.empty((nq, nm), dtype=torch.float64, device=d) if "omega" in want else None
+    s, p = system.c_struct(), points.c_struct()
+    _lib.check(lib.epw_imsigma_backward(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params),
+                                        _ptr(w), _ptr(dg), _ptr(dh), _ptr(dom), _ptr(buf), buf.numel(),
+                                        _stream(d)))
+    return dg, dh, dom
+
+
+def epw_timing_enable(on=True):
+    _lib.check(_lib.load().epw_timing_enable(1 if on else 0))
+
+
+def epw_timing_read(stage):
+    """(total milliseconds, launches) recorded for a stage since the last read."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _lib.check(_lib.load().epw_timing_read(int(stage), ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value
