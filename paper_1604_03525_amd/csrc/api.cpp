@@ -105,6 +105,24 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, bool 
     if (!store) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
 }
 
+// a5 as a strided GEMM: out[e][q][c] = sum_p phi_q[q][p] gR[e][p][c]
+GemmDesc rp_desc(int qc, int ne, int np_, int ncol, const void* phi_q, const void* gR, void* out) {
+    GemmDesc d;
+    d.M = qc;
+    d.N = ne * ncol;
+    d.K = np_;
+    d.A = phi_q;
+    d.lda = np_;
+    d.B = gR;
+    d.ncb = ncol;
+    d.sBe = (long)np_ * ncol;
+    d.sBk = ncol;
+    d.C = out;
+    d.sCe = (long)qc * ncol;
+    d.sCm = ncol;
+    return d;
+}
+
 // Shared forward pipeline: store mode writes g_mn,nu(k,q) to gkq,
 // otherwise Im Sigma goes to imsig.
 void run_forward(const epw_system* s, const epw_points* p, const epw_params* par, Layout& L,
@@ -146,7 +164,7 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         launch_phase_table(prec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
         {
             StageTimer t(EPW_STAGE_GEMM_RP, st);
-            launch_gemm_rp(prec, qc, ne, np_, nm * nb * nb, L.phi_q, np_, gsrc, L.gq, st);
+            launch_cgemm(prec, rp_desc(qc, ne, np_, nm * nb * nb, L.phi_q, gsrc, L.gq), st);
         }
         {
             StageTimer t(EPW_STAGE_MODEROT, st);
@@ -186,6 +204,219 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         if (L.nchunks == 0 && !par->accumulate && nk > 0)
             EPW_HIP(hipMemsetAsync(imsig, 0, 8 * (size_t)nk * nb, st));
         launch_degenerate_average(nk, nb, L.eps, par->deg_tol, imsig, st);
+    }
+}
+
+// ---------------------------------------------------------------- adjoint
+
+struct BwdLayout {
+    Prec prec;
+    int nbp, Q, nchunks;
+    double* eps = nullptr;
+    void* U = nullptr;
+    double* ftab = nullptr;
+    double* wbar = nullptr;
+    void* phi_k = nullptr;
+    double* ebar = nullptr;
+    void* Ubar = nullptr;
+    void* Xbar = nullptr;
+    double* omega_c = nullptr;
+    void* evec_c = nullptr;
+    double* sc = nullptr;
+    double* nbose = nullptr;
+    void* phi_q = nullptr;
+    void* gq = nullptr;      // a5 output, reused for the mode-basis adjoint
+    void* Bnu = nullptr;     // a6 output, reused for gbar_nu(R_e,q)
+    void* G = nullptr;       // recomputed Wannier-basis g(k,q), overwritten by its adjoint
+    double* ek_c = nullptr;
+    double* ekq_c = nullptr;
+    void* Uk_c = nullptr;
+    void* Ukq_c = nullptr;
+    double* om_c = nullptr;
+    int32_t* inv = nullptr;
+};
+
+constexpr size_t AUTO_BWD_CHUNK_BYTES = (size_t)4 << 30;
+
+void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, Arena& A, BwdLayout& L) {
+    L.prec = (Prec)par->dtype;
+    L.nbp = pow2_at_least(s->nb);
+    const size_t cb = cbytes(L.prec);
+    const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
+    const bool given = p->omega && p->evec;
+    const size_t nbp2 = (size_t)L.nbp * L.nbp;
+    const size_t per_q = cb * ((size_t)nk * nm * nbp2 + 2 * (size_t)ne * nm * nbp2 + np_) +
+                         (size_t)nk * (16 * nb + 32 * (size_t)nb * nb + 8 * nm + 4) +
+                         (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm;
+    long Q = par->chunk_q > 0 ? par->chunk_q : (long)(AUTO_BWD_CHUNK_BYTES / per_q);
+    if (Q < 1) Q = 1;
+    if (Q > nq) Q = nq > 0 ? nq : 1;
+    L.Q = (int)Q;
+    L.nchunks = nq > 0 ? (int)((nq + Q - 1) / Q) : 0;
+    L.eps = (double*)A.take(8 * (size_t)nk * nb);
+    L.U = A.take(16 * (size_t)nk * nb * nb);
+    L.ftab = (double*)A.take(8 * (size_t)nk * nb);
+    L.wbar = (double*)A.take(8 * (size_t)nk * nb);
+    L.phi_k = A.take(cb * (size_t)nk * ne);
+    L.ebar = (double*)A.take(8 * (size_t)nk * nb);
+    L.Ubar = A.take(16 * (size_t)nk * nb * nb);
+    L.Xbar = A.take(16 * (size_t)nk * nb * nb);
+    if (!given) {
+        L.omega_c = (double*)A.take(8 * (size_t)L.Q * nm);
+        L.evec_c = A.take(16 * (size_t)L.Q * nm * nm);
+    }
+    L.sc = (double*)A.take(8 * (size_t)L.Q * nm);
+    L.nbose = (double*)A.take(8 * (size_t)L.Q * nm);
+    L.phi_q = A.take(cb * (size_t)L.Q * np_);
+    L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
+    L.Bnu = A.take(cb * (size_t)ne * L.Q * nm * nbp2);
+    L.G = A.take(cb * (size_t)nk * L.Q * nm * nbp2);
+    L.ek_c = (double*)A.take(8 * (size_t)nk * L.Q * nb);
+    L.ekq_c = (double*)A.take(8 * (size_t)nk * L.Q * nb);
+    L.Uk_c = A.take(16 * (size_t)nk * L.Q * nb * nb);
+    L.Ukq_c = A.take(16 * (size_t)nk * L.Q * nb * nb);
+    L.om_c = (double*)A.take(8 * (size_t)nk * L.Q * nm);
+    L.inv = (int32_t*)A.take(4 * (size_t)nk * L.Q);
+}
+
+void run_backward(const epw_system* s, const epw_points* p, const epw_params* par, BwdLayout& L, const double* w,
+                  void* dgR, void* dHR, double* domega, hipStream_t st) {
+    const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
+    const Prec prec = L.prec;
+    const bool given = p->omega && p->evec;
+    const int acc0 = par->accumulate ? 1 : 0;
+    const size_t ncol_g = (size_t)nm * nb * nb;
+    {
+        StageTimer t(EPW_STAGE_EIGH, st);
+        launch_interp_eigh(false, false, nb, ne, s->Re, s->ndeg_e, (const double*)s->HR, nk, p->kfrac, L.eps,
+                           L.U, st);
+    }
+    launch_fermi_table((size_t)nk * nb, L.eps, par->mu, par->T, L.ftab, st);
+    EPW_HIP(hipMemcpyAsync(L.wbar, w, 8 * (size_t)nk * nb, hipMemcpyDeviceToDevice, st));
+    launch_degenerate_average(nk, nb, L.eps, par->deg_tol, L.wbar, st);
+    launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_k, st);
+    launch_fill((size_t)nk * nb, 0.0, L.ebar, st);
+    launch_fill(2 * (size_t)nk * nb * nb, 0.0, (double*)L.Ubar, st);
+    if (dgR && (L.nchunks == 0) && !acc0)
+        launch_fill(2 * (size_t)ne * np_ * ncol_g, 0.0, (double*)dgR, st);
+    const double nqn = par->nq_norm > 0.0 ? par->nq_norm : (double)nq;
+    const double C = M_PI / (nqn * par->sigma * std::sqrt(M_PI));
+    const double kT = 8.617333262e-5 * par->T;
+    for (int c = 0; c < L.nchunks; ++c) {
+        const int q0 = c * L.Q;
+        const int qc = (q0 + L.Q <= nq) ? L.Q : nq - q0;
+        const double* om;
+        const void* ev;
+        if (given) {
+            om = p->omega + (size_t)q0 * nm;
+            ev = (const char*)p->evec + 16 * (size_t)q0 * nm * nm;
+        } else {
+            StageTimer t(EPW_STAGE_EIGH, st);
+            launch_interp_eigh(true, true, nm, np_, s->Rp, s->ndeg_p, s->DR, qc, p->qfrac + 3 * (size_t)q0,
+                               L.omega_c, L.evec_c, st);
+            om = L.omega_c;
+            ev = L.evec_c;
+        }
+        launch_phonon_factors(qc, nm, om, par->omega_cut, par->T, L.sc, L.nbose, st);
+        launch_phase_table(prec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
+        const long ncols = (long)qc * nm * L.nbp * L.nbp;
+        StageTimer tb(EPW_STAGE_BACKWARD, st);
+        launch_cgemm(prec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, s->gR, L.gq), st);
+        launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st);
+        {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
+            GemmDesc d;
+            d.M = nk;
+            d.N = (int)ncols;
+            d.K = ne;
+            d.A = L.phi_k;
+            d.lda = ne;
+            d.B = L.Bnu;
+            d.ncb = (int)ncols;
+            d.sBk = ncols;
+            d.C = L.G;
+            d.sCm = ncols;
+            launch_cgemm(prec, d, st);
+        }
+        PairBwdArgs a;
+        a.nk = nk;
+        a.nb = nb;
+        a.nbp = L.nbp;
+        a.nm = nm;
+        a.qc = qc;
+        a.q0 = q0;
+        a.nq_total = nq;
+        a.G = L.G;
+        a.eps = L.eps;
+        a.U = L.U;
+        a.ftab = L.ftab;
+        a.wbar = L.wbar;
+        a.kq = p->kq;
+        a.omega = om;
+        a.nbose = L.nbose;
+        a.sc = L.sc;
+        a.sigma = par->sigma;
+        a.kT = kT;
+        a.C = C;
+        a.ek_c = L.ek_c;
+        a.Uk_c = L.Uk_c;
+        a.ekq_c = L.ekq_c;
+        a.Ukq_c = L.Ukq_c;
+        a.om_c = L.om_c;
+        launch_pair_bwd(prec, a, st);
+        if (dHR) {
+            launch_kq_inverse(nk, qc, q0, nq, p->kq, L.inv, st);
+            launch_gather_state_adjoint(nk, nb, qc, L.inv, L.ek_c, L.Uk_c, L.ekq_c, L.Ukq_c, L.ebar, L.Ubar, st);
+        }
+        if (domega) launch_reduce_omega(nk, qc, nm, L.om_c, acc0, domega + (size_t)q0 * nm, st);
+        if (dgR) {
+            GemmDesc d;   // gbar_nu(R_e, q) = sum_k conj(Phi_k[k][R_e]) Gbar[k][col]
+            d.M = ne;
+            d.N = (int)ncols;
+            d.K = nk;
+            d.A = L.phi_k;
+            d.lda = ne;
+            d.conj_trans_a = 1;
+            d.B = L.G;
+            d.ncb = (int)ncols;
+            d.sBk = ncols;
+            d.C = L.Bnu;
+            d.sCm = ncols;
+            launch_cgemm(prec, d, st);
+            launch_mode_rotate_adjoint(prec, ne, qc, nm, nb, L.nbp, L.Bnu, ev, L.sc, L.gq, st);
+            GemmDesc e;   // dgR[e][p][c] (+)= sum_q conj(Phi_q[q][p]) gbar_a[e][q][c]
+            e.M = np_;
+            e.N = (int)(ne * ncol_g);
+            e.K = qc;
+            e.A = L.phi_q;
+            e.lda = np_;
+            e.conj_trans_a = 1;
+            e.B = L.gq;
+            e.ncb = (int)ncol_g;
+            e.sBe = (long)qc * ncol_g;
+            e.sBk = (long)ncol_g;
+            e.C = dgR;
+            e.sCe = (long)np_ * ncol_g;
+            e.sCm = (long)ncol_g;
+            e.accumulate = (c > 0 || acc0) ? 1 : 0;
+            launch_cgemm(prec, e, st);
+        }
+    }
+    if (dHR) {
+        launch_eigh_adjoint(nk, nb, L.eps, L.U, L.ebar, L.Ubar, par->deg_tol, L.Xbar, st);
+        GemmDesc d;   // dHR[e][ij] (+)= sum_k conj(Phi_k[k][R_e]) Xbar[k][ij]
+        d.M = ne;
+        d.N = nb * nb;
+        d.K = nk;
+        d.A = L.phi_k;
+        d.lda = ne;
+        d.conj_trans_a = 1;
+        d.B = L.Xbar;
+        d.ncb = nb * nb;
+        d.sBk = nb * nb;
+        d.C = dHR;
+        d.sCm = nb * nb;
+        d.accumulate = acc0;
+        launch_cgemm(Prec::F64, d, st);
     }
 }
 
@@ -262,8 +493,13 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
     if (check_common(&s, &p, par, "epw_workspace_size") != EPW_OK) return 0;
     Arena A;
     A.dry = true;
-    Layout L;
-    plan(&s, &p, par, which == EPW_WS_INTERP_G, A, L);
+    if (which == EPW_WS_IMSIGMA_BACKWARD) {
+        BwdLayout L;
+        plan_bwd(&s, &p, par, A, L);
+    } else {
+        Layout L;
+        plan(&s, &p, par, which == EPW_WS_INTERP_G, A, L);
+    }
     return A.used + 256;
 }
 
@@ -321,6 +557,21 @@ extern "C" int epw_imsigma_backward(const epw_system* sys, const epw_points* pts
     clear_error();
     int rc = check_common(sys, pts, par, "epw_imsigma_backward");
     if (rc != EPW_OK) return rc;
-    (void)w; (void)dgR; (void)dHR; (void)domega; (void)ws; (void)ws_bytes; (void)stream;
-    return fail(EPW_ESHAPE, "epw_imsigma_backward: not available yet");
+    if (pts->nk == 0) return EPW_OK;
+    if (!w) return fail(EPW_EINVAL, "epw_imsigma_backward: NULL weights");
+    if (par->dtype != EPW_FP64) return fail(EPW_EDTYPE, "epw_imsigma_backward: only EPW_FP64 is available");
+    Arena dry;
+    dry.dry = true;
+    BwdLayout L;
+    plan_bwd(sys, pts, par, dry, L);
+    if (!ws || ws_bytes < dry.used + 256)
+        return fail(EPW_ENOMEM, "epw_imsigma_backward: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
+    return guarded("epw_imsigma_backward", [&]() {
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        plan_bwd(sys, pts, par, A, L);
+        run_backward(sys, pts, par, L, w, dgR, dHR, domega, (hipStream_t)stream);
+        return EPW_OK;
+    });
 }

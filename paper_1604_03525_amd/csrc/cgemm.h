@@ -1,0 +1,141 @@
+// Complex GEMM building blocks on MFMA 16x16x4 (float64 and float32),
+// shared by the forward and adjoint kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace epw {
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Cx;
+template <> struct Cx<double> { typedef double2 type; typedef d4 acc; };
+template <> struct Cx<float> { typedef float2 type; typedef f4 acc; };
+
+__device__ inline d4 mfma4(double a, double b, d4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ inline f4 mfma4(float a, float b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ inline typename Cx<T>::type cz() {
+    typename Cx<T>::type z;
+    z.x = T(0);
+    z.y = T(0);
+    return z;
+}
+
+
+// ------------------------------------------------------------ GEMM main loop
+//
+// Block tile BM x BN (complex), K step BK, 256 threads = 4 waves; each wave
+// owns a 16 x 64 sub-tile = four 16x16 MFMA blocks.  Operands are staged
+// global -> registers -> LDS (split into re/im planes, K-major) with the
+// next K step's global loads issued before the current step's MFMAs.
+//
+// MFMA 16x16x4 operand layout (f64 and f32): lane l holds A[l%16][l/16] and
+// B[l/16][l%16].  Accumulator element i of lane l is C[crow][l%16] with
+// crow = l/16 + 4i for f64 and 4*(l/16) + i for f32 (measured on gfx950).
+template <typename T> __device__ inline int crow(int lane, int i);
+template <> __device__ inline int crow<double>(int lane, int i) { return (lane >> 4) + 4 * i; }
+template <> __device__ inline int crow<float>(int lane, int i) { return 4 * (lane >> 4) + i; }
+
+template <typename T, int BM, int BN, int BK>
+struct Stage {
+    T a_re[BK][BM];
+    T a_im[BK][BM];
+    T b_re[BK][BN];
+    T b_im[BK][BN];
+};
+
+// A_KMAJOR selects which index of the A tile varies fastest across threads
+// when it is fetched: k (row-major A, default) or m (A read transposed).
+template <typename T, int BM, int BN, int BK, class AF, class BF, bool A_KMAJOR = false>
+__device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>& st, int K, AF afetch, BF bfetch,
+                                      typename Cx<T>::acc (&cr)[4], typename Cx<T>::acc (&ci)[4])
+{
+    typedef typename Cx<T>::type CT;
+    constexpr int WN = BN / 64;
+    constexpr int AE = BM * BK / 256;
+    constexpr int BE = BK * BN / 256;
+    static_assert(AE >= 1 && BE >= 1, "tile too small for 256 threads");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    CT ra[AE], rb[BE];
+    for (int c = 0; c < 4; ++c) {
+        for (int i = 0; i < 4; ++i) {
+            cr[c][i] = T(0);
+            ci[c][i] = T(0);
+        }
+    }
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            const int idx = tid * AE + e;
+            if (A_KMAJOR)
+                ra[e] = afetch(idx % BM, k0 + idx / BM);
+            else
+                ra[e] = afetch(idx / BK, k0 + idx % BK);
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            const int idx = tid * BE + e;
+            rb[e] = bfetch(k0 + idx / BN, idx % BN);
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            const int idx = tid * AE + e;
+            const int m = A_KMAJOR ? idx % BM : idx / BK;
+            const int k = A_KMAJOR ? idx / BM : idx % BK;
+            st.a_re[k][m] = ra[e].x;
+            st.a_im[k][m] = ra[e].y;
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            const int idx = tid * BE + e;
+            st.b_re[idx / BN][idx % BN] = rb[e].x;
+            st.b_im[idx / BN][idx % BN] = rb[e].y;
+        }
+    };
+    gload(0);
+    sstore();
+    __syncthreads();
+    for (int k0 = 0; k0 < K; k0 += BK) {
+        const bool more = k0 + BK < K;
+        if (more) gload(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            const T ar = st.a_re[kr][wm * 16 + (lane & 15)];
+            const T ai = st.a_im[kr][wm * 16 + (lane & 15)];
+            T br[4], bi[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                br[c] = st.b_re[kr][wn * 64 + c * 16 + (lane & 15)];
+                bi[c] = st.b_im[kr][wn * 64 + c * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cr[c] = mfma4(ar, br[c], cr[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ci[c] = mfma4(ar, bi[c], ci[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cr[c] = mfma4(-ai, bi[c], cr[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ci[c] = mfma4(ai, br[c], ci[c]);
+        }
+        __syncthreads();
+        if (more) {
+            sstore();
+            __syncthreads();
+        }
+    }
+}
+
+
+}  // namespace
+}  // namespace epw

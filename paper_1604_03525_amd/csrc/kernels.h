@@ -68,6 +68,67 @@ struct FusedArgs {
 void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t stream);
 int fused_slices(int nk, int nbp, int ncols_tiles, int num_cu);
 
+// ---- k_gemm.hip ----
+// C(m, n) (+)= sum_k A(m, k) B(k, n), complex in `prec` (F64 or F32).
+//   A(m, k) = conj_trans_a ? conj(A[k*lda + m]) : A[m*lda + k]
+//   n = e*ncb + c:  B(k, n) = B[e*sBe + k*sBk + c],  C(m, n) = C[e*sCe + m*sCm + c]
+struct GemmDesc {
+    int M = 0, N = 0, K = 0;
+    const void* A = nullptr;
+    long lda = 0;
+    int conj_trans_a = 0;
+    const void* B = nullptr;
+    long sBe = 0, sBk = 0;
+    int ncb = 1;
+    void* C = nullptr;
+    long sCe = 0, sCm = 0;
+    int accumulate = 0;
+};
+void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream);
+
+// ---- k_backward.hip (adjoint of L = sum_nk w_nk Im Sigma_nk) ----
+struct PairBwdArgs {
+    int nk, nb, nbp, nm;
+    int qc, q0, nq_total;
+    void* G;               // [nk][qc*nm*nbp*nbp] complex(prec): Wannier-basis g_nu(k,q) in,
+                           // adjoint Gbar out (in place)
+    const double* eps;     // [nk][nb]
+    const void* U;         // [nk][nb][nb] c128
+    const double* ftab;    // [nk][nb]
+    const double* wbar;    // [nk][nb] degenerate-averaged loss weights
+    const int32_t* kq;     // [nk][nq_total]
+    const double* omega;   // [qc][nm]
+    const double* nbose;   // [qc][nm]
+    const double* sc;      // [qc][nm]
+    double sigma, kT, C;   // C = pi / (N_q sigma sqrt(pi))
+    double* ek_c;          // [nk][qc][nb]      d/d eps_nk
+    void* Uk_c;            // [nk][qc][nb][nb]  d/dU_k
+    double* ekq_c;         // [nk][qc][nb]      d/d eps_m,k+q
+    void* Ukq_c;           // [nk][qc][nb][nb]  d/dU_k+q
+    double* om_c;          // [nk][qc][nm]      d/d omega
+};
+void launch_pair_bwd(Prec prec, const PairBwdArgs& a, hipStream_t stream);
+// inv[k'][j] = k with kq[k][q0+j] = k', else -1   (j < qc)
+void launch_kq_inverse(int nk, int qc, int q0, int nq_total, const int32_t* kq, int32_t* inv,
+                       hipStream_t stream);
+// ebar[k] += sum_j ek_c[k][j] + ekq_c[inv[k][j]][j];  Ubar likewise (fixed order)
+void launch_gather_state_adjoint(int nk, int nb, int qc, const int32_t* inv, const double* ek_c,
+                                 const void* Uk_c, const double* ekq_c, const void* Ukq_c,
+                                 double* ebar, void* Ubar, hipStream_t stream);
+// domega[q][nu] (+)= sum_k om_c[k][q][nu] (fixed order)
+void launch_reduce_omega(int nk, int qc, int nm, const double* om_c, int accumulate, double* domega,
+                         hipStream_t stream);
+// gbar_a[e][q][a][i][j] = sum_nu conj(e_q[a][nu]) sc[q][nu] gbar_nu[e][q][nu][i][j]  (i, j < nb)
+void launch_mode_rotate_adjoint(Prec prec, int ne, int nq, int nm, int nb, int nbp, const void* gnu,
+                                const void* evec, const double* sc, void* ga, hipStream_t stream);
+// Xbar(k) from (eps, U, ebar, Ubar): Hermitian part of U (F o U^dag Ubar + diag ebar) U^dag
+void launch_eigh_adjoint(int nk, int nb, const double* eps, const void* U, const double* ebar,
+                         const void* Ubar, double deg_tol, void* Xbar, hipStream_t stream);
+// f64 fill
+void launch_fill(size_t n, double v, double* p, hipStream_t stream);
+// convert c64 -> c128 with optional accumulate
+void launch_c64_to_c128(size_t n, const void* in, int accumulate, void* out, hipStream_t stream);
+
 // imsig[k][n] = (acc ? imsig : 0) + scale * sum_s part[s][k][n]
 void launch_reduce_partials(int nk, int nb, int S, const double* part, double scale,
                             int accumulate, double* imsig, hipStream_t stream);

@@ -1,0 +1,126 @@
+"""Hand-written adjoint of L = sum w Im Sigma against the FP64 CPU reference
+gradient (torch autograd of the oracle forward) and central finite
+differences of the HIP forward; tolerance 1e-6 relative (infinity norm over
+all entries for the reference, over the checked entries for FD)."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import interp, lattice, torch_ref
+from paper_1604_03525_amd import autograd, epw
+from paper_1604_03525_amd import inputs as I
+from tests.helpers import fcc_small_case, rel_err, toy_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _setup(c, kg):
+    om, ev = interp.phonons(c["DR"], c["R"], c["nd"], c["q"])      # oracle phonon states
+    w = I.loss_weights(len(c["k"]), c["HR"].shape[1], 1)
+    kw = dict(Re=c["R"], ndeg_e=c["nd"], Rp=c["R"], ndeg_p=c["nd"], kpoints=c["k"], qpoints=c["q"],
+              kq=c["kq"], T=c["T"], mu=c["mu"], sigma=c["sigma"])
+    return om, ev, w, kw
+
+
+def _hip_grads(c, om, ev, w):
+    g = torch.tensor(c["gR"], device=DEV, requires_grad=True)
+    h = torch.tensor(c["HR"], device=DEV, requires_grad=True)
+    o = torch.tensor(om, device=DEV, requires_grad=True)
+    ims = autograd.imsigma(g, h, o, torch.as_tensor(ev).to(DEV), c["R"], c["nd"], c["R"], c["nd"], c["k"], c["q"],
+                           c["kq"], T=c["T"], mu=c["mu"], sigma=c["sigma"])
+    L = torch.sum(torch.as_tensor(w, device=DEV) * ims)
+    L.backward()
+    return float(L.detach()), g.grad.cpu().numpy(), h.grad.cpu().numpy(), o.grad.cpu().numpy()
+
+
+@pytest.mark.parametrize("case", ["toy12", "fcc3"])
+def test_adjoint_matches_reference_gradient(case):
+    if case == "toy12":
+        c = toy_case((12, 12, 12))          # the differentiation workload: 12^3 k x 12^3 q
+    else:
+        c = fcc_small_case(nb=3, kg=(3, 3, 3))
+    _say("gradients", case)
+    om, ev, w, kw = _setup(c, None)
+    L_ref, ims_ref, dg_ref, dh_ref, dom_ref = torch_ref.loss_and_grads(c["gR"], c["HR"], om, ev, w, **kw)
+    L, dg, dh, dom = _hip_grads(c, om, ev, w)
+    _say("  L", L, L_ref, "rel errs g/h/omega", rel_err(dg, dg_ref), rel_err(dh, dh_ref), rel_err(dom, dom_ref))
+    assert abs(L - L_ref) < 1e-10 * abs(L_ref)
+    assert rel_err(dg, dg_ref) < 1e-6
+    assert rel_err(dh, dh_ref) < 1e-6
+    assert rel_err(dom, dom_ref) < 1e-6
+    # Euler: L is homogeneous of degree 2 in g
+    assert abs(np.sum(np.real(np.conj(dg) * c["gR"])) - 2 * L) < 1e-9 * abs(L)
+
+
+def test_adjoint_finite_differences_toy12():
+    """Central differences (h = 1e-6) of the HIP forward on 64 random entries
+    per gradient (entries from seed 4)."""
+    c = toy_case((12, 12, 12))
+    om, ev, w, kw = _setup(c, None)
+    L0, dg, dh, dom = _hip_grads(c, om, ev, w)
+    sysd_cache = {}
+    pts = epw.Points(c["k"], c["q"], c["kq"], omega=om, evec=ev, device=DEV)
+    par = epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"])
+    wt = torch.as_tensor(w, device=DEV)
+    ws = epw.Workspace(DEV)
+
+    def loss(g=None, h=None, o=None):
+        s = epw.System(c["R"], c["nd"], c["R"], c["nd"], c["HR"] if h is None else h, None,
+                       c["gR"] if g is None else g, DEV)
+        p = pts if o is None else epw.Points(c["k"], c["q"], c["kq"], omega=o, evec=ev, device=DEV)
+        return float(torch.sum(wt * epw.epw_imsigma(s, p, par, workspace=ws)))
+
+    rng = np.random.default_rng(4)
+    hs = 1e-6
+    _say("FD gR")
+    worst = 0.0
+    flat = c["gR"].reshape(-1)
+    for idx in rng.choice(flat.size, 64, replace=False):
+        for unit in (1.0, 1j):
+            gp = flat.copy(); gp[idx] += hs * unit
+            gm = flat.copy(); gm[idx] -= hs * unit
+            fd = (loss(g=gp.reshape(c["gR"].shape)) - loss(g=gm.reshape(c["gR"].shape))) / (2 * hs)
+            an = dg.reshape(-1)[idx]
+            an = an.real if unit == 1.0 else an.imag
+            worst = max(worst, abs(fd - an))
+    assert worst < 1e-6 * np.abs(dg).max(), worst / np.abs(dg).max()
+    _say("FD HR")
+    worst = 0.0
+    flatH = c["HR"].reshape(-1)
+    for idx in rng.choice(flatH.size, min(64, flatH.size), replace=False):
+        for unit in (1.0, 1j):
+            hp = flatH.copy(); hp[idx] += hs * unit
+            hm = flatH.copy(); hm[idx] -= hs * unit
+            fd = (loss(h=hp.reshape(c["HR"].shape)) - loss(h=hm.reshape(c["HR"].shape))) / (2 * hs)
+            an = dh.reshape(-1)[idx]
+            an = an.real if unit == 1.0 else an.imag
+            worst = max(worst, abs(fd - an))
+    assert worst < 1e-6 * np.abs(dh).max(), worst / np.abs(dh).max()
+    _say("FD omega")
+    worst = 0.0
+    kept = np.flatnonzero(om.reshape(-1) >= 2e-3)
+    for idx in rng.choice(kept, 64, replace=False):
+        op = om.reshape(-1).copy(); op[idx] += hs
+        omn = om.reshape(-1).copy(); omn[idx] -= hs
+        fd = (loss(o=op.reshape(om.shape)) - loss(o=omn.reshape(om.shape))) / (2 * hs)
+        worst = max(worst, abs(fd - dom.reshape(-1)[idx]))
+    assert worst < 1e-6 * np.abs(dom).max(), worst / np.abs(dom).max()
+
+
+def test_adjoint_chunking_and_accumulate():
+    """q chunks of 5 and the accumulate flag give the same gradients."""
+    c = fcc_small_case(nb=2, kg=(3, 3, 3), seed=5)
+    om, ev, w, kw = _setup(c, None)
+    sysd = epw.System(c["R"], c["nd"], c["R"], c["nd"], c["HR"], None, c["gR"], DEV)
+    pts = epw.Points(c["k"], c["q"], c["kq"], omega=om, evec=ev, device=DEV)
+    a = epw.epw_imsigma_backward(sysd, pts, epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"]), w)
+    b = epw.epw_imsigma_backward(sysd, pts, epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"], chunk_q=5), w)
+    for x, y in zip(a, b):
+        assert rel_err(y.cpu().numpy(), x.cpu().numpy()) < 1e-12
