@@ -48,7 +48,7 @@ int check_common(const epw_system* s, const epw_points* p, const epw_params* par
 
 struct Layout {
     Prec prec;
-    int nbp, Q, nchunks, S;
+    int nbp, Q, nchunks, S, kpad;
     // fixed tables
     double* eps = nullptr;
     void* U = nullptr;
@@ -79,8 +79,11 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, bool 
     const size_t cb = cbytes(L.prec);
     const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
     const bool given = p->omega && p->evec;
+    const bool bf = L.prec == Prec::BF16X2;
+    L.kpad = (ne + 31) / 32 * 32;
+    const size_t bcol_bytes = bf ? 8 * (size_t)L.kpad : cb * (size_t)ne;   // B bytes per column
     // chunk size
-    const size_t per_q = cb * ((size_t)ne * nm * nb * nb + (size_t)ne * nm * L.nbp * L.nbp + np_) +
+    const size_t per_q = cb * ((size_t)ne * nm * nb * nb + np_) + bcol_bytes * nm * L.nbp * L.nbp +
                          (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm;
     long Q = par->chunk_q > 0 ? par->chunk_q : (long)(AUTO_CHUNK_BYTES / per_q);
     if (Q < 1) Q = 1;
@@ -91,7 +94,7 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, bool 
     L.eps = (double*)A.take(8 * (size_t)nk * nb);
     L.U = A.take(16 * (size_t)nk * nb * nb);
     L.ftab = (double*)A.take(8 * (size_t)nk * nb);
-    L.phi_k = A.take(cb * (size_t)nk * ne);
+    L.phi_k = A.take(bf ? 8 * (size_t)nk * L.kpad : cb * (size_t)nk * ne);
     if (L.prec != Prec::F64) L.gR_t = A.take(cb * (size_t)ne * np_ * nm * nb * nb);
     if (!given) {
         L.omega_c = (double*)A.take(8 * (size_t)L.Q * nm);
@@ -101,7 +104,7 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, bool 
     L.nbose = (double*)A.take(8 * (size_t)L.Q * nm);
     L.phi_q = A.take(cb * (size_t)L.Q * np_);
     L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
-    L.Bnu = A.take(cb * (size_t)ne * L.Q * nm * L.nbp * L.nbp);
+    L.Bnu = A.take(bcol_bytes * L.Q * nm * L.nbp * L.nbp);
     if (!store) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
 }
 
@@ -137,9 +140,11 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
                            L.eps, L.U, st);
     }
     launch_fermi_table((size_t)nk * nb, L.eps, par->mu, par->T, L.ftab, st);
-    launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_k, st);
+    const bool bf = prec == Prec::BF16X2;
+    const Prec rprec = bf ? Prec::F32 : prec;      // precision of the R_p -> q step
+    launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, bf ? L.kpad : ne, L.phi_k, st);
     const void* gsrc = s->gR;
-    if (prec == Prec::F32) {
+    if (prec != Prec::F64) {
         launch_c128_to_c64((size_t)ne * np_ * nm * nb * nb, s->gR, L.gR_t, st);
         gsrc = L.gR_t;
     }
@@ -161,14 +166,17 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
             ev = L.evec_c;
         }
         launch_phonon_factors(qc, nm, om, par->omega_cut, par->T, L.sc, L.nbose, st);
-        launch_phase_table(prec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
+        launch_phase_table(rprec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
         {
             StageTimer t(EPW_STAGE_GEMM_RP, st);
-            launch_cgemm(prec, rp_desc(qc, ne, np_, nm * nb * nb, L.phi_q, gsrc, L.gq), st);
+            launch_cgemm(rprec, rp_desc(qc, ne, np_, nm * nb * nb, L.phi_q, gsrc, L.gq), st);
         }
         {
             StageTimer t(EPW_STAGE_MODEROT, st);
-            launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st);
+            if (bf)
+                launch_mode_rotate_bf16(ne, qc, nm, nb, L.nbp, L.kpad, L.gq, ev, L.sc, L.Bnu, st);
+            else
+                launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st);
         }
         FusedArgs a;
         a.nk = nk;
@@ -180,7 +188,9 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.q0 = q0;
         a.nq_total = nq;
         a.phi_k = L.phi_k;
-        a.ldk = ne;
+        a.ldk = bf ? L.kpad : ne;
+        a.ldk_b = L.kpad;
+        a.kpad = L.kpad;
         a.B = L.Bnu;
         a.eps = L.eps;
         a.U = L.U;
@@ -510,7 +520,6 @@ extern "C" int epw_interp_g(const epw_system* sys, const epw_points* pts, const 
     if (rc != EPW_OK) return rc;
     if (pts->nk == 0 || pts->nq == 0) return EPW_OK;
     if (!gkq) return fail(EPW_EINVAL, "epw_interp_g: NULL output");
-    if (par->dtype == EPW_SPLIT_BF16) return fail(EPW_EDTYPE, "epw_interp_g: split-bf16 not available yet");
     Arena dry;
     dry.dry = true;
     Layout L;
@@ -534,7 +543,6 @@ extern "C" int epw_imsigma(const epw_system* sys, const epw_points* pts, const e
     if (rc != EPW_OK) return rc;
     if (pts->nk == 0) return EPW_OK;
     if (!imsig) return fail(EPW_EINVAL, "epw_imsigma: NULL output");
-    if (par->dtype == EPW_SPLIT_BF16) return fail(EPW_EDTYPE, "epw_imsigma: split-bf16 not available yet");
     Arena dry;
     dry.dry = true;
     Layout L;

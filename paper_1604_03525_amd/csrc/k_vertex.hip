@@ -191,21 +191,167 @@ template <int NBP> struct FusedShape {
     static constexpr int BM = 4096 / BN;          // 64 x 64 or 16 x 256
 };
 
-template <typename T, int NBP, bool STORE>
+// ---- split-bf16 tile: x = hi + lo (bf16 each), products hi.hi + hi.lo + lo.hi
+// on MFMA 16x16x32 bf16 with float32 accumulation.  Operands are four bf16
+// planes (re_hi, re_lo, im_hi, im_lo), K contiguous: A [4][rows][lda],
+// B [4][cols][ldb]; K is padded with zeros to a multiple of 32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline bf16x8 as_bf8(uint4 v) { return __builtin_bit_cast(bf16x8, v); }
+__device__ inline uint4 neg_bf8(uint4 v) {
+    v.x ^= 0x80008000u;
+    v.y ^= 0x80008000u;
+    v.z ^= 0x80008000u;
+    v.w ^= 0x80008000u;
+    return v;
+}
+__device__ inline f4 mfma_bf(uint4 a, uint4 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf8(a), as_bf8(b), c, 0, 0, 0);
+}
+
+template <int BM, int BN>
+struct BfStage {
+    static constexpr int BKP = 40;                 // 32 + 8 bf16 of padding per row
+    uint16_t a[4][BM][BKP];
+    uint16_t b[4][BN][BKP];
+};
+
+// Computes the BM x BN complex tile and leaves it in registers (same
+// fragment layout as the f32 MFMA: element i of lane l is row 4(l/16)+i).
+template <int BM, int BN>
+__device__ inline void bf16_mainloop(BfStage<BM, BN>& st, const uint16_t* __restrict__ A, long lda, long aplane,
+                                     int arows, int m0, const uint16_t* __restrict__ B, long ldb, long bplane,
+                                     long bcols, long n0, int Kpad, f4 (&cr)[4], f4 (&ci)[4])
+{
+    constexpr int WN = BN / 64;
+    constexpr int ACH = 4 * BM * 4 / 256;          // 16-byte chunks per thread
+    constexpr int BCH = 4 * BN * 4 / 256;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    uint4 ra[ACH], rb[BCH];
+    for (int c = 0; c < 4; ++c)
+        for (int i = 0; i < 4; ++i) {
+            cr[c][i] = 0.f;
+            ci[c][i] = 0.f;
+        }
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < ACH; ++e) {
+            const int c = tid * ACH + e;
+            const int p = c / (BM * 4), row = (c / 4) % BM, part = c % 4;
+            const int grow = m0 + row;
+            ra[e] = grow < arows ? *reinterpret_cast<const uint4*>(A + p * aplane + (size_t)grow * lda + k0 + part * 8)
+                                 : make_uint4(0, 0, 0, 0);
+        }
+#pragma unroll
+        for (int e = 0; e < BCH; ++e) {
+            const int c = tid * BCH + e;
+            const int p = c / (BN * 4), col = (c / 4) % BN, part = c % 4;
+            const long gcol = n0 + col;
+            rb[e] = gcol < bcols ? *reinterpret_cast<const uint4*>(B + p * bplane + (size_t)gcol * ldb + k0 + part * 8)
+                                 : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int e = 0; e < ACH; ++e) {
+            const int c = tid * ACH + e;
+            const int p = c / (BM * 4), row = (c / 4) % BM, part = c % 4;
+            *reinterpret_cast<uint4*>(&st.a[p][row][part * 8]) = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < BCH; ++e) {
+            const int c = tid * BCH + e;
+            const int p = c / (BN * 4), col = (c / 4) % BN, part = c % 4;
+            *reinterpret_cast<uint4*>(&st.b[p][col][part * 8]) = rb[e];
+        }
+    };
+    gload(0);
+    sstore();
+    __syncthreads();
+    const int koff = 8 * (lane >> 4);
+    for (int k0 = 0; k0 < Kpad; k0 += 32) {
+        const bool more = k0 + 32 < Kpad;
+        if (more) gload(k0 + 32);
+        const int arow = wm * 16 + (lane & 15);
+        const uint4 arh = *reinterpret_cast<const uint4*>(&st.a[0][arow][koff]);
+        const uint4 arl = *reinterpret_cast<const uint4*>(&st.a[1][arow][koff]);
+        const uint4 aih = *reinterpret_cast<const uint4*>(&st.a[2][arow][koff]);
+        const uint4 ail = *reinterpret_cast<const uint4*>(&st.a[3][arow][koff]);
+        const uint4 naih = neg_bf8(aih), nail = neg_bf8(ail);
+        uint4 brh[4], brl[4], bih[4], bil[4];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const int bcol = wn * 64 + c * 16 + (lane & 15);
+            brh[c] = *reinterpret_cast<const uint4*>(&st.b[0][bcol][koff]);
+            brl[c] = *reinterpret_cast<const uint4*>(&st.b[1][bcol][koff]);
+            bih[c] = *reinterpret_cast<const uint4*>(&st.b[2][bcol][koff]);
+            bil[c] = *reinterpret_cast<const uint4*>(&st.b[3][bcol][koff]);
+        }
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arh, brh[c], cr[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arh, bih[c], ci[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arh, brl[c], cr[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arh, bil[c], ci[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arl, brh[c], cr[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arl, bih[c], ci[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(naih, bih[c], cr[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(aih, brh[c], ci[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(naih, bil[c], cr[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(aih, brl[c], ci[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(nail, bih[c], cr[c]);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(ail, brh[c], ci[c]);
+        __syncthreads();
+        if (more) {
+            sstore();
+            __syncthreads();
+        }
+    }
+}
+
+// MODE 0: float64 MFMA, float64 epilogue.  MODE 1: float32 MFMA, MODE 2:
+// split-bf16 MFMA; both with a float32 rotation and float32 weights from
+// float64 energy differences, accumulated in float64.
+template <int MODE> struct ModeTypes;
+template <> struct ModeTypes<0> { typedef double T; typedef double2 CT; typedef double TE; typedef double2 CE; };
+template <> struct ModeTypes<1> { typedef float T; typedef float2 CT; typedef float TE; typedef float2 CE; };
+template <> struct ModeTypes<2> { typedef float T; typedef float2 CT; typedef float TE; typedef float2 CE; };
+
+__device__ inline double2 mk2(double x, double y) { return make_double2(x, y); }
+__device__ inline float2 mk2(float x, float y) { return make_float2(x, y); }
+__device__ inline double fexp(double x) { return exp(x); }
+__device__ inline float fexp(float x) { return __expf(x); }
+
+template <int MODE, int NBP, bool STORE>
 __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
 {
-    typedef typename Cx<T>::type CT;
+    typedef typename ModeTypes<MODE>::T T;
+    typedef typename ModeTypes<MODE>::CT CT;
+    typedef typename ModeTypes<MODE>::TE TE;
+    typedef typename ModeTypes<MODE>::CE CE;
     constexpr int BM = FusedShape<NBP>::BM, BN = FusedShape<NBP>::BN, BK = 16;
     constexpr int NB2 = NBP * NBP;
     constexpr int NBLK = BN / NB2;                 // band blocks per tile
     constexpr int TPR = 256 / BM;                  // threads per k row
     constexpr int JN = (NBP + TPR - 1) / TPR;      // n values per thread when nb > TPR
     typedef Stage<T, BM, BN, BK> St;
+    typedef BfStage<BM, BN> Sb;
     constexpr size_t CBYTES = sizeof(CT) * BM * BN;
-    constexpr size_t SBYTES = sizeof(St) > CBYTES ? sizeof(St) : CBYTES;
+    constexpr size_t STB = MODE == 2 ? sizeof(Sb) : sizeof(St);
+    constexpr size_t SBYTES = STB > CBYTES ? STB : CBYTES;
     __shared__ __attribute__((aligned(16))) char smem[SBYTES];
     __shared__ double red[256];
-    St& st = *reinterpret_cast<St*>(smem);
     CT* Cs = reinterpret_cast<CT*>(smem);
 
     // XCD-aware remap: consecutive workgroup ids land on different XCDs
@@ -225,9 +371,6 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
     const int r = tid / TPR, sub = tid % TPR;
     const int k = m0 + r;
     const long ncols = (long)a.qc * nm * NB2;
-    const long ldb = ncols;
-    const CT* phi = reinterpret_cast<const CT*>(a.phi_k);
-    const CT* Bm = reinterpret_cast<const CT*>(a.B);
     const double2* U = reinterpret_cast<const double2*>(a.U);
 
     // thread -> (n, block subset)
@@ -239,37 +382,58 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
     const bool active_thr = active_row && (!fewn || n_single < nb);
 
     double acc[JN];
+    #pragma unroll
     for (int j = 0; j < JN; ++j) acc[j] = 0.0;
 
     const double inv_sig = 1.0 / a.sigma;
     double eps_k[JN];
-    double2 Uk[JN][NBP];
+    CE Uk[JN][NBP];
+    #pragma unroll
     for (int j = 0; j < JN; ++j) {
         const int n = fewn ? n_single : sub + j * TPR;
         eps_k[j] = 0.0;
-        for (int jj = 0; jj < NBP; ++jj) Uk[j][jj] = make_double2(0.0, 0.0);
+        for (int jj = 0; jj < NBP; ++jj) Uk[j][jj] = mk2(TE(0), TE(0));
         if (active_thr && n < nb) {
             eps_k[j] = a.eps[(size_t)k * nb + n];
-            for (int jj = 0; jj < nb; ++jj) Uk[j][jj] = U[((size_t)k * nb + jj) * nb + n];
+            for (int jj = 0; jj < nb; ++jj) {
+                const double2 u = U[((size_t)k * nb + jj) * nb + n];
+                Uk[j][jj] = mk2((TE)u.x, (TE)u.y);
+            }
         }
     }
 
     for (int nt = s; nt < tiles_n; nt += a.S) {
         const long n0 = (long)nt * BN;
-        auto afetch = [&](int m, int kk) -> CT {
-            const int row = m0 + m;
-            if (row < a.nk && kk < a.ne) return phi[(size_t)row * a.ldk + kk];
-            return cz<T>();
-        };
-        auto bfetch = [&](int kk, int n) -> CT {
-            const long col = n0 + n;
-            if (kk < a.ne && col < ncols) return Bm[(size_t)kk * ldb + col];
-            return cz<T>();
-        };
-        typename Cx<T>::acc cr[4], ci[4];
-        cgemm_mainloop<T, BM, BN, BK>(st, a.ne, afetch, bfetch, cr, ci);
-        // C fragments -> LDS tile [BM][BN]
-        {
+        if constexpr (MODE == 2) {
+            f4 cr[4], ci[4];
+            const uint16_t* Ap = reinterpret_cast<const uint16_t*>(a.phi_k);
+            const uint16_t* Bp = reinterpret_cast<const uint16_t*>(a.B);
+            bf16_mainloop<BM, BN>(*reinterpret_cast<Sb*>(smem), Ap, a.ldk, (long)a.nk * a.ldk, a.nk, m0, Bp,
+                                  a.ldk_b, ncols * a.ldk_b, ncols, n0, a.kpad, cr, ci);
+            const int lane = tid & 63, wave = tid >> 6;
+            constexpr int WN = BN / 64;
+            const int wm = wave / WN, wn = wave % WN;
+            for (int c = 0; c < 4; ++c)
+                for (int i = 0; i < 4; ++i) {
+                    const int row = wm * 16 + 4 * (lane >> 4) + i;
+                    const int col = wn * 64 + c * 16 + (lane & 15);
+                    Cs[row * BN + col] = make_float2(cr[c][i], ci[c][i]);
+                }
+        } else {
+            const CT* phi = reinterpret_cast<const CT*>(a.phi_k);
+            const CT* Bm = reinterpret_cast<const CT*>(a.B);
+            auto afetch = [&](int m, int kk) -> CT {
+                const int row = m0 + m;
+                if (row < a.nk && kk < a.ne) return phi[(size_t)row * a.ldk + kk];
+                return cz<T>();
+            };
+            auto bfetch = [&](int kk, int n) -> CT {
+                const long col = n0 + n;
+                if (kk < a.ne && col < ncols) return Bm[(size_t)kk * ncols + col];
+                return cz<T>();
+            };
+            typename Cx<T>::acc cr[4], ci[4];
+            cgemm_mainloop<T, BM, BN, BK>(*reinterpret_cast<St*>(smem), a.ne, afetch, bfetch, cr, ci);
             const int lane = tid & 63, wave = tid >> 6;
             constexpr int WN = BN / 64;
             const int wm = wave / WN, wn = wave % WN;
@@ -297,50 +461,53 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
                 if ((unsigned)kq >= (unsigned)a.nk) continue;   // invalid map entry: no access
                 const double w = a.omega[(size_t)ql * nm + nu];
                 const double nB = a.nbose[(size_t)ql * nm + nu];
-                const CT* G = Cs + r * BN + b * NB2;
+                const CT* Gt = Cs + r * BN + b * NB2;
+                #pragma unroll
                 for (int j = 0; j < JN; ++j) {
                     const int n = fewn ? n_single : sub + j * TPR;
                     if (n >= nb) continue;
                     // v = G U_k[:, n]
-                    double2 v[NBP];
+                    CE v[NBP];
 #pragma unroll
                     for (int i = 0; i < NBP; ++i) {
-                        double vr = 0.0, vi = 0.0;
+                        TE vr = TE(0), vi = TE(0);
                         if (i < nb) {
 #pragma unroll
                             for (int jj = 0; jj < NBP; ++jj) {
                                 if (jj < nb) {
-                                    const CT g = G[i * NBP + jj];
-                                    const double2 u = Uk[j][jj];
-                                    vr += (double)g.x * u.x - (double)g.y * u.y;
-                                    vi += (double)g.x * u.y + (double)g.y * u.x;
+                                    const CT g = Gt[i * NBP + jj];
+                                    const CE u = Uk[j][jj];
+                                    vr += (TE)g.x * u.x - (TE)g.y * u.y;
+                                    vi += (TE)g.x * u.y + (TE)g.y * u.x;
                                 }
                             }
                         }
-                        v[i] = make_double2(vr, vi);
+                        v[i] = mk2(vr, vi);
                     }
                     for (int m = 0; m < nb; ++m) {
-                        double gr = 0.0, gi = 0.0;
+                        TE gr = TE(0), gi = TE(0);
 #pragma unroll
                         for (int i = 0; i < NBP; ++i) {
                             if (i < nb) {
-                                const double2 u = U[((size_t)kq * nb + i) * nb + m];
+                                const double2 ud = U[((size_t)kq * nb + i) * nb + m];
+                                const TE ux = (TE)ud.x, uy = (TE)ud.y;
                                 // conj(u) * v_i
-                                gr += u.x * v[i].x + u.y * v[i].y;
-                                gi += u.x * v[i].y - u.y * v[i].x;
+                                gr += ux * v[i].x + uy * v[i].y;
+                                gi += ux * v[i].y - uy * v[i].x;
                             }
                         }
                         if (STORE) {
                             reinterpret_cast<double2*>(a.gkq)
                                 [((((size_t)k * a.nq_total + q) * nm + nu) * nb + m) * nb + n] =
-                                make_double2(gr, gi);
+                                make_double2((double)gr, (double)gi);
                         } else {
                             const double em = a.eps[(size_t)kq * nb + m];
                             const double fm = a.ftab[(size_t)kq * nb + m];
                             const double x = eps_k[j] - em;
                             const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
-                            const double W = (nB + fm) * exp(-y1 * y1) + (nB + 1.0 - fm) * exp(-y2 * y2);
-                            acc[j] += (gr * gr + gi * gi) * W;
+                            const TE W = (TE)(nB + fm) * fexp((TE)(-y1 * y1)) +
+                                         (TE)(nB + 1.0 - fm) * fexp((TE)(-y2 * y2));
+                            acc[j] += (double)((gr * gr + gi * gi) * W);
                         }
                     }
                 }
@@ -359,9 +526,86 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
             a.part[((size_t)s * a.nk + k) * nb + n_single] = t;
         }
     } else if (active_row) {
+        #pragma unroll
         for (int j = 0; j < JN; ++j) {
             const int n = sub + j * TPR;
             if (n < nb) a.part[((size_t)s * a.nk + k) * nb + n] = acc[j];
+        }
+    }
+}
+
+// a6 for the split-bf16 path: float32 g(R_e,q) [ne][qc][nm*nb*nb] ->
+// four bf16 planes [4][qc*nm*NBP*NBP][kpad] with R_e contiguous (the K index
+// of the R_e -> k contraction), transposed through LDS in 64 x 64 tiles.
+__global__ __launch_bounds__(256) void mode_rotate_bf16_kernel(int ne, int qc, int nm, int nb, int nbp, int kpad,
+                                                              const float2* __restrict__ in,
+                                                              const double2* __restrict__ evec,
+                                                              const double* __restrict__ sc,
+                                                              uint16_t* __restrict__ out)
+{
+    __shared__ float2 tile[64][65];
+    const int q = blockIdx.x;
+    const int e0 = blockIdx.y * 64;
+    const int nbp2 = nbp * nbp;
+    const long ncols = (long)qc * nm * nbp2;
+    const long plane = ncols * kpad;
+    const int tid = threadIdx.x;
+    for (int nu = 0; nu < nm; ++nu) {
+        const float s = (float)sc[(size_t)q * nm + nu];
+        for (int ij0 = 0; ij0 < nbp2; ij0 += 64) {
+            // compute: item (e_local, ij_local), ij fastest for coalesced reads
+            for (int it = tid; it < 64 * 64; it += 256) {
+                const int el = it / 64, il = it % 64;
+                const int e = e0 + el, ij = ij0 + il;
+                float2 v = make_float2(0.f, 0.f);
+                if (ij < nbp2 && e < ne && s != 0.f) {
+                    const int i = ij / nbp, j = ij % nbp;
+                    if (i < nb && j < nb) {
+                        const float2* x = in + ((size_t)e * qc + q) * nm * nb * nb + i * nb + j;
+                        float re = 0.f, im = 0.f;
+                        for (int aa = 0; aa < nm; ++aa) {
+                            const double2 ev = evec[((size_t)q * nm + aa) * nm + nu];
+                            const float2 g = x[(size_t)aa * nb * nb];
+                            re += g.x * (float)ev.x - g.y * (float)ev.y;
+                            im += g.x * (float)ev.y + g.y * (float)ev.x;
+                        }
+                        v = make_float2(re * s, im * s);
+                    }
+                }
+                tile[il][el] = v;
+            }
+            __syncthreads();
+            // write: row (column of B) ij, 8 consecutive R_e per item
+            for (int it = tid; it < 64 * 8; it += 256) {
+                const int il = it / 8, part = it % 8;
+                const int ij = ij0 + il;
+                if (ij >= nbp2) continue;
+                const int eb = e0 + part * 8;
+                if (eb >= kpad) continue;
+                const long col = ((long)q * nm + nu) * nbp2 + ij;
+                uint32_t hr[4], lr[4], hi[4], li[4];
+                for (int t = 0; t < 4; ++t) {
+                    hr[t] = lr[t] = hi[t] = li[t] = 0u;
+                }
+                for (int t = 0; t < 8; ++t) {
+                    const float2 v = tile[il][part * 8 + t];
+                    const __hip_bfloat16 xh = __float2bfloat16(v.x);
+                    const __hip_bfloat16 xl = __float2bfloat16(v.x - __bfloat162float(xh));
+                    const __hip_bfloat16 yh = __float2bfloat16(v.y);
+                    const __hip_bfloat16 yl = __float2bfloat16(v.y - __bfloat162float(yh));
+                    const int sh = 16 * (t & 1);
+                    hr[t >> 1] |= (uint32_t)__builtin_bit_cast(uint16_t, xh) << sh;
+                    lr[t >> 1] |= (uint32_t)__builtin_bit_cast(uint16_t, xl) << sh;
+                    hi[t >> 1] |= (uint32_t)__builtin_bit_cast(uint16_t, yh) << sh;
+                    li[t >> 1] |= (uint32_t)__builtin_bit_cast(uint16_t, yl) << sh;
+                }
+                uint16_t* o = out + (size_t)col * kpad + eb;
+                *reinterpret_cast<uint4*>(o) = make_uint4(hr[0], hr[1], hr[2], hr[3]);
+                *reinterpret_cast<uint4*>(o + plane) = make_uint4(lr[0], lr[1], lr[2], lr[3]);
+                *reinterpret_cast<uint4*>(o + 2 * plane) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+                *reinterpret_cast<uint4*>(o + 3 * plane) = make_uint4(li[0], li[1], li[2], li[3]);
+            }
+            __syncthreads();
         }
     }
 }
@@ -400,7 +644,7 @@ __global__ void degenerate_average_kernel(int nk, int nb, const double* __restri
 
 inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
-template <typename T, int NBP>
+template <int MODE, int NBP>
 void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     constexpr int BM = FusedShape<NBP>::BM, BN = FusedShape<NBP>::BN;
     const int tiles_m = (a.nk + BM - 1) / BM;
@@ -411,20 +655,20 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     (void)num_cu;
     (void)tiles_n;
     if (a.gkq)
-        fused_k_kernel<T, NBP, true><<<dim3((unsigned)G), dim3(256), 0, stream>>>(a, tiles_m, tiles_n);
+        fused_k_kernel<MODE, NBP, true><<<dim3((unsigned)G), dim3(256), 0, stream>>>(a, tiles_m, tiles_n);
     else
-        fused_k_kernel<T, NBP, false><<<dim3((unsigned)G), dim3(256), 0, stream>>>(a, tiles_m, tiles_n);
+        fused_k_kernel<MODE, NBP, false><<<dim3((unsigned)G), dim3(256), 0, stream>>>(a, tiles_m, tiles_n);
     launch_check("fused_k_kernel");
 }
 
-template <typename T>
+template <int MODE>
 void launch_fused_nbp(const FusedArgs& a, int num_cu, hipStream_t stream) {
     switch (a.nbp) {
-        case 1: launch_fused_t<T, 1>(a, num_cu, stream); break;
-        case 2: launch_fused_t<T, 2>(a, num_cu, stream); break;
-        case 4: launch_fused_t<T, 4>(a, num_cu, stream); break;
-        case 8: launch_fused_t<T, 8>(a, num_cu, stream); break;
-        case 16: launch_fused_t<T, 16>(a, num_cu, stream); break;
+        case 1: launch_fused_t<MODE, 1>(a, num_cu, stream); break;
+        case 2: launch_fused_t<MODE, 2>(a, num_cu, stream); break;
+        case 4: launch_fused_t<MODE, 4>(a, num_cu, stream); break;
+        case 8: launch_fused_t<MODE, 8>(a, num_cu, stream); break;
+        case 16: launch_fused_t<MODE, 16>(a, num_cu, stream); break;
         default: break;
     }
 }
@@ -501,9 +745,11 @@ int fused_slices(int nk, int nbp, int tiles_n, int num_cu) {
 void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t stream) {
     if (a.nk == 0 || a.qc == 0) return;
     if (prec == Prec::F64)
-        launch_fused_nbp<double>(a, num_cu, stream);
+        launch_fused_nbp<0>(a, num_cu, stream);
+    else if (prec == Prec::F32)
+        launch_fused_nbp<1>(a, num_cu, stream);
     else
-        launch_fused_nbp<float>(a, num_cu, stream);
+        launch_fused_nbp<2>(a, num_cu, stream);
 }
 
 void launch_reduce_partials(int nk, int nb, int S, const double* part, double scale, int accumulate,
@@ -520,4 +766,15 @@ void launch_degenerate_average(int nk, int nb, const double* eps, double tol, do
     launch_check("degenerate_average_kernel");
 }
 
+}  // namespace epw
+
+namespace epw {
+void launch_mode_rotate_bf16(int ne, int qc, int nm, int nb, int nbp, int kpad, const void* in, const void* evec,
+                             const double* sc, void* out, hipStream_t stream) {
+    if (qc == 0) return;
+    dim3 grid((unsigned)qc, (unsigned)((kpad + 63) / 64));
+    mode_rotate_bf16_kernel<<<grid, 256, 0, stream>>>(ne, qc, nm, nb, nbp, kpad, (const float2*)in,
+                                                     (const double2*)evec, sc, (uint16_t*)out);
+    launch_check("mode_rotate_bf16_kernel");
+}
 }  // namespace epw

@@ -44,13 +44,20 @@ void launch_gemm_rp(Prec prec, int nq, int ne, int np_, int ncol, const void* ph
 void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, const void* in,
                         const void* evec, const double* sc, void* out, hipStream_t stream);
 
+// a6 for split-bf16: float32 g(R_e,q) [ne][qc][nm*nb*nb] -> four bf16 planes
+// [4][qc*nm*nbp*nbp][kpad] (R_e contiguous), scaled by sc and rotated by e_q.
+void launch_mode_rotate_bf16(int ne, int qc, int nm, int nb, int nbp, int kpad, const void* in, const void* evec,
+                             const double* sc, void* out, hipStream_t stream);
+
 struct FusedArgs {
     int nk, ne, nb, nbp, nm;
     int qc;            // q points in this chunk
     int q0;            // global index of the first q of the chunk
     int nq_total;      // row length of kq
-    const void* phi_k; // [nk][ldk] complex in prec
+    const void* phi_k; // [nk][ldk] complex in prec (split-bf16: [4][nk][ldk] planes)
     int ldk;
+    int ldk_b;         // split-bf16: row length (kpad) of the B planes [4][cols][kpad]
+    int kpad;          // split-bf16: K padded to a multiple of 32
     const void* B;     // [ne][qc*nm*nbp*nbp] complex in prec
     const double* eps; // [nk][nb]
     const void* U;     // [nk][nb][nb] c128

@@ -75,7 +75,7 @@ def test_interp_g_gauge_invariant_parity():
     """g_mn,nu(k,q) is gauge dependent; |g|^2 summed over degenerate groups
     of m, n and nu is not (Sec. 10.4) and must match the oracle."""
     for name, c in (("toy", toy_case((4, 4, 4))), ("fcc3", fcc_small_case(kg=(3, 3, 3)))):
-        for dtype, tol in (("fp64", 1e-10), ("fp32", 1e-5)):
+        for dtype, tol in (("fp64", 1e-10), ("fp32", 1e-5), ("split_bf16", 1e-4)):
             _say("interp_g", name, dtype)
             sysd = _system(c)
             pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
@@ -139,14 +139,30 @@ def test_imsigma_band_counts_fp64(nb):
     assert rel_err(got, ref) < 1e-10
 
 
-def test_imsigma_fp32_toy():
+@pytest.mark.parametrize("dtype,tol", [("fp32", 1e-5), ("split_bf16", 1e-4)])
+def test_imsigma_low_precision_toy(dtype, tol):
+    """The toy system with the contractions and rotations in FP32 or
+    split-BF16 (eigensolves, phase arguments and energies stay FP64)."""
     c = toy_case()
-    _say("imsigma toy fp32")
+    _say("imsigma toy", dtype)
     sysd = _system(c)
     pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
-    got = epw.epw_imsigma(sysd, pts, _params(c, dtype="fp32")).cpu().numpy()
+    got = epw.epw_imsigma(sysd, pts, _params(c, dtype=dtype)).cpu().numpy()
     ref = _oracle_imsigma(c)
-    assert rel_err(got, ref) < 1e-5
+    _say("  rel err", rel_err(got, ref))
+    assert rel_err(got, ref) < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp32", 1e-5), ("split_bf16", 1e-4)])
+@pytest.mark.parametrize("nb", [3, 8, 16])
+def test_imsigma_low_precision_bands(dtype, tol, nb):
+    c = fcc_small_case(nb=nb, kg=(3, 3, 3), seed=nb)
+    _say("imsigma", dtype, "nb", nb)
+    sysd = _system(c)
+    pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
+    got = epw.epw_imsigma(sysd, pts, _params(c, dtype=dtype, chunk_q=10)).cpu().numpy()
+    ref = _oracle_imsigma(c)
+    assert rel_err(got, ref) < tol
 
 
 def test_imsigma_options_and_edges():
@@ -196,3 +212,7 @@ def test_imsigma_realistic_full_size_sampled():
     _say("realistic rel err", rel_err(got[kidx], ref))
     assert rel_err(got[kidx], ref) < 1e-10
     assert np.all(got >= 0)
+    for dtype, tol in (("fp32", 1e-5), ("split_bf16", 1e-4)):
+        low = epw.epw_imsigma(sysd, pts, _params(c, dtype=dtype)).cpu().numpy()
+        _say("realistic", dtype, "rel err", rel_err(low[kidx], ref))
+        assert rel_err(low[kidx], ref) < tol
