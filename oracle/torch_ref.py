@@ -43,7 +43,7 @@ def imsigma_torch(gR, HR, omega, evec, Re, ndeg_e, Rp, ndeg_p, kpoints, qpoints,
     ph_q = _phases(qpoints, Rp, ndeg_p)                        # [Q][Np]
     ph_k = _phases(kpoints, Re, ndeg_e)                        # [K][Ne]
     evec = torch.as_tensor(evec)
-    kq = torch.as_tensor(np.asarray(kq, dtype=np.int64))
+    kq = None if kq is None else torch.as_tensor(np.asarray(kq, dtype=np.int64))
     # R_p -> q, mode rotation with 1/sqrt(2 omega) (masked modes -> 0)
     gq = torch.einsum("qp,epaij->eqaij", ph_q, gR)
     keep = omega.detach() >= omega_cut
@@ -59,8 +59,18 @@ def imsigma_torch(gR, HR, omega, evec, Re, ndeg_e, Rp, ndeg_p, kpoints, qpoints,
     Hk = Hk.reshape(-1, nb, nb)
     Hk = 0.5 * (Hk + Hk.conj().transpose(-1, -2))
     eps, U = torch.linalg.eigh(Hk)
-    eps_kq = eps[kq]                                           # [K][Q][nb]
-    U_kq = U[kq]                                               # [K][Q][nb][nb]
+    if kq is not None:
+        eps_kq = eps[kq]                                       # [K][Q][nb]
+        U_kq = U[kq]                                           # [K][Q][nb][nb]
+    else:
+        # off-grid: diagonalise H at every k+q
+        kqp = (np.asarray(kpoints, dtype=np.float64)[:, None, :] +
+               np.asarray(qpoints, dtype=np.float64)[None, :, :]).reshape(-1, 3)
+        Hq = (_phases(kqp, Re, ndeg_e) @ HR.reshape(ne, -1)).reshape(-1, nb, nb)
+        Hq = 0.5 * (Hq + Hq.conj().transpose(-1, -2))
+        e2, U2 = torch.linalg.eigh(Hq)
+        eps_kq = e2.reshape(len(kpoints), len(qpoints), nb)
+        U_kq = U2.reshape(len(kpoints), len(qpoints), nb, nb)
     gb = torch.einsum("kqim,kqvij,kjn->kqvmn", U_kq.conj(), gk, U)
     # weights of Eq. (8)
     if T == 0.0:

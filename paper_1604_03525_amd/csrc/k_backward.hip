@@ -59,17 +59,21 @@ __global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
     const int nb = a.nb, nm = a.nm, nbp = a.nbp;
     const int nb2 = nb * nb;
     const int q = a.q0 + ql;
-    const int kq = a.kq[(size_t)k * a.nq_total + q];
-    const bool valid = (unsigned)kq < (unsigned)a.nk;
     const size_t pair = (size_t)k * a.qc + ql;
-    CT* G = reinterpret_cast<CT*>(a.G);
     const double2* U = reinterpret_cast<const double2*>(a.U);
+    // states at k+q: a member of the k set (grid runs) or per pair
+    const int kq = a.kq ? a.kq[(size_t)k * a.nq_total + q] : 0;
+    const bool valid = a.kq ? (unsigned)kq < (unsigned)a.nk : true;
+    const double2* Uqs = a.kq ? U + (size_t)kq * nb * nb : reinterpret_cast<const double2*>(a.U_pair) + pair * nb * nb;
+    const double* eqs = a.kq ? a.eps + (size_t)kq * nb : a.eps_pair + pair * nb;
+    const double* fqs = a.kq ? a.ftab + (size_t)kq * nb : a.f_pair + pair * nb;
+    CT* G = reinterpret_cast<CT*>(a.G);
     const size_t ncols = (size_t)a.qc * nm * nbp * nbp;
 
     for (int e = lane; e < nb2; e += 64) {
         const int r = e / nb, c = e % nb;
         Uk[r][c] = valid ? U[((size_t)k * nb + r) * nb + c] : make_double2(0.0, 0.0);
-        Uq[r][c] = valid ? U[((size_t)kq * nb + r) * nb + c] : make_double2(0.0, 0.0);
+        Uq[r][c] = valid ? Uqs[r * nb + c] : make_double2(0.0, 0.0);
         UkA[r][c] = make_double2(0.0, 0.0);
         UqA[r][c] = make_double2(0.0, 0.0);
     }
@@ -113,8 +117,8 @@ __global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
                 g.y += p.y;
             }
             const double en = a.eps[(size_t)k * nb + n];
-            const double em = a.eps[(size_t)kq * nb + m];
-            const double f = a.ftab[(size_t)kq * nb + m];
+            const double em = eqs[m];
+            const double f = fqs[m];
             const double fp = a.kT > 0.0 ? -f * (1.0 - f) / a.kT : 0.0;
             const double x = en - em;
             const double e1 = exp(-(x + w) * (x + w) * inv_s2);

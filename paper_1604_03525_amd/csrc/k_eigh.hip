@@ -37,11 +37,12 @@ __device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
 
 // REAL_IN: X(R) is real (dynamical matrix); else complex interleaved.
 // SQRT_OUT: write omega = sign(l) sqrt|l| instead of the eigenvalue l.
-// pts_a/pts_b: point p is pts_a[ia] (+ pts_b[ib] when pair mode is used).
+// Pair mode (pts2 != nullptr): point p is pts[p / npts2] + pts2[p % npts2].
 template <bool REAL_IN, bool SQRT_OUT>
 __global__ __launch_bounds__(64) void interp_eigh_kernel(
     int n, int nR, const int32_t* __restrict__ R, const int32_t* __restrict__ ndeg,
     const double* __restrict__ XR, int np, const double* __restrict__ pts,
+    const double* __restrict__ pts2, int npts2,
     double* __restrict__ evals, double2* __restrict__ evecs)
 {
     __shared__ double2 A[MAXN + 1][LDA];
@@ -55,9 +56,17 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     const int lane = threadIdx.x;
     const int p = blockIdx.x;
     if (p >= np) return;
-    const double k0 = pts[3 * (size_t)p + 0];
-    const double k1 = pts[3 * (size_t)p + 1];
-    const double k2 = pts[3 * (size_t)p + 2];
+    // point p, or the sum pts[p / npts2] + pts2[p % npts2] in pair mode
+    const size_t ia = pts2 ? (size_t)(p / npts2) : (size_t)p;
+    double k0 = pts[3 * ia + 0];
+    double k1 = pts[3 * ia + 1];
+    double k2 = pts[3 * ia + 2];
+    if (pts2) {
+        const size_t ib = (size_t)(p % npts2);
+        k0 += pts2[3 * ib + 0];
+        k1 += pts2[3 * ib + 1];
+        k2 += pts2[3 * ib + 2];
+    }
     const int E = n * n;
     const int P = (E >= 64) ? 1 : 64 / E;          // R partitions per entry
     const int EPL = (E + 63) / 64;                   // entries per lane when P == 1
@@ -263,19 +272,19 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
 
 void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_t* R,
                         const int32_t* ndeg, const double* XR, int np, const double* pts,
-                        double* evals, void* evecs, hipStream_t stream)
+                        double* evals, void* evecs, hipStream_t stream, const double* pts2, int n2)
 {
     if (np <= 0) return;
     dim3 grid(np), block(64);
     double2* ev = reinterpret_cast<double2*>(evecs);
     if (real_in && sqrt_out)
-        interp_eigh_kernel<true, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, evals, ev);
+        interp_eigh_kernel<true, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
     else if (real_in)
-        interp_eigh_kernel<true, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, evals, ev);
+        interp_eigh_kernel<true, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
     else if (sqrt_out)
-        interp_eigh_kernel<false, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, evals, ev);
+        interp_eigh_kernel<false, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
     else
-        interp_eigh_kernel<false, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, evals, ev);
+        interp_eigh_kernel<false, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
     launch_check("interp_eigh_kernel");
 }
 

@@ -457,8 +457,22 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
                 const double scv = a.sc[(size_t)ql * nm + nu];
                 if (scv == 0.0 && !STORE) continue;
                 const int q = a.q0 + ql;
-                const int kq = a.kq[(size_t)k * a.nq_total + q];
-                if ((unsigned)kq >= (unsigned)a.nk) continue;   // invalid map entry: no access
+                // states at k+q: a member of the k set (grid runs) or per pair
+                const double2* Uq;
+                const double* eq;
+                const double* fq;
+                if (a.kq) {
+                    const int kq = a.kq[(size_t)k * a.nq_total + q];
+                    if ((unsigned)kq >= (unsigned)a.nk) continue;   // invalid map entry: no access
+                    Uq = U + (size_t)kq * nb * nb;
+                    eq = a.eps + (size_t)kq * nb;
+                    fq = a.ftab + (size_t)kq * nb;
+                } else {
+                    const size_t pr = (size_t)k * a.qc + ql;
+                    Uq = reinterpret_cast<const double2*>(a.U_pair) + pr * nb * nb;
+                    eq = a.eps_pair + pr * nb;
+                    fq = a.f_pair + pr * nb;
+                }
                 const double w = a.omega[(size_t)ql * nm + nu];
                 const double nB = a.nbose[(size_t)ql * nm + nu];
                 const CT* Gt = Cs + r * BN + b * NB2;
@@ -489,7 +503,7 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
 #pragma unroll
                         for (int i = 0; i < NBP; ++i) {
                             if (i < nb) {
-                                const double2 ud = U[((size_t)kq * nb + i) * nb + m];
+                                const double2 ud = Uq[i * nb + m];
                                 const TE ux = (TE)ud.x, uy = (TE)ud.y;
                                 // conj(u) * v_i
                                 gr += ux * v[i].x + uy * v[i].y;
@@ -501,8 +515,8 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
                                 [((((size_t)k * a.nq_total + q) * nm + nu) * nb + m) * nb + n] =
                                 make_double2((double)gr, (double)gi);
                         } else {
-                            const double em = a.eps[(size_t)kq * nb + m];
-                            const double fm = a.ftab[(size_t)kq * nb + m];
+                            const double em = eq[m];
+                            const double fm = fq[m];
                             const double x = eps_k[j] - em;
                             const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
                             const TE W = (TE)(nB + fm) * fexp((TE)(-y1 * y1)) +

@@ -11,9 +11,11 @@ namespace epw {
 // Interpolate n x n matrices at np points from nR real-space matrices and
 // diagonalise them in float64.  real_in: X(R) real (dynamical matrix);
 // sqrt_out: eigenvalues l -> sign(l) sqrt|l|.  evecs: [np][n][n] c128.
+// Pair mode (pts2 != nullptr): point p is pts[p / n2] + pts2[p % n2].
 void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_t* R,
                         const int32_t* ndeg, const double* XR, int np, const double* pts,
-                        double* evals, void* evecs, hipStream_t stream);
+                        double* evals, void* evecs, hipStream_t stream,
+                        const double* pts2 = nullptr, int n2 = 1);
 
 // ---- k_vertex.hip ----
 enum class Prec { F64 = 0, F32 = 1, BF16X2 = 2 };
@@ -62,7 +64,10 @@ struct FusedArgs {
     const double* eps; // [nk][nb]
     const void* U;     // [nk][nb][nb] c128
     const double* ftab;// [nk][nb]
-    const int32_t* kq; // [nk][nq_total]
+    const int32_t* kq; // [nk][nq_total], or nullptr: per-pair states below
+    const double* eps_pair;  // [nk][qc][nb]      eps at k+q (kq == nullptr)
+    const void* U_pair;      // [nk][qc][nb][nb]  U at k+q (c128)
+    const double* f_pair;    // [nk][qc][nb]      Fermi factors at k+q
     const double* omega;   // [qc][nm] (chunk-local)
     const double* nbose;   // [qc][nm] (chunk-local)
     const double* sc;      // [qc][nm] (chunk-local)
@@ -103,7 +108,10 @@ struct PairBwdArgs {
     const void* U;         // [nk][nb][nb] c128
     const double* ftab;    // [nk][nb]
     const double* wbar;    // [nk][nb] degenerate-averaged loss weights
-    const int32_t* kq;     // [nk][nq_total]
+    const int32_t* kq;     // [nk][nq_total], or nullptr: per-pair states below
+    const double* eps_pair;  // [nk][qc][nb]
+    const void* U_pair;      // [nk][qc][nb][nb] c128
+    const double* f_pair;    // [nk][qc][nb]
     const double* omega;   // [qc][nm]
     const double* nbose;   // [qc][nm]
     const double* sc;      // [qc][nm]

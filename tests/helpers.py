@@ -46,3 +46,16 @@ def realistic_case():
     kq = lattice.kq_index(m.kgrid, m.qgrid)
     return dict(model=m, R=R, nd=nd, HR=HR, DR=DR, gR=gR, k=k, q=k, kq=kq,
                 T=m.T, mu=m.mu, sigma=m.sigma)
+
+
+def mobility_small_case(coarse=(3, 3, 3), nk=24, nq=40, nb=16, seed=20):
+    """The mobility-scale system's shape (fcc, 3 atoms, 16 bands, 9 modes,
+    random k and q, off-grid k+q) on a small coarse grid so the oracle can
+    evaluate it completely."""
+    R, nd = lattice.ws_vectors(I.FCC_METRIC, coarse)
+    HR = I.random_hamiltonian(R, I.FCC_VECTORS, nb, seed=seed, decay=1.5, scale=0.6)
+    DR = I.spring_dynmat(R, I.FCC_VECTORS, I.ATOMS_FCC3, shells=2, seed=seed + 1, scale=4e-4)
+    gR = I.random_vertex(R, R, I.FCC_VECTORS, 9, nb, seed=seed + 2, g0=0.05)
+    k = I.random_points(nk, 3)
+    q = I.random_points(nq, 2)
+    return dict(R=R, nd=nd, HR=HR, DR=DR, gR=gR, k=k, q=q, kq=None, T=300.0, mu=0.0, sigma=0.1)

@@ -110,3 +110,16 @@ def test_workspace_size_empty_point_sets():
         s, p = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=nk, nq=nq)
         for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA):
             assert lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par)) > 0
+
+
+def test_workspace_size_counts_per_pair_states():
+    """Without a k+q map the k+q states are per pair and need more scratch."""
+    lib = _lib.load()
+    par = epw.make_params(chunk_q=16)
+    s, p = _shape_only(nb=16, nm=9, ne=89, np_=89, nk=24, nq=40)
+    kq = (ctypes.c_int32 * 1)()
+    p_grid = _lib.EpwPoints(24, 40, None, None, ctypes.cast(kq, ctypes.c_void_p), None, None)
+    for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_IMSIGMA_BACKWARD):
+        off = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
+        on = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p_grid), ctypes.byref(par))
+        assert off >= on + 24 * 16 * (16 * 16 * 16 + 16 * 16)
