@@ -141,7 +141,16 @@ typedef struct {
                               phonon states are given in epw_points              */
     const void* gR;        /* device [nRe][nRp][nm][nb][nb] c128: g_{ka}(R_e,R_p),
                               row index = Wannier function on the k+q side      */
+    int32_t nmax_e;        /* optional: max |Re[r][a]| over all r, a.  When set
+                              (1..EPW_MAX_NMAX) the electron phases of the R_e -> k
+                              contraction are generated in the kernel from
+                              per-axis factors exp(2 pi i k_a n) instead of being
+                              streamed from a table; 0 = use the table.  A value
+                              smaller than the true maximum gives wrong results. */
+    int32_t reserved;
 } epw_system;
+
+#define EPW_MAX_NMAX 8
 
 /* Fine points. */
 typedef struct {

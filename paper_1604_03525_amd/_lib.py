@@ -31,6 +31,7 @@ EPW_STAGE_BACKWARD = 4
 
 EPW_MAX_NB = 16
 EPW_MAX_NM = 16
+EPW_MAX_NMAX = 8
 
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -42,7 +43,8 @@ class EpwSystem(ctypes.Structure):
     _fields_ = [("nb", ctypes.c_int32), ("nm", ctypes.c_int32),
                 ("nRe", ctypes.c_int32), ("nRp", ctypes.c_int32),
                 ("Re", _vp), ("ndeg_e", _vp), ("Rp", _vp), ("ndeg_p", _vp),
-                ("HR", _vp), ("DR", _vp), ("gR", _vp)]
+                ("HR", _vp), ("DR", _vp), ("gR", _vp), ("nmax_e", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class EpwPoints(ctypes.Structure):

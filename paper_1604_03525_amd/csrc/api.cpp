@@ -33,6 +33,8 @@ int check_common(const epw_system* s, const epw_points* p, const epw_params* par
     if (!(par->nq_norm >= 0.0)) return fail(EPW_EINVAL, "%s: nq_norm must be >= 0", fn);
     if (!std::isfinite(par->omega_cut)) return fail(EPW_EINVAL, "%s: omega_cut not finite", fn);
     if (par->chunk_q < 0) return fail(EPW_EINVAL, "%s: chunk_q < 0", fn);
+    if (s->nmax_e < 0 || s->nmax_e > EPW_MAX_NMAX)
+        return fail(EPW_EINVAL, "%s: nmax_e = %d not in 0..%d", fn, s->nmax_e, EPW_MAX_NMAX);
     const bool given = p->omega && p->evec;
     if ((p->omega != nullptr) != (p->evec != nullptr))
         return fail(EPW_EINVAL, "%s: omega and evec must be given together", fn);
@@ -172,7 +174,14 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
     launch_fermi_table((size_t)nk * nb, L.eps, par->mu, par->T, L.ftab, st);
     const bool bf = prec == Prec::BF16X2;
     const Prec rprec = bf ? Prec::F32 : prec;      // precision of the R_p -> q step
-    launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, bf ? L.kpad : ne, L.phi_k, st);
+    // Phases of the R_e -> k contraction: generated inside the fused kernel
+    // from per-axis factors for the FP32 / split-BF16 paths (saves the table
+    // traffic there), read from a table for FP64, where the extra VALU work of
+    // generating them costs more than the table reads.  Generation needs the
+    // R_e offsets of a tile in LDS, hence the bound on ne.  The 1/ndeg weights
+    // of R_e are folded into the B operand (mode rotation) in both cases.
+    const bool gen = prec != Prec::F64 && s->nmax_e > 0 && ne <= 4096;
+    if (!gen) launch_phase_table(prec, nk, p->kfrac, ne, s->Re, nullptr, bf ? L.kpad : ne, L.phi_k, st);
     const void* gsrc = s->gR;
     if (prec != Prec::F64) {
         launch_c128_to_c64((size_t)ne * np_ * nm * nb * nb, s->gR, L.gR_t, st);
@@ -205,9 +214,9 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         {
             StageTimer t(EPW_STAGE_MODEROT, st);
             if (bf)
-                launch_mode_rotate_bf16(ne, qc, nm, nb, L.nbp, L.kpad, L.gq, ev, L.sc, L.Bnu, st);
+                launch_mode_rotate_bf16(ne, qc, nm, nb, L.nbp, L.kpad, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e);
             else
-                launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st);
+                launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e);
         }
         FusedArgs a;
         a.nk = nk;
@@ -220,6 +229,10 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.nq_total = nq;
         a.phi_k = L.phi_k;
         a.ldk = bf ? L.kpad : ne;
+        a.nmax = gen ? s->nmax_e : 0;
+        a.Re = s->Re;
+        a.ndeg_e = s->ndeg_e;
+        a.kfrac = p->kfrac;
         a.ldk_b = L.kpad;
         a.kpad = L.kpad;
         a.B = L.Bnu;

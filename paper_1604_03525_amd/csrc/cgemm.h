@@ -102,6 +102,13 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>& st, int K, AF afetch
             st.b_im[idx / BN][idx % BN] = rb[e].y;
         }
     };
+    // Gauss's three-multiplication complex product: with P1 = sum ar br,
+    // P2 = sum ai bi, P3 = sum (ar + ai)(br + bi):  re = P1 - P2,
+    // im = P3 - P1 - P2.  Three real MFMAs per complex block product instead
+    // of four; the operand sums are formed in registers from the LDS planes.
+    typename Cx<T>::acc cm[4];
+    for (int c = 0; c < 4; ++c)
+        for (int i = 0; i < 4; ++i) cm[c][i] = T(0);
     gload(0);
     sstore();
     __syncthreads();
@@ -113,20 +120,20 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>& st, int K, AF afetch
             const int kr = kk + (lane >> 4);
             const T ar = st.a_re[kr][wm * 16 + (lane & 15)];
             const T ai = st.a_im[kr][wm * 16 + (lane & 15)];
-            T br[4], bi[4];
+            const T as = ar + ai;
+            T br[4], bi[4], bs[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 br[c] = st.b_re[kr][wn * 64 + c * 16 + (lane & 15)];
                 bi[c] = st.b_im[kr][wn * 64 + c * 16 + (lane & 15)];
+                bs[c] = br[c] + bi[c];
             }
 #pragma unroll
             for (int c = 0; c < 4; ++c) cr[c] = mfma4(ar, br[c], cr[c]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) ci[c] = mfma4(ar, bi[c], ci[c]);
+            for (int c = 0; c < 4; ++c) cm[c] = mfma4(ai, bi[c], cm[c]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cr[c] = mfma4(-ai, bi[c], cr[c]);
-#pragma unroll
-            for (int c = 0; c < 4; ++c) ci[c] = mfma4(ai, br[c], ci[c]);
+            for (int c = 0; c < 4; ++c) ci[c] = mfma4(as, bs[c], ci[c]);
         }
         __syncthreads();
         if (more) {
@@ -134,6 +141,12 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>& st, int K, AF afetch
             __syncthreads();
         }
     }
+    for (int c = 0; c < 4; ++c)
+        for (int i = 0; i < 4; ++i) {
+            const T p1 = cr[c][i], p2 = cm[c][i];
+            cr[c][i] = p1 - p2;
+            ci[c][i] = ci[c][i] - p1 - p2;
+        }
 }
 
 

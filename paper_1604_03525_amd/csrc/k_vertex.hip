@@ -37,7 +37,7 @@ __global__ void phase_table_kernel(int np, const double* __restrict__ pts, int n
                    pts[3 * (size_t)p + 2] * (double)R[3 * r + 2];
         x -= rint(x);
         sincospi(2.0 * x, &s, &c);
-        const double w = 1.0 / (double)ndeg[r];
+        const double w = ndeg ? 1.0 / (double)ndeg[r] : 1.0;
         c *= w;
         s *= w;
     }
@@ -89,50 +89,7 @@ __global__ void fermi_kernel(size_t n, const double* __restrict__ eps, double mu
     }
 }
 
-// ------------------------------------------------------------ a5: R_p -> q
-
-template <typename T>
-__global__ __launch_bounds__(256) void gemm_rp_kernel(int nq, int ne, int np_, int ncol,
-                                                      const typename Cx<T>::type* __restrict__ phi, int ldphi,
-                                                      const typename Cx<T>::type* __restrict__ gR,
-                                                      typename Cx<T>::type* __restrict__ out)
-{
-    typedef typename Cx<T>::type CT;
-    constexpr int BM = 64, BN = 64, BK = 16;
-    __shared__ Stage<T, BM, BN, BK> st;
-    const int m0 = blockIdx.y * BM;
-    const long n0 = (long)blockIdx.x * BN;
-    const long N = (long)ne * ncol;
-    auto afetch = [&](int m, int k) -> CT {
-        const int q = m0 + m;
-        if (q < nq && k < np_) return phi[(size_t)q * ldphi + k];
-        return cz<T>();
-    };
-    auto bfetch = [&](int k, int n) -> CT {
-        const long col = n0 + n;
-        if (k < np_ && col < N) {
-            const long e = col / ncol, c = col % ncol;
-            return gR[((size_t)e * np_ + k) * ncol + c];
-        }
-        return cz<T>();
-    };
-    typename Cx<T>::acc cr[4], ci[4];
-    cgemm_mainloop<T, BM, BN, BK>(st, np_, afetch, bfetch, cr, ci);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    for (int c = 0; c < 4; ++c) {
-        const long col = n0 + c * 16 + (lane & 15);
-        if (col >= N) continue;
-        const long e = col / ncol, cc = col % ncol;
-        for (int i = 0; i < 4; ++i) {
-            const int q = m0 + wave * 16 + crow<T>(lane, i);
-            if (q >= nq) continue;
-            CT v;
-            v.x = cr[c][i];
-            v.y = ci[c][i];
-            out[((size_t)e * nq + q) * ncol + cc] = v;
-        }
-    }
-}
+// (a5, the R_p -> q contraction, runs on the generic complex GEMM of k_gemm.hip)
 
 // ------------------------------------------------------------ a6: modes
 
@@ -140,6 +97,7 @@ template <typename T>
 __global__ void mode_rotate_kernel(int ne, int nq, int nm, int nb, int nbp,
                                    const typename Cx<T>::type* __restrict__ in,
                                    const double2* __restrict__ evec, const double* __restrict__ sc,
+                                   const int32_t* __restrict__ ndeg_fold,
                                    typename Cx<T>::type* __restrict__ out)
 {
     typedef typename Cx<T>::type CT;
@@ -157,8 +115,9 @@ __global__ void mode_rotate_kernel(int ne, int nq, int nm, int nb, int nbp,
         return;
     }
     const CT* x = in + eq * (size_t)nm * nb * nb + i * nb + j;
+    const double wfold = ndeg_fold ? 1.0 / (double)ndeg_fold[eq / nq] : 1.0;
     for (int v = 0; v < nm; ++v) {
-        const double s = sc[(size_t)q * nm + v];
+        const double s = sc[(size_t)q * nm + v] * wfold;
         T re = T(0), im = T(0);
         if (s != 0.0) {
             for (int a = 0; a < nm; ++a) {
@@ -218,13 +177,25 @@ struct BfStage {
 
 // Computes the BM x BN complex tile and leaves it in registers (same
 // fragment layout as the f32 MFMA: element i of lane l is row 4(l/16)+i).
-template <int BM, int BN>
+// split x into bf16 hi + lo, packed pairwise into 32-bit words
+__device__ inline void split_pack(float x0, float x1, uint32_t& hi, uint32_t& lo) {
+    const __hip_bfloat16 h0 = __float2bfloat16(x0), h1 = __float2bfloat16(x1);
+    const __hip_bfloat16 l0 = __float2bfloat16(x0 - __bfloat162float(h0));
+    const __hip_bfloat16 l1 = __float2bfloat16(x1 - __bfloat162float(h1));
+    hi = (uint32_t)__builtin_bit_cast(uint16_t, h0) | ((uint32_t)__builtin_bit_cast(uint16_t, h1) << 16);
+    lo = (uint32_t)__builtin_bit_cast(uint16_t, l0) | ((uint32_t)__builtin_bit_cast(uint16_t, l1) << 16);
+}
+
+// GEN: the A operand (phases) is produced by agen(local_row, k) -> float2
+// instead of being loaded; thread t < 4 BM generates row t/4, k = k0 + 8 (t%4) .. +7.
+template <int BM, int BN, bool GEN, class AG>
 __device__ inline void bf16_mainloop(BfStage<BM, BN>& st, const uint16_t* __restrict__ A, long lda, long aplane,
                                      int arows, int m0, const uint16_t* __restrict__ B, long ldb, long bplane,
-                                     long bcols, long n0, int Kpad, f4 (&cr)[4], f4 (&ci)[4])
+                                     long bcols, long n0, int Kpad, AG agen, f4 (&cr)[4], f4 (&ci)[4])
 {
     constexpr int WN = BN / 64;
-    constexpr int ACH = 4 * BM * 4 / 256;          // 16-byte chunks per thread
+    constexpr int ACH0 = 4 * BM * 4 / 256;         // 16-byte chunks per thread
+    constexpr int ACH = GEN ? 4 : ACH0;
     constexpr int BCH = 4 * BN * 4 / 256;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
@@ -235,13 +206,29 @@ __device__ inline void bf16_mainloop(BfStage<BM, BN>& st, const uint16_t* __rest
             ci[c][i] = 0.f;
         }
     auto gload = [&](int k0) {
+        if constexpr (GEN) {
+            if (tid < 4 * BM) {
+                const int row = tid >> 2, part = tid & 3;
+                uint32_t w[4][4];
 #pragma unroll
-        for (int e = 0; e < ACH; ++e) {
-            const int c = tid * ACH + e;
-            const int p = c / (BM * 4), row = (c / 4) % BM, part = c % 4;
-            const int grow = m0 + row;
-            ra[e] = grow < arows ? *reinterpret_cast<const uint4*>(A + p * aplane + (size_t)grow * lda + k0 + part * 8)
-                                 : make_uint4(0, 0, 0, 0);
+                for (int t = 0; t < 8; t += 2) {
+                    const float2 p0 = agen(row, k0 + part * 8 + t);
+                    const float2 p1 = agen(row, k0 + part * 8 + t + 1);
+                    split_pack(p0.x, p1.x, w[0][t >> 1], w[1][t >> 1]);
+                    split_pack(p0.y, p1.y, w[2][t >> 1], w[3][t >> 1]);
+                }
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl) ra[pl] = make_uint4(w[pl][0], w[pl][1], w[pl][2], w[pl][3]);
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < ACH; ++e) {
+                const int c = tid * ACH + e;
+                const int p = c / (BM * 4), row = (c / 4) % BM, part = c % 4;
+                const int grow = m0 + row;
+                ra[e] = grow < arows ? *reinterpret_cast<const uint4*>(A + p * aplane + (size_t)grow * lda + k0 + part * 8)
+                                     : make_uint4(0, 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int e = 0; e < BCH; ++e) {
@@ -253,11 +240,19 @@ __device__ inline void bf16_mainloop(BfStage<BM, BN>& st, const uint16_t* __rest
         }
     };
     auto sstore = [&]() {
+        if constexpr (GEN) {
+            if (tid < 4 * BM) {
+                const int row = tid >> 2, part = tid & 3;
 #pragma unroll
-        for (int e = 0; e < ACH; ++e) {
-            const int c = tid * ACH + e;
-            const int p = c / (BM * 4), row = (c / 4) % BM, part = c % 4;
-            *reinterpret_cast<uint4*>(&st.a[p][row][part * 8]) = ra[e];
+                for (int pl = 0; pl < 4; ++pl) *reinterpret_cast<uint4*>(&st.a[pl][row][part * 8]) = ra[pl];
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < ACH; ++e) {
+                const int c = tid * ACH + e;
+                const int p = c / (BM * 4), row = (c / 4) % BM, part = c % 4;
+                *reinterpret_cast<uint4*>(&st.a[p][row][part * 8]) = ra[e];
+            }
         }
 #pragma unroll
         for (int e = 0; e < BCH; ++e) {
@@ -333,14 +328,27 @@ __device__ inline float2 mk2(float x, float y) { return make_float2(x, y); }
 __device__ inline double fexp(double x) { return exp(x); }
 __device__ inline float fexp(float x) { return __expf(x); }
 
-template <int MODE, int NBP, bool STORE>
-__global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
+__device__ inline double2 cmulx(double2 a, double2 b) {
+    return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ inline float2 cmulx(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// GEN: the electron phases exp(2 pi i k.R_e) are generated from per-axis
+// factors exp(2 pi i k_a n), |n| <= nmax, kept in (dynamic) LDS for the
+// block's k rows: three complex products per element instead of a table
+// streamed from memory once per column tile.  The 1/ndeg weights are then
+// carried by the B operand.
+template <int MODE, int NBP, bool STORE, bool GEN>
+__global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
 {
     typedef typename ModeTypes<MODE>::T T;
     typedef typename ModeTypes<MODE>::CT CT;
     typedef typename ModeTypes<MODE>::TE TE;
     typedef typename ModeTypes<MODE>::CE CE;
-    constexpr int BM = FusedShape<NBP>::BM, BN = FusedShape<NBP>::BN, BK = 16;
+    constexpr int BM = FusedShape<NBP>::BM, BN = FusedShape<NBP>::BN;
+    constexpr int BK = (BN == 64 && sizeof(T) == 4) ? 32 : 16;   // deeper K step where registers allow
     constexpr int NB2 = NBP * NBP;
     constexpr int NBLK = BN / NB2;                 // band blocks per tile
     constexpr int TPR = 256 / BM;                  // threads per k row
@@ -352,7 +360,10 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
     constexpr size_t SBYTES = STB > CBYTES ? STB : CBYTES;
     __shared__ __attribute__((aligned(16))) char smem[SBYTES];
     __shared__ double red[256];
+    extern __shared__ __attribute__((aligned(16))) char dsm[];
     CT* Cs = reinterpret_cast<CT*>(smem);
+    CE* Et = reinterpret_cast<CE*>(dsm);          // [3][BM][2 nmax + 1] when GEN
+    int* Roff = reinterpret_cast<int*>(dsm + (size_t)3 * BM * (2 * a.nmax + 1) * sizeof(CE));  // [ne]
 
     // XCD-aware remap: consecutive workgroup ids land on different XCDs
     // (round-robin over 8); give each XCD a contiguous range of (s, mt)
@@ -365,6 +376,34 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
     const int s = lin / tiles_m;
     const int mt = lin % tiles_m;
     const int m0 = mt * BM;
+    const int NE = 2 * a.nmax + 1;
+    if constexpr (GEN) {
+        for (int idx = threadIdx.x; idx < 3 * BM * NE; idx += 256) {
+            const int ax = idx / (BM * NE), rem = idx % (BM * NE);
+            const int row = rem / NE, j = rem % NE;
+            const int kr = m0 + row;
+            double x = kr < a.nk ? a.kfrac[3 * (size_t)kr + ax] * (double)(j - a.nmax) : 0.0;
+            x -= rint(x);
+            double sn, cs;
+            sincospi(2.0 * x, &sn, &cs);
+            Et[idx] = mk2((TE)cs, (TE)sn);
+        }
+        // table offsets of each R_e, packed 8 bits per axis
+        for (int r = threadIdx.x; r < a.ne; r += 256) {
+            const int* rr = a.Re + 3 * r;
+            Roff[r] = (rr[0] + a.nmax) | ((rr[1] + a.nmax) << 8) | ((rr[2] + a.nmax) << 16);
+        }
+        __syncthreads();
+    }
+    // phase of (local row m, R_e index kk), zero outside the valid range
+    auto phase = [&](int m, int kk) -> CE {
+        if (m0 + m >= a.nk || kk >= a.ne) return mk2(TE(0), TE(0));
+        const int off = Roff[kk];
+        const CE p0 = Et[(0 * BM + m) * NE + (off & 255)];
+        const CE p1 = Et[(1 * BM + m) * NE + ((off >> 8) & 255)];
+        const CE p2 = Et[(2 * BM + m) * NE + (off >> 16)];
+        return cmulx(cmulx(p0, p1), p2);
+    };
 
     const int nb = a.nb, nm = a.nm;
     const int tid = threadIdx.x;
@@ -387,19 +426,10 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
 
     const double inv_sig = 1.0 / a.sigma;
     double eps_k[JN];
-    CE Uk[JN][NBP];
     #pragma unroll
     for (int j = 0; j < JN; ++j) {
         const int n = fewn ? n_single : sub + j * TPR;
-        eps_k[j] = 0.0;
-        for (int jj = 0; jj < NBP; ++jj) Uk[j][jj] = mk2(TE(0), TE(0));
-        if (active_thr && n < nb) {
-            eps_k[j] = a.eps[(size_t)k * nb + n];
-            for (int jj = 0; jj < nb; ++jj) {
-                const double2 u = U[((size_t)k * nb + jj) * nb + n];
-                Uk[j][jj] = mk2((TE)u.x, (TE)u.y);
-            }
-        }
+        eps_k[j] = (active_thr && n < nb) ? a.eps[(size_t)k * nb + n] : 0.0;
     }
 
     for (int nt = s; nt < tiles_n; nt += a.S) {
@@ -408,8 +438,9 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
             f4 cr[4], ci[4];
             const uint16_t* Ap = reinterpret_cast<const uint16_t*>(a.phi_k);
             const uint16_t* Bp = reinterpret_cast<const uint16_t*>(a.B);
-            bf16_mainloop<BM, BN>(*reinterpret_cast<Sb*>(smem), Ap, a.ldk, (long)a.nk * a.ldk, a.nk, m0, Bp,
-                                  a.ldk_b, ncols * a.ldk_b, ncols, n0, a.kpad, cr, ci);
+            auto agen = [&](int m, int kk) -> float2 { return phase(m, kk); };
+            bf16_mainloop<BM, BN, GEN>(*reinterpret_cast<Sb*>(smem), Ap, a.ldk, (long)a.nk * a.ldk, a.nk, m0, Bp,
+                                       a.ldk_b, ncols * a.ldk_b, ncols, n0, a.kpad, agen, cr, ci);
             const int lane = tid & 63, wave = tid >> 6;
             constexpr int WN = BN / 64;
             const int wm = wave / WN, wn = wave % WN;
@@ -423,9 +454,13 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
             const CT* phi = reinterpret_cast<const CT*>(a.phi_k);
             const CT* Bm = reinterpret_cast<const CT*>(a.B);
             auto afetch = [&](int m, int kk) -> CT {
-                const int row = m0 + m;
-                if (row < a.nk && kk < a.ne) return phi[(size_t)row * a.ldk + kk];
-                return cz<T>();
+                if constexpr (GEN) {
+                    return phase(m, kk);
+                } else {
+                    const int row = m0 + m;
+                    if (row < a.nk && kk < a.ne) return phi[(size_t)row * a.ldk + kk];
+                    return cz<T>();
+                }
             };
             auto bfetch = [&](int kk, int n) -> CT {
                 const long col = n0 + n;
@@ -490,7 +525,8 @@ __global__ __launch_bounds__(256) void fused_k_kernel(FusedArgs a, int tiles_m, 
                             for (int jj = 0; jj < NBP; ++jj) {
                                 if (jj < nb) {
                                     const CT g = Gt[i * NBP + jj];
-                                    const CE u = Uk[j][jj];
+                                    const double2 ud = U[((size_t)k * nb + jj) * nb + n];
+                                    const CE u = mk2((TE)ud.x, (TE)ud.y);
                                     vr += (TE)g.x * u.x - (TE)g.y * u.y;
                                     vi += (TE)g.x * u.y + (TE)g.y * u.x;
                                 }
@@ -555,6 +591,7 @@ __global__ __launch_bounds__(256) void mode_rotate_bf16_kernel(int ne, int qc, i
                                                               const float2* __restrict__ in,
                                                               const double2* __restrict__ evec,
                                                               const double* __restrict__ sc,
+                                                              const int32_t* __restrict__ ndeg_fold,
                                                               uint16_t* __restrict__ out)
 {
     __shared__ float2 tile[64][65];
@@ -574,6 +611,7 @@ __global__ __launch_bounds__(256) void mode_rotate_bf16_kernel(int ne, int qc, i
                 float2 v = make_float2(0.f, 0.f);
                 if (ij < nbp2 && e < ne && s != 0.f) {
                     const int i = ij / nbp, j = ij % nbp;
+                    const float wf = ndeg_fold ? s / (float)ndeg_fold[e] : s;
                     if (i < nb && j < nb) {
                         const float2* x = in + ((size_t)e * qc + q) * nm * nb * nb + i * nb + j;
                         float re = 0.f, im = 0.f;
@@ -583,7 +621,7 @@ __global__ __launch_bounds__(256) void mode_rotate_bf16_kernel(int ne, int qc, i
                             re += g.x * (float)ev.x - g.y * (float)ev.y;
                             im += g.x * (float)ev.y + g.y * (float)ev.x;
                         }
-                        v = make_float2(re * s, im * s);
+                        v = make_float2(re * wf, im * wf);
                     }
                 }
                 tile[il][el] = v;
@@ -668,10 +706,23 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     const long G = ((total + 7) / 8) * 8;
     (void)num_cu;
     (void)tiles_n;
-    if (a.gkq)
-        fused_k_kernel<MODE, NBP, true><<<dim3((unsigned)G), dim3(256), 0, stream>>>(a, tiles_m, tiles_n);
-    else
-        fused_k_kernel<MODE, NBP, false><<<dim3((unsigned)G), dim3(256), 0, stream>>>(a, tiles_m, tiles_n);
+    // the float64 path always reads its phases from a table
+    if (MODE == 0 && a.nmax > 0) throw HipFailure{(int)hipErrorInvalidValue, "fused_k_kernel (f64, nmax > 0)", __FILE__, __LINE__};
+    constexpr bool CAN_GEN = MODE != 0;
+    const bool gen = CAN_GEN && a.nmax > 0;
+    const size_t dyn = gen ? (size_t)3 * BM * (2 * a.nmax + 1) * 8 + 4 * (size_t)a.ne : 0;
+    const dim3 grid((unsigned)G), block(256);
+    if (a.gkq) {
+        if (gen)
+            fused_k_kernel<MODE, NBP, true, CAN_GEN><<<grid, block, dyn, stream>>>(a, tiles_m, tiles_n);
+        else
+            fused_k_kernel<MODE, NBP, true, false><<<grid, block, 0, stream>>>(a, tiles_m, tiles_n);
+    } else {
+        if (gen)
+            fused_k_kernel<MODE, NBP, false, CAN_GEN><<<grid, block, dyn, stream>>>(a, tiles_m, tiles_n);
+        else
+            fused_k_kernel<MODE, NBP, false, false><<<grid, block, 0, stream>>>(a, tiles_m, tiles_n);
+    }
     launch_check("fused_k_kernel");
 }
 
@@ -718,29 +769,17 @@ void launch_fermi_table(size_t n, const double* eps, double mu, double T, double
     launch_check("fermi_kernel");
 }
 
-void launch_gemm_rp(Prec prec, int nq, int ne, int np_, int ncol, const void* phi_q, int ldphi,
-                    const void* gR, void* out, hipStream_t stream) {
-    const long N = (long)ne * ncol;
-    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((nq + 63) / 64));
-    if (prec == Prec::F64)
-        gemm_rp_kernel<double><<<grid, 256, 0, stream>>>(nq, ne, np_, ncol, (const double2*)phi_q, ldphi,
-                                                         (const double2*)gR, (double2*)out);
-    else
-        gemm_rp_kernel<float><<<grid, 256, 0, stream>>>(nq, ne, np_, ncol, (const float2*)phi_q, ldphi,
-                                                        (const float2*)gR, (float2*)out);
-    launch_check("gemm_rp_kernel");
-}
-
 void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, const void* in,
-                        const void* evec, const double* sc, void* out, hipStream_t stream) {
+                        const void* evec, const double* sc, void* out, hipStream_t stream,
+                        const int32_t* ndeg_fold) {
     const size_t total = (size_t)ne * nq * nbp * nbp;
     if (total == 0) return;
     if (prec == Prec::F64)
         mode_rotate_kernel<double><<<blocks_for(total, 256), 256, 0, stream>>>(
-            ne, nq, nm, nb, nbp, (const double2*)in, (const double2*)evec, sc, (double2*)out);
+            ne, nq, nm, nb, nbp, (const double2*)in, (const double2*)evec, sc, ndeg_fold, (double2*)out);
     else
         mode_rotate_kernel<float><<<blocks_for(total, 256), 256, 0, stream>>>(
-            ne, nq, nm, nb, nbp, (const float2*)in, (const double2*)evec, sc, (float2*)out);
+            ne, nq, nm, nb, nbp, (const float2*)in, (const double2*)evec, sc, ndeg_fold, (float2*)out);
     launch_check("mode_rotate_kernel");
 }
 
@@ -748,9 +787,10 @@ int fused_slices(int nk, int nbp, int tiles_n, int num_cu) {
     const int BM = (nbp * nbp >= 64) ? 4096 / (nbp * nbp) : 64;
     const int tiles_m = (nk + BM - 1) / BM;
     if (tiles_m <= 0 || tiles_n <= 0) return 1;
-    // about four resident blocks per CU, in whole multiples of the k tiles
-    long want = 4L * (num_cu > 0 ? num_cu : 256);
-    long S = (want + tiles_m - 1) / tiles_m;
+    // one round of resident blocks (two per CU): every block gets the same
+    // number of column tiles and no partial second round is left over
+    const long slots = 2L * (num_cu > 0 ? num_cu : 256);
+    long S = slots / tiles_m;
     if (S > tiles_n) S = tiles_n;
     if (S < 1) S = 1;
     return (int)S;
@@ -784,11 +824,11 @@ void launch_degenerate_average(int nk, int nb, const double* eps, double tol, do
 
 namespace epw {
 void launch_mode_rotate_bf16(int ne, int qc, int nm, int nb, int nbp, int kpad, const void* in, const void* evec,
-                             const double* sc, void* out, hipStream_t stream) {
+                             const double* sc, void* out, hipStream_t stream, const int32_t* ndeg_fold) {
     if (qc == 0) return;
     dim3 grid((unsigned)qc, (unsigned)((kpad + 63) / 64));
     mode_rotate_bf16_kernel<<<grid, 256, 0, stream>>>(ne, qc, nm, nb, nbp, kpad, (const float2*)in,
-                                                     (const double2*)evec, sc, (uint16_t*)out);
+                                                     (const double2*)evec, sc, ndeg_fold, (uint16_t*)out);
     launch_check("mode_rotate_bf16_kernel");
 }
 }  // namespace epw

@@ -20,7 +20,8 @@ void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_
 // ---- k_vertex.hip ----
 enum class Prec { F64 = 0, F32 = 1, BF16X2 = 2 };
 
-// exp(2 pi i p.R)/ndeg(R) -> [np][ld] complex in `prec` (columns >= nR zero).
+// exp(2 pi i p.R)/ndeg(R) -> [np][ld] complex in `prec` (columns >= nR zero;
+// ndeg == nullptr: weight 1).
 // F64/F32 write interleaved complex; BF16X2 writes four bf16 planes
 // (re_hi, re_lo, im_hi, im_lo), each [np][ld].
 void launch_phase_table(Prec prec, int np, const double* pts, int nR, const int32_t* R,
@@ -38,18 +39,17 @@ void launch_phonon_factors(int nq, int nm, const double* omega, double omega_cut
 void launch_fermi_table(size_t n, const double* eps, double mu, double T, double* f,
                         hipStream_t stream);
 
-// a5: g(R_e, q) = sum_p Phi_q[q][p] g(R_e, R_p): out[e][q][col], col < ncol.
-void launch_gemm_rp(Prec prec, int nq, int ne, int np_, int ncol, const void* phi_q, int ldphi,
-                    const void* gR, void* out, hipStream_t stream);
-
 // a6: out[e][q][nu][i][j] (NBP-padded) = sum_a in[e][q][a][i][j] e_q[a][nu] sc[q][nu]
+// ndeg_fold (optional): also multiply row e by 1/ndeg_fold[e] (the phase table
+// of the following R_e -> k contraction then carries no 1/ndeg).
 void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, const void* in,
-                        const void* evec, const double* sc, void* out, hipStream_t stream);
+                        const void* evec, const double* sc, void* out, hipStream_t stream,
+                        const int32_t* ndeg_fold = nullptr);
 
 // a6 for split-bf16: float32 g(R_e,q) [ne][qc][nm*nb*nb] -> four bf16 planes
 // [4][qc*nm*nbp*nbp][kpad] (R_e contiguous), scaled by sc and rotated by e_q.
 void launch_mode_rotate_bf16(int ne, int qc, int nm, int nb, int nbp, int kpad, const void* in, const void* evec,
-                             const double* sc, void* out, hipStream_t stream);
+                             const double* sc, void* out, hipStream_t stream, const int32_t* ndeg_fold = nullptr);
 
 struct FusedArgs {
     int nk, ne, nb, nbp, nm;
@@ -58,6 +58,12 @@ struct FusedArgs {
     int nq_total;      // row length of kq
     const void* phi_k; // [nk][ldk] complex in prec (split-bf16: [4][nk][ldk] planes)
     int ldk;
+    // phases generated in the kernel (nmax > 0) from per-axis factors
+    // exp(2 pi i k_a n), |n| <= nmax, instead of read from phi_k
+    int nmax;
+    const int32_t* Re;     // [ne][3]
+    const int32_t* ndeg_e; // [ne]
+    const double* kfrac;   // [nk][3]
     int ldk_b;         // split-bf16: row length (kpad) of the B planes [4][cols][kpad]
     int kpad;          // split-bf16: K padded to a multiple of 32
     const void* B;     // [ne][qc*nm*nbp*nbp] complex in prec

@@ -120,11 +120,15 @@ class System:
         self.gR = _dev(gR, torch.complex128, d)
         self.nb = self.HR.shape[-1]
         self.nm = self.gR.shape[2]
+        # largest |R_e| component: lets the kernels generate the electron phases
+        Rh = np.asarray(Re.cpu() if isinstance(Re, torch.Tensor) else Re)
+        nmax = int(np.abs(Rh).max()) if Rh.size else 0
+        self.nmax_e = nmax if 1 <= nmax <= _lib.EPW_MAX_NMAX else 0
 
     def c_struct(self):
         return _lib.EpwSystem(self.nb, self.nm, self.Re.shape[0], self.Rp.shape[0],
                               _ptr(self.Re), _ptr(self.ndeg_e), _ptr(self.Rp), _ptr(self.ndeg_p),
-                              _ptr(self.HR), _ptr(self.DR), _ptr(self.gR))
+                              _ptr(self.HR), _ptr(self.DR), _ptr(self.gR), self.nmax_e, 0)
 
 
 class Points:

@@ -216,3 +216,20 @@ def test_imsigma_realistic_full_size_sampled():
         low = epw.epw_imsigma(sysd, pts, _params(c, dtype=dtype)).cpu().numpy()
         _say("realistic", dtype, "rel err", rel_err(low[kidx], ref))
         assert rel_err(low[kidx], ref) < tol
+
+
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-10), ("fp32", 1e-5), ("split_bf16", 1e-4)])
+def test_phase_table_and_generated_phases_agree(dtype, tol):
+    """The R_e -> k contraction either streams a phase table or (FP32 and
+    split-BF16 with nmax_e > 0) generates the phases in the kernel from
+    per-axis factors; nmax_e = 0 forces the table.  Both match the oracle."""
+    c = fcc_small_case(nb=5, kg=(3, 3, 3), seed=7)
+    pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
+    ref = _oracle_imsigma(c)
+    sysd = _system(c)
+    assert sysd.nmax_e > 0
+    gen = epw.epw_imsigma(sysd, pts, _params(c, dtype=dtype)).cpu().numpy()
+    sysd.nmax_e = 0
+    tab = epw.epw_imsigma(sysd, pts, _params(c, dtype=dtype)).cpu().numpy()
+    assert rel_err(gen, ref) < tol
+    assert rel_err(tab, ref) < tol
