@@ -350,16 +350,22 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     constexpr int BM = FusedShape<NBP>::BM, BN = FusedShape<NBP>::BN;
     constexpr int BK = (BN == 64 && sizeof(T) == 4) ? 32 : 16;   // deeper K step where registers allow
     constexpr int NB2 = NBP * NBP;
-    constexpr int NBLK = BN / NB2;                 // band blocks per tile
     constexpr int TPR = 256 / BM;                  // threads per k row
-    constexpr int JN = (NBP + TPR - 1) / TPR;      // n values per thread when nb > TPR
+    // Epilogue work items of a row: (band block b, band x), x < NBP; thread
+    // `sub` of the row owns items sub*JI .. sub*JI + JI - 1, in runs of RUN
+    // consecutive items that share one band block.
+    constexpr int JI = BN / (NBP * TPR);
+    constexpr int RUN = JI < NBP ? JI : NBP;
+    constexpr int NRUN = JI / RUN;
+    static_assert(JI * NBP * TPR == BN && JI % RUN == 0 && NBP % RUN == 0, "epilogue split");
+    constexpr int LDC = BN + 1;                    // C tile row stride: rows start on different LDS banks
     typedef Stage<T, BM, BN, BK> St;
     typedef BfStage<BM, BN> Sb;
-    constexpr size_t CBYTES = sizeof(CT) * BM * BN;
+    constexpr size_t CBYTES = sizeof(CT) * BM * LDC;
     constexpr size_t STB = MODE == 2 ? sizeof(Sb) : sizeof(St);
     constexpr size_t SBYTES = STB > CBYTES ? STB : CBYTES;
+    static_assert(SBYTES >= sizeof(double) * 256 * NBP, "row reduction buffer");
     __shared__ __attribute__((aligned(16))) char smem[SBYTES];
-    __shared__ double red[256];
     extern __shared__ __attribute__((aligned(16))) char dsm[];
     CT* Cs = reinterpret_cast<CT*>(smem);
     CE* Et = reinterpret_cast<CE*>(dsm);          // [3][BM][2 nmax + 1] when GEN
@@ -411,26 +417,40 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     const int k = m0 + r;
     const long ncols = (long)a.qc * nm * NB2;
     const double2* U = reinterpret_cast<const double2*>(a.U);
-
-    // thread -> (n, block subset)
-    const bool fewn = nb <= TPR;
-    const int NT = fewn ? TPR / nb : 1;               // threads per n value
-    const int n_single = fewn ? sub / NT : 0;
-    const int bsub = fewn ? sub % NT : 0;
     const bool active_row = k < a.nk;
-    const bool active_thr = active_row && (!fewn || n_single < nb);
+    // a Gaussian factor exp(-y^2) is exactly zero in TE beyond this y^2
+    const double ylim = sizeof(TE) == 8 ? 750.0 : 110.0;
 
-    double acc[JN];
-    #pragma unroll
-    for (int j = 0; j < JN; ++j) acc[j] = 0.0;
-
-    const double inv_sig = 1.0 / a.sigma;
-    double eps_k[JN];
-    #pragma unroll
-    for (int j = 0; j < JN; ++j) {
-        const int n = fewn ? n_single : sub + j * TPR;
-        eps_k[j] = (active_thr && n < nb) ? a.eps[(size_t)k * nb + n] : 0.0;
+    // Items of one run are bands x0 .. x0 + RUN - 1 of one band block, with
+    // x0 = (sub*JI) % NBP the same for every run of the thread.
+    const int x0 = (sub * JI) % NBP;
+    // U_k columns x0 .. x0 + RUN - 1 (phase 1), in TE
+    auto load_uk = [&](CE (&uk)[RUN][NBP]) {
+#pragma unroll
+        for (int t = 0; t < RUN; ++t)
+#pragma unroll
+            for (int jj = 0; jj < NBP; ++jj) {
+                const int n = x0 + t;
+                const double2 u = (active_row && n < nb && jj < nb) ? U[((size_t)k * nb + jj) * nb + n]
+                                                                    : make_double2(0.0, 0.0);
+                uk[t][jj] = mk2((TE)u.x, (TE)u.y);
+            }
+    };
+    // Per-row state kept over the block's tiles: the Im Sigma accumulators of
+    // the row's bands and, in the float32 modes, eps_nk and the U_k columns
+    // (the float64 mode reloads those per tile to stay within its registers).
+    constexpr bool HOIST = MODE != 0;
+    double acc[NBP];
+    double eps_h[HOIST ? NBP : 1];
+    CE uk_h[HOIST ? RUN : 1][NBP];
+#pragma unroll
+    for (int n = 0; n < NBP; ++n) acc[n] = 0.0;
+    if constexpr (HOIST) {
+#pragma unroll
+        for (int n = 0; n < NBP; ++n) eps_h[n] = (active_row && n < nb) ? a.eps[(size_t)k * nb + n] : 0.0;
+        load_uk(uk_h);
     }
+    const double inv_sig = 1.0 / a.sigma;
 
     for (int nt = s; nt < tiles_n; nt += a.S) {
         const long n0 = (long)nt * BN;
@@ -448,7 +468,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 for (int i = 0; i < 4; ++i) {
                     const int row = wm * 16 + 4 * (lane >> 4) + i;
                     const int col = wn * 64 + c * 16 + (lane & 15);
-                    Cs[row * BN + col] = make_float2(cr[c][i], ci[c][i]);
+                    Cs[row * LDC + col] = make_float2(cr[c][i], ci[c][i]);
                 }
         } else {
             const CT* phi = reinterpret_cast<const CT*>(a.phi_k);
@@ -479,16 +499,80 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     CT v;
                     v.x = cr[c][i];
                     v.y = ci[c][i];
-                    Cs[row * BN + col] = v;
+                    Cs[row * LDC + col] = v;
                 }
         }
         __syncthreads();
-        if (active_thr) {
-            for (int b = 0; b < NBLK; ++b) {
-                if (fewn && (b % NT) != bsub) continue;
+        // phase 1: V = G U_k for the thread's items (b, n), all rows i of V,
+        // written over G in LDS.  With JI >= NBP a thread owns whole band
+        // blocks; otherwise the TPR threads of a row share the single block
+        // and wait for each other between reading G and writing V.
+        {
+            CE uk[RUN][NBP];
+            if constexpr (HOIST) {
+#pragma unroll
+                for (int t = 0; t < RUN; ++t)
+#pragma unroll
+                    for (int jj = 0; jj < NBP; ++jj) uk[t][jj] = uk_h[t][jj];
+            } else {
+                load_uk(uk);
+            }
+#pragma unroll
+            for (int rr = 0; rr < NRUN; ++rr) {
+                const int b = (sub * JI + rr * RUN) / NBP;
+                CT* Gt = Cs + r * LDC + b * NB2;
+                CE v[RUN][NBP];
+#pragma unroll
+                for (int t = 0; t < RUN; ++t)
+#pragma unroll
+                    for (int i = 0; i < NBP; ++i) v[t][i] = mk2(TE(0), TE(0));
+                if (active_row) {
+#pragma unroll
+                    for (int i = 0; i < NBP; ++i) {
+                        if (i >= nb) break;
+#pragma unroll
+                        for (int jj = 0; jj < NBP; ++jj) {
+                            if (jj >= nb) break;
+                            const CT g = Gt[i * NBP + jj];
+                            const TE gx = (TE)g.x, gy = (TE)g.y;
+#pragma unroll
+                            for (int t = 0; t < RUN; ++t) {
+                                const CE u = uk[t][jj];
+                                v[t][i].x += gx * u.x - gy * u.y;
+                                v[t][i].y += gx * u.y + gy * u.x;
+                            }
+                        }
+                    }
+                }
+                if constexpr (JI < NBP) __syncthreads();   // all of G has been read
+                if (active_row) {
+#pragma unroll
+                    for (int t = 0; t < RUN; ++t) {
+                        const int n = x0 + t;
+                        if (n >= nb) break;
+#pragma unroll
+                        for (int i = 0; i < NBP; ++i) {
+                            if (i >= nb) break;
+                            CT o;
+                            o.x = (T)v[t][i].x;
+                            o.y = (T)v[t][i].y;
+                            Gt[i * NBP + n] = o;
+                        }
+                    }
+                }
+            }
+            if constexpr (JI < NBP) __syncthreads();
+        }
+        // phase 2: g_mn = sum_i conj(U_k+q[i][m]) V[i][n] for the thread's
+        // items (b, m), all n; weights and |g|^2 accumulated per n
+        if (active_row) {
+#pragma unroll
+            for (int rr = 0; rr < NRUN; ++rr) {
+                const int b = (sub * JI + rr * RUN) / NBP;
+                if (x0 >= nb) continue;
                 const long gblk = n0 / NB2 + b;            // (q_local, nu)
                 const int ql = (int)(gblk / nm), nu = (int)(gblk % nm);
-                if (ql >= a.qc) break;
+                if (ql >= a.qc) continue;
                 const double scv = a.sc[(size_t)ql * nm + nu];
                 if (scv == 0.0 && !STORE) continue;
                 const int q = a.q0 + ql;
@@ -510,76 +594,88 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 }
                 const double w = a.omega[(size_t)ql * nm + nu];
                 const double nB = a.nbose[(size_t)ql * nm + nu];
-                const CT* Gt = Cs + r * BN + b * NB2;
-                #pragma unroll
-                for (int j = 0; j < JN; ++j) {
-                    const int n = fewn ? n_single : sub + j * TPR;
-                    if (n >= nb) continue;
-                    // v = G U_k[:, n]
-                    CE v[NBP];
+                CE uq[RUN][NBP];
+                double em[RUN], fm[RUN];
+                bool mv[RUN];
+#pragma unroll
+                for (int t = 0; t < RUN; ++t) {
+                    const int m = x0 + t;
+                    mv[t] = m < nb;
+                    em[t] = mv[t] ? eq[m] : 0.0;
+                    fm[t] = mv[t] ? fq[m] : 0.0;
 #pragma unroll
                     for (int i = 0; i < NBP; ++i) {
-                        TE vr = TE(0), vi = TE(0);
-                        if (i < nb) {
-#pragma unroll
-                            for (int jj = 0; jj < NBP; ++jj) {
-                                if (jj < nb) {
-                                    const CT g = Gt[i * NBP + jj];
-                                    const double2 ud = U[((size_t)k * nb + jj) * nb + n];
-                                    const CE u = mk2((TE)ud.x, (TE)ud.y);
-                                    vr += (TE)g.x * u.x - (TE)g.y * u.y;
-                                    vi += (TE)g.x * u.y + (TE)g.y * u.x;
-                                }
-                            }
-                        }
-                        v[i] = mk2(vr, vi);
+                        const double2 u = (mv[t] && i < nb) ? Uq[i * nb + m] : make_double2(0.0, 0.0);
+                        uq[t][i] = mk2((TE)u.x, (TE)u.y);
                     }
-                    for (int m = 0; m < nb; ++m) {
-                        TE gr = TE(0), gi = TE(0);
+                }
+                const CT* Vt = Cs + r * LDC + b * NB2;
 #pragma unroll
-                        for (int i = 0; i < NBP; ++i) {
-                            if (i < nb) {
-                                const double2 ud = Uq[i * nb + m];
-                                const TE ux = (TE)ud.x, uy = (TE)ud.y;
-                                // conj(u) * v_i
-                                gr += ux * v[i].x + uy * v[i].y;
-                                gi += ux * v[i].y - uy * v[i].x;
-                            }
+                for (int n = 0; n < NBP; ++n) {
+                    if (n >= nb) break;
+                    double epsn;
+                    if constexpr (HOIST) epsn = eps_h[n]; else epsn = a.eps[(size_t)k * nb + n];
+                    TE W[RUN];
+                    bool need = STORE;
+#pragma unroll
+                    for (int t = 0; t < RUN; ++t) {
+                        W[t] = TE(0);
+                        if (STORE || !mv[t]) continue;
+                        const double x = epsn - em[t];
+                        const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
+                        const double s1 = y1 * y1, s2 = y2 * y2;
+                        if (s1 < ylim) W[t] += (TE)(nB + fm[t]) * fexp((TE)(-s1));
+                        if (s2 < ylim) W[t] += (TE)(nB + 1.0 - fm[t]) * fexp((TE)(-s2));
+                        need = need || (s1 < ylim) || (s2 < ylim);
+                    }
+                    if (!need) continue;
+                    TE gr[RUN], gi[RUN];
+#pragma unroll
+                    for (int t = 0; t < RUN; ++t) {
+                        gr[t] = TE(0);
+                        gi[t] = TE(0);
+                    }
+#pragma unroll
+                    for (int i = 0; i < NBP; ++i) {
+                        if (i >= nb) break;
+                        const CT vv = Vt[i * NBP + n];
+                        const TE vx = (TE)vv.x, vy = (TE)vv.y;
+#pragma unroll
+                        for (int t = 0; t < RUN; ++t) {
+                            // conj(u) * v
+                            gr[t] += uq[t][i].x * vx + uq[t][i].y * vy;
+                            gi[t] += uq[t][i].x * vy - uq[t][i].y * vx;
                         }
+                    }
+#pragma unroll
+                    for (int t = 0; t < RUN; ++t) {
+                        if (!mv[t]) continue;
                         if (STORE) {
                             reinterpret_cast<double2*>(a.gkq)
-                                [((((size_t)k * a.nq_total + q) * nm + nu) * nb + m) * nb + n] =
-                                make_double2((double)gr, (double)gi);
+                                [((((size_t)k * a.nq_total + q) * nm + nu) * nb + x0 + t) * nb + n] =
+                                make_double2((double)gr[t], (double)gi[t]);
                         } else {
-                            const double em = eq[m];
-                            const double fm = fq[m];
-                            const double x = eps_k[j] - em;
-                            const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
-                            const TE W = (TE)(nB + fm) * fexp((TE)(-y1 * y1)) +
-                                         (TE)(nB + 1.0 - fm) * fexp((TE)(-y2 * y2));
-                            acc[j] += (double)((gr * gr + gi * gi) * W);
+                            acc[n] += (double)((gr[t] * gr[t] + gi[t] * gi[t]) * W[t]);
                         }
                     }
+                    // keep the scheduler from overlapping band iterations (register pressure)
+                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
         __syncthreads();
     }
     if (STORE) return;
-    // fixed-order reduction of the NT partial sums of each (k, n)
-    if (fewn) {
-        red[tid] = acc[0];
-        __syncthreads();
-        if (active_thr && bsub == 0) {
+    // fixed-order reduction over the TPR threads of each row
+    double* red = reinterpret_cast<double*>(smem);   // [BM][TPR][NBP]
+#pragma unroll
+    for (int n = 0; n < NBP; ++n) red[(size_t)tid * NBP + n] = acc[n];
+    __syncthreads();
+    if (active_row) {
+        for (int n = sub; n < nb; n += TPR) {
             double t = 0.0;
-            for (int u = 0; u < NT; ++u) t += red[r * TPR + n_single * NT + u];
-            a.part[((size_t)s * a.nk + k) * nb + n_single] = t;
-        }
-    } else if (active_row) {
-        #pragma unroll
-        for (int j = 0; j < JN; ++j) {
-            const int n = sub + j * TPR;
-            if (n < nb) a.part[((size_t)s * a.nk + k) * nb + n] = acc[j];
+            for (int u = 0; u < TPR; ++u) t += red[((size_t)r * TPR + u) * NBP + n];
+            a.part[((size_t)s * a.nk + k) * nb + n] = t;
         }
     }
 }
