@@ -53,10 +53,13 @@ struct Stage {
 
 // A_KMAJOR selects which index of the A tile varies fastest across threads
 // when it is fetched: k (row-major A, default) or m (A read transposed).
-template <typename T, int BM, int BN, int BK, class AF, class BF, bool A_KMAJOR = false>
-__device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>& st, int K, AF afetch, BF bfetch,
+// NS = 1: one LDS stage, two barriers per K step; NS = 2: the next K step is
+// stored into the other stage while this one is read, one barrier per step.
+template <typename T, int BM, int BN, int BK, class AF, class BF, bool A_KMAJOR = false, int NS = 1>
+__device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF afetch, BF bfetch,
                                       typename Cx<T>::acc (&cr)[4], typename Cx<T>::acc (&ci)[4])
 {
+    static_assert(NS == 1 || NS == 2, "one or two LDS stages");
     typedef typename Cx<T>::type CT;
     constexpr int WN = BN / 64;
     constexpr int AE = BM * BK / 256;
@@ -86,7 +89,7 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>& st, int K, AF afetch
             rb[e] = bfetch(k0 + idx / BN, idx % BN);
         }
     };
-    auto sstore = [&]() {
+    auto sstore = [&](Stage<T, BM, BN, BK>& st) {
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
             const int idx = tid * AE + e;
@@ -110,11 +113,12 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>& st, int K, AF afetch
     for (int c = 0; c < 4; ++c)
         for (int i = 0; i < 4; ++i) cm[c][i] = T(0);
     gload(0);
-    sstore();
+    sstore(stages[0]);
     __syncthreads();
-    for (int k0 = 0; k0 < K; k0 += BK) {
+    for (int k0 = 0, it = 0; k0 < K; k0 += BK, ++it) {
         const bool more = k0 + BK < K;
         if (more) gload(k0 + BK);
+        const Stage<T, BM, BN, BK>& st = stages[NS == 2 ? (it & 1) : 0];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + (lane >> 4);
@@ -135,10 +139,16 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>& st, int K, AF afetch
 #pragma unroll
             for (int c = 0; c < 4; ++c) ci[c] = mfma4(as, bs[c], ci[c]);
         }
-        __syncthreads();
-        if (more) {
-            sstore();
+        if constexpr (NS == 2) {
+            // the other stage was last read in the previous step, before its barrier
+            if (more) sstore(stages[(it + 1) & 1]);
             __syncthreads();
+        } else {
+            __syncthreads();
+            if (more) {
+                sstore(stages[0]);
+                __syncthreads();
+            }
         }
     }
     for (int c = 0; c < 4; ++c)

@@ -19,7 +19,7 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
 {
     typedef typename Cx<T>::type CT;
     constexpr int BM = 64, BN = 64, BK = 16;
-    __shared__ Stage<T, BM, BN, BK> st;
+    __shared__ Stage<T, BM, BN, BK> st[2];
     const int m0 = blockIdx.y * BM;
     const long n0 = (long)blockIdx.x * BN;
     const CT* A = reinterpret_cast<const CT*>(d.A);
@@ -46,7 +46,7 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
         return cz<T>();
     };
     typename Cx<T>::acc cr[4], ci[4];
-    cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), CONJ_TRANS_A>(st, d.K, afetch, bfetch, cr, ci);
+    cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), CONJ_TRANS_A, 2>(st, d.K, afetch, bfetch, cr, ci);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = 0; c < 4; ++c) {
         const long col = n0 + c * 16 + (lane & 15);

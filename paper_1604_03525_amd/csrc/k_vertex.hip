@@ -348,7 +348,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     typedef typename ModeTypes<MODE>::TE TE;
     typedef typename ModeTypes<MODE>::CE CE;
     constexpr int BM = FusedShape<NBP>::BM, BN = FusedShape<NBP>::BN;
-    constexpr int BK = (BN == 64 && sizeof(T) == 4) ? 32 : 16;   // deeper K step where registers allow
+    constexpr int BK = 16;
     constexpr int NB2 = NBP * NBP;
     constexpr int TPR = 256 / BM;                  // threads per k row
     // Epilogue work items of a row: (band block b, band x), x < NBP; thread
@@ -362,7 +362,11 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     typedef Stage<T, BM, BN, BK> St;
     typedef BfStage<BM, BN> Sb;
     constexpr size_t CBYTES = sizeof(CT) * BM * LDC;
-    constexpr size_t STB = MODE == 2 ? sizeof(Sb) : sizeof(St);
+    // two LDS stages (one barrier per K step) for float32, where they fit
+    // beside a second resident block; the float64 loop measured faster with
+    // a single stage
+    constexpr int NS = (sizeof(T) == 4 && 2 * sizeof(St) <= 72 * 1024) ? 2 : 1;
+    constexpr size_t STB = MODE == 2 ? sizeof(Sb) : NS * sizeof(St);
     constexpr size_t SBYTES = STB > CBYTES ? STB : CBYTES;
     static_assert(SBYTES >= sizeof(double) * 256 * NBP, "row reduction buffer");
     __shared__ __attribute__((aligned(16))) char smem[SBYTES];
@@ -488,7 +492,8 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 return cz<T>();
             };
             typename Cx<T>::acc cr[4], ci[4];
-            cgemm_mainloop<T, BM, BN, BK>(*reinterpret_cast<St*>(smem), a.ne, afetch, bfetch, cr, ci);
+            cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), false, NS>(
+                reinterpret_cast<St*>(smem), a.ne, afetch, bfetch, cr, ci);
             const int lane = tid & 63, wave = tid >> 6;
             constexpr int WN = BN / 64;
             const int wm = wave / WN, wn = wave % WN;
