@@ -70,6 +70,51 @@ def timed(fn, steps, warmup, torch):
     return dt, stages
 
 
+# HBM traffic of the dominant kernel, from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+# counters recorded in this profile (scaled by the counts of a plain 1 GiB
+# device copy, see --copy-calibration).  It describes the kernel sources whose
+# hash it records: once those change, the figure is reported as null.
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fused_k_kernel_fcc20.md")
+TRAFFIC_SOURCES = ["paper_1604_03525_amd/csrc/k_vertex.hip", "paper_1604_03525_amd/csrc/cgemm.h",
+                   "paper_1604_03525_amd/csrc/api.cpp"]
+
+
+def sources_sha256():
+    import hashlib
+    h = hashlib.sha256()
+    for rel in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(dtype):
+    """Bytes per launch of the fused kernel for `dtype`, or None when the
+    profile is missing or was taken on other kernel sources."""
+    try:
+        with open(TRAFFIC_PROFILE) as f:
+            for line in f:
+                if line.startswith("traffic-record: "):
+                    rec = json.loads(line[len("traffic-record: "):])
+                    if rec.get("sources_sha256") != sources_sha256():
+                        return None
+                    return rec.get("bytes_per_launch", {}).get(dtype)
+    except (OSError, ValueError):
+        return None
+    return None
+
+
+def copy_calibration(torch):
+    """A plain device copy of 1 GiB (two launches): the reference dispatch
+    whose FETCH_SIZE / WRITE_SIZE counts calibrate the traffic counters."""
+    x = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(2):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": x.numel() * 4}), flush=True)
+
+
 def cpu_baseline(host, model, seconds_target=15.0):
     """The FP64 oracle on a bounded sample: a few k points against all q."""
     import numpy as np
@@ -98,6 +143,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants", default="fp32,split_bf16,backward")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -108,6 +155,9 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs a HIP device", file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(torch)
+        return
     dev = torch.device("cuda:0")
     model, sysd, pts, host = setup(dev)
     nk, nq = pts.k.shape[0], pts.q.shape[0]
@@ -138,7 +188,8 @@ def main():
                    "parallelism": "1 GPU"},
         "roofline": {"bound": "mfma", "kernel": "fused_k_kernel (R_e->k contraction + rotation + reduction)",
                      "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
-                     "frac": (achieved / PEAK_TFLOPS["fp64"]) if achieved else None, "traffic": None,
+                     "frac": (achieved / PEAK_TFLOPS["fp64"]) if achieved else None,
+                     "traffic": recorded_traffic("fp64"),
                      "launches": fn, "avg_launch_ms": fms / fn if fn else None},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
     }
@@ -152,7 +203,9 @@ def main():
                 ach = flops / (fmsv * 1e-3) / 1e12 if fmsv > 0 else None
                 variants[var] = {"value": pairs * args.steps / dtv, "ms_per_step": 1e3 * dtv / args.steps,
                                  "speedup_vs_fp64": (pairs * args.steps / dtv) / value,
-                                 "fused_tflops": ach, "fused_frac_of_peak": ach / PEAK_TFLOPS[var] if ach else None}
+                                 "fused_tflops": ach, "fused_frac_of_peak": ach / PEAK_TFLOPS[var] if ach else None,
+                                 "fused_avg_launch_ms": fmsv / fnv if fnv else None,
+                                 "fused_traffic": recorded_traffic(var)}
             elif var == "backward":
                 log("bench: fp64 backward")
                 par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
