@@ -142,7 +142,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp32,split_bf16,backward")
+    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -206,13 +206,15 @@ def main():
                                  "fused_tflops": ach, "fused_frac_of_peak": ach / PEAK_TFLOPS[var] if ach else None,
                                  "fused_avg_launch_ms": fmsv / fnv if fnv else None,
                                  "fused_traffic": recorded_traffic(var)}
-            elif var == "backward":
-                log("bench: fp64 backward")
-                par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
+            elif var in ("backward", "backward_fp32"):
+                bdt = "fp32" if var == "backward_fp32" else "fp64"
+                log("bench: %s backward" % bdt)
+                par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma, dtype=bdt)
                 w = torch.rand((nk, nb), dtype=torch.float64, device=dev)
                 dtb, _ = timed(lambda: epw.epw_imsigma_backward(sysd, pts, par, w, workspace=ws),
                                args.steps, args.warmup, torch)
-                variants[var] = {"value": pairs * args.steps / dtb, "ms_per_step": 1e3 * dtb / args.steps}
+                variants[var] = {"value": pairs * args.steps / dtb, "ms_per_step": 1e3 * dtb / args.steps,
+                                 "dtype": bdt, "outputs": "dL/dg(R_e,R_p), dL/dH(R_e), dL/domega"}
         except epw.EpwError as e:
             variants[var] = {"unavailable": str(e)}
     result["variants"] = variants

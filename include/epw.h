@@ -219,6 +219,9 @@ int epw_imsigma(const epw_system* sys, const epw_points* pts, const epw_params* 
  *  dHR     device [nRe][nb][nb] c128 out (NULL to skip; grid runs only)
  *  domega  device [nq][nm] double out (NULL to skip)
  * Outputs are overwritten (par->accumulate = 1 adds instead).
+ * par->dtype: EPW_FP64 or EPW_FP32 (the contractions, rotations and the
+ * per-pair adjoint in complex64; the eigen-adjoint, the dL/dH(R_e)
+ * contraction and all outputs in float64); EPW_SPLIT_BF16 -> EPW_EDTYPE.
  * Errors: as epw_imsigma. */
 int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw_params* par,
                          const double* w, void* dgR, void* dHR, double* domega,

@@ -294,6 +294,11 @@ struct BwdLayout {
     double* eps_pair = nullptr;
     void* U_pair = nullptr;
     double* f_pair = nullptr;
+    // float32 runs: g(R_e,R_p) and dL/dg(R_e,R_p) in complex64, and a float64
+    // phase table for the dL/dH(R_e) contraction
+    void* gR_t = nullptr;
+    void* dgR_t = nullptr;
+    void* phi_k64 = nullptr;
 };
 
 constexpr size_t AUTO_BWD_CHUNK_BYTES = (size_t)4 << 30;
@@ -339,6 +344,12 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     L.om_c = (double*)A.take(8 * (size_t)nk * L.Q * nm);
     L.inv = (int32_t*)A.take(4 * (size_t)nk * L.Q);
     take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair);
+    if (L.prec == Prec::F32) {
+        const size_t ng = (size_t)ne * np_ * nm * nb * nb;
+        L.gR_t = A.take(8 * ng);
+        L.dgR_t = A.take(8 * ng);
+        L.phi_k64 = A.take(16 * (size_t)nk * ne);
+    }
 }
 
 void run_backward(const epw_system* s, const epw_points* p, const epw_params* par, BwdLayout& L, const double* w,
@@ -364,6 +375,12 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
     const double nqn = par->nq_norm > 0.0 ? par->nq_norm : (double)nq;
     const double C = M_PI / (nqn * par->sigma * std::sqrt(M_PI));
     const double kT = 8.617333262e-5 * par->T;
+    const bool f32 = prec == Prec::F32;
+    const void* gsrc = s->gR;
+    if (f32) {
+        launch_c128_to_c64((size_t)ne * np_ * ncol_g, s->gR, L.gR_t, st);
+        gsrc = L.gR_t;
+    }
     for (int c = 0; c < L.nchunks; ++c) {
         const int q0 = c * L.Q;
         const int qc = (q0 + L.Q <= nq) ? L.Q : nq - q0;
@@ -384,7 +401,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
         pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, st);
         const long ncols = (long)qc * nm * L.nbp * L.nbp;
         StageTimer tb(EPW_STAGE_BACKWARD, st);
-        launch_cgemm(prec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, s->gR, L.gq), st);
+        launch_cgemm(prec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, gsrc, L.gq), st);
         launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st);
         {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
             GemmDesc d;
@@ -460,20 +477,23 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             e.ncb = (int)ncol_g;
             e.sBe = (long)qc * ncol_g;
             e.sBk = (long)ncol_g;
-            e.C = dgR;
+            // float32: accumulated over chunks in complex64, converted at the end
+            e.C = f32 ? L.dgR_t : dgR;
             e.sCe = (long)np_ * ncol_g;
             e.sCm = (long)ncol_g;
-            e.accumulate = (c > 0 || acc0) ? 1 : 0;
+            e.accumulate = (c > 0 || (acc0 && !f32)) ? 1 : 0;
             launch_cgemm(prec, e, st);
         }
     }
+    if (dgR && f32 && L.nchunks > 0) launch_c64_to_c128((size_t)ne * np_ * ncol_g, L.dgR_t, acc0, dgR, st);
     if (dHR) {
         launch_eigh_adjoint(nk, nb, L.eps, L.U, L.ebar, L.Ubar, par->deg_tol, L.Xbar, st);
+        if (f32) launch_phase_table(Prec::F64, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_k64, st);
         GemmDesc d;   // dHR[e][ij] (+)= sum_k conj(Phi_k[k][R_e]) Xbar[k][ij]
         d.M = ne;
         d.N = nb * nb;
         d.K = nk;
-        d.A = L.phi_k;
+        d.A = f32 ? L.phi_k64 : L.phi_k;
         d.lda = ne;
         d.conj_trans_a = 1;
         d.B = L.Xbar;
@@ -624,7 +644,8 @@ extern "C" int epw_imsigma_backward(const epw_system* sys, const epw_points* pts
     if (!w) return fail(EPW_EINVAL, "epw_imsigma_backward: NULL weights");
     if (dHR && !pts->kq)
         return fail(EPW_ESHAPE, "epw_imsigma_backward: dL/dH(R) needs the k+q states in the k set (a kq map)");
-    if (par->dtype != EPW_FP64) return fail(EPW_EDTYPE, "epw_imsigma_backward: only EPW_FP64 is available");
+    if (par->dtype != EPW_FP64 && par->dtype != EPW_FP32)
+        return fail(EPW_EDTYPE, "epw_imsigma_backward: EPW_FP64 or EPW_FP32 (the split-bf16 adjoint is not built)");
     Arena dry;
     dry.dry = true;
     BwdLayout L;

@@ -29,12 +29,12 @@ def _setup(c, kg):
     return om, ev, w, kw
 
 
-def _hip_grads(c, om, ev, w):
+def _hip_grads(c, om, ev, w, dtype="fp64"):
     g = torch.tensor(c["gR"], device=DEV, requires_grad=True)
     h = torch.tensor(c["HR"], device=DEV, requires_grad=True)
     o = torch.tensor(om, device=DEV, requires_grad=True)
     ims = autograd.imsigma(g, h, o, torch.as_tensor(ev).to(DEV), c["R"], c["nd"], c["R"], c["nd"], c["k"], c["q"],
-                           c["kq"], T=c["T"], mu=c["mu"], sigma=c["sigma"])
+                           c["kq"], T=c["T"], mu=c["mu"], sigma=c["sigma"], dtype=dtype)
     L = torch.sum(torch.as_tensor(w, device=DEV) * ims)
     L.backward()
     return float(L.detach()), g.grad.cpu().numpy(), h.grad.cpu().numpy(), o.grad.cpu().numpy()
@@ -124,3 +124,47 @@ def test_adjoint_chunking_and_accumulate():
     b = epw.epw_imsigma_backward(sysd, pts, epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"], chunk_q=5), w)
     for x, y in zip(a, b):
         assert rel_err(y.cpu().numpy(), x.cpu().numpy()) < 1e-12
+
+
+@pytest.mark.parametrize("case", ["toy12", "fcc3"])
+def test_adjoint_fp32_matches_reference_gradient(case):
+    """The float32 adjoint (complex64 contractions, rotations and per-pair
+    adjoint; float64 eigen-adjoint and outputs) against the FP64 reference
+    gradient.  Tolerance 1e-4 relative: float32 rounding (6e-8) grown by the
+    contraction lengths (N_e, N_k up to ~1.7e3 terms) and by the forward's own
+    float32 error, which enters every weight of the adjoint."""
+    if case == "toy12":
+        c = toy_case((12, 12, 12))
+    else:
+        c = fcc_small_case(nb=3, kg=(3, 3, 3))
+    om, ev, w, kw = _setup(c, None)
+    L_ref, ims_ref, dg_ref, dh_ref, dom_ref = torch_ref.loss_and_grads(c["gR"], c["HR"], om, ev, w, **kw)
+    L, dg, dh, dom = _hip_grads(c, om, ev, w, dtype="fp32")
+    _say("fp32 gradients", case, "rel errs L/g/h/omega", abs(L - L_ref) / abs(L_ref), rel_err(dg, dg_ref),
+         rel_err(dh, dh_ref), rel_err(dom, dom_ref))
+    assert abs(L - L_ref) < 1e-5 * abs(L_ref)
+    assert rel_err(dg, dg_ref) < 1e-4
+    assert rel_err(dh, dh_ref) < 1e-4
+    assert rel_err(dom, dom_ref) < 1e-4
+
+
+def test_adjoint_fp32_chunking_accumulate_and_bf16_refused():
+    """float32: chunks of 5 q give the result of one chunk (to float32
+    rounding), accumulate adds onto the outputs, and the split-bf16 adjoint
+    is refused with EPW_EDTYPE."""
+    c = fcc_small_case(nb=2, kg=(3, 3, 3), seed=5)
+    om, ev, w, kw = _setup(c, None)
+    sysd = epw.System(c["R"], c["nd"], c["R"], c["nd"], c["HR"], None, c["gR"], DEV)
+    pts = epw.Points(c["k"], c["q"], c["kq"], omega=om, evec=ev, device=DEV)
+    mk = lambda **kw2: epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"], dtype="fp32", **kw2)
+    a = epw.epw_imsigma_backward(sysd, pts, mk(), w)
+    b = epw.epw_imsigma_backward(sysd, pts, mk(chunk_q=5), w)
+    for x, y in zip(a, b):
+        assert rel_err(y.cpu().numpy(), x.cpu().numpy()) < 1e-5
+    ref = epw.epw_imsigma_backward(sysd, pts, epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"]), w)
+    for x, y in zip(a, ref):
+        assert rel_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-4
+    with pytest.raises(epw.EpwError) as ei:
+        epw.epw_imsigma_backward(sysd, pts, epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"],
+                                                            dtype="split_bf16"), w)
+    assert ei.value.code == -3
