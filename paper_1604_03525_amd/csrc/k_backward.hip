@@ -19,10 +19,10 @@
 #include "epw_internal.h"
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace epw {
 namespace {
-
-constexpr int PMAX = 16;
 
 __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -39,9 +39,14 @@ template <typename CT> __device__ inline CT from_d2(double2 v);
 template <> __device__ inline double2 from_d2<double2>(double2 v) { return v; }
 template <> __device__ inline float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
-template <typename CT>
-__global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
+// One block per (k, q) pair (64 threads, or one per matrix element for
+// P = 16); the per-pair matrices live in LDS sized for the padded band count
+// P, so small band counts keep many blocks resident per CU.
+template <typename CT, int P>
+__global__ __launch_bounds__(P * P > 64 ? P * P : 64) void pair_bwd_kernel(PairBwdArgs a)
 {
+    constexpr int PMAX = P;
+    constexpr int NT = P * P > 64 ? P * P : 64;       // threads: at least one per matrix element
     __shared__ double2 Uk[PMAX][PMAX + 1];
     __shared__ double2 Uq[PMAX][PMAX + 1];
     __shared__ double2 X[PMAX][PMAX + 1];
@@ -70,7 +75,7 @@ __global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
     CT* G = reinterpret_cast<CT*>(a.G);
     const size_t ncols = (size_t)a.qc * nm * nbp * nbp;
 
-    for (int e = lane; e < nb2; e += 64) {
+    for (int e = lane; e < nb2; e += NT) {
         const int r = e / nb, c = e % nb;
         Uk[r][c] = valid ? U[((size_t)k * nb + r) * nb + c] : make_double2(0.0, 0.0);
         Uq[r][c] = valid ? Uqs[r * nb + c] : make_double2(0.0, 0.0);
@@ -88,13 +93,13 @@ __global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
         const double scv = a.sc[(size_t)ql * nm + nu];
         if (!valid || scv == 0.0) {
             // no contribution: the adjoint of this block is zero
-            for (int e = lane; e < nb2; e += 64) Gb[(e / nb) * nbp + e % nb] = from_d2<CT>(make_double2(0.0, 0.0));
+            for (int e = lane; e < nb2; e += NT) Gb[(e / nb) * nbp + e % nb] = from_d2<CT>(make_double2(0.0, 0.0));
             if (lane == 0) a.om_c[pair * nm + nu] = 0.0;
             continue;
         }
-        for (int e = lane; e < nb2; e += 64) X[e / nb][e % nb] = to_d2(Gb[(e / nb) * nbp + e % nb]);
+        for (int e = lane; e < nb2; e += NT) X[e / nb][e % nb] = to_d2(Gb[(e / nb) * nbp + e % nb]);
         __syncthreads();
-        for (int e = lane; e < nb2; e += 64) {          // T = X U_k
+        for (int e = lane; e < nb2; e += NT) {          // T = X U_k
             const int i = e / nb, n = e % nb;
             double2 t = make_double2(0.0, 0.0);
             for (int j = 0; j < nb; ++j) {
@@ -108,7 +113,7 @@ __global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
         const double w = a.omega[(size_t)ql * nm + nu];
         const double nB = a.nbose[(size_t)ql * nm + nu];
         const double dnB = a.kT > 0.0 ? -nB * (nB + 1.0) / a.kT : 0.0;
-        for (int e = lane; e < nb2; e += 64) {          // g' = U_kq^dag T, weights
+        for (int e = lane; e < nb2; e += NT) {          // g' = U_kq^dag T, weights
             const int m = e / nb, n = e % nb;
             double2 g = make_double2(0.0, 0.0);
             for (int i = 0; i < nb; ++i) {
@@ -135,7 +140,7 @@ __global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
             S3[m][n] = cw * amp * (dWdw - Wv / w);
         }
         __syncthreads();
-        for (int e = lane; e < nb2; e += 64) {          // Y = U_kq gbar'; Ubar_kq += T gbar'^dag
+        for (int e = lane; e < nb2; e += NT) {          // Y = U_kq gbar'; Ubar_kq += T gbar'^dag
             const int i = e / nb, c = e % nb;
             double2 y = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
             for (int m = 0; m < nb; ++m) {
@@ -159,14 +164,19 @@ __global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
             ekA[lane] += s1;
             eqA[lane] += s2;
         }
-        if (lane == 0) {
-            double s3 = 0.0;
-            for (int m = 0; m < nb; ++m)
-                for (int n = 0; n < nb; ++n) s3 += S3[m][n];
-            a.om_c[pair * nm + nu] = s3;
+        __syncthreads();
+        if (lane < nb) {                                 // row sums of S3, then their sum (fixed order)
+            double r3 = 0.0;
+            for (int n = 0; n < nb; ++n) r3 += S3[lane][n];
+            S3[lane][PMAX] = r3;
         }
         __syncthreads();
-        for (int e = lane; e < nb2; e += 64) {          // Ubar_k += X^dag Y; Gbar = Y U_k^dag
+        if (lane == 0) {
+            double s3 = 0.0;
+            for (int m = 0; m < nb; ++m) s3 += S3[m][PMAX];
+            a.om_c[pair * nm + nu] = s3;
+        }
+        for (int e = lane; e < nb2; e += NT) {          // Ubar_k += X^dag Y; Gbar = Y U_k^dag
             const int r = e / nb, c = e % nb;
             double2 u = make_double2(0.0, 0.0), gbar = make_double2(0.0, 0.0);
             for (int i = 0; i < nb; ++i) {
@@ -187,7 +197,7 @@ __global__ __launch_bounds__(64) void pair_bwd_kernel(PairBwdArgs a)
     }
     double2* Ukc = reinterpret_cast<double2*>(a.Uk_c);
     double2* Uqc = reinterpret_cast<double2*>(a.Ukq_c);
-    for (int e = lane; e < nb2; e += 64) {
+    for (int e = lane; e < nb2; e += NT) {
         Ukc[pair * nb2 + e] = UkA[e / nb][e % nb];
         Uqc[pair * nb2 + e] = UqA[e / nb][e % nb];
     }
@@ -298,7 +308,8 @@ __global__ void mode_rotate_adjoint_kernel(int ne, int nq, int nm, int nb, int n
     }
 }
 
-// one 64-thread block per k
+// one 64-thread block per k (runs once per call: sized for the largest band count)
+constexpr int PMAX = 16;
 __global__ __launch_bounds__(64) void eigh_adjoint_kernel(int nk, int nb, const double* __restrict__ eps,
                                                           const double2* __restrict__ U,
                                                           const double* __restrict__ ebar,
@@ -375,10 +386,20 @@ inline unsigned nblk(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 void launch_pair_bwd(Prec prec, const PairBwdArgs& a, hipStream_t stream) {
     if (a.nk == 0 || a.qc == 0) return;
     dim3 grid((unsigned)a.qc, (unsigned)a.nk);
-    if (prec == Prec::F64)
-        pair_bwd_kernel<double2><<<grid, 64, 0, stream>>>(a);
-    else
-        pair_bwd_kernel<float2><<<grid, 64, 0, stream>>>(a);
+    auto go = [&](auto tag) {
+        constexpr int P = decltype(tag)::value;
+        if (prec == Prec::F64)
+            pair_bwd_kernel<double2, P><<<grid, P * P > 64 ? P * P : 64, 0, stream>>>(a);
+        else
+            pair_bwd_kernel<float2, P><<<grid, P * P > 64 ? P * P : 64, 0, stream>>>(a);
+    };
+    switch (a.nbp) {
+        case 1: go(std::integral_constant<int, 1>()); break;
+        case 2: go(std::integral_constant<int, 2>()); break;
+        case 4: go(std::integral_constant<int, 4>()); break;
+        case 8: go(std::integral_constant<int, 8>()); break;
+        default: go(std::integral_constant<int, 16>()); break;
+    }
     launch_check("pair_bwd_kernel");
 }
 
