@@ -3,6 +3,7 @@
 // stream; nothing here blocks on the device.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 
@@ -299,6 +300,8 @@ struct BwdLayout {
     void* gR_t = nullptr;
     void* dgR_t = nullptr;
     void* phi_k64 = nullptr;
+    int kparts = 1;          // split-K slices of the sum over k (conjugate-transposed GEMM)
+    void* kpart = nullptr;   // [kparts][N_e][Q n_m NBP^2] partial products
 };
 
 constexpr size_t AUTO_BWD_CHUNK_BYTES = (size_t)4 << 30;
@@ -310,7 +313,7 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
     const bool given = p->omega && p->evec;
     const size_t nbp2 = (size_t)L.nbp * L.nbp;
-    const size_t per_q = cb * ((size_t)nk * nm * nbp2 + 2 * (size_t)ne * nm * nbp2 + np_) +
+    const size_t per_q = cb * ((size_t)nk * nm * nbp2 + 6 * (size_t)ne * nm * nbp2 + np_) +
                          (size_t)nk * (16 * nb + 32 * (size_t)nb * nb + 8 * nm + 4) +
                          (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm +
                          pair_bytes_per_q(s, p);
@@ -344,6 +347,8 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     L.om_c = (double*)A.take(8 * (size_t)nk * L.Q * nm);
     L.inv = (int32_t*)A.take(4 * (size_t)nk * L.Q);
     take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair);
+    L.kparts = splitk_parts(ne, (int)((size_t)L.Q * nm * nbp2), nk);
+    if (L.kparts > 1) L.kpart = A.take(cb * (size_t)L.kparts * ne * L.Q * nm * nbp2);
     if (L.prec == Prec::F32) {
         const size_t ng = (size_t)ne * np_ * nm * nb * nb;
         L.gR_t = A.take(8 * ng);
@@ -464,7 +469,8 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.sBk = ncols;
             d.C = L.Bnu;
             d.sCm = ncols;
-            launch_cgemm(prec, d, st);
+            // K = N_k is long and M = N_e short: split the sum over k so the grid fills the chip
+            launch_cgemm_splitk(prec, d, std::min(splitk_parts(d.M, d.N, d.K), L.kparts), L.kpart, st);
             launch_mode_rotate_adjoint(prec, ne, qc, nm, nb, L.nbp, L.Bnu, ev, L.sc, L.gq, st);
             GemmDesc e;   // dgR[e][p][c] (+)= sum_q conj(Phi_q[q][p]) gbar_a[e][q][c]
             e.M = np_;

@@ -20,14 +20,24 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
     typedef typename Cx<T>::type CT;
     constexpr int BM = 64, BN = 64, BK = 16;
     __shared__ Stage<T, BM, BN, BK> st[2];
-    const int m0 = blockIdx.y * BM;
-    const long n0 = (long)blockIdx.x * BN;
+    // 1-D grid: with few row tiles the row tile varies fastest, so the blocks
+    // sharing a column tile of B run together and share it in L2
+    const int tiles_m = (d.M + BM - 1) / BM;
+    const long tiles_n = ((long)d.N + BN - 1) / BN;
+    const long bx = blockIdx.x;
+    const int mt = tiles_m <= 8 ? (int)(bx % tiles_m) : (int)(bx / tiles_n);
+    const long nt = tiles_m <= 8 ? bx / tiles_m : bx % tiles_n;
+    const int m0 = mt * BM;
+    const long n0 = nt * BN;
+    // split K: block z covers k in [kb, kb + Kz) and writes its own partial C
+    const int kb = d.kchunk > 0 ? (int)blockIdx.z * d.kchunk : 0;
+    const int Kz = d.kchunk > 0 ? min(d.kchunk, d.K - kb) : d.K;
     const CT* A = reinterpret_cast<const CT*>(d.A);
     const CT* B = reinterpret_cast<const CT*>(d.B);
-    CT* C = reinterpret_cast<CT*>(d.C);
-    auto afetch = [&](int m, int k) -> CT {
-        const int row = m0 + m;
-        if (row < d.M && k < d.K) {
+    CT* C = reinterpret_cast<CT*>(d.C) + (size_t)blockIdx.z * d.sCz;
+    auto afetch = [&](int m, int kl) -> CT {
+        const int row = m0 + m, k = kb + kl;
+        if (row < d.M && kl < Kz) {
             if (CONJ_TRANS_A) {
                 CT v = A[(size_t)k * d.lda + row];
                 v.y = -v.y;
@@ -37,16 +47,16 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
         }
         return cz<T>();
     };
-    auto bfetch = [&](int k, int n) -> CT {
+    auto bfetch = [&](int kl, int n) -> CT {
         const long col = n0 + n;
-        if (k < d.K && col < d.N) {
+        if (kl < Kz && col < d.N) {
             const long e = col / d.ncb, c = col % d.ncb;
-            return B[(size_t)e * d.sBe + (size_t)k * d.sBk + c];
+            return B[(size_t)e * d.sBe + (size_t)(kb + kl) * d.sBk + c];
         }
         return cz<T>();
     };
     typename Cx<T>::acc cr[4], ci[4];
-    cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), CONJ_TRANS_A, 2>(st, d.K, afetch, bfetch, cr, ci);
+    cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), CONJ_TRANS_A, 2>(st, Kz, afetch, bfetch, cr, ci);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = 0; c < 4; ++c) {
         const long col = n0 + c * 16 + (lane & 15);
@@ -69,11 +79,72 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
     }
 }
 
+// C[m][n] (+)= sum_z P[z][m][n] in fixed z order (split-K partials, C with row stride ldc)
+template <typename CT>
+__global__ void splitk_reduce_kernel(int M, int N, int parts, const CT* __restrict__ P, long ldc, int accumulate,
+                                     CT* __restrict__ C)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t MN = (size_t)M * N;
+    if (idx >= MN) return;
+    const size_t m = idx / N, n = idx % N;
+    CT v = P[idx];
+    for (int z = 1; z < parts; ++z) {
+        const CT p = P[(size_t)z * MN + idx];
+        v.x += p.x;
+        v.y += p.y;
+    }
+    CT* dst = C + m * ldc + n;
+    if (accumulate) {
+        v.x += dst->x;
+        v.y += dst->y;
+    }
+    *dst = v;
+}
+
 }  // namespace
 
-void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream) {
+int splitk_parts(int M, int N, int K) {
+    // enough blocks for ~8 rounds of two resident blocks per CU on 256 CUs,
+    // at least 512 K values per part, at most 4 parts
+    const long blocks = (long)((N + 63) / 64) * ((M + 63) / 64);
+    long parts = blocks > 0 ? (4096 + blocks - 1) / blocks : 1;
+    const long kmax = K / 512;
+    if (parts > kmax) parts = kmax;
+    if (parts > 4) parts = 4;
+    return parts < 1 ? 1 : (int)parts;
+}
+
+void launch_cgemm_splitk(Prec prec, const GemmDesc& d, int parts, void* scratch, hipStream_t stream) {
     if (d.M <= 0 || d.N <= 0) return;
-    dim3 grid((unsigned)((d.N + 63) / 64), (unsigned)((d.M + 63) / 64));
+    if (parts <= 1 || d.ncb != d.N || d.kchunk != 0) {
+        launch_cgemm(prec, d, stream);
+        return;
+    }
+    GemmDesc e = d;
+    e.kchunk = ((d.K + parts - 1) / parts + 15) / 16 * 16;
+    const int nz = (d.K + e.kchunk - 1) / e.kchunk;
+    e.C = scratch;
+    e.sCe = 0;
+    e.sCm = d.N;
+    e.sCz = (long)d.M * d.N;
+    e.accumulate = 0;
+    launch_cgemm(prec, e, stream, nz);
+    const size_t MN = (size_t)d.M * d.N;
+    const unsigned nb = (unsigned)((MN + 255) / 256);
+    if (prec == Prec::F64)
+        splitk_reduce_kernel<double2><<<nb, 256, 0, stream>>>(d.M, d.N, nz, (const double2*)scratch, d.sCm,
+                                                               d.accumulate, (double2*)d.C);
+    else
+        splitk_reduce_kernel<float2><<<nb, 256, 0, stream>>>(d.M, d.N, nz, (const float2*)scratch, d.sCm,
+                                                             d.accumulate, (float2*)d.C);
+    launch_check("splitk_reduce_kernel");
+}
+
+void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream, int kparts) {
+    if (d.M <= 0 || d.N <= 0) return;
+    const long tiles = (long)((d.N + 63) / 64) * ((d.M + 63) / 64);
+    dim3 grid((unsigned)tiles, 1, (unsigned)(kparts > 1 ? kparts : 1));
     if (prec == Prec::F64) {
         if (d.conj_trans_a) cgemm_generic_kernel<double, true><<<grid, 256, 0, stream>>>(d);
         else cgemm_generic_kernel<double, false><<<grid, 256, 0, stream>>>(d);

@@ -101,8 +101,16 @@ struct GemmDesc {
     void* C = nullptr;
     long sCe = 0, sCm = 0;
     int accumulate = 0;
+    int kchunk = 0;    // split K: blockIdx.z covers [z*kchunk, (z+1)*kchunk) (0: all of K)
+    long sCz = 0;      // C offset between the split-K partial outputs
 };
-void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream);
+// kparts > 1 launches that many K slices (d.kchunk must cover K)
+void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream, int kparts = 1);
+// number of K slices launch_cgemm_splitk uses for an M x N x K product
+int splitk_parts(int M, int N, int K);
+// C (+)= A B as `parts` K slices into scratch ([parts][M][N] complex in prec),
+// summed in fixed order into C; needs a single column slab (d.ncb == d.N)
+void launch_cgemm_splitk(Prec prec, const GemmDesc& d, int parts, void* scratch, hipStream_t stream);
 
 // ---- k_backward.hip (adjoint of L = sum_nk w_nk Im Sigma_nk) ----
 struct PairBwdArgs {
