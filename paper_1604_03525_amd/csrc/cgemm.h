@@ -43,12 +43,15 @@ template <typename T> __device__ inline int crow(int lane, int i);
 template <> __device__ inline int crow<double>(int lane, int i) { return (lane >> 4) + 4 * i; }
 template <> __device__ inline int crow<float>(int lane, int i) { return 4 * (lane >> 4) + i; }
 
+// Rows are padded by 16 elements: the four K rows one MFMA operand read
+// touches then start in different LDS bank ranges.
 template <typename T, int BM, int BN, int BK>
 struct Stage {
-    T a_re[BK][BM];
-    T a_im[BK][BM];
-    T b_re[BK][BN];
-    T b_im[BK][BN];
+    static constexpr int PAD = 16;
+    T a_re[BK][BM + PAD];
+    T a_im[BK][BM + PAD];
+    T b_re[BK][BN + PAD];
+    T b_im[BK][BN + PAD];
 };
 
 // A_KMAJOR selects which index of the A tile varies fastest across threads
