@@ -115,6 +115,65 @@ def copy_calibration(torch):
     print(json.dumps({"copy_calibration_bytes": x.numel() * 4}), flush=True)
 
 
+def mobility_shard(dev, dtypes, steps, warmup, torch):
+    """One 4096-q chunk of the mobility-scale system, i.e. the per-GPU shard of
+    a q-sharded run: fcc, 3 atoms, 16 bands, 9 modes, 617 + 617 WS vectors,
+    8000 k in the 0.3 eV window above the conduction band minimum x the first
+    4096 of 125,000 random q, off-grid k+q (H interpolated and diagonalised per
+    pair), normalised by N_q = 125,000.  H and D are rescaled on the coarse
+    grid to a 12 eV bandwidth and a 65 meV top phonon; mu is mid-gap on a 40^3
+    grid.  g(R_e,R_p) (14 GB) is drawn on the device."""
+    import numpy as np
+    from paper_1604_03525_amd import epw
+    from paper_1604_03525_amd import inputs as I
+    m = I.mobility_model()
+    x = m.extra
+    R, nd = epw.epw_ws_vectors(m.metric, m.coarse)
+    H0, D0 = I.mobility_unscaled(R)
+    Ht = torch.as_tensor(H0, device=dev)
+    Dt = torch.as_tensor(D0, device=dev)
+    coarse = epw.epw_grid_points(m.coarse)
+    e0, _ = epw.epw_interp_bands(Ht, R, nd, coarse)
+    Ht *= x["bandwidth"] / float(e0.max() - e0.min())
+    w0, _ = epw.epw_interp_phonons(Dt, R, nd, coarse)
+    Dt *= (x["omega_max"] / float(w0.max())) ** 2
+    e40, _ = epw.epw_interp_bands(Ht, R, nd, epw.epw_grid_points((40, 40, 40)))
+    nv = m.nb // 2
+    vbm, cbm = float(e40[:, nv - 1].max()), float(e40[:, nv].min())
+    mu = 0.5 * (vbm + cbm)
+    rng = np.random.default_rng(x["seed_k"])
+    kept, total = [], 0
+    for _ in range(200):
+        cand = rng.random((65536, 3))
+        e, _ = epw.epw_interp_bands(Ht, R, nd, cand)
+        mask = ((e >= cbm) & (e <= cbm + x["window"])).any(dim=1).cpu().numpy()
+        kept.append(cand[mask])
+        total += int(mask.sum())
+        if total >= x["nk"]:
+            break
+    k = np.concatenate(kept)[: x["nk"]]
+    q = I.random_points(x["nq"], x["seed_q"])[: x["chunk"]]
+    gR = I.random_vertex_device(R, R, m.vectors, m.nm, m.nb, seed=x["seed_g"], g0=0.05, decay=1.0, device=dev)
+    sysd = epw.System(R, nd, R, nd, Ht, Dt, gR, dev)
+    del gR
+    pts = epw.Points(k, q, None, device=dev)
+    ws = epw.Workspace(dev)
+    pairs = len(k) * len(q)
+    out = {"workload": "fcc 3 atoms, nb=16, nm=9, WS 617+617, %d window k x %d random q (one chunk of %d), "
+                       "off-grid k+q, T=300 K, sigma=10 meV" % (len(k), len(q), x["nq"]),
+           "mu_eV": mu, "cbm_eV": cbm}
+    for dt in dtypes:
+        log("bench: mobility shard %s" % dt)
+        par = epw.make_params(T=m.T, mu=mu, sigma=m.sigma, nq_norm=float(x["nq"]), dtype=dt)
+        dtv, stv = timed(lambda: epw.epw_imsigma(sysd, pts, par, workspace=ws), steps, warmup, torch)
+        fms, fnn = stv["fused"]
+        ach = fused_flops(len(k), len(q), len(R), m.nm, m.nb) * steps / (fms * 1e-3) / 1e12 if fms > 0 else None
+        out[dt] = {"value": pairs * steps / dtv, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dtv / steps,
+                   "fused_tflops": ach, "fused_frac_of_peak": ach / PEAK_TFLOPS[dt] if ach else None,
+                   "stages_ms_per_step": {s_: v[0] / steps for s_, v in stv.items()}}
+    return out
+
+
 def cpu_baseline(host, model, seconds_target=15.0):
     """The FP64 oracle on a bounded sample: a few k points against all q."""
     import numpy as np
@@ -142,7 +201,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32")
+    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32",
+                    help="comma list of fp32, split_bf16, backward, backward_fp32, mobility (the last is "
+                         "opt-in: one 4096-q shard of the mobility-scale system, ~2 min)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     args = ap.parse_args()
@@ -215,6 +276,8 @@ def main():
                                args.steps, args.warmup, torch)
                 variants[var] = {"value": pairs * args.steps / dtb, "ms_per_step": 1e3 * dtb / args.steps,
                                  "dtype": bdt, "outputs": "dL/dg(R_e,R_p), dL/dH(R_e), dL/domega"}
+            elif var == "mobility":
+                variants[var] = mobility_shard(dev, ("fp32", "split_bf16"), min(args.steps, 2), 1, torch)
         except epw.EpwError as e:
             variants[var] = {"unavailable": str(e)}
     result["variants"] = variants

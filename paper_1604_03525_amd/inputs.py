@@ -146,6 +146,22 @@ def random_vertex(Re, Rp, vectors, nm, nb, seed, g0, decay=1.0):
     return mod[:, :, None, None, None] * np.exp(1j * phi)
 
 
+def random_vertex_device(Re, Rp, vectors, nm, nb, seed, g0, decay=1.0, device="cuda"):
+    """The distribution of random_vertex (same modulus, uniform phase), drawn
+    on a device with torch's seeded generator: a different random stream,
+    for throughput runs at sizes where host generation would dominate
+    (617^2 x 9 x 16^2 entries).  Returns a complex128 device tensor."""
+    import torch
+    gen = torch.Generator(device=device)
+    gen.manual_seed(seed)
+    de = torch.as_tensor(np.linalg.norm(cartesian(Re, vectors), axis=1), device=device)
+    dp = torch.as_tensor(np.linalg.norm(cartesian(Rp, vectors), axis=1), device=device)
+    mod = g0 * torch.exp(-(de[:, None] + dp[None, :]) / decay)
+    phi = torch.rand((len(Re), len(Rp), nm, nb, nb), generator=gen, device=device, dtype=torch.float64)
+    phi.mul_(2.0 * np.pi)
+    return torch.polar(mod[:, :, None, None, None].expand_as(phi).contiguous(), phi)
+
+
 def constant_vertex(Re, Rp, c):
     """g_a(R_e,R_p) = c_a at R_e = R_p = 0 only (single band):
     the constant-coupling model of the closed-form linewidth."""
@@ -224,6 +240,26 @@ def realistic_model():
     return Model("realistic", FCC_METRIC, FCC_VECTORS, (6, 6, 6), 8, 6,
                  (20, 20, 20), (20, 20, 20), T=300.0,
                  mu=C2_MU, sigma=0.02)
+
+
+def mobility_model():
+    """The mobility-scale system: fcc, 3 atoms, 16 bands, 9 modes, coarse
+    8^3 (617 WS vectors), 8000 k in a 0.3 eV window above the conduction
+    band minimum, 125,000 random q in chunks of 4096, T = 300 K, sigma = 10 meV,
+    mu at mid-gap (fixed at run time from the bands)."""
+    return Model("mobility", FCC_METRIC, FCC_VECTORS, (8, 8, 8), 16, 9, None, None, T=300.0,
+                 mu=0.0, sigma=0.01, extra={"nk": 8000, "nq": 125000, "chunk": 4096, "window": 0.3,
+                                            "seed_h": 20, "seed_d": 21, "seed_g": 22,
+                                            "seed_k": 3, "seed_q": 2, "bandwidth": 12.0,
+                                            "omega_max": 0.065})
+
+
+def mobility_unscaled(R):
+    """(HR, DR) of the mobility-scale system before rescaling (seeds 20, 21;
+    decay lengths as the realistic model)."""
+    HR = random_hamiltonian(R, FCC_VECTORS, 16, seed=20, decay=1.5, scale=1.0)
+    DR = spring_dynmat(R, FCC_VECTORS, ATOMS_FCC3, shells=2, seed=21, scale=1.0)
+    return HR, DR
 
 
 def realistic_arrays(Re, Rp, h_scale=None, d_scale=None):
