@@ -48,6 +48,19 @@ int check_common(const epw_system* s, const epw_points* p, const epw_params* par
     return EPW_OK;
 }
 
+// Off-grid k+q: H(k+q) of every (k, q) pair of a chunk is formed as an FP64
+// GEMM over R_e whose A operand is the product of the k and q phase tables
+// (e^{2 pi i (k+q).R} = e^{2 pi i k.R} e^{2 pi i q.R}), in batches of pairs,
+// then diagonalised.  Scratch: both phase tables and one batch of matrices.
+constexpr long PAIR_BATCH = 65536;
+
+struct PairScratch {
+    void* phi_k = nullptr;   // [N_k][N_e] c128, 1/ndeg_e included
+    void* phi_q = nullptr;   // [Q][N_e] c128
+    void* H = nullptr;       // [batch][n_b][n_b] c128
+    long batch = 0;
+};
+
 struct Layout {
     Prec prec;
     int nbp, Q, nchunks, S, kpad;
@@ -70,31 +83,58 @@ struct Layout {
     double* eps_pair = nullptr;
     void* U_pair = nullptr;
     double* f_pair = nullptr;
+    PairScratch ps;
 };
 
 // bytes per q point of the per-pair k+q states (off-grid runs)
 size_t pair_bytes_per_q(const epw_system* s, const epw_points* p) {
     if (p->kq) return 0;
-    return (size_t)p->nk * (16 * (size_t)s->nb + 16 * (size_t)s->nb * s->nb);
+    return (size_t)p->nk * (16 * (size_t)s->nb + 16 * (size_t)s->nb * s->nb) + 16 * (size_t)s->nRe;
 }
 
 void take_pair_states(const epw_system* s, const epw_points* p, int Q, Arena& A, double*& eps_pair, void*& U_pair,
-                      double*& f_pair) {
+                      double*& f_pair, PairScratch& ps) {
     if (p->kq) return;
     const size_t n = (size_t)p->nk * Q;
     eps_pair = (double*)A.take(8 * n * s->nb);
     U_pair = A.take(16 * n * s->nb * s->nb);
     f_pair = (double*)A.take(8 * n * s->nb);
+    ps.phi_k = A.take(16 * (size_t)p->nk * s->nRe);
+    ps.phi_q = A.take(16 * (size_t)Q * s->nRe);
+    ps.batch = std::min<long>(PAIR_BATCH, (long)n);
+    ps.H = A.take(16 * (size_t)ps.batch * s->nb * s->nb);
 }
 
-// eps, U and f at k+q for every (k, q) of a chunk (off-grid runs)
+// eps, U and f at k+q for every (k, q) of a chunk (off-grid runs); pair
+// index k*qc + q.  The k phase table is built with the first chunk.
 void pair_states(const epw_system* s, const epw_points* p, const epw_params* par, int q0, int qc, double* eps_pair,
-                 void* U_pair, double* f_pair, hipStream_t st) {
+                 void* U_pair, double* f_pair, const PairScratch& ps, hipStream_t st) {
     if (p->kq) return;
     StageTimer t(EPW_STAGE_EIGH, st);
-    launch_interp_eigh(false, false, s->nb, s->nRe, s->Re, s->ndeg_e, (const double*)s->HR, p->nk * qc, p->kfrac,
-                       eps_pair, U_pair, st, p->qfrac + 3 * (size_t)q0, qc);
-    launch_fermi_table((size_t)p->nk * qc * s->nb, eps_pair, par->mu, par->T, f_pair, st);
+    const int nb = s->nb, ne = s->nRe, nbb = nb * nb;
+    if (q0 == 0) launch_phase_table(Prec::F64, p->nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, ps.phi_k, st);
+    launch_phase_table(Prec::F64, qc, p->qfrac + 3 * (size_t)q0, ne, s->Re, nullptr, ne, ps.phi_q, st);
+    const long npair = (long)p->nk * qc;
+    for (long b0 = 0; b0 < npair; b0 += ps.batch) {
+        const int nbt = (int)std::min(ps.batch, npair - b0);
+        GemmDesc d;   // H(k+q)[pair][ij] = sum_R Phi_k[k][R] Phi_q[q][R] H(R)[ij]
+        d.M = nbt;
+        d.N = nbb;
+        d.K = ne;
+        d.A = ps.phi_k;
+        d.lda = ne;
+        d.A2 = ps.phi_q;
+        d.n2 = qc;
+        d.row0 = b0;
+        d.B = s->HR;
+        d.ncb = nbb;
+        d.sBk = nbb;
+        d.C = ps.H;
+        d.sCm = nbb;
+        launch_cgemm(Prec::F64, d, st);
+        launch_eigh_given(nb, nbt, ps.H, eps_pair + (size_t)b0 * nb, (char*)U_pair + 16 * (size_t)b0 * nbb, st);
+    }
+    launch_fermi_table((size_t)p->nk * qc * nb, eps_pair, par->mu, par->T, f_pair, st);
 }
 
 int tiles_n_for(int qc, int nm, int nbp) {
@@ -138,7 +178,7 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, bool 
     L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
     L.Bnu = A.take(bcol_bytes * L.Q * nm * L.nbp * L.nbp);
     if (!store) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
-    take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair);
+    take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair, L.ps);
 }
 
 // a5 as a strided GEMM: out[e][q][c] = sum_p phi_q[q][p] gR[e][p][c]
@@ -206,7 +246,7 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
             ev = L.evec_c;
         }
         launch_phonon_factors(qc, nm, om, par->omega_cut, par->T, L.sc, L.nbose, st);
-        pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, st);
+        pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, L.ps, st);
         launch_phase_table(rprec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
         {
             StageTimer t(EPW_STAGE_GEMM_RP, st);
@@ -295,6 +335,7 @@ struct BwdLayout {
     double* eps_pair = nullptr;
     void* U_pair = nullptr;
     double* f_pair = nullptr;
+    PairScratch ps;
     // float32 runs: g(R_e,R_p) and dL/dg(R_e,R_p) in complex64, and a float64
     // phase table for the dL/dH(R_e) contraction
     void* gR_t = nullptr;
@@ -346,7 +387,7 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     L.Ukq_c = A.take(16 * (size_t)nk * L.Q * nb * nb);
     L.om_c = (double*)A.take(8 * (size_t)nk * L.Q * nm);
     L.inv = (int32_t*)A.take(4 * (size_t)nk * L.Q);
-    take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair);
+    take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair, L.ps);
     L.kparts = splitk_parts(ne, (int)((size_t)L.Q * nm * nbp2), nk);
     if (L.kparts > 1) L.kpart = A.take(cb * (size_t)L.kparts * ne * L.Q * nm * nbp2);
     if (L.prec == Prec::F32) {
@@ -403,7 +444,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
         }
         launch_phonon_factors(qc, nm, om, par->omega_cut, par->T, L.sc, L.nbose, st);
         launch_phase_table(prec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
-        pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, st);
+        pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, L.ps, st);
         const long ncols = (long)qc * nm * L.nbp * L.nbp;
         StageTimer tb(EPW_STAGE_BACKWARD, st);
         launch_cgemm(prec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, gsrc, L.gq), st);

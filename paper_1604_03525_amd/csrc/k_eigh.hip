@@ -38,7 +38,8 @@ __device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
 // REAL_IN: X(R) is real (dynamical matrix); else complex interleaved.
 // SQRT_OUT: write omega = sign(l) sqrt|l| instead of the eigenvalue l.
 // Pair mode (pts2 != nullptr): point p is pts[p / npts2] + pts2[p % npts2].
-template <bool REAL_IN, bool SQRT_OUT>
+// GIVEN: the matrices are given ([np][n][n] complex at XR), no Fourier sum.
+template <bool REAL_IN, bool SQRT_OUT, bool GIVEN = false>
 __global__ __launch_bounds__(64) void interp_eigh_kernel(
     int n, int nR, const int32_t* __restrict__ R, const int32_t* __restrict__ ndeg,
     const double* __restrict__ XR, int np, const double* __restrict__ pts,
@@ -56,93 +57,98 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     const int lane = threadIdx.x;
     const int p = blockIdx.x;
     if (p >= np) return;
-    // point p, or the sum pts[p / npts2] + pts2[p % npts2] in pair mode
-    const size_t ia = pts2 ? (size_t)(p / npts2) : (size_t)p;
-    double k0 = pts[3 * ia + 0];
-    double k1 = pts[3 * ia + 1];
-    double k2 = pts[3 * ia + 2];
-    if (pts2) {
-        const size_t ib = (size_t)(p % npts2);
-        k0 += pts2[3 * ib + 0];
-        k1 += pts2[3 * ib + 1];
-        k2 += pts2[3 * ib + 2];
-    }
-    const int E = n * n;
-    const int P = (E >= 64) ? 1 : 64 / E;          // R partitions per entry
-    const int EPL = (E + 63) / 64;                   // entries per lane when P == 1
-
-    double2 acc[4];
-    for (int j = 0; j < 4; ++j) acc[j] = make_double2(0.0, 0.0);
-
-    for (int r0 = 0; r0 < nR; r0 += RBLK) {
-        const int cnt = min(RBLK, nR - r0);
-        __syncthreads();
-        for (int r = lane; r < cnt; r += 64) {
-            const int idx = r0 + r;
-            double x = k0 * (double)R[3 * idx] + k1 * (double)R[3 * idx + 1] +
-                       k2 * (double)R[3 * idx + 2];
-            x -= rint(x);
-            double s, c;
-            sincospi(2.0 * x, &s, &c);
-            const double w = 1.0 / (double)ndeg[idx];
-            ph[r] = make_double2(c * w, s * w);
+    if constexpr (GIVEN) {
+        const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * n * n;
+        for (int e = lane; e < n * n; e += 64) V[e / n][e % n] = X[e];
+    } else {
+        // point p, or the sum pts[p / npts2] + pts2[p % npts2] in pair mode
+        const size_t ia = pts2 ? (size_t)(p / npts2) : (size_t)p;
+        double k0 = pts[3 * ia + 0];
+        double k1 = pts[3 * ia + 1];
+        double k2 = pts[3 * ia + 2];
+        if (pts2) {
+            const size_t ib = (size_t)(p % npts2);
+            k0 += pts2[3 * ib + 0];
+            k1 += pts2[3 * ib + 1];
+            k2 += pts2[3 * ib + 2];
         }
-        __syncthreads();
-        if (P > 1) {
-            const int e = lane % E, part = lane / E;
-            if (part < P) {
-                for (int r = part; r < cnt; r += P) {
-                    const double2 f = ph[r];
-                    if (REAL_IN) {
-                        const double x = XR[(size_t)(r0 + r) * E + e];
-                        acc[0].x += f.x * x;
-                        acc[0].y += f.y * x;
-                    } else {
-                        const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
-                        const double2 t = cmul(f, x);
-                        acc[0].x += t.x;
-                        acc[0].y += t.y;
+        const int E = n * n;
+        const int P = (E >= 64) ? 1 : 64 / E;          // R partitions per entry
+        const int EPL = (E + 63) / 64;                   // entries per lane when P == 1
+
+        double2 acc[4];
+        for (int j = 0; j < 4; ++j) acc[j] = make_double2(0.0, 0.0);
+
+        for (int r0 = 0; r0 < nR; r0 += RBLK) {
+            const int cnt = min(RBLK, nR - r0);
+            __syncthreads();
+            for (int r = lane; r < cnt; r += 64) {
+                const int idx = r0 + r;
+                double x = k0 * (double)R[3 * idx] + k1 * (double)R[3 * idx + 1] +
+                           k2 * (double)R[3 * idx + 2];
+                x -= rint(x);
+                double s, c;
+                sincospi(2.0 * x, &s, &c);
+                const double w = 1.0 / (double)ndeg[idx];
+                ph[r] = make_double2(c * w, s * w);
+            }
+            __syncthreads();
+            if (P > 1) {
+                const int e = lane % E, part = lane / E;
+                if (part < P) {
+                    for (int r = part; r < cnt; r += P) {
+                        const double2 f = ph[r];
+                        if (REAL_IN) {
+                            const double x = XR[(size_t)(r0 + r) * E + e];
+                            acc[0].x += f.x * x;
+                            acc[0].y += f.y * x;
+                        } else {
+                            const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
+                            const double2 t = cmul(f, x);
+                            acc[0].x += t.x;
+                            acc[0].y += t.y;
+                        }
                     }
                 }
+            } else {
+                for (int j = 0; j < EPL; ++j) {
+                    const int e = lane + 64 * j;
+                    if (e >= E) break;
+                    for (int r = 0; r < cnt; ++r) {
+                        const double2 f = ph[r];
+                        if (REAL_IN) {
+                            const double x = XR[(size_t)(r0 + r) * E + e];
+                            acc[j].x += f.x * x;
+                            acc[j].y += f.y * x;
+                        } else {
+                            const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
+                            const double2 t = cmul(f, x);
+                            acc[j].x += t.x;
+                            acc[j].y += t.y;
+                        }
+                    }
+                }
+            }
+        }
+        // raw interpolated matrix -> V (scratch)
+        if (P > 1) {
+            red[lane] = acc[0];
+            __syncthreads();
+            if (lane < E) {
+                double2 s = make_double2(0.0, 0.0);
+                for (int part = 0; part < P; ++part) {
+                    s.x += red[lane + E * part].x;
+                    s.y += red[lane + E * part].y;
+                }
+                V[lane / n][lane % n] = s;
             }
         } else {
             for (int j = 0; j < EPL; ++j) {
                 const int e = lane + 64 * j;
-                if (e >= E) break;
-                for (int r = 0; r < cnt; ++r) {
-                    const double2 f = ph[r];
-                    if (REAL_IN) {
-                        const double x = XR[(size_t)(r0 + r) * E + e];
-                        acc[j].x += f.x * x;
-                        acc[j].y += f.y * x;
-                    } else {
-                        const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
-                        const double2 t = cmul(f, x);
-                        acc[j].x += t.x;
-                        acc[j].y += t.y;
-                    }
-                }
+                if (e < E) V[e / n][e % n] = acc[j];
             }
         }
-    }
-    // raw interpolated matrix -> V (scratch)
-    if (P > 1) {
-        red[lane] = acc[0];
-        __syncthreads();
-        if (lane < E) {
-            double2 s = make_double2(0.0, 0.0);
-            for (int part = 0; part < P; ++part) {
-                s.x += red[lane + E * part].x;
-                s.y += red[lane + E * part].y;
-            }
-            V[lane / n][lane % n] = s;
-        }
-    } else {
-        for (int j = 0; j < EPL; ++j) {
-            const int e = lane + 64 * j;
-            if (e < E) V[e / n][e % n] = acc[j];
-        }
-    }
+    }   // Fourier sum
     __syncthreads();
     // Hermitise into A; V <- identity; padding row/column of zeros
     const int n2 = n + (n & 1);
@@ -269,6 +275,14 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
 }
 
 }  // namespace
+
+void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream) {
+    if (np <= 0) return;
+    interp_eigh_kernel<false, false, true><<<dim3(np), dim3(64), 0, stream>>>(
+        n, 0, nullptr, nullptr, reinterpret_cast<const double*>(X), np, nullptr, nullptr, 1, evals,
+        reinterpret_cast<double2*>(evecs));
+    launch_check("interp_eigh_kernel (given)");
+}
 
 void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_t* R,
                         const int32_t* ndeg, const double* XR, int np, const double* pts,

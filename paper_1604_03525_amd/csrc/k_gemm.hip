@@ -43,6 +43,15 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
                 v.y = -v.y;
                 return v;
             }
+            if (d.A2) {
+                const long r = d.row0 + row;
+                const CT x = A[(size_t)(r / d.n2) * d.lda + k];
+                const CT y = reinterpret_cast<const CT*>(d.A2)[(size_t)(r % d.n2) * d.lda + k];
+                CT v;
+                v.x = x.x * y.x - x.y * y.y;
+                v.y = x.x * y.y + x.y * y.x;
+                return v;
+            }
             return A[(size_t)row * d.lda + k];
         }
         return cz<T>();

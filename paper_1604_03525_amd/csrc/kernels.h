@@ -17,6 +17,10 @@ void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_
                         double* evals, void* evecs, hipStream_t stream,
                         const double* pts2 = nullptr, int n2 = 1);
 
+// Eigendecomposition (float64, Hermitised first) of np given n x n complex
+// matrices X [np][n][n]; evals ascending [np][n], evecs [np][n][n] c128.
+void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream);
+
 // ---- k_vertex.hip ----
 enum class Prec { F64 = 0, F32 = 1, BF16X2 = 2 };
 
@@ -101,6 +105,11 @@ struct GemmDesc {
     void* C = nullptr;
     long sCe = 0, sCm = 0;
     int accumulate = 0;
+    // pair operand (A2 != nullptr, not with conj_trans_a): A(m, k) = A[(r / n2) * lda + k] * A2[(r % n2) * lda + k]
+    // with r = row0 + m -- the phases of the sum k + q of a point pair
+    const void* A2 = nullptr;
+    int n2 = 1;
+    long row0 = 0;
     int kchunk = 0;    // split K: blockIdx.z covers [z*kchunk, (z+1)*kchunk) (0: all of K)
     long sCz = 0;      // C offset between the split-K partial outputs
 };
