@@ -1,5 +1,6 @@
 """FP64 CPU oracle for Wannier-Fourier interpolation of the electron-phonon
-vertex and the imaginary electron self-energy (EPW method, Ponce et al.,
+vertex, the imaginary electron self-energy and the phonon linewidth (EPW
+method, Ponce et al.,
 arXiv:1604.03525).
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product path may import, call or
@@ -18,6 +19,8 @@ interp      Fourier interpolation R -> k of H, D and g; eigensolves;
             Sec. 4; the interpolation itself is only cited by the paper).
 selfenergy  Fermi/Bose occupations, Gaussian delta, Im Sigma_nk of
             Sec. 3 Eq. (8), degenerate averaging (Sec. 10.4).
+phonon      Phonon linewidth Pi''_q,nu (Sec. 3 Eq. (9)) and mode-resolved
+            coupling strength lambda_q,nu (Sec. 3 Eq. (11)).
 torch_ref   The same forward in plain torch CPU float64, differentiated by
             autograd: the reference gradient for the hand-written adjoint.
 
