@@ -208,6 +208,27 @@ int epw_interp_g(const epw_system* sys, const epw_points* pts, const epw_params*
 int epw_imsigma(const epw_system* sys, const epw_points* pts, const epw_params* par,
                 double* imsig, void* ws, size_t ws_bytes, void* stream);
 
+/* Phonon linewidth, Sec. 3 Eq. (9), on shell (omega = omega_q,nu), and the
+ * mode-resolved electron-phonon coupling strength, Sec. 3 Eq. (11):
+ *   Pi''_q,nu = (2 pi / N_k) sum_k sum_mn |g_mn,nu(k,q)|^2
+ *                  [f_nk - f_m,k+q] delta(eps_nk - eps_m,k+q - omega_q,nu)
+ *   lambda_q,nu = 1/(N(eps_F) omega_q,nu N_k) sum_k sum_mn |g_mn,nu(k,q)|^2
+ *                  delta(eps_nk - mu) delta(eps_m,k+q - mu)
+ *   N(eps_F) = (1/N_k) sum_nk delta(eps_nk - mu)   (per spin, on the k set)
+ * with eps_F = mu, the Gaussian delta and the Fermi-Dirac f of epw_imsigma.
+ * The sign is that of the printed delta argument (the magnitude is the
+ * linewidth).  Modes with omega < omega_cut give 0; lambda is 0 where
+ * N(eps_F) = 0.  Both are averaged over modes of one q whose frequencies
+ * differ by less than deg_tol.  The k sum is over the whole k set of the
+ * call (par->nq_norm and par->accumulate are not used); q is chunked as in
+ * epw_imsigma; grid (kq) and off-grid k+q as in epw_imsigma.
+ *  pi_im  device [nq][nm] double out (overwritten)
+ *  lam    device [nq][nm] double out (overwritten), or NULL to skip
+ * Errors: EPW_EINVAL, EPW_ESHAPE (also for an empty k set), EPW_EDTYPE,
+ * EPW_ENOMEM, EPW_EHIP. */
+int epw_phonon_selfenergy(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                          double* pi_im, double* lam, void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint of L = sum_nk w_nk Im Sigma_nk (the forward of epw_imsigma) with
  * respect to g(R_e,R_p), H(R_e) and omega_q,nu.  Complex gradients are
  * dL/dRe + i dL/dIm; H(k) is the Hermitised sum, so every entry of H(R) is
@@ -228,12 +249,13 @@ int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw
                          void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for the call `which` (EPW_WS_INTERP_G, EPW_WS_IMSIGMA,
- * EPW_WS_IMSIGMA_BACKWARD) with these sizes and parameters; device pointers
+ * EPW_WS_IMSIGMA_BACKWARD, EPW_WS_PHONON) with these sizes and parameters; device pointers
  * inside sys/pts are not dereferenced and may be NULL.  Returns 0 and sets
  * the error message on invalid arguments. */
 #define EPW_WS_INTERP_G          1
 #define EPW_WS_IMSIGMA           2
 #define EPW_WS_IMSIGMA_BACKWARD  3
+#define EPW_WS_PHONON            4
 size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
                           const epw_params* par);
 

@@ -59,16 +59,21 @@ def dos_at_fermi(eps, mu, sigma):
 
 
 def phonon_selfenergy(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, kpoints, qpoints, T, mu, sigma,
-                      omega_cut=1e-3, deg_tol=1e-6, kq_points=None, phonon_states=None):
+                      omega_cut=1e-3, deg_tol=1e-6, kq_points=None, phonon_states=None, loop="k"):
     """(Pi'' [Nq][nm], lambda [Nq][nm]) for the given k and q points.
 
     Every step is a direct evaluation, as in selfenergy.imsigma: bands at k
     and at k+q, phonons at q, the Wannier-basis vertex per k, the rotation of
     Eq. (2), the two sums over m, n and k, the normalisations, then the
     average over degenerate modes.  kq_points and phonon_states as in
-    selfenergy.imsigma."""
+    selfenergy.imsigma.  loop="q" takes the q points one at a time with all
+    k at once (the vertex summed over R_p first): the same sums in another
+    order, for few q and many k (kq_points is not used there)."""
     kpoints = np.asarray(kpoints, dtype=np.float64)
     qpoints = np.asarray(qpoints, dtype=np.float64)
+    if loop == "q":
+        return _phonon_selfenergy_by_q(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, kpoints, qpoints, T, mu, sigma,
+                                       omega_cut, deg_tol, phonon_states)
     nk = len(kpoints)
     eps_k, U_k = interp.bands(HR, Re, ndeg_e, kpoints)
     if phonon_states is None:
@@ -85,6 +90,46 @@ def phonon_selfenergy(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, kpoints, qpoints, T, m
         p, l = phonon_sums_one_k(gb, eps_k[ik], eps_kq, omega, mu, T, sigma, omega_cut)
         P += p
         L += l
+    pi_im = (2.0 * np.pi / nk) * P
+    dos = dos_at_fermi(eps_k, mu, sigma)
+    keep = omega >= omega_cut
+    lam = np.zeros(omega.shape)
+    if dos > 0.0:
+        lam[keep] = L[keep] / (nk * dos * omega[keep])
+    return (degenerate_average(omega, pi_im, deg_tol), degenerate_average(omega, lam, deg_tol))
+
+
+def _phonon_selfenergy_by_q(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, kpoints, qpoints, T, mu, sigma,
+                            omega_cut, deg_tol, phonon_states):
+    nk = len(kpoints)
+    eps_k, U_k = interp.bands(HR, Re, ndeg_e, kpoints)
+    if phonon_states is None:
+        omega, evec = interp.phonons(DR, Rp, ndeg_p, qpoints)
+    else:
+        omega, evec = phonon_states
+    ne, npp = gR.shape[0], gR.shape[1]
+    ph_k = interp.phases(kpoints, Re, ndeg_e)                                 # [Nk][Ne]
+    P = np.zeros(omega.shape)
+    L = np.zeros(omega.shape)
+    for iq, q in enumerate(qpoints):
+        ph_q = interp.phases(q[None, :], Rp, ndeg_p)[0]                       # [Np]
+        g_eq = np.tensordot(ph_q, gR, axes=(0, 1))                            # [Ne][nm][nb][nb]
+        gw = (ph_k @ g_eq.reshape(ne, -1)).reshape((nk,) + gR.shape[2:])      # [Nk][nm][nb][nb]
+        eps_kq, U_kq = interp.bands(HR, Re, ndeg_e, kpoints + q[None, :])
+        # Eq. (2) for every k at this q: [U_k+q^dag (sum_a g_a e_a,nu) U_k] / sqrt(2 omega)
+        w = omega[iq]
+        keep = w >= omega_cut
+        scale = np.where(keep, 1.0 / np.sqrt(2.0 * np.where(keep, w, 1.0)), 0.0)
+        gmode = np.einsum("kaij,av->kvij", gw, evec[iq])
+        gb = np.einsum("kim,kvij,kjn->kvmn", np.conj(U_kq), gmode, U_k, optimize=True) * scale[None, :, None, None]
+        amp = np.abs(gb) ** 2                                                 # [Nk][nu][m][n]
+        fn = fermi(eps_k, mu, T)[:, None, None, :]
+        fm = fermi(eps_kq, mu, T)[:, None, :, None]
+        x = eps_k[:, None, None, :] - eps_kq[:, None, :, None] - w[None, :, None, None]
+        P[iq] = np.sum(amp * (fn - fm) * gaussian(x, sigma), axis=(0, 2, 3)) * keep
+        dn = gaussian(eps_k - mu, sigma)[:, None, None, :]
+        dm = gaussian(eps_kq - mu, sigma)[:, None, :, None]
+        L[iq] = np.sum(amp * dn * dm, axis=(0, 2, 3)) * keep
     pi_im = (2.0 * np.pi / nk) * P
     dos = dos_at_fermi(eps_k, mu, sigma)
     keep = omega >= omega_cut

@@ -61,9 +61,13 @@ struct PairScratch {
     long batch = 0;
 };
 
+// what a forward pass produces
+enum class Out { IMSIGMA, STORE, PHONON };
+
 struct Layout {
     Prec prec;
-    int nbp, Q, nchunks, S, kpad;
+    Out out;
+    int nbp, Q, nchunks, S, kpad, tiles_m;
     // fixed tables
     double* eps = nullptr;
     void* U = nullptr;
@@ -79,6 +83,8 @@ struct Layout {
     void* gq = nullptr;
     void* Bnu = nullptr;
     double* part = nullptr;
+    double* part_ph = nullptr;   // [2][tiles_m][Q nm] (phonon mode)
+    double* dos_raw = nullptr;   // [1] (phonon mode)
     // per pair states at k+q when no k+q map is given
     double* eps_pair = nullptr;
     void* U_pair = nullptr;
@@ -144,7 +150,9 @@ int tiles_n_for(int qc, int nm, int nbp) {
 }
 
 // Carve the workspace (or count its size when A.dry).
-void plan(const epw_system* s, const epw_points* p, const epw_params* par, bool store, Arena& A, Layout& L) {
+void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out out, Arena& A, Layout& L) {
+    const bool store = out == Out::STORE;
+    L.out = out;
     L.prec = (Prec)par->dtype;
     L.nbp = pow2_at_least(s->nb);
     const size_t cb = cbytes(L.prec);
@@ -177,7 +185,12 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, bool 
     L.phi_q = A.take(cb * (size_t)L.Q * np_);
     L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
     L.Bnu = A.take(bcol_bytes * L.Q * nm * L.nbp * L.nbp);
-    if (!store) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
+    L.tiles_m = (nk + fused_tile_rows(L.nbp) - 1) / fused_tile_rows(L.nbp);
+    if (out == Out::IMSIGMA) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
+    if (out == Out::PHONON) {
+        L.part_ph = (double*)A.take(8 * 2 * (size_t)L.tiles_m * L.Q * nm);
+        L.dos_raw = (double*)A.take(8);
+    }
     take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair, L.ps);
 }
 
@@ -199,10 +212,12 @@ GemmDesc rp_desc(int qc, int ne, int np_, int ncol, const void* phi_q, const voi
     return d;
 }
 
-// Shared forward pipeline: store mode writes g_mn,nu(k,q) to gkq,
-// otherwise Im Sigma goes to imsig.
+// Shared forward pipeline: store mode writes g_mn,nu(k,q) to gkq, phonon
+// mode writes Pi''_q,nu and lambda_q,nu to pi_im / lam, otherwise Im Sigma
+// goes to imsig.
 void run_forward(const epw_system* s, const epw_points* p, const epw_params* par, Layout& L,
-                 double* imsig, void* gkq, hipStream_t st) {
+                 double* imsig, void* gkq, hipStream_t st, double* pi_im = nullptr, double* lam = nullptr) {
+    const bool phon = L.out == Out::PHONON;
     const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
     const Prec prec = L.prec;
     const bool given = p->omega && p->evec;
@@ -213,6 +228,7 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
                            L.eps, L.U, st);
     }
     launch_fermi_table((size_t)nk * nb, L.eps, par->mu, par->T, L.ftab, st);
+    if (phon) launch_dos_raw((size_t)nk * nb, L.eps, par->mu, par->sigma, L.dos_raw, st);
     const bool bf = prec == Prec::BF16X2;
     const Prec rprec = bf ? Prec::F32 : prec;      // precision of the R_p -> q step
     // Phases of the R_e -> k contraction: generated inside the fused kernel
@@ -288,19 +304,29 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.nbose = L.nbose;
         a.sc = L.sc;
         a.sigma = par->sigma;
+        a.mu = par->mu;
         a.part = L.part;
         a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp), SLICE_CUS);
         a.gkq = gkq;
+        a.part_ph = phon ? L.part_ph : nullptr;
         {
             StageTimer t(EPW_STAGE_FUSED, st);
             launch_fused_k(prec, a, SLICE_CUS, st);
         }
-        if (!gkq)
+        if (phon) {
+            double* pi_c = pi_im + (size_t)q0 * nm;
+            double* lam_c = lam ? lam + (size_t)q0 * nm : nullptr;
+            launch_phonon_finalize(qc, nm, L.tiles_m, L.part_ph, om, par->omega_cut, L.dos_raw, nk, par->sigma,
+                                   pi_c, lam_c, st);
+            // average over degenerate modes of each q
+            launch_degenerate_average(qc, nm, om, par->deg_tol, pi_c, st);
+            if (lam_c) launch_degenerate_average(qc, nm, om, par->deg_tol, lam_c, st);
+        } else if (!gkq) {
             launch_reduce_partials(nk, nb, a.S, L.part, scale, (c > 0 || par->accumulate) ? 1 : 0, imsig, st);
+        }
     }
-    if (!gkq) {
-        if (L.nchunks == 0 && !par->accumulate && nk > 0)
-            EPW_HIP(hipMemsetAsync(imsig, 0, 8 * (size_t)nk * nb, st));
+    if (!gkq && !phon) {
+        if (L.nchunks == 0 && !par->accumulate && nk > 0) launch_fill((size_t)nk * nb, 0.0, imsig, st);
         launch_degenerate_average(nk, nb, L.eps, par->deg_tol, imsig, st);
     }
 }
@@ -600,7 +626,8 @@ extern "C" int epw_interp_phonons(int nm, int nR, const int32_t* R, const int32_
 extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
                                      const epw_params* par) {
     clear_error();
-    if (which != EPW_WS_INTERP_G && which != EPW_WS_IMSIGMA && which != EPW_WS_IMSIGMA_BACKWARD) {
+    if (which != EPW_WS_INTERP_G && which != EPW_WS_IMSIGMA && which != EPW_WS_IMSIGMA_BACKWARD &&
+        which != EPW_WS_PHONON) {
         fail(EPW_EINVAL, "epw_workspace_size: unknown call id %d", which);
         return 0;
     }
@@ -630,7 +657,8 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
         plan_bwd(&s, &p, par, A, L);
     } else {
         Layout L;
-        plan(&s, &p, par, which == EPW_WS_INTERP_G, A, L);
+        plan(&s, &p, par, which == EPW_WS_INTERP_G ? Out::STORE : which == EPW_WS_PHONON ? Out::PHONON : Out::IMSIGMA,
+             A, L);
     }
     return A.used + 256;
 }
@@ -645,14 +673,14 @@ extern "C" int epw_interp_g(const epw_system* sys, const epw_points* pts, const 
     Arena dry;
     dry.dry = true;
     Layout L;
-    plan(sys, pts, par, true, dry, L);
+    plan(sys, pts, par, Out::STORE, dry, L);
     if (!ws || ws_bytes < dry.used + 256)
         return fail(EPW_ENOMEM, "epw_interp_g: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
     return guarded("epw_interp_g", [&]() {
         Arena A;
         A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
         A.cap = ws_bytes;
-        plan(sys, pts, par, true, A, L);
+        plan(sys, pts, par, Out::STORE, A, L);
         run_forward(sys, pts, par, L, nullptr, gkq, (hipStream_t)stream);
         return EPW_OK;
     });
@@ -668,15 +696,39 @@ extern "C" int epw_imsigma(const epw_system* sys, const epw_points* pts, const e
     Arena dry;
     dry.dry = true;
     Layout L;
-    plan(sys, pts, par, false, dry, L);
+    plan(sys, pts, par, Out::IMSIGMA, dry, L);
     if (!ws || ws_bytes < dry.used + 256)
         return fail(EPW_ENOMEM, "epw_imsigma: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
     return guarded("epw_imsigma", [&]() {
         Arena A;
         A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
         A.cap = ws_bytes;
-        plan(sys, pts, par, false, A, L);
+        plan(sys, pts, par, Out::IMSIGMA, A, L);
         run_forward(sys, pts, par, L, imsig, nullptr, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_phonon_selfenergy(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                                     double* pi_im, double* lam, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    int rc = check_common(sys, pts, par, "epw_phonon_selfenergy");
+    if (rc != EPW_OK) return rc;
+    if (pts->nq == 0) return EPW_OK;
+    if (!pi_im) return fail(EPW_EINVAL, "epw_phonon_selfenergy: NULL output");
+    if (pts->nk == 0) return fail(EPW_ESHAPE, "epw_phonon_selfenergy: the k set is empty");
+    Arena dry;
+    dry.dry = true;
+    Layout L;
+    plan(sys, pts, par, Out::PHONON, dry, L);
+    if (!ws || ws_bytes < dry.used + 256)
+        return fail(EPW_ENOMEM, "epw_phonon_selfenergy: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
+    return guarded("epw_phonon_selfenergy", [&]() {
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        plan(sys, pts, par, Out::PHONON, A, L);
+        run_forward(sys, pts, par, L, nullptr, nullptr, (hipStream_t)stream, pi_im, lam);
         return EPW_OK;
     });
 }

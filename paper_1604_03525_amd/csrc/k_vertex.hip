@@ -18,6 +18,8 @@
 #include "epw_internal.h"
 #include "kernels.h"
 
+#include <type_traits>
+
 namespace epw {
 namespace {
 
@@ -340,9 +342,14 @@ __device__ inline float2 cmulx(float2 a, float2 b) {
 // block's k rows: three complex products per element instead of a table
 // streamed from memory once per column tile.  The 1/ndeg weights are then
 // carried by the B operand.
-template <int MODE, int NBP, bool STORE, bool GEN>
+// KIND 0: Im Sigma (Eq. (8)) partial sums per (k, n); 1: store g_mn,nu(k,q);
+// 2: the sums of the phonon linewidth (Eq. (9)) and of the coupling strength
+// (Eq. (11)) per (q, nu), reduced over the tile's k rows in fixed order.
+template <int MODE, int NBP, int KIND, bool GEN>
 __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
 {
+    constexpr bool STORE = KIND == 1;
+    constexpr bool PH = KIND == 2;
     typedef typename ModeTypes<MODE>::T T;
     typedef typename ModeTypes<MODE>::CT CT;
     typedef typename ModeTypes<MODE>::TE TE;
@@ -569,7 +576,14 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
             if constexpr (JI < NBP) __syncthreads();
         }
         // phase 2: g_mn = sum_i conj(U_k+q[i][m]) V[i][n] for the thread's
-        // items (b, m), all n; weights and |g|^2 accumulated per n
+        // items (b, m), all n; weights and |g|^2 accumulated per n (Im Sigma)
+        // or per run (phonon sums)
+        double pp[NRUN], pl[NRUN];
+#pragma unroll
+        for (int rr = 0; rr < NRUN; ++rr) {
+            pp[rr] = 0.0;
+            pl[rr] = 0.0;
+        }
         if (active_row) {
 #pragma unroll
             for (int rr = 0; rr < NRUN; ++rr) {
@@ -600,7 +614,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 const double w = a.omega[(size_t)ql * nm + nu];
                 const double nB = a.nbose[(size_t)ql * nm + nu];
                 CE uq[RUN][NBP];
-                double em[RUN], fm[RUN];
+                double em[RUN], fm[RUN], dm[RUN];
                 bool mv[RUN];
 #pragma unroll
                 for (int t = 0; t < RUN; ++t) {
@@ -608,6 +622,10 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     mv[t] = m < nb;
                     em[t] = mv[t] ? eq[m] : 0.0;
                     fm[t] = mv[t] ? fq[m] : 0.0;
+                    if constexpr (PH) {
+                        const double ym = (em[t] - a.mu) * inv_sig;
+                        dm[t] = mv[t] ? exp(-ym * ym) : 0.0;
+                    }
 #pragma unroll
                     for (int i = 0; i < NBP; ++i) {
                         const double2 u = (mv[t] && i < nb) ? Uq[i * nb + m] : make_double2(0.0, 0.0);
@@ -620,18 +638,38 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     if (n >= nb) break;
                     double epsn;
                     if constexpr (HOIST) epsn = eps_h[n]; else epsn = a.eps[(size_t)k * nb + n];
-                    TE W[RUN];
+                    TE W[RUN], WL[RUN];
                     bool need = STORE;
+                    if constexpr (PH) {
+                        // Eq. (9): [f_nk - f_m,k+q] exp(-((eps_nk - eps_m,k+q - omega)/sigma)^2);
+                        // Eq. (11): exp(-((eps_nk - mu)/sigma)^2) exp(-((eps_m,k+q - mu)/sigma)^2)
+                        const double fn = a.ftab[(size_t)k * nb + n];
+                        const double yn = (epsn - a.mu) * inv_sig;
+                        const double dn = exp(-yn * yn);
 #pragma unroll
-                    for (int t = 0; t < RUN; ++t) {
-                        W[t] = TE(0);
-                        if (STORE || !mv[t]) continue;
-                        const double x = epsn - em[t];
-                        const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
-                        const double s1 = y1 * y1, s2 = y2 * y2;
-                        if (s1 < ylim) W[t] += (TE)(nB + fm[t]) * fexp((TE)(-s1));
-                        if (s2 < ylim) W[t] += (TE)(nB + 1.0 - fm[t]) * fexp((TE)(-s2));
-                        need = need || (s1 < ylim) || (s2 < ylim);
+                        for (int t = 0; t < RUN; ++t) {
+                            W[t] = TE(0);
+                            WL[t] = TE(0);
+                            if (!mv[t]) continue;
+                            const double y = (epsn - em[t] - w) * inv_sig;
+                            const double s1 = y * y;
+                            if (s1 < ylim) W[t] = (TE)(fn - fm[t]) * fexp((TE)(-s1));
+                            WL[t] = (TE)(dn * dm[t]);
+                            need = need || (s1 < ylim) || (WL[t] != TE(0));
+                        }
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < RUN; ++t) {
+                            W[t] = TE(0);
+                            WL[t] = TE(0);
+                            if (STORE || !mv[t]) continue;
+                            const double x = epsn - em[t];
+                            const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
+                            const double s1 = y1 * y1, s2 = y2 * y2;
+                            if (s1 < ylim) W[t] += (TE)(nB + fm[t]) * fexp((TE)(-s1));
+                            if (s2 < ylim) W[t] += (TE)(nB + 1.0 - fm[t]) * fexp((TE)(-s2));
+                            need = need || (s1 < ylim) || (s2 < ylim);
+                        }
                     }
                     if (!need) continue;
                     TE gr[RUN], gi[RUN];
@@ -659,6 +697,10 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                             reinterpret_cast<double2*>(a.gkq)
                                 [((((size_t)k * a.nq_total + q) * nm + nu) * nb + x0 + t) * nb + n] =
                                 make_double2((double)gr[t], (double)gi[t]);
+                        } else if (PH) {
+                            const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
+                            pp[rr] += (double)(g2 * W[t]);
+                            pl[rr] += (double)(g2 * WL[t]);
                         } else {
                             acc[n] += (double)((gr[t] * gr[t] + gi[t] * gi[t]) * W[t]);
                         }
@@ -668,9 +710,43 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 }
             }
         }
+        if constexpr (PH) {
+            // fixed-order sums over the tile's k rows, per band block (q, nu):
+            // slot (b, r, j) holds run j of row r; rows are summed after the
+            // slots of each row, for Eq. (9) and then Eq. (11)
+            constexpr int NBLK = BN / NB2;
+            constexpr int SPB = NBP / RUN;                  // runs per band block and row
+            static_assert(SBYTES >= sizeof(double) * NBLK * BM * SPB, "phonon reduction buffer");
+            double* red = reinterpret_cast<double*>(smem);
+            const int jslot = x0 / RUN;
+            const size_t ncb = (size_t)a.qc * nm;
+#pragma unroll
+            for (int kind = 0; kind < 2; ++kind) {
+                __syncthreads();                            // V, or the previous pass, no longer read
+#pragma unroll
+                for (int rr = 0; rr < NRUN; ++rr) {
+                    const int b = (sub * JI + rr * RUN) / NBP;
+                    red[((size_t)b * BM + r) * SPB + jslot] = kind == 0 ? pp[rr] : pl[rr];
+                }
+                __syncthreads();
+                for (int t = tid; t < NBLK * BM; t += 256) {
+                    double v = 0.0;
+                    for (int j = 0; j < SPB; ++j) v += red[(size_t)t * SPB + j];
+                    red[(size_t)t * SPB] = v;
+                }
+                __syncthreads();
+                for (int b = tid; b < NBLK; b += 256) {
+                    const long gblk = n0 / NB2 + b;         // q_local * nm + nu
+                    if (gblk >= (long)ncb) continue;
+                    double v = 0.0;
+                    for (int rw = 0; rw < BM; ++rw) v += red[((size_t)b * BM + rw) * SPB];
+                    a.part_ph[((size_t)kind * tiles_m + mt) * ncb + gblk] = v;
+                }
+            }
+        }
         __syncthreads();
     }
-    if (STORE) return;
+    if constexpr (KIND != 0) return;
     // fixed-order reduction over the TPR threads of each row
     double* red = reinterpret_cast<double*>(smem);   // [BM][TPR][NBP]
 #pragma unroll
@@ -795,6 +871,54 @@ __global__ void degenerate_average_kernel(int nk, int nb, const double* __restri
     }
 }
 
+// raw[0] = sum_i exp(-((eps_i - mu)/sigma)^2): one block, strided partial
+// sums then a fixed tree (bit-reproducible)
+__global__ __launch_bounds__(256) void dos_raw_kernel(size_t n, const double* __restrict__ eps, double mu,
+                                                     double inv_sig, double* __restrict__ raw)
+{
+    __shared__ double part[256];
+    double t = 0.0;
+    for (size_t i = threadIdx.x; i < n; i += 256) {
+        const double y = (eps[i] - mu) * inv_sig;
+        t += exp(-y * y);
+    }
+    part[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) raw[0] = part[0];
+}
+
+// Eq. (9) and Eq. (11) from the per-row-tile sums: fixed-order sum over row
+// tiles, then the normalisations (the Gaussian 1/(sigma sqrt pi) per delta,
+// 2 pi / N_k for Pi'', 1/(N(eps_F) omega N_k) for lambda with
+// N(eps_F) = raw / (N_k sigma sqrt pi))
+__global__ void phonon_finalize_kernel(int qc, int nm, int tiles_m, const double* __restrict__ part_ph,
+                                       const double* __restrict__ omega, double omega_cut,
+                                       const double* __restrict__ raw_dos, int nk, double sigma,
+                                       double* __restrict__ pi_im, double* __restrict__ lam)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int ncb = qc * nm;
+    if (idx >= ncb) return;
+    double P = 0.0, L = 0.0;
+    for (int t = 0; t < tiles_m; ++t) {
+        P += part_ph[(size_t)t * ncb + idx];
+        L += part_ph[((size_t)tiles_m + t) * ncb + idx];
+    }
+    const double w = omega[idx];
+    const bool keep = w >= omega_cut;
+    constexpr double kPi = 3.141592653589793;
+    const double gnorm = 1.0 / (sigma * sqrt(kPi));
+    pi_im[idx] = keep ? 2.0 * kPi * gnorm * P / (double)nk : 0.0;
+    if (lam) {
+        const double raw = raw_dos[0];
+        lam[idx] = (keep && raw > 0.0) ? gnorm * L / (raw * w) : 0.0;
+    }
+}
+
 inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <int MODE, int NBP>
@@ -813,17 +937,16 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     const bool gen = CAN_GEN && a.nmax > 0;
     const size_t dyn = gen ? (size_t)3 * BM * (2 * a.nmax + 1) * 8 + 4 * (size_t)a.ne : 0;
     const dim3 grid((unsigned)G), block(256);
-    if (a.gkq) {
+    auto go = [&](auto kind) {
+        constexpr int K = decltype(kind)::value;
         if (gen)
-            fused_k_kernel<MODE, NBP, true, CAN_GEN><<<grid, block, dyn, stream>>>(a, tiles_m, tiles_n);
+            fused_k_kernel<MODE, NBP, K, CAN_GEN><<<grid, block, dyn, stream>>>(a, tiles_m, tiles_n);
         else
-            fused_k_kernel<MODE, NBP, true, false><<<grid, block, 0, stream>>>(a, tiles_m, tiles_n);
-    } else {
-        if (gen)
-            fused_k_kernel<MODE, NBP, false, CAN_GEN><<<grid, block, dyn, stream>>>(a, tiles_m, tiles_n);
-        else
-            fused_k_kernel<MODE, NBP, false, false><<<grid, block, 0, stream>>>(a, tiles_m, tiles_n);
-    }
+            fused_k_kernel<MODE, NBP, K, false><<<grid, block, 0, stream>>>(a, tiles_m, tiles_n);
+    };
+    if (a.gkq) go(std::integral_constant<int, 1>());
+    else if (a.part_ph) go(std::integral_constant<int, 2>());
+    else go(std::integral_constant<int, 0>());
     launch_check("fused_k_kernel");
 }
 
@@ -905,6 +1028,21 @@ void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t strea
         launch_fused_nbp<1>(a, num_cu, stream);
     else
         launch_fused_nbp<2>(a, num_cu, stream);
+}
+
+void launch_dos_raw(size_t n, const double* eps, double mu, double sigma, double* raw, hipStream_t stream) {
+    dos_raw_kernel<<<1, 256, 0, stream>>>(n, eps, mu, 1.0 / sigma, raw);
+    launch_check("dos_raw_kernel");
+}
+
+void launch_phonon_finalize(int qc, int nm, int tiles_m, const double* part_ph, const double* omega,
+                            double omega_cut, const double* raw_dos, int nk, double sigma, double* pi_im,
+                            double* lam, hipStream_t stream) {
+    const int n = qc * nm;
+    if (n == 0) return;
+    phonon_finalize_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(qc, nm, tiles_m, part_ph, omega, omega_cut,
+                                                                  raw_dos, nk, sigma, pi_im, lam);
+    launch_check("phonon_finalize_kernel");
 }
 
 void launch_reduce_partials(int nk, int nb, int S, const double* part, double scale, int accumulate,

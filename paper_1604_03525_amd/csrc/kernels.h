@@ -82,13 +82,25 @@ struct FusedArgs {
     const double* nbose;   // [qc][nm] (chunk-local)
     const double* sc;      // [qc][nm] (chunk-local)
     double sigma;
+    double mu;         // chemical potential (phonon mode)
     double* part;      // [S][nk][nb] partial sums (imsigma mode)
     int S;             // number of slices
     void* gkq;         // [nk][nq_total][nm][nb][nb] c128 (store mode)
+    double* part_ph;   // [2][tiles_m][qc*nm] per-row-tile sums (phonon mode): Eq. (9), Eq. (11)
 };
-// a7 + a8 + a9 (imsigma mode) or a7 + a8 (store mode, gkq != nullptr)
+// a7 + a8 + a9 (imsigma mode), a7 + a8 (store mode, gkq != nullptr), or
+// a7 + a8 + the phonon-linewidth sums (phonon mode, part_ph != nullptr)
 void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t stream);
 int fused_slices(int nk, int nbp, int ncols_tiles, int num_cu);
+// k rows per tile of the fused kernel for a padded band count
+inline int fused_tile_rows(int nbp) { return nbp * nbp >= 64 ? 4096 / (nbp * nbp) : 64; }
+// raw[0] = sum_i exp(-((eps_i - mu)/sigma)^2) over n values (fixed order)
+void launch_dos_raw(size_t n, const double* eps, double mu, double sigma, double* raw, hipStream_t stream);
+// Pi''[q][nu] = 2 pi / (N_k sigma sqrt pi) sum_t part[0][t][q][nu];
+// lam[q][nu] = sum_t part[1][t][q][nu] / (sigma sqrt(pi) raw_dos omega) (0 for cut modes or raw_dos = 0)
+void launch_phonon_finalize(int qc, int nm, int tiles_m, const double* part_ph, const double* omega,
+                            double omega_cut, const double* raw_dos, int nk, double sigma, double* pi_im,
+                            double* lam, hipStream_t stream);
 
 // ---- k_gemm.hip ----
 // C(m, n) (+)= sum_k A(m, k) B(k, n), complex in `prec` (F64 or F32).

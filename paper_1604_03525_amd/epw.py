@@ -11,7 +11,7 @@ import torch
 
 from . import _lib
 from ._lib import (EPW_FP32, EPW_FP64, EPW_SPLIT_BF16, EPW_WS_IMSIGMA,  # noqa: F401
-                   EPW_WS_IMSIGMA_BACKWARD, EPW_WS_INTERP_G, EpwError)
+                   EPW_WS_IMSIGMA_BACKWARD, EPW_WS_INTERP_G, EPW_WS_PHONON, EpwError)
 
 DTYPES = {"fp64": EPW_FP64, "fp32": EPW_FP32, "split_bf16": EPW_SPLIT_BF16}
 
@@ -206,6 +206,24 @@ def epw_imsigma(system, points, params, out=None, workspace=None):
     _lib.check(lib.epw_imsigma(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), _ptr(out),
                                _ptr(buf), buf.numel(), _stream(system.device)))
     return out
+
+
+def epw_phonon_selfenergy(system, points, params, want_lambda=True, workspace=None):
+    """(Pi''_q,nu [nq][nm], lambda_q,nu [nq][nm] or None) float64: the phonon
+    linewidth of Sec. 3 Eq. (9) on shell and the coupling strength of
+    Sec. 3 Eq. (11)."""
+    lib = _lib.load()
+    ws = workspace or Workspace(system.device)
+    nbytes = epw_workspace_size(EPW_WS_PHONON, system, points, params)
+    buf = ws.get(nbytes)
+    d = system.device
+    nq, nm = points.q.shape[0], system.nm
+    pi_im = torch.empty((nq, nm), dtype=torch.float64, device=d)
+    lam = torch.empty((nq, nm), dtype=torch.float64, device=d) if want_lambda else None
+    s, p = system.c_struct(), points.c_struct()
+    _lib.check(lib.epw_phonon_selfenergy(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), _ptr(pi_im),
+                                         _ptr(lam), _ptr(buf), buf.numel(), _stream(d)))
+    return pi_im, lam
 
 
 def epw_imsigma_backward(system, points, params, w, want=("gR", "HR", "omega"), workspace=None):

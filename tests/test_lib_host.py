@@ -108,7 +108,7 @@ def test_workspace_size_empty_point_sets():
     par = epw.make_params()
     for nk, nq in [(0, 27), (27, 0), (0, 0)]:
         s, p = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=nk, nq=nq)
-        for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA):
+        for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_PHONON):
             assert lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par)) > 0
 
 
@@ -119,7 +119,29 @@ def test_workspace_size_counts_per_pair_states():
     s, p = _shape_only(nb=16, nm=9, ne=89, np_=89, nk=24, nq=40)
     kq = (ctypes.c_int32 * 1)()
     p_grid = _lib.EpwPoints(24, 40, None, None, ctypes.cast(kq, ctypes.c_void_p), None, None)
-    for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_IMSIGMA_BACKWARD):
+    for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_IMSIGMA_BACKWARD, _lib.EPW_WS_PHONON):
         off = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
         on = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p_grid), ctypes.byref(par))
         assert off >= on + 24 * 16 * (16 * 16 * 16 + 16 * 16)
+
+
+def test_phonon_selfenergy_argument_errors():
+    """The phonon linewidth call rejects a NULL output, an empty k set and an
+    unknown precision before touching any device memory, and accepts an
+    empty q set as a no-op."""
+    lib = _lib.load()
+    par = epw.make_params()
+    s, p = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=27, nq=8)
+    assert lib.epw_phonon_selfenergy(ctypes.byref(s), ctypes.byref(p), ctypes.byref(par), None, None, None, 0,
+                                     None) == _lib.EPW_EINVAL
+    dummy = (ctypes.c_double * 1)()
+    s0, p0 = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=0, nq=8)
+    assert lib.epw_phonon_selfenergy(ctypes.byref(s0), ctypes.byref(p0), ctypes.byref(par), dummy, None, None, 0,
+                                     None) == _lib.EPW_ESHAPE
+    sq, pq = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=27, nq=0)
+    assert lib.epw_phonon_selfenergy(ctypes.byref(sq), ctypes.byref(pq), ctypes.byref(par), None, None, None, 0,
+                                     None) == _lib.EPW_OK
+    bad = epw.make_params(dtype=7)
+    assert lib.epw_phonon_selfenergy(ctypes.byref(s), ctypes.byref(p), ctypes.byref(bad), dummy, None, None, 0,
+                                     None) == _lib.EPW_EDTYPE
+    assert lib.epw_workspace_size(_lib.EPW_WS_PHONON, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par)) > 0

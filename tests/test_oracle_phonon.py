@@ -188,3 +188,18 @@ def test_gauge_invariance_degenerate_modes_and_bands():
     assert np.max(np.abs(pi2 - ref_pi)) < 1e-12 * np.abs(ref_pi).max()
     assert np.max(np.abs(lam2 - ref_lam)) < 1e-12 * np.abs(ref_lam).max()
     assert np.max(np.abs(P - P0)) > 1e-6 * np.abs(P0).max()
+
+
+def test_q_outer_order_matches_k_outer_order():
+    """The q-outer evaluation (R_p first, all k at once) equals the k-outer
+    one: a different order of the same finite sums (fcc, 3 bands)."""
+    R, nd = lattice.ws_vectors(I.FCC_METRIC, (2, 2, 2))
+    HR = I.random_hamiltonian(R, I.FCC_VECTORS, 3, seed=4, decay=1.5, scale=0.8)
+    DR = I.spring_dynmat(R, I.FCC_VECTORS, I.ATOMS_FCC2, shells=2, seed=5, scale=2e-3)
+    gR = I.random_vertex(R, R, I.FCC_VECTORS, 6, 3, seed=6, g0=0.05)
+    k = lattice.grid_points(3, 3, 3)
+    q = np.random.default_rng(8).random((5, 3))
+    a = ph.phonon_selfenergy(HR, R, nd, DR, R, nd, gR, k, q, 600.0, 0.2, 0.15)
+    b = ph.phonon_selfenergy(HR, R, nd, DR, R, nd, gR, k, q, 600.0, 0.2, 0.15, loop="q")
+    for x, y in zip(a, b):
+        assert np.max(np.abs(x - y)) < 1e-12 * np.abs(x).max()
