@@ -201,8 +201,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32",
-                    help="comma list of fp32, split_bf16, backward, backward_fp32, mobility (the last is "
+    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32,phonon",
+                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, mobility (the last is "
                          "opt-in: one 4096-q shard of the mobility-scale system, ~2 min)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
@@ -276,6 +276,16 @@ def main():
                                args.steps, args.warmup, torch)
                 variants[var] = {"value": pairs * args.steps / dtb, "ms_per_step": 1e3 * dtb / args.steps,
                                  "dtype": bdt, "outputs": "dL/dg(R_e,R_p), dL/dH(R_e), dL/domega"}
+            elif var == "phonon":
+                log("bench: phonon linewidth and lambda (fp64)")
+                par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
+                dtp, stp = timed(lambda: epw.epw_phonon_selfenergy(sysd, pts, par, workspace=ws),
+                                 args.steps, args.warmup, torch)
+                fmsp, fnp = stp["fused"]
+                achp = flops / (fmsp * 1e-3) / 1e12 if fmsp > 0 else None
+                variants[var] = {"value": pairs * args.steps / dtp, "ms_per_step": 1e3 * dtp / args.steps,
+                                 "dtype": "fp64", "outputs": "Pi''_q,nu (Eq. 9) and lambda_q,nu (Eq. 11)",
+                                 "fused_tflops": achp, "fused_frac_of_peak": achp / PEAK_TFLOPS["fp64"] if achp else None}
             elif var == "mobility":
                 variants[var] = mobility_shard(dev, ("fp32", "split_bf16"), min(args.steps, 2), 1, torch)
         except epw.EpwError as e:
