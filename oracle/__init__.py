@@ -21,6 +21,8 @@ selfenergy  Fermi/Bose occupations, Gaussian delta, Im Sigma_nk of
             Sec. 3 Eq. (8), degenerate averaging (Sec. 10.4).
 phonon      Phonon linewidth Pi''_q,nu (Sec. 3 Eq. (9)) and mode-resolved
             coupling strength lambda_q,nu (Sec. 3 Eq. (11)).
+realpart    On-shell real part of the electron self-energy (Sec. 3 Eq. (3))
+            and its Fermi-level-referenced form (Sec. 3 Eq. (5)).
 torch_ref   The same forward in plain torch CPU float64, differentiated by
             autograd: the reference gradient for the hand-written adjoint.
 
