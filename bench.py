@@ -201,8 +201,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32,phonon",
-                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, mobility (the last is "
+    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32,phonon,resigma",
+                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, resigma, mobility (the last is "
                          "opt-in: one 4096-q shard of the mobility-scale system, ~2 min)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
@@ -286,6 +286,16 @@ def main():
                 variants[var] = {"value": pairs * args.steps / dtp, "ms_per_step": 1e3 * dtp / args.steps,
                                  "dtype": "fp64", "outputs": "Pi''_q,nu (Eq. 9) and lambda_q,nu (Eq. 11)",
                                  "fused_tflops": achp, "fused_frac_of_peak": achp / PEAK_TFLOPS["fp64"] if achp else None}
+            elif var == "resigma":
+                log("bench: on-shell Re Sigma and Sigma~' (fp64)")
+                par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
+                dtr, str_ = timed(lambda: epw.epw_resigma(sysd, pts, par, workspace=ws),
+                                  args.steps, args.warmup, torch)
+                fmsr, fnr = str_["fused"]
+                achr = flops / (fmsr * 1e-3) / 1e12 if fmsr > 0 else None
+                variants[var] = {"value": pairs * args.steps / dtr, "ms_per_step": 1e3 * dtr / args.steps,
+                                 "dtype": "fp64", "outputs": "Sigma'_nk on shell (Eq. 3) and Sigma~'_nk (Eq. 5)",
+                                 "fused_tflops": achr, "fused_frac_of_peak": achr / PEAK_TFLOPS["fp64"] if achr else None}
             elif var == "mobility":
                 variants[var] = mobility_shard(dev, ("fp32", "split_bf16"), min(args.steps, 2), 1, torch)
         except epw.EpwError as e:

@@ -208,6 +208,20 @@ int epw_interp_g(const epw_system* sys, const epw_points* pts, const epw_params*
 int epw_imsigma(const epw_system* sys, const epw_points* pts, const epw_params* par,
                 double* imsig, void* ws, size_t ws_bytes, void* stream);
 
+/* Real part of the electron self-energy, Sec. 3 Eq. (3), on shell, and its
+ * Fermi-level-referenced form, Sec. 3 Eq. (5):
+ *   Sigma'_nk(omega) = (1/N_q) sum_q sum_m,nu |g_mn,nu(k,q)|^2 Re{
+ *       [n_q,nu + f_m,k+q] / (omega - (eps_m,k+q - eps_F) + omega_q,nu + i delta)
+ *     + [n_q,nu + 1 - f_m,k+q] / (omega - (eps_m,k+q - eps_F) - omega_q,nu + i delta) }
+ *   re_shell = Sigma'_nk(eps_nk - eps_F),  re_tilde = re_shell - Sigma'_nk(0)
+ * with eps_F = mu and delta = par->sigma; occupations, nq_norm, omega_cut,
+ * chunking, accumulate and the degenerate average as for epw_imsigma.
+ *  re_shell  device [nk][nb] double out
+ *  re_tilde  device [nk][nb] double out, or NULL to skip
+ * Errors: as epw_imsigma. */
+int epw_resigma(const epw_system* sys, const epw_points* pts, const epw_params* par, double* re_shell,
+                double* re_tilde, void* ws, size_t ws_bytes, void* stream);
+
 /* Phonon linewidth, Sec. 3 Eq. (9), on shell (omega = omega_q,nu), and the
  * mode-resolved electron-phonon coupling strength, Sec. 3 Eq. (11):
  *   Pi''_q,nu = (2 pi / N_k) sum_k sum_mn |g_mn,nu(k,q)|^2
@@ -249,13 +263,14 @@ int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw
                          void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for the call `which` (EPW_WS_INTERP_G, EPW_WS_IMSIGMA,
- * EPW_WS_IMSIGMA_BACKWARD, EPW_WS_PHONON) with these sizes and parameters; device pointers
+ * EPW_WS_IMSIGMA_BACKWARD, EPW_WS_PHONON, EPW_WS_RESIGMA) with these sizes and parameters; device pointers
  * inside sys/pts are not dereferenced and may be NULL.  Returns 0 and sets
  * the error message on invalid arguments. */
 #define EPW_WS_INTERP_G          1
 #define EPW_WS_IMSIGMA           2
 #define EPW_WS_IMSIGMA_BACKWARD  3
 #define EPW_WS_PHONON            4
+#define EPW_WS_RESIGMA           5
 size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
                           const epw_params* par);
 

@@ -23,6 +23,7 @@ EPW_WS_INTERP_G = 1
 EPW_WS_IMSIGMA = 2
 EPW_WS_IMSIGMA_BACKWARD = 3
 EPW_WS_PHONON = 4
+EPW_WS_RESIGMA = 5
 
 EPW_STAGE_EIGH = 0
 EPW_STAGE_GEMM_RP = 1
@@ -77,6 +78,8 @@ PROTOTYPES = {
                                     ctypes.POINTER(EpwParams), _vp, _vp, ctypes.c_size_t, _vp]),
     "epw_imsigma": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
                                    ctypes.POINTER(EpwParams), _vp, _vp, ctypes.c_size_t, _vp]),
+    "epw_resigma": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
+                                   ctypes.POINTER(EpwParams), _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "epw_phonon_selfenergy": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
                                              ctypes.POINTER(EpwParams), _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "epw_imsigma_backward": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),

@@ -62,7 +62,7 @@ struct PairScratch {
 };
 
 // what a forward pass produces
-enum class Out { IMSIGMA, STORE, PHONON };
+enum class Out { IMSIGMA, STORE, PHONON, RESIGMA };
 
 struct Layout {
     Prec prec;
@@ -83,6 +83,7 @@ struct Layout {
     void* gq = nullptr;
     void* Bnu = nullptr;
     double* part = nullptr;
+    double* part2 = nullptr;     // [S][nk][nb] (real-part mode: Sigma' at eps_F)
     double* part_ph = nullptr;   // [2][tiles_m][Q nm] (phonon mode)
     double* dos_raw = nullptr;   // [1] (phonon mode)
     // per pair states at k+q when no k+q map is given
@@ -186,7 +187,8 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
     L.Bnu = A.take(bcol_bytes * L.Q * nm * L.nbp * L.nbp);
     L.tiles_m = (nk + fused_tile_rows(L.nbp) - 1) / fused_tile_rows(L.nbp);
-    if (out == Out::IMSIGMA) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
+    if (out == Out::IMSIGMA || out == Out::RESIGMA) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
+    if (out == Out::RESIGMA) L.part2 = (double*)A.take(8 * (size_t)L.S * nk * nb);
     if (out == Out::PHONON) {
         L.part_ph = (double*)A.take(8 * 2 * (size_t)L.tiles_m * L.Q * nm);
         L.dos_raw = (double*)A.take(8);
@@ -216,8 +218,10 @@ GemmDesc rp_desc(int qc, int ne, int np_, int ncol, const void* phi_q, const voi
 // mode writes Pi''_q,nu and lambda_q,nu to pi_im / lam, otherwise Im Sigma
 // goes to imsig.
 void run_forward(const epw_system* s, const epw_points* p, const epw_params* par, Layout& L,
-                 double* imsig, void* gkq, hipStream_t st, double* pi_im = nullptr, double* lam = nullptr) {
+                 double* imsig, void* gkq, hipStream_t st, double* pi_im = nullptr, double* lam = nullptr,
+                 double* re_tilde = nullptr) {
     const bool phon = L.out == Out::PHONON;
+    const bool re = L.out == Out::RESIGMA;     // imsig then receives Sigma' on shell
     const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
     const Prec prec = L.prec;
     const bool given = p->omega && p->evec;
@@ -309,6 +313,7 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp), SLICE_CUS);
         a.gkq = gkq;
         a.part_ph = phon ? L.part_ph : nullptr;
+        a.part2 = re ? L.part2 : nullptr;
         {
             StageTimer t(EPW_STAGE_FUSED, st);
             launch_fused_k(prec, a, SLICE_CUS, st);
@@ -321,13 +326,22 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
             // average over degenerate modes of each q
             launch_degenerate_average(qc, nm, om, par->deg_tol, pi_c, st);
             if (lam_c) launch_degenerate_average(qc, nm, om, par->deg_tol, lam_c, st);
+        } else if (re) {
+            // Eq. (3) carries no pi: the BZ mean only
+            const int acc = (c > 0 || par->accumulate) ? 1 : 0;
+            launch_reduce_partials(nk, nb, a.S, L.part, 1.0 / nqn, acc, imsig, st);
+            if (re_tilde) launch_reduce_partials_diff(nk, nb, a.S, L.part, L.part2, 1.0 / nqn, acc, re_tilde, st);
         } else if (!gkq) {
             launch_reduce_partials(nk, nb, a.S, L.part, scale, (c > 0 || par->accumulate) ? 1 : 0, imsig, st);
         }
     }
     if (!gkq && !phon) {
-        if (L.nchunks == 0 && !par->accumulate && nk > 0) launch_fill((size_t)nk * nb, 0.0, imsig, st);
+        if (L.nchunks == 0 && !par->accumulate && nk > 0) {
+            launch_fill((size_t)nk * nb, 0.0, imsig, st);
+            if (re_tilde) launch_fill((size_t)nk * nb, 0.0, re_tilde, st);
+        }
         launch_degenerate_average(nk, nb, L.eps, par->deg_tol, imsig, st);
+        if (re_tilde) launch_degenerate_average(nk, nb, L.eps, par->deg_tol, re_tilde, st);
     }
 }
 
@@ -627,7 +641,7 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
                                      const epw_params* par) {
     clear_error();
     if (which != EPW_WS_INTERP_G && which != EPW_WS_IMSIGMA && which != EPW_WS_IMSIGMA_BACKWARD &&
-        which != EPW_WS_PHONON) {
+        which != EPW_WS_PHONON && which != EPW_WS_RESIGMA) {
         fail(EPW_EINVAL, "epw_workspace_size: unknown call id %d", which);
         return 0;
     }
@@ -657,8 +671,10 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
         plan_bwd(&s, &p, par, A, L);
     } else {
         Layout L;
-        plan(&s, &p, par, which == EPW_WS_INTERP_G ? Out::STORE : which == EPW_WS_PHONON ? Out::PHONON : Out::IMSIGMA,
-             A, L);
+        const Out o = which == EPW_WS_INTERP_G ? Out::STORE
+                      : which == EPW_WS_PHONON ? Out::PHONON
+                      : which == EPW_WS_RESIGMA ? Out::RESIGMA : Out::IMSIGMA;
+        plan(&s, &p, par, o, A, L);
     }
     return A.used + 256;
 }
@@ -705,6 +721,29 @@ extern "C" int epw_imsigma(const epw_system* sys, const epw_points* pts, const e
         A.cap = ws_bytes;
         plan(sys, pts, par, Out::IMSIGMA, A, L);
         run_forward(sys, pts, par, L, imsig, nullptr, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_resigma(const epw_system* sys, const epw_points* pts, const epw_params* par, double* re_shell,
+                           double* re_tilde, void* ws, size_t ws_bytes, void* stream) {
+    clear_error();
+    int rc = check_common(sys, pts, par, "epw_resigma");
+    if (rc != EPW_OK) return rc;
+    if (pts->nk == 0) return EPW_OK;
+    if (!re_shell) return fail(EPW_EINVAL, "epw_resigma: NULL output");
+    Arena dry;
+    dry.dry = true;
+    Layout L;
+    plan(sys, pts, par, Out::RESIGMA, dry, L);
+    if (!ws || ws_bytes < dry.used + 256)
+        return fail(EPW_ENOMEM, "epw_resigma: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
+    return guarded("epw_resigma", [&]() {
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        plan(sys, pts, par, Out::RESIGMA, A, L);
+        run_forward(sys, pts, par, L, re_shell, nullptr, (hipStream_t)stream, nullptr, nullptr, re_tilde);
         return EPW_OK;
     });
 }

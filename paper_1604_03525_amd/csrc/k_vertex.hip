@@ -344,12 +344,14 @@ __device__ inline float2 cmulx(float2 a, float2 b) {
 // carried by the B operand.
 // KIND 0: Im Sigma (Eq. (8)) partial sums per (k, n); 1: store g_mn,nu(k,q);
 // 2: the sums of the phonon linewidth (Eq. (9)) and of the coupling strength
-// (Eq. (11)) per (q, nu), reduced over the tile's k rows in fixed order.
+// (Eq. (11)) per (q, nu), reduced over the tile's k rows in fixed order;
+// 3: the real part of Eq. (3) per (k, n), on shell and at omega = eps_F.
 template <int MODE, int NBP, int KIND, bool GEN>
 __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
 {
     constexpr bool STORE = KIND == 1;
     constexpr bool PH = KIND == 2;
+    constexpr bool RE = KIND == 3;
     typedef typename ModeTypes<MODE>::T T;
     typedef typename ModeTypes<MODE>::CT CT;
     typedef typename ModeTypes<MODE>::TE TE;
@@ -451,11 +453,15 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     // the row's bands and, in the float32 modes, eps_nk and the U_k columns
     // (the float64 mode reloads those per tile to stay within its registers).
     constexpr bool HOIST = MODE != 0;
-    double acc[NBP];
+    double acc[NBP], acc2[RE ? NBP : 1];
     double eps_h[HOIST ? NBP : 1];
     CE uk_h[HOIST ? RUN : 1][NBP];
 #pragma unroll
     for (int n = 0; n < NBP; ++n) acc[n] = 0.0;
+    if constexpr (RE) {
+#pragma unroll
+        for (int n = 0; n < NBP; ++n) acc2[n] = 0.0;
+    }
     if constexpr (HOIST) {
 #pragma unroll
         for (int n = 0; n < NBP; ++n) eps_h[n] = (active_row && n < nb) ? a.eps[(size_t)k * nb + n] : 0.0;
@@ -657,6 +663,22 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                             WL[t] = (TE)(dn * dm[t]);
                             need = need || (s1 < ylim) || (WL[t] != TE(0));
                         }
+                    } else if constexpr (RE) {
+                        // Eq. (3), Re 1/(x + i delta) = x/(x^2 + delta^2), delta = sigma:
+                        // on shell x = eps_nk - eps_m,k+q +- omega; at eps_F x = mu - eps_m,k+q +- omega
+                        const double d2 = a.sigma * a.sigma;
+                        need = true;
+#pragma unroll
+                        for (int t = 0; t < RUN; ++t) {
+                            W[t] = TE(0);
+                            WL[t] = TE(0);
+                            if (!mv[t]) continue;
+                            const double A1 = nB + fm[t], A2 = nB + 1.0 - fm[t];
+                            const double x1 = epsn - em[t] + w, x2 = epsn - em[t] - w;
+                            const double y1 = a.mu - em[t] + w, y2 = a.mu - em[t] - w;
+                            W[t] = (TE)(A1 * x1 / (x1 * x1 + d2) + A2 * x2 / (x2 * x2 + d2));
+                            WL[t] = (TE)(A1 * y1 / (y1 * y1 + d2) + A2 * y2 / (y2 * y2 + d2));
+                        }
                     } else {
 #pragma unroll
                         for (int t = 0; t < RUN; ++t) {
@@ -701,6 +723,10 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                             const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
                             pp[rr] += (double)(g2 * W[t]);
                             pl[rr] += (double)(g2 * WL[t]);
+                        } else if (RE) {
+                            const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
+                            acc[n] += (double)(g2 * W[t]);
+                            acc2[n] += (double)(g2 * WL[t]);
                         } else {
                             acc[n] += (double)((gr[t] * gr[t] + gi[t] * gi[t]) * W[t]);
                         }
@@ -746,17 +772,23 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
         }
         __syncthreads();
     }
-    if constexpr (KIND != 0) return;
-    // fixed-order reduction over the TPR threads of each row
+    if constexpr (KIND == 1 || KIND == 2) return;
+    // fixed-order reduction over the TPR threads of each row (real-part
+    // mode: the on-shell sums, then the sums at eps_F)
     double* red = reinterpret_cast<double*>(smem);   // [BM][TPR][NBP]
 #pragma unroll
-    for (int n = 0; n < NBP; ++n) red[(size_t)tid * NBP + n] = acc[n];
-    __syncthreads();
-    if (active_row) {
-        for (int n = sub; n < nb; n += TPR) {
-            double t = 0.0;
-            for (int u = 0; u < TPR; ++u) t += red[((size_t)r * TPR + u) * NBP + n];
-            a.part[((size_t)s * a.nk + k) * nb + n] = t;
+    for (int pass = 0; pass < (RE ? 2 : 1); ++pass) {
+        if (pass) __syncthreads();
+#pragma unroll
+        for (int n = 0; n < NBP; ++n) red[(size_t)tid * NBP + n] = pass ? acc2[RE ? n : 0] : acc[n];
+        __syncthreads();
+        double* dst = pass ? a.part2 : a.part;
+        if (active_row) {
+            for (int n = sub; n < nb; n += TPR) {
+                double t = 0.0;
+                for (int u = 0; u < TPR; ++u) t += red[((size_t)r * TPR + u) * NBP + n];
+                dst[((size_t)s * a.nk + k) * nb + n] = t;
+            }
         }
     }
 }
@@ -847,6 +879,18 @@ __global__ void reduce_partials_kernel(int nk, int nb, int S, const double* __re
     if (idx >= total) return;
     double t = 0.0;
     for (int s = 0; s < S; ++s) t += part[(size_t)s * total + idx];
+    out[idx] = (accumulate ? out[idx] : 0.0) + scale * t;
+}
+
+__global__ void reduce_partials_diff_kernel(int nk, int nb, int S, const double* __restrict__ A,
+                                            const double* __restrict__ B, double scale, int accumulate,
+                                            double* __restrict__ out)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)nk * nb;
+    if (idx >= total) return;
+    double t = 0.0;
+    for (int s = 0; s < S; ++s) t += A[(size_t)s * total + idx] - B[(size_t)s * total + idx];
     out[idx] = (accumulate ? out[idx] : 0.0) + scale * t;
 }
 
@@ -946,6 +990,7 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     };
     if (a.gkq) go(std::integral_constant<int, 1>());
     else if (a.part_ph) go(std::integral_constant<int, 2>());
+    else if (a.part2) go(std::integral_constant<int, 3>());
     else go(std::integral_constant<int, 0>());
     launch_check("fused_k_kernel");
 }
@@ -1051,6 +1096,15 @@ void launch_reduce_partials(int nk, int nb, int S, const double* part, double sc
     if (total == 0) return;
     reduce_partials_kernel<<<blocks_for(total, 256), 256, 0, stream>>>(nk, nb, S, part, scale, accumulate, imsig);
     launch_check("reduce_partials_kernel");
+}
+
+void launch_reduce_partials_diff(int nk, int nb, int S, const double* A, const double* B, double scale,
+                                 int accumulate, double* out, hipStream_t stream) {
+    const size_t total = (size_t)nk * nb;
+    if (total == 0) return;
+    reduce_partials_diff_kernel<<<blocks_for(total, 256), 256, 0, stream>>>(nk, nb, S, A, B, scale, accumulate,
+                                                                            out);
+    launch_check("reduce_partials_diff_kernel");
 }
 
 void launch_degenerate_average(int nk, int nb, const double* eps, double tol, double* v, hipStream_t stream) {

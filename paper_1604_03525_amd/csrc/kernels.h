@@ -87,9 +87,12 @@ struct FusedArgs {
     int S;             // number of slices
     void* gkq;         // [nk][nq_total][nm][nb][nb] c128 (store mode)
     double* part_ph;   // [2][tiles_m][qc*nm] per-row-tile sums (phonon mode): Eq. (9), Eq. (11)
+    double* part2;     // [S][nk][nb] second partials (real-part mode: Sigma' at omega = 0; part
+                       // then holds Sigma' on shell)
 };
-// a7 + a8 + a9 (imsigma mode), a7 + a8 (store mode, gkq != nullptr), or
-// a7 + a8 + the phonon-linewidth sums (phonon mode, part_ph != nullptr)
+// a7 + a8 + a9 (imsigma mode), a7 + a8 (store mode, gkq != nullptr),
+// a7 + a8 + the phonon-linewidth sums (phonon mode, part_ph != nullptr), or
+// a7 + a8 + the real-part sums of Eq. (3) (real-part mode, part2 != nullptr)
 void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t stream);
 int fused_slices(int nk, int nbp, int ncols_tiles, int num_cu);
 // k rows per tile of the fused kernel for a padded band count
@@ -182,6 +185,9 @@ void launch_c64_to_c128(size_t n, const void* in, int accumulate, void* out, hip
 // imsig[k][n] = (acc ? imsig : 0) + scale * sum_s part[s][k][n]
 void launch_reduce_partials(int nk, int nb, int S, const double* part, double scale,
                             int accumulate, double* imsig, hipStream_t stream);
+// out[k][n] = (acc ? out : 0) + scale * sum_s (A[s][k][n] - B[s][k][n])  (fixed order)
+void launch_reduce_partials_diff(int nk, int nb, int S, const double* A, const double* B, double scale,
+                                 int accumulate, double* out, hipStream_t stream);
 // average over bands whose consecutive energies differ by < tol
 void launch_degenerate_average(int nk, int nb, const double* eps, double tol, double* v,
                                hipStream_t stream);

@@ -11,7 +11,8 @@ import torch
 
 from . import _lib
 from ._lib import (EPW_FP32, EPW_FP64, EPW_SPLIT_BF16, EPW_WS_IMSIGMA,  # noqa: F401
-                   EPW_WS_IMSIGMA_BACKWARD, EPW_WS_INTERP_G, EPW_WS_PHONON, EpwError)
+                   EPW_WS_IMSIGMA_BACKWARD, EPW_WS_INTERP_G, EPW_WS_PHONON, EPW_WS_RESIGMA,
+                   EpwError)
 
 DTYPES = {"fp64": EPW_FP64, "fp32": EPW_FP32, "split_bf16": EPW_SPLIT_BF16}
 
@@ -206,6 +207,23 @@ def epw_imsigma(system, points, params, out=None, workspace=None):
     _lib.check(lib.epw_imsigma(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), _ptr(out),
                                _ptr(buf), buf.numel(), _stream(system.device)))
     return out
+
+
+def epw_resigma(system, points, params, want_tilde=True, workspace=None):
+    """(Sigma'_nk on shell, Sigma~'_nk or None) [nk][nb] float64: the real part
+    of Sec. 3 Eq. (3) at omega = eps_nk - eps_F and its Eq. (5) form."""
+    lib = _lib.load()
+    ws = workspace or Workspace(system.device)
+    nbytes = epw_workspace_size(EPW_WS_RESIGMA, system, points, params)
+    buf = ws.get(nbytes)
+    d = system.device
+    shape = (points.k.shape[0], system.nb)
+    shell = torch.empty(shape, dtype=torch.float64, device=d)
+    tilde = torch.empty(shape, dtype=torch.float64, device=d) if want_tilde else None
+    s, p = system.c_struct(), points.c_struct()
+    _lib.check(lib.epw_resigma(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), _ptr(shell), _ptr(tilde),
+                               _ptr(buf), buf.numel(), _stream(d)))
+    return shell, tilde
 
 
 def epw_phonon_selfenergy(system, points, params, want_lambda=True, workspace=None):

@@ -108,7 +108,7 @@ def test_workspace_size_empty_point_sets():
     par = epw.make_params()
     for nk, nq in [(0, 27), (27, 0), (0, 0)]:
         s, p = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=nk, nq=nq)
-        for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_PHONON):
+        for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_PHONON, _lib.EPW_WS_RESIGMA):
             assert lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par)) > 0
 
 
@@ -119,7 +119,8 @@ def test_workspace_size_counts_per_pair_states():
     s, p = _shape_only(nb=16, nm=9, ne=89, np_=89, nk=24, nq=40)
     kq = (ctypes.c_int32 * 1)()
     p_grid = _lib.EpwPoints(24, 40, None, None, ctypes.cast(kq, ctypes.c_void_p), None, None)
-    for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_IMSIGMA_BACKWARD, _lib.EPW_WS_PHONON):
+    for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_IMSIGMA_BACKWARD, _lib.EPW_WS_PHONON,
+                  _lib.EPW_WS_RESIGMA):
         off = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
         on = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p_grid), ctypes.byref(par))
         assert off >= on + 24 * 16 * (16 * 16 * 16 + 16 * 16)
@@ -145,3 +146,24 @@ def test_phonon_selfenergy_argument_errors():
     assert lib.epw_phonon_selfenergy(ctypes.byref(s), ctypes.byref(p), ctypes.byref(bad), dummy, None, None, 0,
                                      None) == _lib.EPW_EDTYPE
     assert lib.epw_workspace_size(_lib.EPW_WS_PHONON, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par)) > 0
+
+
+def test_resigma_argument_errors():
+    """The real-part call rejects a NULL output and an unknown precision
+    before any device work, takes an empty k set as a no-op, and its
+    workspace exceeds the Im Sigma one by the second partial-sum buffer."""
+    lib = _lib.load()
+    par = epw.make_params()
+    s, p = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=27, nq=8)
+    assert lib.epw_resigma(ctypes.byref(s), ctypes.byref(p), ctypes.byref(par), None, None, None, 0,
+                           None) == _lib.EPW_EINVAL
+    s0, p0 = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=0, nq=8)
+    assert lib.epw_resigma(ctypes.byref(s0), ctypes.byref(p0), ctypes.byref(par), None, None, None, 0,
+                           None) == _lib.EPW_OK
+    dummy = (ctypes.c_double * 1)()
+    bad = epw.make_params(dtype=7)
+    assert lib.epw_resigma(ctypes.byref(s), ctypes.byref(p), ctypes.byref(bad), dummy, None, None, 0,
+                           None) == _lib.EPW_EDTYPE
+    im = lib.epw_workspace_size(_lib.EPW_WS_IMSIGMA, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
+    re = lib.epw_workspace_size(_lib.EPW_WS_RESIGMA, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
+    assert re >= im + 8 * 27 * 3
