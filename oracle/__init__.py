@@ -23,6 +23,8 @@ phonon      Phonon linewidth Pi''_q,nu (Sec. 3 Eq. (9)) and mode-resolved
             coupling strength lambda_q,nu (Sec. 3 Eq. (11)).
 realpart    On-shell real part of the electron self-energy (Sec. 3 Eq. (3))
             and its Fermi-level-referenced form (Sec. 3 Eq. (5)).
+spectral    Complex Sigma_nk(omega) of Sec. 3 Eq. (3) on a frequency grid
+            and the spectral function A_nk(omega) of Sec. 3 Eq. (10).
 torch_ref   The same forward in plain torch CPU float64, differentiated by
             autograd: the reference gradient for the hand-written adjoint.
 
