@@ -63,7 +63,8 @@ def timed(fn, steps, warmup, torch):
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     stages = {}
-    for name, sid in (("eigh", 0), ("gemm_rp", 1), ("moderot", 2), ("fused", 3), ("backward", 4)):
+    for name, sid in (("eigh", 0), ("gemm_rp", 1), ("moderot", 2), ("fused", 3), ("backward", 4),
+                      ("spectral", 5)):
         ms, n = epw.epw_timing_read(sid)
         stages[name] = (ms, n)
     epw.epw_timing_enable(False)
@@ -174,6 +175,46 @@ def mobility_shard(dev, dtypes, steps, warmup, torch):
     return out
 
 
+def spectral_flops(nk, nq, nw, nm, nb):
+    """Algorithmic flops of the frequency-resolved sum (Eq. (3) on a grid):
+    per (k, pole family (q, nu, m), frequency incl. omega = 0) 14 flops for the
+    two complex poles (two subtractions, two x^2 + d^2, two reciprocals, the
+    weights and the real and imaginary sums) plus a complex update of every
+    band n (4 flops)."""
+    return float(nk) * (nw + 1) * nq * nm * nb * (14.0 + 4.0 * nb)
+
+
+def spectral_run(sysd, model, dev, steps, warmup, torch):
+    """Frequency-resolved Sigma_nk(omega) (Eq. (3)) and A_nk(omega)
+    (Eq. (10)) on the spectral workload: the realistic system, 64 k on
+    Gamma-X, 10^5 random q (off-grid k+q), 512 frequencies, FP64."""
+    from paper_1604_03525_amd import epw
+    from paper_1604_03525_amd import inputs as I
+    wl = I.spectral_workload()
+    pts = epw.Points(wl["k"], wl["q"], None, device=dev)
+    w = torch.as_tensor(wl["wgrid"], device=dev)
+    par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
+    ws = epw.Workspace(dev)
+    nk, nq, nw = len(wl["k"]), len(wl["q"]), len(wl["wgrid"])
+    log("bench: spectral function (%d k x %d q x %d frequencies)" % (nk, nq, nw))
+    dt, st = timed(lambda: epw.spectral_function(sysd, pts, par, w, workspace=ws), steps, warmup, torch)
+    sms, sn = st["spectral"]
+    fl = spectral_flops(nk, nq, nw, sysd.nm, sysd.nb) * steps
+    ach = fl / (sms * 1e-3) / 1e12 if sms > 0 else None
+    fms, _ = st["fused"]
+    fa = fused_flops(nk, nq, sysd.Re.shape[0], sysd.nm, sysd.nb) * steps / (fms * 1e-3) / 1e12 if fms > 0 else None
+    return {"value": nk * nq * steps / dt, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dt / steps,
+            "dtype": "fp64", "workload": "realistic fcc system, %d k on Gamma-X x %d random q (off-grid k+q), "
+                                         "%d frequencies on [-1, 1] eV, delta = 20 meV" % (nk, nq, nw),
+            "outputs": "Sigma_nk(omega) complex (Eq. 3), Sigma_nk(0), A_nk(omega) (Eq. 10)",
+            "spectral_kernel": {"kernel": "sigma_omega_kernel", "bound": "alu", "achieved": ach,
+                                "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                                "frac": ach / PEAK_TFLOPS["fp64"] if ach else None,
+                                "launches": sn, "avg_launch_ms": sms / sn if sn else None},
+            "fused_tflops": fa,
+            "stages_ms_per_step": {s_: v[0] / steps for s_, v in st.items()}}
+
+
 def cpu_baseline(host, model, seconds_target=15.0):
     """The FP64 oracle on a bounded sample: a few k points against all q."""
     import numpy as np
@@ -201,8 +242,9 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32,phonon,resigma",
-                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, resigma, mobility (the last is "
+    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32,phonon,resigma,spectral",
+                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, resigma, spectral, "
+                         "mobility (the last is "
                          "opt-in: one 4096-q shard of the mobility-scale system, ~2 min)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
@@ -296,6 +338,8 @@ def main():
                 variants[var] = {"value": pairs * args.steps / dtr, "ms_per_step": 1e3 * dtr / args.steps,
                                  "dtype": "fp64", "outputs": "Sigma'_nk on shell (Eq. 3) and Sigma~'_nk (Eq. 5)",
                                  "fused_tflops": achr, "fused_frac_of_peak": achr / PEAK_TFLOPS["fp64"] if achr else None}
+            elif var == "spectral":
+                variants[var] = spectral_run(sysd, model, dev, args.steps, args.warmup, torch)
             elif var == "mobility":
                 variants[var] = mobility_shard(dev, ("fp32", "split_bf16"), min(args.steps, 2), 1, torch)
         except epw.EpwError as e:

@@ -58,6 +58,7 @@ extern "C" {
 /* ---- size limits ---- */
 #define EPW_MAX_NB  16      /* Wannier bands                                        */
 #define EPW_MAX_NM  16      /* phonon modes (3 x atoms)                             */
+#define EPW_MAX_NW  (1 << 20) /* frequencies of epw_selfenergy_omega                  */
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* epw_last_error(void);
@@ -222,6 +223,44 @@ int epw_imsigma(const epw_system* sys, const epw_points* pts, const epw_params* 
 int epw_resigma(const epw_system* sys, const epw_points* pts, const epw_params* par, double* re_shell,
                 double* re_tilde, void* ws, size_t ws_bytes, void* stream);
 
+/* The complex electron self-energy of Sec. 3 Eq. (3) on a frequency grid:
+ *   Sigma_nk(omega) = (1/N_q) sum_q sum_m,nu |g_mn,nu(k,q)|^2 {
+ *       [n_q,nu + f_m,k+q] / (omega - (eps_m,k+q - eps_F) + omega_q,nu + i delta)
+ *     + [n_q,nu + 1 - f_m,k+q] / (omega - (eps_m,k+q - eps_F) - omega_q,nu + i delta) }
+ * with omega measured from eps_F = mu and delta = par->sigma, at every
+ * wgrid[j] and at omega = 0 (the Sigma'(eps_F) of Eq. (5)).  Each q chunk
+ * writes one record per (k, q, nu, m) to the workspace (8 (4 + nb) bytes),
+ * then a second kernel sums the records per frequency.  Occupations,
+ * nq_norm, omega_cut, chunking, accumulate and the degenerate average (at
+ * every frequency) as for epw_imsigma; the precision selects the contraction
+ * arithmetic, the frequency sums are float64.
+ *  nw       frequencies, 0..EPW_MAX_NW
+ *  wgrid    device [nw] double (eV, from eps_F)
+ *  sigma_w  device [nk][nb][nw] c128 out (overwritten or accumulated)
+ *  sigma0   device [nk][nb] c128 out: Sigma_nk(omega = 0)
+ *  ws       workspace of epw_workspace_size_omega() bytes
+ * Errors: as epw_imsigma; EPW_ESHAPE for nw out of range. */
+int epw_selfenergy_omega(const epw_system* sys, const epw_points* pts, const epw_params* par, int nw,
+                         const double* wgrid, void* sigma_w, void* sigma0, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Workspace bytes of epw_selfenergy_omega for nw frequencies (0 on error). */
+size_t epw_workspace_size_omega(const epw_system* sys, const epw_points* pts, const epw_params* par, int nw);
+
+/* The electronic spectral function of Sec. 3 Eq. (10) from a frequency-
+ * resolved self-energy, with Sigma~' of Sec. 3 Eq. (5):
+ *   A_nk(omega) = (1/pi) |Sigma''| / ((omega - (eps_nk - mu) - Sigma~')^2 + Sigma''^2)
+ *   Sigma~' = Re Sigma_nk(omega) - Re Sigma_nk(0),  Sigma'' = Im Sigma_nk(omega)
+ * (the squared Sigma'' of the denominator makes A a normalised density).
+ *  eps      device [nk][nb] double: band energies at the k points (eV)
+ *  wgrid    device [nw] double (eV, from eps_F = mu)
+ *  sigma_w  device [nk][nb][nw] c128, sigma0 device [nk][nb] c128 (as
+ *           written by epw_selfenergy_omega)
+ *  A        device [nk][nb][nw] double out (1/eV)
+ * Errors: EPW_ESHAPE, EPW_EINVAL (NULL pointer, mu not finite), EPW_EHIP. */
+int epw_spectral_function(int nk, int nb, int nw, const double* eps, double mu, const double* wgrid,
+                          const void* sigma_w, const void* sigma0, double* A, void* stream);
+
 /* Phonon linewidth, Sec. 3 Eq. (9), on shell (omega = omega_q,nu), and the
  * mode-resolved electron-phonon coupling strength, Sec. 3 Eq. (11):
  *   Pi''_q,nu = (2 pi / N_k) sum_k sum_mn |g_mn,nu(k,q)|^2
@@ -286,7 +325,8 @@ size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pt
 #define EPW_STAGE_MODEROT   2   /* mode rotation and 1/sqrt(2 omega)             */
 #define EPW_STAGE_FUSED     3   /* R_e -> k contraction + rotation + reduction   */
 #define EPW_STAGE_BACKWARD  4   /* adjoint kernels                               */
-#define EPW_NUM_STAGES      5
+#define EPW_STAGE_SPECTRAL  5   /* frequency-resolved sum over pole records      */
+#define EPW_NUM_STAGES      6
 
 /* enable != 0 starts recording (and discards earlier records); 0 stops. */
 int epw_timing_enable(int enable);

@@ -30,6 +30,7 @@ EPW_STAGE_GEMM_RP = 1
 EPW_STAGE_MODEROT = 2
 EPW_STAGE_FUSED = 3
 EPW_STAGE_BACKWARD = 4
+EPW_STAGE_SPECTRAL = 5
 
 EPW_MAX_NB = 16
 EPW_MAX_NM = 16
@@ -89,6 +90,13 @@ PROTOTYPES = {
     "epw_timing_read": (ctypes.c_int, [ctypes.c_int, _dp, _i64p]),
     "epw_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(EpwSystem),
                                              ctypes.POINTER(EpwPoints), ctypes.POINTER(EpwParams)]),
+    "epw_selfenergy_omega": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
+                                            ctypes.POINTER(EpwParams), ctypes.c_int, _vp, _vp, _vp, _vp,
+                                            ctypes.c_size_t, _vp]),
+    "epw_workspace_size_omega": (ctypes.c_size_t, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
+                                                   ctypes.POINTER(EpwParams), ctypes.c_int]),
+    "epw_spectral_function": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int, _vp, ctypes.c_double,
+                                             _vp, _vp, _vp, _vp, _vp]),
 }
 
 _LIB = None

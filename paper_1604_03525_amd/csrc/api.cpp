@@ -62,7 +62,7 @@ struct PairScratch {
 };
 
 // what a forward pass produces
-enum class Out { IMSIGMA, STORE, PHONON, RESIGMA };
+enum class Out { IMSIGMA, STORE, PHONON, RESIGMA, OMEGA };
 
 struct Layout {
     Prec prec;
@@ -86,6 +86,10 @@ struct Layout {
     double* part2 = nullptr;     // [S][nk][nb] (real-part mode: Sigma' at eps_F)
     double* part_ph = nullptr;   // [2][tiles_m][Q nm] (phonon mode)
     double* dos_raw = nullptr;   // [1] (phonon mode)
+    int nw = 0;                  // frequency-grid mode: grid size,
+    double* rec = nullptr;       // [nk][Q][nm][nb] pole records of 4 + nbp doubles (+ 1),
+    void* spart = nullptr;       // [S_w][nk][nb][nw + 1] c128 slice partials
+    int Sw = 1;
     // per pair states at k+q when no k+q map is given
     double* eps_pair = nullptr;
     void* U_pair = nullptr;
@@ -151,8 +155,10 @@ int tiles_n_for(int qc, int nm, int nbp) {
 }
 
 // Carve the workspace (or count its size when A.dry).
-void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out out, Arena& A, Layout& L) {
+void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out out, Arena& A, Layout& L,
+          int nw = 0) {
     const bool store = out == Out::STORE;
+    const bool omg = out == Out::OMEGA;
     L.out = out;
     L.prec = (Prec)par->dtype;
     L.nbp = pow2_at_least(s->nb);
@@ -165,13 +171,13 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     // chunk size
     const size_t per_q = cb * ((size_t)ne * nm * nb * nb + np_) + bcol_bytes * nm * L.nbp * L.nbp +
                          (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm +
-                         pair_bytes_per_q(s, p);
+                         pair_bytes_per_q(s, p) + (omg ? 8 * (size_t)nk * nm * nb * (4 + L.nbp) : 0);
     long Q = par->chunk_q > 0 ? par->chunk_q : (long)(AUTO_CHUNK_BYTES / per_q);
     if (Q < 1) Q = 1;
     if (Q > nq) Q = nq > 0 ? nq : 1;
     L.Q = (int)Q;
     L.nchunks = nq > 0 ? (int)((nq + Q - 1) / Q) : 0;
-    L.S = store ? 0 : fused_slices(nk, L.nbp, tiles_n_for(L.Q, nm, L.nbp), SLICE_CUS);
+    L.S = (store || omg) ? 0 : fused_slices(nk, L.nbp, tiles_n_for(L.Q, nm, L.nbp), SLICE_CUS);
     L.eps = (double*)A.take(8 * (size_t)nk * nb);
     L.U = A.take(16 * (size_t)nk * nb * nb);
     L.ftab = (double*)A.take(8 * (size_t)nk * nb);
@@ -189,6 +195,20 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     L.tiles_m = (nk + fused_tile_rows(L.nbp) - 1) / fused_tile_rows(L.nbp);
     if (out == Out::IMSIGMA || out == Out::RESIGMA) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
     if (out == Out::RESIGMA) L.part2 = (double*)A.take(8 * (size_t)L.S * nk * nb);
+    if (omg) {
+        L.nw = nw;
+        // one record of padding: the frequency kernel reads one record ahead
+        L.rec = (double*)A.take(8 * ((size_t)nk * L.Q * nm * nb + 1) * (4 + L.nbp));
+        // slice count of the largest chunk bounds every chunk's
+        int smax = 1;
+        for (int qc : {L.Q, nq % L.Q}) {
+            if (qc <= 0) continue;
+            const int sw = sigma_omega_slices(nk, nw, (long)qc * nm * nb);
+            if (sw > smax) smax = sw;
+        }
+        L.Sw = smax;
+        L.spart = A.take(16 * (size_t)smax * nk * nb * ((size_t)nw + 1));
+    }
     if (out == Out::PHONON) {
         L.part_ph = (double*)A.take(8 * 2 * (size_t)L.tiles_m * L.Q * nm);
         L.dos_raw = (double*)A.take(8);
@@ -219,8 +239,10 @@ GemmDesc rp_desc(int qc, int ne, int np_, int ncol, const void* phi_q, const voi
 // goes to imsig.
 void run_forward(const epw_system* s, const epw_points* p, const epw_params* par, Layout& L,
                  double* imsig, void* gkq, hipStream_t st, double* pi_im = nullptr, double* lam = nullptr,
-                 double* re_tilde = nullptr) {
+                 double* re_tilde = nullptr, const double* wgrid = nullptr, void* sig_w = nullptr,
+                 void* sig0 = nullptr) {
     const bool phon = L.out == Out::PHONON;
+    const bool omg = L.out == Out::OMEGA;
     const bool re = L.out == Out::RESIGMA;     // imsig then receives Sigma' on shell
     const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
     const Prec prec = L.prec;
@@ -310,15 +332,26 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.sigma = par->sigma;
         a.mu = par->mu;
         a.part = L.part;
+        // (pole mode: the slices only spread the column tiles over blocks)
         a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp), SLICE_CUS);
         a.gkq = gkq;
         a.part_ph = phon ? L.part_ph : nullptr;
         a.part2 = re ? L.part2 : nullptr;
+        a.rec = omg ? L.rec : nullptr;
         {
             StageTimer t(EPW_STAGE_FUSED, st);
             launch_fused_k(prec, a, SLICE_CUS, st);
         }
-        if (phon) {
+        if (omg) {
+            const long npole = (long)qc * nm * nb;
+            const int sw = sigma_omega_slices(nk, L.nw, npole);
+            {
+                StageTimer t(EPW_STAGE_SPECTRAL, st);
+                launch_sigma_omega(nk, nb, npole, L.nw, wgrid, par->sigma, L.rec, sw, L.spart, st);
+            }
+            launch_sigma_omega_reduce(nk, nb, L.nw, sw, L.spart, L.eps, par->deg_tol, 1.0 / nqn,
+                                      (c > 0 || par->accumulate) ? 1 : 0, sig_w, sig0, st);
+        } else if (phon) {
             double* pi_c = pi_im + (size_t)q0 * nm;
             double* lam_c = lam ? lam + (size_t)q0 * nm : nullptr;
             launch_phonon_finalize(qc, nm, L.tiles_m, L.part_ph, om, par->omega_cut, L.dos_raw, nk, par->sigma,
@@ -335,7 +368,12 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
             launch_reduce_partials(nk, nb, a.S, L.part, scale, (c > 0 || par->accumulate) ? 1 : 0, imsig, st);
         }
     }
-    if (!gkq && !phon) {
+    if (omg) {
+        if (L.nchunks == 0 && !par->accumulate && nk > 0) {
+            launch_fill(2 * (size_t)nk * nb * L.nw, 0.0, (double*)sig_w, st);
+            launch_fill(2 * (size_t)nk * nb, 0.0, (double*)sig0, st);
+        }
+    } else if (!gkq && !phon) {
         if (L.nchunks == 0 && !par->accumulate && nk > 0) {
             launch_fill((size_t)nk * nb, 0.0, imsig, st);
             if (re_tilde) launch_fill((size_t)nk * nb, 0.0, re_tilde, st);
@@ -721,6 +759,78 @@ extern "C" int epw_imsigma(const epw_system* sys, const epw_points* pts, const e
         A.cap = ws_bytes;
         plan(sys, pts, par, Out::IMSIGMA, A, L);
         run_forward(sys, pts, par, L, imsig, nullptr, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" size_t epw_workspace_size_omega(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                                           int nw) {
+    clear_error();
+    if (!sys || !pts || !par) {
+        fail(EPW_EINVAL, "epw_workspace_size_omega: NULL argument");
+        return 0;
+    }
+    if (nw < 0 || nw > EPW_MAX_NW) {
+        fail(EPW_ESHAPE, "epw_workspace_size_omega: nw = %d not in 0..%d", nw, EPW_MAX_NW);
+        return 0;
+    }
+    epw_points p = *pts;
+    epw_system s = *sys;
+    static const int32_t dummy_i = 0;
+    static const double dummy_d = 0.0;
+    if (!p.kfrac) p.kfrac = &dummy_d;
+    if (!p.qfrac) p.qfrac = &dummy_d;
+    if (!s.Re) s.Re = &dummy_i;
+    if (!s.Rp) s.Rp = &dummy_i;
+    if (!s.ndeg_e) s.ndeg_e = &dummy_i;
+    if (!s.ndeg_p) s.ndeg_p = &dummy_i;
+    if (!s.HR) s.HR = &dummy_d;
+    if (!s.gR) s.gR = &dummy_d;
+    if (!s.DR && !(p.omega && p.evec)) s.DR = &dummy_d;
+    if (check_common(&s, &p, par, "epw_workspace_size_omega") != EPW_OK) return 0;
+    Arena A;
+    A.dry = true;
+    Layout L;
+    plan(&s, &p, par, Out::OMEGA, A, L, nw);
+    return A.used + 256;
+}
+
+extern "C" int epw_selfenergy_omega(const epw_system* sys, const epw_points* pts, const epw_params* par, int nw,
+                                    const double* wgrid, void* sigma_w, void* sigma0, void* ws, size_t ws_bytes,
+                                    void* stream) {
+    clear_error();
+    if (nw < 0 || nw > EPW_MAX_NW) return fail(EPW_ESHAPE, "epw_selfenergy_omega: nw = %d not in 0..%d", nw, EPW_MAX_NW);
+    int rc = check_common(sys, pts, par, "epw_selfenergy_omega");
+    if (rc != EPW_OK) return rc;
+    if (pts->nk == 0) return EPW_OK;
+    if (!sigma0 || (nw > 0 && (!sigma_w || !wgrid))) return fail(EPW_EINVAL, "epw_selfenergy_omega: NULL output or grid");
+    Arena dry;
+    dry.dry = true;
+    Layout L;
+    plan(sys, pts, par, Out::OMEGA, dry, L, nw);
+    if (!ws || ws_bytes < dry.used + 256)
+        return fail(EPW_ENOMEM, "epw_selfenergy_omega: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
+    return guarded("epw_selfenergy_omega", [&]() {
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        plan(sys, pts, par, Out::OMEGA, A, L, nw);
+        run_forward(sys, pts, par, L, nullptr, nullptr, (hipStream_t)stream, nullptr, nullptr, nullptr, wgrid,
+                    sigma_w, sigma0);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_spectral_function(int nk, int nb, int nw, const double* eps, double mu, const double* wgrid,
+                                     const void* sigma_w, const void* sigma0, double* A, void* stream) {
+    clear_error();
+    if (nk < 0 || nw < 0 || nb < 1 || nb > EPW_MAX_NB)
+        return fail(EPW_ESHAPE, "epw_spectral_function: nk = %d, nb = %d, nw = %d", nk, nb, nw);
+    if (!std::isfinite(mu)) return fail(EPW_EINVAL, "epw_spectral_function: mu not finite");
+    if (nk == 0 || nw == 0) return EPW_OK;
+    if (!eps || !wgrid || !sigma_w || !sigma0 || !A) return fail(EPW_EINVAL, "epw_spectral_function: NULL argument");
+    return guarded("epw_spectral_function", [&]() {
+        launch_spectral_function(nk, nb, nw, eps, mu, wgrid, sigma_w, sigma0, A, (hipStream_t)stream);
         return EPW_OK;
     });
 }

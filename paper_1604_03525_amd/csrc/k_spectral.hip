@@ -1,0 +1,227 @@
+// Frequency-resolved electron self-energy (Sec. 3 Eq. (3)) and the electronic
+// spectral function (Sec. 3 Eq. (10)).
+//
+// The fused kernel's pole mode leaves, per k and q chunk, one record per pole
+// family (q, nu, m):  {c1, c2, A1, A2, |g_mn|^2 for n < nb, zeros up to the
+// padded band count} with
+// c1 = xi_m - omega_q,nu, c2 = xi_m + omega_q,nu, A1 = n + f, A2 = n + 1 - f.
+// The braces of Eq. (3) do not depend on the band n at k, so one evaluation
+// of the two complex poles at a frequency serves every n:
+//
+//   Sigma_n(w) += |g_mn|^2 [A1 / (w - c1 + i d) + A2 / (w - c2 + i d)]
+//   1/(x + i d) = (x - i d) / (x^2 + d^2)
+//
+// One wave per (frequency tile of 64, k, pole slice): lane j owns frequency
+// j of the tile and all n; the records are read at wave-uniform addresses
+// (scalar loads), so the VALU does only the pole arithmetic.  Slices are
+// summed in fixed order by the reduction kernel, which also averages over
+// degenerate bands and accumulates the chunk into the output.
+#include <hip/hip_runtime.h>
+
+#include "epw_internal.h"
+#include "kernels.h"
+
+namespace epw {
+namespace {
+
+// 1/d for d > 0 of moderate range: the hardware reciprocal estimate refined by
+// two Newton-Raphson steps r <- r + r (1 - d r) (each step squares the
+// relative error), which reaches the rounding level of float64.
+__device__ __forceinline__ double recip_pos(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-d, r, 1.0);
+    return fma(r, e, r);
+}
+
+template <int NBT>
+__global__ __launch_bounds__(64) void sigma_omega_kernel(int nk, int nb, long npole, int nw, int nwt,
+                                                         const double* __restrict__ wgrid, double delta,
+                                                         const double* __restrict__ rec, int S,
+                                                         double2* __restrict__ part)
+{
+    constexpr int RS = 4 + NBT;                        // record: c1, c2, A1, A2, |g|^2 [NBT]
+    const int wt = blockIdx.x % nwt;
+    const int k = blockIdx.x / nwt;
+    const int s = blockIdx.y;
+    const int j = wt * 64 + threadIdx.x;               // frequency index; j == nw is omega = 0
+    const double w = j < nw ? wgrid[j] : 0.0;
+    const long p0 = npole * s / S, p1 = npole * (s + 1) / S;
+    const double d2 = delta * delta;
+    double are[NBT], aim[NBT];
+#pragma unroll
+    for (int n = 0; n < NBT; ++n) {
+        are[n] = 0.0;
+        aim[n] = 0.0;
+    }
+    // records at wave-uniform addresses, one record read ahead (the buffer
+    // holds one record of padding past the last)
+    const double* r = rec + ((size_t)k * npole + p0) * RS;
+    double cur[RS];
+#pragma unroll
+    for (int i = 0; i < RS; ++i) cur[i] = r[i];
+    for (long p = p0; p < p1; ++p) {
+        r += RS;
+        double nxt[RS];
+#pragma unroll
+        for (int i = 0; i < RS; ++i) nxt[i] = r[i];
+        const double x1 = w - cur[0], x2 = w - cur[1];
+        const double t1 = cur[2] * recip_pos(fma(x1, x1, d2));
+        const double t2 = cur[3] * recip_pos(fma(x2, x2, d2));
+        const double wre = fma(t1, x1, t2 * x2);       // real part of the braces
+        const double wim = t1 + t2;                    // imaginary part is -d wim
+#pragma unroll
+        for (int n = 0; n < NBT; ++n) {
+            are[n] = fma(cur[4 + n], wre, are[n]);
+            aim[n] = fma(cur[4 + n], wim, aim[n]);
+        }
+#pragma unroll
+        for (int i = 0; i < RS; ++i) cur[i] = nxt[i];
+    }
+    if (j > nw) return;
+    const size_t ld = (size_t)nw + 1;
+#pragma unroll
+    for (int n = 0; n < NBT; ++n) {
+        if (n >= nb) break;
+        part[(((size_t)s * nk + k) * nb + n) * ld + j] = make_double2(are[n], -delta * aim[n]);
+    }
+}
+
+// out[k][n][j] (+)= scale x (degenerate average over n of) sum_s part[s][k][n][j];
+// column j == nw goes to out0[k][n].
+template <int NBT>
+__global__ void sigma_omega_reduce_kernel(int nk, int nb, int nw, int S, const double2* __restrict__ part,
+                                          const double* __restrict__ eps, double tol, double scale, int acc,
+                                          double2* __restrict__ out, double2* __restrict__ out0)
+{
+    const size_t ld = (size_t)nw + 1;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nk * ld) return;
+    const int k = (int)(idx / ld), j = (int)(idx % ld);
+    double vr[NBT], vi[NBT];
+#pragma unroll
+    for (int n = 0; n < NBT; ++n) {
+        vr[n] = 0.0;
+        vi[n] = 0.0;
+        if (n >= nb) continue;
+        for (int s = 0; s < S; ++s) {
+            const double2 v = part[(((size_t)s * nk + k) * nb + n) * ld + j];
+            vr[n] += v.x;
+            vi[n] += v.y;
+        }
+        vr[n] *= scale;
+        vi[n] *= scale;
+    }
+    // average over runs of bands whose sorted energies differ by < tol
+    const double* e = eps + (size_t)k * nb;
+    int start = 0;
+    while (start < nb) {
+        int stop = start + 1;
+        while (stop < nb && fabs(e[stop] - e[stop - 1]) < tol) ++stop;
+        if (stop - start > 1) {
+            double tr = 0.0, ti = 0.0;
+#pragma unroll
+            for (int n = 0; n < NBT; ++n)
+                if (n >= start && n < stop) {
+                    tr += vr[n];
+                    ti += vi[n];
+                }
+            tr /= (double)(stop - start);
+            ti /= (double)(stop - start);
+#pragma unroll
+            for (int n = 0; n < NBT; ++n)
+                if (n >= start && n < stop) {
+                    vr[n] = tr;
+                    vi[n] = ti;
+                }
+        }
+        start = stop;
+    }
+#pragma unroll
+    for (int n = 0; n < NBT; ++n) {
+        if (n >= nb) break;
+        double2* o = j < nw ? out + ((size_t)k * nb + n) * nw + j : out0 + (size_t)k * nb + n;
+        double2 v = make_double2(vr[n], vi[n]);
+        if (acc) {
+            const double2 old = *o;
+            v.x += old.x;
+            v.y += old.y;
+        }
+        *o = v;
+    }
+}
+
+// Eq. (10) with Sigma~' of Eq. (5): A = (1/pi) |S''| / ((w - xi - S~')^2 + S''^2)
+__global__ void spectral_function_kernel(int nk, int nb, int nw, const double* __restrict__ eps, double mu,
+                                         const double* __restrict__ wgrid, const double2* __restrict__ sig,
+                                         const double2* __restrict__ sig0, double* __restrict__ A)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (size_t)nk * nb * nw) return;
+    const size_t kn = idx / nw;
+    const int j = (int)(idx % nw);
+    const double2 s = sig[idx];
+    const double im = fabs(s.y);
+    const double x = wgrid[j] - (eps[kn] - mu) - (s.x - sig0[kn].x);
+    A[idx] = im / (M_PI * (x * x + im * im));
+}
+
+}  // namespace
+
+int sigma_omega_slices(int nk, int nw, long npole) {
+    const long waves = (long)nk * ((nw + 1 + 63) / 64);
+    if (waves <= 0 || npole <= 0) return 1;
+    long S = (8192 + waves - 1) / waves;              // about 8 waves per SIMD
+    const long cap = npole / 64 > 0 ? npole / 64 : 1;  // at least 64 poles per wave
+    if (S > cap) S = cap;
+    if (S > 1024) S = 1024;
+    return S < 1 ? 1 : (int)S;
+}
+
+void launch_sigma_omega(int nk, int nb, long npole, int nw, const double* wgrid, double delta, const double* rec,
+                        int S, void* part, hipStream_t stream) {
+    if (nk == 0 || npole == 0) return;
+    const int nwt = (nw + 1 + 63) / 64;
+    const dim3 grid((unsigned)(nk * nwt), (unsigned)S);
+    double2* p = (double2*)part;
+    switch (pow2_at_least(nb)) {
+        case 1: sigma_omega_kernel<1><<<grid, 64, 0, stream>>>(nk, nb, npole, nw, nwt, wgrid, delta, rec, S, p); break;
+        case 2: sigma_omega_kernel<2><<<grid, 64, 0, stream>>>(nk, nb, npole, nw, nwt, wgrid, delta, rec, S, p); break;
+        case 4: sigma_omega_kernel<4><<<grid, 64, 0, stream>>>(nk, nb, npole, nw, nwt, wgrid, delta, rec, S, p); break;
+        case 8: sigma_omega_kernel<8><<<grid, 64, 0, stream>>>(nk, nb, npole, nw, nwt, wgrid, delta, rec, S, p); break;
+        case 16: sigma_omega_kernel<16><<<grid, 64, 0, stream>>>(nk, nb, npole, nw, nwt, wgrid, delta, rec, S, p); break;
+        default: break;
+    }
+    launch_check("sigma_omega_kernel");
+}
+
+void launch_sigma_omega_reduce(int nk, int nb, int nw, int S, const void* part, const double* eps, double tol,
+                               double scale, int acc, void* out, void* out0, hipStream_t stream) {
+    const size_t n = (size_t)nk * (nw + 1);
+    if (n == 0) return;
+    const unsigned blocks = (unsigned)((n + 127) / 128);
+    const double2* p = (const double2*)part;
+    double2* o = (double2*)out;
+    double2* o0 = (double2*)out0;
+    switch (pow2_at_least(nb)) {
+        case 1: sigma_omega_reduce_kernel<1><<<blocks, 128, 0, stream>>>(nk, nb, nw, S, p, eps, tol, scale, acc, o, o0); break;
+        case 2: sigma_omega_reduce_kernel<2><<<blocks, 128, 0, stream>>>(nk, nb, nw, S, p, eps, tol, scale, acc, o, o0); break;
+        case 4: sigma_omega_reduce_kernel<4><<<blocks, 128, 0, stream>>>(nk, nb, nw, S, p, eps, tol, scale, acc, o, o0); break;
+        case 8: sigma_omega_reduce_kernel<8><<<blocks, 128, 0, stream>>>(nk, nb, nw, S, p, eps, tol, scale, acc, o, o0); break;
+        case 16: sigma_omega_reduce_kernel<16><<<blocks, 128, 0, stream>>>(nk, nb, nw, S, p, eps, tol, scale, acc, o, o0); break;
+        default: break;
+    }
+    launch_check("sigma_omega_reduce_kernel");
+}
+
+void launch_spectral_function(int nk, int nb, int nw, const double* eps, double mu, const double* wgrid,
+                              const void* sig, const void* sig0, double* A, hipStream_t stream) {
+    const size_t n = (size_t)nk * nb * nw;
+    if (n == 0) return;
+    spectral_function_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(
+        nk, nb, nw, eps, mu, wgrid, (const double2*)sig, (const double2*)sig0, A);
+    launch_check("spectral_function_kernel");
+}
+
+}  // namespace epw

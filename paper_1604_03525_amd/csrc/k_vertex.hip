@@ -345,13 +345,18 @@ __device__ inline float2 cmulx(float2 a, float2 b) {
 // KIND 0: Im Sigma (Eq. (8)) partial sums per (k, n); 1: store g_mn,nu(k,q);
 // 2: the sums of the phonon linewidth (Eq. (9)) and of the coupling strength
 // (Eq. (11)) per (q, nu), reduced over the tile's k rows in fixed order;
-// 3: the real part of Eq. (3) per (k, n), on shell and at omega = eps_F.
+// 3: the real part of Eq. (3) per (k, n), on shell and at omega = eps_F;
+// 4: one pole record of 4 + NBP doubles per (k, q, nu, m) for the
+// frequency-resolved Eq. (3): {xi_m - omega, xi_m + omega, n + f, n + 1 - f,
+// |g_mn|^2 for n < nb, 0 up to NBP}, with xi_m = eps_m,k+q - mu (the records
+// of modes below omega_cut carry zero weights).
 template <int MODE, int NBP, int KIND, bool GEN>
 __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
 {
     constexpr bool STORE = KIND == 1;
     constexpr bool PH = KIND == 2;
     constexpr bool RE = KIND == 3;
+    constexpr bool POLE = KIND == 4;
     typedef typename ModeTypes<MODE>::T T;
     typedef typename ModeTypes<MODE>::CT CT;
     typedef typename ModeTypes<MODE>::TE TE;
@@ -599,7 +604,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 const int ql = (int)(gblk / nm), nu = (int)(gblk % nm);
                 if (ql >= a.qc) continue;
                 const double scv = a.sc[(size_t)ql * nm + nu];
-                if (scv == 0.0 && !STORE) continue;
+                if (scv == 0.0 && !STORE && !POLE) continue;
                 const int q = a.q0 + ql;
                 // states at k+q: a member of the k set (grid runs) or per pair
                 const double2* Uq;
@@ -607,7 +612,16 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 const double* fq;
                 if (a.kq) {
                     const int kq = a.kq[(size_t)k * a.nq_total + q];
-                    if ((unsigned)kq >= (unsigned)a.nk) continue;   // invalid map entry: no access
+                    if ((unsigned)kq >= (unsigned)a.nk) {           // invalid map entry: no access
+                        if constexpr (POLE) {
+                            for (int t = 0; t < RUN; ++t) {
+                                if (x0 + t >= nb) break;
+                                double* rec = a.rec + ((((size_t)k * a.qc + ql) * nm + nu) * nb + x0 + t) * (4 + NBP);
+                                for (int j = 0; j < 4 + NBP; ++j) rec[j] = 0.0;
+                            }
+                        }
+                        continue;
+                    }
                     Uq = U + (size_t)kq * nb * nb;
                     eq = a.eps + (size_t)kq * nb;
                     fq = a.ftab + (size_t)kq * nb;
@@ -645,7 +659,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     double epsn;
                     if constexpr (HOIST) epsn = eps_h[n]; else epsn = a.eps[(size_t)k * nb + n];
                     TE W[RUN], WL[RUN];
-                    bool need = STORE;
+                    bool need = STORE || POLE;
                     if constexpr (PH) {
                         // Eq. (9): [f_nk - f_m,k+q] exp(-((eps_nk - eps_m,k+q - omega)/sigma)^2);
                         // Eq. (11): exp(-((eps_nk - mu)/sigma)^2) exp(-((eps_m,k+q - mu)/sigma)^2)
@@ -684,7 +698,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                         for (int t = 0; t < RUN; ++t) {
                             W[t] = TE(0);
                             WL[t] = TE(0);
-                            if (STORE || !mv[t]) continue;
+                            if (STORE || POLE || !mv[t]) continue;
                             const double x = epsn - em[t];
                             const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
                             const double s1 = y1 * y1, s2 = y2 * y2;
@@ -727,6 +741,18 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                             const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
                             acc[n] += (double)(g2 * W[t]);
                             acc2[n] += (double)(g2 * WL[t]);
+                        } else if (POLE) {
+                            double* rec = a.rec + ((((size_t)k * a.qc + ql) * nm + nu) * nb + x0 + t) * (4 + NBP);
+                            rec[4 + n] = (double)(gr[t] * gr[t] + gi[t] * gi[t]);
+                            if (n == 0) {
+                                const double xi = em[t] - a.mu;
+                                const bool kept = scv != 0.0;
+                                rec[0] = xi - w;
+                                rec[1] = xi + w;
+                                rec[2] = kept ? nB + fm[t] : 0.0;
+                                rec[3] = kept ? nB + 1.0 - fm[t] : 0.0;
+                                for (int j = nb; j < NBP; ++j) rec[4 + j] = 0.0;   // padded bands
+                            }
                         } else {
                             acc[n] += (double)((gr[t] * gr[t] + gi[t] * gi[t]) * W[t]);
                         }
@@ -772,7 +798,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
         }
         __syncthreads();
     }
-    if constexpr (KIND == 1 || KIND == 2) return;
+    if constexpr (KIND == 1 || KIND == 2 || KIND == 4) return;
     // fixed-order reduction over the TPR threads of each row (real-part
     // mode: the on-shell sums, then the sums at eps_F)
     double* red = reinterpret_cast<double*>(smem);   // [BM][TPR][NBP]
@@ -989,6 +1015,7 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
             fused_k_kernel<MODE, NBP, K, false><<<grid, block, 0, stream>>>(a, tiles_m, tiles_n);
     };
     if (a.gkq) go(std::integral_constant<int, 1>());
+    else if (a.rec) go(std::integral_constant<int, 4>());
     else if (a.part_ph) go(std::integral_constant<int, 2>());
     else if (a.part2) go(std::integral_constant<int, 3>());
     else go(std::integral_constant<int, 0>());

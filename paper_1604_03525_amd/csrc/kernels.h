@@ -89,6 +89,7 @@ struct FusedArgs {
     double* part_ph;   // [2][tiles_m][qc*nm] per-row-tile sums (phonon mode): Eq. (9), Eq. (11)
     double* part2;     // [S][nk][nb] second partials (real-part mode: Sigma' at omega = 0; part
                        // then holds Sigma' on shell)
+    double* rec;       // [nk][qc][nm][nb] pole records of 4 + nbp doubles (pole mode)
 };
 // a7 + a8 + a9 (imsigma mode), a7 + a8 (store mode, gkq != nullptr),
 // a7 + a8 + the phonon-linewidth sums (phonon mode, part_ph != nullptr), or
@@ -189,6 +190,17 @@ void launch_reduce_partials(int nk, int nb, int S, const double* part, double sc
 void launch_reduce_partials_diff(int nk, int nb, int S, const double* A, const double* B, double scale,
                                  int accumulate, double* out, hipStream_t stream);
 // average over bands whose consecutive energies differ by < tol
+// Frequency-resolved Eq. (3) from pole records (k_spectral.hip): slices of
+// the pole list per (k, frequency tile), their fixed-order reduction (with the
+// degenerate average, scaled, accumulated into out [nk][nb][nw] c128 and, for
+// omega = 0, out0 [nk][nb] c128), and Eq. (10).
+int sigma_omega_slices(int nk, int nw, long npole);
+void launch_sigma_omega(int nk, int nb, long npole, int nw, const double* wgrid, double delta, const double* rec,
+                        int S, void* part, hipStream_t stream);
+void launch_sigma_omega_reduce(int nk, int nb, int nw, int S, const void* part, const double* eps, double tol,
+                               double scale, int acc, void* out, void* out0, hipStream_t stream);
+void launch_spectral_function(int nk, int nb, int nw, const double* eps, double mu, const double* wgrid,
+                              const void* sig, const void* sig0, double* A, hipStream_t stream);
 void launch_degenerate_average(int nk, int nb, const double* eps, double tol, double* v,
                                hipStream_t stream);
 

@@ -226,6 +226,53 @@ def epw_resigma(system, points, params, want_tilde=True, workspace=None):
     return shell, tilde
 
 
+def epw_selfenergy_omega(system, points, params, wgrid, out=None, out0=None, workspace=None):
+    """(Sigma_nk(omega) [nk][nb][nw] complex128, Sigma_nk(0) [nk][nb]
+    complex128): the complex self-energy of Sec. 3 Eq. (3) at the frequencies
+    wgrid (eV from eps_F), delta = params.sigma."""
+    lib = _lib.load()
+    ws = workspace or Workspace(system.device)
+    d = system.device
+    w = _dev(wgrid, torch.float64, d).contiguous()
+    nw = w.shape[0]
+    s, p = system.c_struct(), points.c_struct()
+    nbytes = lib.epw_workspace_size_omega(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), nw)
+    if nbytes == 0:
+        msg = lib.epw_last_error()
+        raise EpwError(_lib.EPW_EINVAL, msg.decode() if msg else "")
+    buf = ws.get(nbytes)
+    nk, nb = points.k.shape[0], system.nb
+    if out is None:
+        out = torch.empty((nk, nb, nw), dtype=torch.complex128, device=d)
+    if out0 is None:
+        out0 = torch.empty((nk, nb), dtype=torch.complex128, device=d)
+    _lib.check(lib.epw_selfenergy_omega(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), nw, _ptr(w),
+                                        _ptr(out), _ptr(out0), _ptr(buf), buf.numel(), _stream(d)))
+    return out, out0
+
+
+def epw_spectral_function(eps, mu, wgrid, sigma_w, sigma0):
+    """A_nk(omega) [nk][nb][nw] float64 of Sec. 3 Eq. (10) from the output of
+    epw_selfenergy_omega and the band energies eps [nk][nb] at the k points."""
+    lib = _lib.load()
+    d = sigma_w.device
+    eps = _dev(eps, torch.float64, d).contiguous()
+    w = _dev(wgrid, torch.float64, d).contiguous()
+    nk, nb, nw = sigma_w.shape
+    A = torch.empty((nk, nb, nw), dtype=torch.float64, device=d)
+    _lib.check(lib.epw_spectral_function(nk, nb, nw, _ptr(eps), float(mu), _ptr(w), _ptr(sigma_w.contiguous()),
+                                         _ptr(sigma0.contiguous()), _ptr(A), _stream(d)))
+    return A
+
+
+def spectral_function(system, points, params, wgrid, workspace=None):
+    """(A [nk][nb][nw], Sigma(omega), Sigma(0), eps_k): Eq. (3) on the grid,
+    then Eq. (10) with the band energies at the k points."""
+    sig, sig0 = epw_selfenergy_omega(system, points, params, wgrid, workspace=workspace)
+    eps, _ = epw_interp_bands(system.HR, system.Re, system.ndeg_e, points.k)
+    return epw_spectral_function(eps, params.mu, wgrid, sig, sig0), sig, sig0, eps
+
+
 def epw_phonon_selfenergy(system, points, params, want_lambda=True, workspace=None):
     """(Pi''_q,nu [nq][nm], lambda_q,nu [nq][nm] or None) float64: the phonon
     linewidth of Sec. 3 Eq. (9) on shell and the coupling strength of

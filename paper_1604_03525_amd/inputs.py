@@ -242,6 +242,22 @@ def realistic_model():
                  mu=C2_MU, sigma=0.02)
 
 
+def line_points(a, b, n):
+    """n fractional points from a to b inclusive (a band-structure path)."""
+    t = np.linspace(0.0, 1.0, n)[:, None]
+    return (1.0 - t) * np.asarray(a, dtype=np.float64)[None, :] + t * np.asarray(b, dtype=np.float64)[None, :]
+
+
+def spectral_workload(nq=100000):
+    """The frequency-resolved self-energy and spectral-function workload on
+    the realistic system: 64 k points on the line Gamma -> X = (0, 1/2, 1/2)
+    (two bands cross eps_F on it), nq uniform random q (seed 7; spectral
+    functions are integrated on random q sets, Sec. 10.1), 512 frequencies on
+    [-1, 1] eV from eps_F; T, mu and delta = sigma as the realistic model."""
+    return {"k": line_points((0.0, 0.0, 0.0), (0.0, 0.5, 0.5), 64), "q": random_points(nq, 7),
+            "wgrid": np.linspace(-1.0, 1.0, 512)}
+
+
 def mobility_model():
     """The mobility-scale system: fcc, 3 atoms, 16 bands, 9 modes, coarse
     8^3 (617 WS vectors), 8000 k in a 0.3 eV window above the conduction

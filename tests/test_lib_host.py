@@ -167,3 +167,49 @@ def test_resigma_argument_errors():
     im = lib.epw_workspace_size(_lib.EPW_WS_IMSIGMA, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
     re = lib.epw_workspace_size(_lib.EPW_WS_RESIGMA, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
     assert re >= im + 8 * 27 * 3
+
+
+def test_selfenergy_omega_argument_errors_and_workspace():
+    """The frequency-grid call rejects a negative or oversized grid and NULL
+    outputs before any device work, takes an empty k set as a no-op, and its
+    workspace grows with the number of frequencies; the spectral function
+    rejects bad shapes and NULL pointers and accepts empty sets."""
+    lib = _lib.load()
+    par = epw.make_params()
+    s, p = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=27, nq=8)
+    dummy = (ctypes.c_double * 2)()
+    for nw in (-1, (1 << 20) + 1):
+        assert lib.epw_selfenergy_omega(ctypes.byref(s), ctypes.byref(p), ctypes.byref(par), nw, dummy, dummy,
+                                        dummy, None, 0, None) == _lib.EPW_ESHAPE
+        assert lib.epw_workspace_size_omega(ctypes.byref(s), ctypes.byref(p), ctypes.byref(par), nw) == 0
+    # every system and point pointer set (never dereferenced: the checks fail first)
+    host = (ctypes.c_double * 64)()
+    hp = ctypes.cast(host, ctypes.c_void_p)
+    sf = _lib.EpwSystem(3, 6, 19, 19, hp, hp, hp, hp, hp, hp, hp)
+    pf = _lib.EpwPoints(27, 8, hp, hp, None, None, None)
+    assert lib.epw_selfenergy_omega(ctypes.byref(sf), ctypes.byref(pf), ctypes.byref(par), 4, dummy, None, dummy,
+                                    None, 0, None) == _lib.EPW_EINVAL
+    assert lib.epw_selfenergy_omega(ctypes.byref(sf), ctypes.byref(pf), ctypes.byref(par), 4, dummy, dummy, None,
+                                    None, 0, None) == _lib.EPW_EINVAL
+    assert lib.epw_selfenergy_omega(ctypes.byref(sf), ctypes.byref(pf), ctypes.byref(par), 4, None, dummy, dummy,
+                                    None, 0, None) == _lib.EPW_EINVAL
+    assert lib.epw_selfenergy_omega(ctypes.byref(sf), ctypes.byref(pf), ctypes.byref(par), 4, dummy, dummy, dummy,
+                                    None, 0, None) == _lib.EPW_ENOMEM
+    s0, p0 = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=0, nq=8)
+    assert lib.epw_selfenergy_omega(ctypes.byref(s0), ctypes.byref(p0), ctypes.byref(par), 4, None, None, None,
+                                    None, 0, None) == _lib.EPW_OK
+    a = lib.epw_workspace_size_omega(ctypes.byref(s), ctypes.byref(p), ctypes.byref(par), 1)
+    b = lib.epw_workspace_size_omega(ctypes.byref(s), ctypes.byref(p), ctypes.byref(par), 1000)
+    im = lib.epw_workspace_size(_lib.EPW_WS_IMSIGMA, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
+    assert b > a > 0
+    # the pole records of one chunk: nk x Q x nm x nb records of 4 + 4 doubles
+    assert a >= 8 * 27 * 8 * 6 * 3 * 8
+    assert a > 0 and im > 0
+    assert lib.epw_spectral_function(3, 0, 4, dummy, ctypes.c_double(0.0), dummy, dummy, dummy, dummy,
+                                     None) == _lib.EPW_ESHAPE
+    assert lib.epw_spectral_function(3, 2, 4, None, ctypes.c_double(0.0), dummy, dummy, dummy, dummy,
+                                     None) == _lib.EPW_EINVAL
+    assert lib.epw_spectral_function(3, 2, 4, dummy, ctypes.c_double(float("nan")), dummy, dummy, dummy, dummy,
+                                     None) == _lib.EPW_EINVAL
+    assert lib.epw_spectral_function(0, 2, 4, None, ctypes.c_double(0.0), None, None, None, None,
+                                     None) == _lib.EPW_OK
