@@ -25,6 +25,8 @@ realpart    On-shell real part of the electron self-energy (Sec. 3 Eq. (3))
             and its Fermi-level-referenced form (Sec. 3 Eq. (5)).
 spectral    Complex Sigma_nk(omega) of Sec. 3 Eq. (3) on a frequency grid
             and the spectral function A_nk(omega) of Sec. 3 Eq. (10).
+polar       Long-range (polar) vertex g^L of Sec. 4 added to the
+            interpolated short-range vertex.
 torch_ref   The same forward in plain torch CPU float64, differentiated by
             autograd: the reference gradient for the hand-written adjoint.
 

@@ -242,6 +242,24 @@ def realistic_model():
                  mu=C2_MU, sigma=0.02)
 
 
+def polar_params(seed=30, z=2.0, eps=5.5, prefactor=0.5, alpha=10.0, cutoff=50.0):
+    """Synthetic polar data for the two-atom fcc models (zincblende-like,
+    atoms at ATOMS_FCC2, unit masses as the spring dynamical matrices): Born
+    charges Z*_1 = z I + a random symmetric part (entries U(-0.2, 0.2)) and a
+    random antisymmetric part (U(-0.1, 0.1)), Z*_2 = -Z*_1 (charge
+    neutrality); eps_inf = eps I + a random symmetric part (U(-0.3, 0.3));
+    the overall factor C, the Gaussian parameter alpha and the cutoff of the
+    G sum."""
+    rng = np.random.default_rng(seed)
+    s = rng.uniform(-0.2, 0.2, (3, 3))
+    a = rng.uniform(-0.1, 0.1, (3, 3))
+    z1 = z * np.eye(3) + 0.5 * (s + s.T) + 0.5 * (a - a.T)
+    e = rng.uniform(-0.3, 0.3, (3, 3))
+    return {"vectors": FCC_VECTORS.copy(), "tau": ATOMS_FCC2.copy(), "zstar": np.stack([z1, -z1]),
+            "eps_inf": eps * np.eye(3) + 0.5 * (e + e.T), "masses": np.ones(2), "prefactor": prefactor,
+            "alpha": alpha, "cutoff": cutoff}
+
+
 def line_points(a, b, n):
     """n fractional points from a to b inclusive (a band-structure path)."""
     t = np.linspace(0.0, 1.0, n)[:, None]

@@ -1,0 +1,140 @@
+"""Pins for the oracle's long-range (polar) vertex (Sec. 4)."""
+import numpy as np
+
+from oracle import interp, lattice, polar
+from oracle.selfenergy import imsigma
+from paper_1604_03525_amd import inputs as I
+
+
+def _fcc2(seed=1):
+    """Two-atom fcc springs on a 3^3 coarse set (every bond inside it, so the
+    acoustic sum rule holds and the acoustic modes vanish at Gamma)."""
+    R, nd = lattice.ws_vectors(I.FCC_METRIC, (3, 3, 3))
+    DR = I.spring_dynmat(R, I.FCC_VECTORS, I.ATOMS_FCC2, shells=2, seed=seed, scale=4e-4)
+    return R, nd, DR
+
+
+def test_reciprocal_vectors():
+    B = polar.reciprocal_vectors(I.FCC_VECTORS)
+    assert np.allclose(I.FCC_VECTORS @ B.T, 2 * np.pi * np.eye(3), atol=1e-13)
+
+
+def test_small_q_optical_closed_form():
+    """Isotropic Z*_1 = -Z*_2 = Z I, eps_inf = eps I, unit masses, alpha so
+    small that only G = 0 survives the cutoff: near Gamma the optical triplet
+    is (u, -u)/sqrt(2) and
+      |q|^2 sum_optical 2 omega_nu |L_nu(q)|^2 -> 2 C^2 Z^2 / eps^2
+    (the 1/|q| divergence of the longitudinal coupling), independent of the
+    choice of eigenvectors inside the triplet."""
+    R, nd, DR = _fcc2()
+    Z, eps, C = 1.7, 4.0, 0.05
+    par = dict(vectors=I.FCC_VECTORS, tau=I.ATOMS_FCC2, zstar=np.stack([Z * np.eye(3), -Z * np.eye(3)]),
+               eps_inf=eps * np.eye(3), masses=np.ones(2), prefactor=C, alpha=0.5, cutoff=50.0)
+    for d in ([1.0, 0.0, 0.0], [0.3, -0.2, 0.5]):
+        q = 1e-5 * np.array([d])
+        om, ev = interp.phonons(DR, R, nd, q)
+        L = polar.long_range_factor(q, om, ev, **par)
+        opt = om[0] > 0.5 * om[0].max()
+        assert opt.sum() == 3
+        qc = q @ polar.reciprocal_vectors(I.FCC_VECTORS)
+        val = float(np.sum(qc * qc)) * np.sum(2 * om[0, opt] * np.abs(L[0, opt]) ** 2)
+        assert abs(val / (2 * C ** 2 * Z ** 2 / eps ** 2) - 1) < 1e-3
+        # acoustic modes are below omega_cut here, or carry no net dipole
+        assert np.all(np.abs(L[0, ~opt]) < 1e-3 * np.abs(L[0, opt]).max())
+
+
+def test_single_term_tensor_order():
+    """With alpha small enough for the G = 0 term alone, identity modes
+    (nu = (kappa, b), omega = 1) and a Born charge with only Z_xy set,
+    L_(kappa,b)(q) = i C / sqrt(2) exp(-q.eps.q / 4 alpha) / (q.eps.q)
+    (q . Z_kappa)_b exp(-i q . tau_kappa): for q along x only b = y is
+    nonzero (the transposed tensor would give b = x)."""
+    zs = np.zeros((2, 3, 3))
+    zs[0, 0, 1] = 1.3
+    zs[1] = -zs[0]
+    eps = np.diag([3.0, 4.0, 5.0])
+    C = 0.2
+    par = dict(vectors=I.FCC_VECTORS, tau=I.ATOMS_FCC2, zstar=zs, eps_inf=eps, masses=np.ones(2),
+               prefactor=C, alpha=0.3, cutoff=40.0)
+    B = polar.reciprocal_vectors(I.FCC_VECTORS)
+    qc = np.array([0.37, 0.0, 0.0])
+    qf = qc @ np.linalg.inv(B)
+    L = polar.long_range_factor(qf[None, :], np.ones((1, 6)), np.eye(6)[None].astype(complex), **par)[0]
+    x = 3.0 * 0.37 ** 2
+    f = np.exp(-x / (4 * 0.3)) / x
+    want = np.zeros(6, dtype=complex)
+    want[1] = 1j * C / np.sqrt(2) * f * 0.37 * 1.3
+    want[4] = 1j * C / np.sqrt(2) * f * 0.37 * (-1.3) * np.exp(-1j * 0.37 * 0.25)
+    assert np.max(np.abs(L - want)) < 1e-14 * np.abs(want).max()
+
+
+def test_box_and_cutoff_complete():
+    """The G box holds every term inside the cutoff (a larger box adds
+    nothing), and the Gaussian makes the dropped tail negligible (a larger
+    cutoff changes L below 1e-15 relative)."""
+    R, nd, DR = _fcc2()
+    par = I.polar_params()
+    q = I.random_points(5, 9)
+    om, ev = interp.phonons(DR, R, nd, q)
+    L = polar.long_range_factor(q, om, ev, **par)
+    g = polar._gmax(par["vectors"], par["eps_inf"], par["alpha"], par["cutoff"])
+    Lbig = polar.long_range_factor(q, om, ev, gmax=g + 3, **par)
+    assert np.max(np.abs(L - Lbig)) < 1e-14 * np.abs(L).max()
+    par2 = dict(par, cutoff=80.0)
+    L2 = polar.long_range_factor(q, om, ev, **par2)
+    assert np.max(np.abs(L - L2)) < 1e-15 * np.abs(L).max()
+    # several G shells contribute at these parameters
+    par3 = dict(par, alpha=0.5)
+    L3 = polar.long_range_factor(q, om, ev, **par3)
+    assert np.max(np.abs(L - L3)) > 1e-3 * np.abs(L).max()
+
+
+def test_time_reversal_and_periodicity():
+    """Real D(R): e(-q) = conj(e(q)) gives L(-q) = conj(L(q)); the sum over
+    all G makes L periodic: L(q + G0) = L(q) with the same modes."""
+    R, nd, DR = _fcc2()
+    par = I.polar_params()
+    q = I.random_points(4, 11)
+    om, ev = interp.phonons(DR, R, nd, q)
+    L = polar.long_range_factor(q, om, ev, **par)
+    Lm = polar.long_range_factor(-q, om, np.conj(ev), **par)
+    assert np.max(np.abs(Lm - np.conj(L))) < 1e-13 * np.abs(L).max()
+    Lp = polar.long_range_factor(q + np.array([1.0, -2.0, 3.0]), om, ev, **par)
+    assert np.max(np.abs(Lp - L)) < 1e-13 * np.abs(L).max()
+
+
+def test_mass_scaling_and_mode_cut():
+    """L scales as M^(-1/2) when every mass is scaled, and vanishes for
+    modes below omega_cut."""
+    R, nd, DR = _fcc2()
+    par = I.polar_params()
+    q = np.vstack([I.random_points(3, 12), np.zeros((1, 3))])
+    om, ev = interp.phonons(DR, R, nd, q)
+    L = polar.long_range_factor(q, om, ev, **par)
+    L4 = polar.long_range_factor(q, om, ev, **dict(par, masses=4.0 * par["masses"]))
+    assert np.max(np.abs(L4 - 0.5 * L)) < 1e-14 * np.abs(L).max()
+    assert np.all(L[3, om[3] < 1e-3] == 0)
+
+
+def test_vertex_overlap_at_lattice_translation_and_zero_field():
+    """At q = G0 the k+q states are those of k, the overlap is the identity
+    and g^L_mn = L delta_mn; with zero Born charges the vertex is the
+    short-range one and Im Sigma equals the plain oracle's."""
+    R, nd = lattice.ws_vectors(I.FCC_METRIC, (3, 3, 3))
+    HR = I.random_hamiltonian(R, I.FCC_VECTORS, 3, seed=4, scale=0.8)
+    DR = I.spring_dynmat(R, I.FCC_VECTORS, I.ATOMS_FCC2, shells=2, seed=5, scale=4e-4)
+    gR = I.random_vertex(R, R, I.FCC_VECTORS, 6, 3, seed=6, g0=0.05)
+    par = I.polar_params()
+    k = np.array([0.1, 0.2, -0.3])
+    g0 = np.zeros((1, 3)) + np.array([[1.0, 0.0, 0.0]])
+    g, _, _, om = polar.vertex_band(HR, R, nd, DR, R, nd, gR, k, g0, par)
+    gS, _, _, _ = polar.vertex_band(HR, R, nd, DR, R, nd, gR, k, g0, dict(par, zstar=0 * par["zstar"]))
+    L = polar.long_range_factor(g0, om, interp.phonons(DR, R, nd, g0)[1], **par)
+    want = gS + L[:, :, None, None] * np.eye(3)[None, None]
+    assert np.max(np.abs(g - want)) < 1e-12 * np.abs(g).max()
+    kk = lattice.grid_points(3, 3, 3)
+    a = polar.imsigma(HR, R, nd, DR, R, nd, gR, kk, kk, 300.0, 0.1, 0.15, dict(par, zstar=0 * par["zstar"]))
+    b = imsigma(HR, R, nd, DR, R, nd, gR, kk, kk, 300.0, 0.1, 0.15)
+    assert np.max(np.abs(a - b)) < 1e-13 * np.abs(b).max()
+    c = polar.imsigma(HR, R, nd, DR, R, nd, gR, kk, kk, 300.0, 0.1, 0.15, par)
+    assert np.max(np.abs(c - b)) > 3e-4 * np.abs(b).max()
