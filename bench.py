@@ -242,8 +242,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32,phonon,resigma,spectral",
-                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, resigma, spectral, "
+    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32,phonon,resigma,polar,spectral",
+                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, resigma, polar, spectral, "
                          "mobility (the last is "
                          "opt-in: one 4096-q shard of the mobility-scale system, ~2 min)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -338,6 +338,19 @@ def main():
                 variants[var] = {"value": pairs * args.steps / dtr, "ms_per_step": 1e3 * dtr / args.steps,
                                  "dtype": "fp64", "outputs": "Sigma'_nk on shell (Eq. 3) and Sigma~'_nk (Eq. 5)",
                                  "fused_tflops": achr, "fused_frac_of_peak": achr / PEAK_TFLOPS["fp64"] if achr else None}
+            elif var == "polar":
+                log("bench: fp64 forward with the polar long-range term")
+                from paper_1604_03525_amd import inputs as I
+                R_, nd_, HR_, DR_, gR_, _ = host
+                sysp = epw.System(R_, nd_, R_, nd_, HR_, DR_, gR_, dev, polar=I.polar_params())
+                par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
+                outp = torch.empty((nk, nb), dtype=torch.float64, device=dev)
+                dtq, stq = timed(lambda: epw.epw_imsigma(sysp, pts, par, out=outp, workspace=ws), args.steps,
+                                 args.warmup, torch)
+                variants[var] = {"value": pairs * args.steps / dtq, "ms_per_step": 1e3 * dtq / args.steps,
+                                 "dtype": "fp64", "outputs": "Im Sigma_nk with g = g^S + g^L (Sec. 4)",
+                                 "stages_ms_per_step": {s_: v[0] / args.steps for s_, v in stq.items()}}
+                del sysp
             elif var == "spectral":
                 variants[var] = spectral_run(sysd, model, dev, args.steps, args.warmup, torch)
             elif var == "mobility":

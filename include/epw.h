@@ -59,6 +59,8 @@ extern "C" {
 #define EPW_MAX_NB  16      /* Wannier bands                                        */
 #define EPW_MAX_NM  16      /* phonon modes (3 x atoms)                             */
 #define EPW_MAX_NW  (1 << 20) /* frequencies of epw_selfenergy_omega                  */
+#define EPW_MAX_ATOMS 5     /* atoms of the polar long-range term (3 x 5 <= 16)   */
+#define EPW_MAX_GMAX  24    /* half-width of the G box of the polar term          */
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* epw_last_error(void);
@@ -127,6 +129,32 @@ int epw_interp_phonons(int nm, int nR, const int32_t* R, const int32_t* ndeg,
                        const double* DR, int nq, const double* qfrac,
                        double* omega, void* evec, void* stream);
 
+/* Long-range (polar) part of the vertex, Sec. 4:
+ *   g_mn,nu(k,q) = g^S_mn,nu(k,q) + L_nu(q) [U_k+q^dagger U_k]_mn
+ *   L_nu(q) = i C sum_kappa (2 M_kappa omega_q,nu)^(-1/2) sum_{G, K = q+G != 0}
+ *             exp(-K.eps.K/(4 alpha)) / (K.eps.K) (K . Z*_kappa . e_kappa,nu(q))
+ *             exp(-i K . tau_kappa)
+ * (the overlap in the small-(q+G) form of Sec. 4; the Gaussian damping, the
+ * atomic phase and the overall factor C = 4 pi e^2 / Omega are those of the
+ * method the paper cites, absent from its printed equation).  The
+ * interpolated g(R_e,R_p) is then the short-range part g^S.  Host struct,
+ * copied into the kernel arguments; all vectors Cartesian in one length unit
+ * (K in the inverse unit, 2 pi included). */
+typedef struct {
+    int32_t nat;                          /* atoms, 3 nat = nm, 1..EPW_MAX_ATOMS  */
+    int32_t reserved;
+    double vectors[3][3];                 /* primitive lattice vectors a_i (rows) */
+    double tau[EPW_MAX_ATOMS][3];         /* atomic positions in the cell         */
+    double zstar[EPW_MAX_ATOMS][3][3];    /* Born charges Z*_kappa[a][b]: K_a Z_ab e_b */
+    double eps_inf[3][3];                 /* dielectric tensor (symmetric, > 0)   */
+    double mass[EPW_MAX_ATOMS];           /* M_kappa (> 0), the mass unit of D    */
+    double prefactor;                     /* C                                    */
+    double alpha;                         /* Gaussian parameter (> 0)             */
+    double cutoff;                        /* keep terms with K.eps.K/(4 alpha) <
+                                             cutoff (> 0); the G box this needs
+                                             must fit EPW_MAX_GMAX               */
+} epw_polar;
+
 /* Real-space system shared by the vertex and self-energy calls. */
 typedef struct {
     int32_t nb;            /* Wannier bands (1..EPW_MAX_NB)                      */
@@ -149,6 +177,9 @@ typedef struct {
                               streamed from a table; 0 = use the table.  A value
                               smaller than the true maximum gives wrong results. */
     int32_t reserved;
+    const epw_polar* polar;  /* optional long-range term, NULL = none.  Used by
+                              every forward call; epw_imsigma_backward refuses
+                              it (EPW_EINVAL).                                  */
 } epw_system;
 
 #define EPW_MAX_NMAX 8

@@ -95,10 +95,12 @@ def long_range_factor(qpoints, omega, evec, vectors, tau, zstar, eps_inf, masses
     return out
 
 
-def vertex_band(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, k, qpoints, polar, omega_cut=1e-3, phonon_states=None):
+def vertex_band(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, k, qpoints, polar, omega_cut=1e-3, phonon_states=None,
+                lr=None):
     """(g [Q][nu][m][n] = g^S + g^L for ONE k and all q, eps_k [nb], eps_kq [Q][nb],
     omega [Q][nm]).  polar: dict(vectors, tau, zstar, eps_inf, masses,
-    prefactor, alpha, cutoff)."""
+    prefactor, alpha, cutoff); lr, when given, is L_nu(q) for these q
+    (it does not depend on k)."""
     k = np.asarray(k, dtype=np.float64)
     qpoints = np.asarray(qpoints, dtype=np.float64)
     eps_k, U_k = interp.bands(HR, Re, ndeg_e, k[None, :])
@@ -109,22 +111,26 @@ def vertex_band(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, k, qpoints, polar, omega_cut
         omega, evec = phonon_states
     gw = interp.vertex_wannier(gR, Re, ndeg_e, Rp, ndeg_p, k, qpoints)
     gS = interp.rotate(gw, U_k[0], U_kq, evec, omega, omega_cut)
-    L = long_range_factor(qpoints, omega, evec, omega_cut=omega_cut, **polar)
+    L = long_range_factor(qpoints, omega, evec, omega_cut=omega_cut, **polar) if lr is None else lr
     ov = np.einsum("qim,in->qmn", np.conj(U_kq), U_k[0])          # [U_k+q^dag U_k]_mn
     return gS + L[:, :, None, None] * ov[:, None, :, :], eps_k[0], eps_kq, omega
 
 
 def imsigma(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, kpoints, qpoints, T, mu, sigma, polar,
             omega_cut=1e-3, deg_tol=1e-6, nq_norm=None):
-    """Im Sigma_nk of Sec. 3 Eq. (8) with the polar vertex g^S + g^L."""
+    """Im Sigma_nk of Sec. 3 Eq. (8) with the polar vertex g^S + g^L (the
+    phonons and L_nu(q) are evaluated once for all k)."""
     from .selfenergy import degenerate_average, imsigma_from_states
     kpoints = np.asarray(kpoints, dtype=np.float64)
     qpoints = np.asarray(qpoints, dtype=np.float64)
     if nq_norm is None:
         nq_norm = len(qpoints)
     eps_all, _ = interp.bands(HR, Re, ndeg_e, kpoints)
+    ph = interp.phonons(DR, Rp, ndeg_p, qpoints)
+    L = long_range_factor(qpoints, ph[0], ph[1], omega_cut=omega_cut, **polar)
     out = np.zeros(eps_all.shape)
     for ik, k in enumerate(kpoints):
-        g, ek, ekq, om = vertex_band(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, k, qpoints, polar, omega_cut)
+        g, ek, ekq, om = vertex_band(HR, Re, ndeg_e, DR, Rp, ndeg_p, gR, k, qpoints, polar, omega_cut,
+                                     phonon_states=ph, lr=L)
         out[ik] = imsigma_from_states(g, ek, ekq, om, mu, T, sigma, nq_norm, omega_cut)
     return degenerate_average(eps_all, out, deg_tol)

@@ -35,6 +35,7 @@ EPW_STAGE_SPECTRAL = 5
 EPW_MAX_NB = 16
 EPW_MAX_NM = 16
 EPW_MAX_NMAX = 8
+EPW_MAX_ATOMS = 5
 
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -47,7 +48,15 @@ class EpwSystem(ctypes.Structure):
                 ("nRe", ctypes.c_int32), ("nRp", ctypes.c_int32),
                 ("Re", _vp), ("ndeg_e", _vp), ("Rp", _vp), ("ndeg_p", _vp),
                 ("HR", _vp), ("DR", _vp), ("gR", _vp), ("nmax_e", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("reserved", ctypes.c_int32), ("polar", _vp)]
+
+
+class EpwPolar(ctypes.Structure):
+    _fields_ = [("nat", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("vectors", ctypes.c_double * 9), ("tau", ctypes.c_double * 15),
+                ("zstar", ctypes.c_double * 45), ("eps_inf", ctypes.c_double * 9),
+                ("mass", ctypes.c_double * 5), ("prefactor", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("cutoff", ctypes.c_double)]
 
 
 class EpwPoints(ctypes.Structure):

@@ -18,6 +18,91 @@ constexpr size_t AUTO_CHUNK_BYTES = (size_t)4 << 30;
 
 size_t cbytes(Prec p) { return p == Prec::F64 ? 16 : 8; }
 
+// Smallest eigenvalue of a symmetric 3 x 3 matrix (cyclic Jacobi).
+double sym3_min_eig(const double (&m)[3][3]) {
+    double a[3][3];
+    std::memcpy(a, m, sizeof(a));
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        double off = std::fabs(a[0][1]) + std::fabs(a[0][2]) + std::fabs(a[1][2]);
+        if (off < 1e-300) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (a[p][q] == 0.0) continue;
+                const double th = 0.5 * std::atan2(2.0 * a[p][q], a[q][q] - a[p][p]);
+                const double c = std::cos(th), sn = std::sin(th);
+                for (int k = 0; k < 3; ++k) {           // A <- A J
+                    const double x = a[k][p], y = a[k][q];
+                    a[k][p] = c * x - sn * y;
+                    a[k][q] = sn * x + c * y;
+                }
+                for (int k = 0; k < 3; ++k) {           // A <- J^T A
+                    const double x = a[p][k], y = a[q][k];
+                    a[p][k] = c * x - sn * y;
+                    a[q][k] = sn * x + c * y;
+                }
+            }
+    }
+    return std::min(a[0][0], std::min(a[1][1], a[2][2]));
+}
+
+// Device copy of the polar data: reciprocal vectors, 1/sqrt(M) and the half-
+// width of a G box holding every K = q + G (q reduced to [-1/2, 1/2)^3) with
+// K.eps.K/(4 alpha) < cutoff.  Returns an error message or nullptr.
+const char* polar_device(const epw_polar* pp, int nm, PolarDev& P) {
+    if (pp->nat < 1 || pp->nat > EPW_MAX_ATOMS || 3 * pp->nat != nm) return "polar: nat must be nm / 3 (1..EPW_MAX_ATOMS)";
+    if (!(pp->alpha > 0.0) || !(pp->cutoff > 0.0) || !std::isfinite(pp->alpha) || !std::isfinite(pp->cutoff))
+        return "polar: alpha and cutoff must be > 0";
+    if (!std::isfinite(pp->prefactor)) return "polar: prefactor not finite";
+    const double(&A)[3][3] = pp->vectors;
+    const double det = A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+                       A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+                       A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+    if (!(std::fabs(det) > 1e-300) || !std::isfinite(det)) return "polar: singular lattice vectors";
+    // B = 2 pi (A^-1)^T: row i of B is 2 pi times column i of A^-1
+    double inv[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int i1 = (i + 1) % 3, i2 = (i + 2) % 3, j1 = (j + 1) % 3, j2 = (j + 2) % 3;
+            inv[j][i] = (A[i1][j1] * A[i2][j2] - A[i1][j2] * A[i2][j1]) / det;   // cofactor transpose
+        }
+    P.nat = pp->nat;
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a) P.B[i][a] = 2.0 * M_PI * inv[a][i];
+    double mx = 0.0;
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            if (!std::isfinite(pp->eps_inf[a][b])) return "polar: eps_inf not finite";
+            mx = std::max(mx, std::fabs(pp->eps_inf[a][b]));
+        }
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b)
+            if (std::fabs(pp->eps_inf[a][b] - pp->eps_inf[b][a]) > 1e-12 * mx) return "polar: eps_inf not symmetric";
+    const double lmin = sym3_min_eig(pp->eps_inf);
+    if (!(lmin > 0.0)) return "polar: eps_inf not positive definite";
+    std::memcpy(P.eps, pp->eps_inf, sizeof(P.eps));
+    for (int k = 0; k < pp->nat; ++k) {
+        if (!(pp->mass[k] > 0.0) || !std::isfinite(pp->mass[k])) return "polar: masses must be > 0";
+        P.rsm[k] = 1.0 / std::sqrt(pp->mass[k]);
+        for (int a = 0; a < 3; ++a) {
+            P.tau[k][a] = pp->tau[k][a];
+            for (int b = 0; b < 3; ++b) P.zstar[k][a][b] = pp->zstar[k][a][b];
+        }
+    }
+    P.prefactor = pp->prefactor;
+    P.alpha = pp->alpha;
+    P.cutoff = pp->cutoff;
+    const double kmax = std::sqrt(4.0 * pp->alpha * pp->cutoff / lmin);
+    double qmax = 0.0, amax = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        for (int a = 0; a < 3; ++a) qmax += 0.5 * std::fabs(P.B[i][a]);
+        amax = std::max(amax, std::sqrt(A[i][0] * A[i][0] + A[i][1] * A[i][1] + A[i][2] * A[i][2]));
+    }
+    const double g = std::ceil(amax * (kmax + qmax) / (2.0 * M_PI)) + 1.0;
+    if (!(g <= EPW_MAX_GMAX)) return "polar: the G box for this cutoff exceeds EPW_MAX_GMAX";
+    P.gmax = (int)g;
+    return nullptr;
+}
+
 int check_common(const epw_system* s, const epw_points* p, const epw_params* par, const char* fn) {
     if (!s || !p || !par) return fail(EPW_EINVAL, "%s: NULL argument", fn);
     if (s->nb < 1 || s->nb > EPW_MAX_NB) return fail(EPW_ESHAPE, "%s: nb = %d not in 1..%d", fn, s->nb, EPW_MAX_NB);
@@ -36,6 +121,11 @@ int check_common(const epw_system* s, const epw_points* p, const epw_params* par
     if (par->chunk_q < 0) return fail(EPW_EINVAL, "%s: chunk_q < 0", fn);
     if (s->nmax_e < 0 || s->nmax_e > EPW_MAX_NMAX)
         return fail(EPW_EINVAL, "%s: nmax_e = %d not in 0..%d", fn, s->nmax_e, EPW_MAX_NMAX);
+    if (s->polar) {
+        PolarDev P;
+        const char* msg = polar_device(s->polar, s->nm, P);
+        if (msg) return fail(EPW_EINVAL, "%s: %s", fn, msg);
+    }
     const bool given = p->omega && p->evec;
     if ((p->omega != nullptr) != (p->evec != nullptr))
         return fail(EPW_EINVAL, "%s: omega and evec must be given together", fn);
@@ -90,6 +180,7 @@ struct Layout {
     double* rec = nullptr;       // [nk][Q][nm][nb] pole records of 4 + nbp doubles (+ 1),
     void* spart = nullptr;       // [S_w][nk][nb][nw + 1] c128 slice partials
     int Sw = 1;
+    void* polar_L = nullptr;     // [Q][nm] c128 long-range factors (polar systems)
     // per pair states at k+q when no k+q map is given
     double* eps_pair = nullptr;
     void* U_pair = nullptr;
@@ -192,6 +283,7 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     L.phi_q = A.take(cb * (size_t)L.Q * np_);
     L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
     L.Bnu = A.take(bcol_bytes * L.Q * nm * L.nbp * L.nbp);
+    if (s->polar) L.polar_L = A.take(16 * (size_t)L.Q * nm);
     L.tiles_m = (nk + fused_tile_rows(L.nbp) - 1) / fused_tile_rows(L.nbp);
     if (out == Out::IMSIGMA || out == Out::RESIGMA) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
     if (out == Out::RESIGMA) L.part2 = (double*)A.take(8 * (size_t)L.S * nk * nb);
@@ -288,6 +380,12 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
             ev = L.evec_c;
         }
         launch_phonon_factors(qc, nm, om, par->omega_cut, par->T, L.sc, L.nbose, st);
+        if (s->polar) {
+            StageTimer t(EPW_STAGE_MODEROT, st);
+            PolarDev P;
+            polar_device(s->polar, nm, P);          // validated by check_common
+            launch_polar_factor(P, qc, nm, p->qfrac + 3 * (size_t)q0, ev, L.sc, L.polar_L, st);
+        }
         pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, L.ps, st);
         launch_phase_table(rprec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
         {
@@ -297,9 +395,11 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         {
             StageTimer t(EPW_STAGE_MODEROT, st);
             if (bf)
-                launch_mode_rotate_bf16(ne, qc, nm, nb, L.nbp, L.kpad, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e);
+                launch_mode_rotate_bf16(ne, qc, nm, nb, L.nbp, L.kpad, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e,
+                                        L.polar_L, s->Re);
             else
-                launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e);
+                launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e, L.polar_L,
+                                   s->Re);
         }
         FusedArgs a;
         a.nk = nk;
@@ -888,6 +988,7 @@ extern "C" int epw_imsigma_backward(const epw_system* sys, const epw_points* pts
     clear_error();
     int rc = check_common(sys, pts, par, "epw_imsigma_backward");
     if (rc != EPW_OK) return rc;
+    if (sys->polar) return fail(EPW_EINVAL, "epw_imsigma_backward: the polar long-range term has no adjoint here");
     if (pts->nk == 0) return EPW_OK;
     if (!w) return fail(EPW_EINVAL, "epw_imsigma_backward: NULL weights");
     if (dHR && !pts->kq)

@@ -100,6 +100,7 @@ __global__ void mode_rotate_kernel(int ne, int nq, int nm, int nb, int nbp,
                                    const typename Cx<T>::type* __restrict__ in,
                                    const double2* __restrict__ evec, const double* __restrict__ sc,
                                    const int32_t* __restrict__ ndeg_fold,
+                                   const double2* __restrict__ Lq, const int32_t* __restrict__ Re,
                                    typename Cx<T>::type* __restrict__ out)
 {
     typedef typename Cx<T>::type CT;
@@ -130,6 +131,16 @@ __global__ void mode_rotate_kernel(int ne, int nq, int nm, int nb, int nbp,
             }
             re *= (T)s;
             im *= (T)s;
+        }
+        if (Lq && i == j) {
+            // polar long-range term: L_nu(q) delta_ij at R_e = 0, where the
+            // phase is 1 for every k and the degeneracy is 1
+            const int32_t* rv = Re + 3 * (eq / nq);
+            if ((rv[0] | rv[1] | rv[2]) == 0) {
+                const double2 l = Lq[(size_t)q * nm + v];
+                re += (T)l.x;
+                im += (T)l.y;
+            }
         }
         CT r;
         r.x = re;
@@ -827,6 +838,8 @@ __global__ __launch_bounds__(256) void mode_rotate_bf16_kernel(int ne, int qc, i
                                                               const double2* __restrict__ evec,
                                                               const double* __restrict__ sc,
                                                               const int32_t* __restrict__ ndeg_fold,
+                                                              const double2* __restrict__ Lq,
+                                                              const int32_t* __restrict__ Re,
                                                               uint16_t* __restrict__ out)
 {
     __shared__ float2 tile[64][65];
@@ -857,6 +870,15 @@ __global__ __launch_bounds__(256) void mode_rotate_bf16_kernel(int ne, int qc, i
                             im += g.x * (float)ev.y + g.y * (float)ev.x;
                         }
                         v = make_float2(re * wf, im * wf);
+                    }
+                }
+                if (Lq && ij < nbp2 && e < ne) {
+                    const int i = ij / nbp, j = ij % nbp;
+                    const int32_t* rv = Re + 3 * (size_t)e;
+                    if (i == j && i < nb && (rv[0] | rv[1] | rv[2]) == 0) {
+                        const double2 l = Lq[(size_t)q * nm + nu];
+                        v.x += (float)l.x;
+                        v.y += (float)l.y;
                     }
                 }
                 tile[il][el] = v;
@@ -1067,15 +1089,17 @@ void launch_fermi_table(size_t n, const double* eps, double mu, double T, double
 
 void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, const void* in,
                         const void* evec, const double* sc, void* out, hipStream_t stream,
-                        const int32_t* ndeg_fold) {
+                        const int32_t* ndeg_fold, const void* Lq, const int32_t* Re) {
     const size_t total = (size_t)ne * nq * nbp * nbp;
     if (total == 0) return;
     if (prec == Prec::F64)
         mode_rotate_kernel<double><<<blocks_for(total, 256), 256, 0, stream>>>(
-            ne, nq, nm, nb, nbp, (const double2*)in, (const double2*)evec, sc, ndeg_fold, (double2*)out);
+            ne, nq, nm, nb, nbp, (const double2*)in, (const double2*)evec, sc, ndeg_fold, (const double2*)Lq, Re,
+            (double2*)out);
     else
         mode_rotate_kernel<float><<<blocks_for(total, 256), 256, 0, stream>>>(
-            ne, nq, nm, nb, nbp, (const float2*)in, (const double2*)evec, sc, ndeg_fold, (float2*)out);
+            ne, nq, nm, nb, nbp, (const float2*)in, (const double2*)evec, sc, ndeg_fold, (const double2*)Lq, Re,
+            (float2*)out);
     launch_check("mode_rotate_kernel");
 }
 
@@ -1144,11 +1168,13 @@ void launch_degenerate_average(int nk, int nb, const double* eps, double tol, do
 
 namespace epw {
 void launch_mode_rotate_bf16(int ne, int qc, int nm, int nb, int nbp, int kpad, const void* in, const void* evec,
-                             const double* sc, void* out, hipStream_t stream, const int32_t* ndeg_fold) {
+                             const double* sc, void* out, hipStream_t stream, const int32_t* ndeg_fold,
+                             const void* Lq, const int32_t* Re) {
     if (qc == 0) return;
     dim3 grid((unsigned)qc, (unsigned)((kpad + 63) / 64));
     mode_rotate_bf16_kernel<<<grid, 256, 0, stream>>>(ne, qc, nm, nb, nbp, kpad, (const float2*)in,
-                                                     (const double2*)evec, sc, ndeg_fold, (uint16_t*)out);
+                                                     (const double2*)evec, sc, ndeg_fold, (const double2*)Lq, Re,
+                                                     (uint16_t*)out);
     launch_check("mode_rotate_bf16_kernel");
 }
 }  // namespace epw

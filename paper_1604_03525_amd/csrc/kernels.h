@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "epw.h"
+
 namespace epw {
 
 // ---- k_eigh.hip ----
@@ -46,14 +48,32 @@ void launch_fermi_table(size_t n, const double* eps, double mu, double T, double
 // a6: out[e][q][nu][i][j] (NBP-padded) = sum_a in[e][q][a][i][j] e_q[a][nu] sc[q][nu]
 // ndeg_fold (optional): also multiply row e by 1/ndeg_fold[e] (the phase table
 // of the following R_e -> k contraction then carries no 1/ndeg).
+// Lq (optional, [nq][nm] c128, with Re): add Lq[q][nu] to the diagonal i == j
+// of the row with R_e = 0 (the polar long-range term, in the Wannier basis).
 void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, const void* in,
                         const void* evec, const double* sc, void* out, hipStream_t stream,
-                        const int32_t* ndeg_fold = nullptr);
+                        const int32_t* ndeg_fold = nullptr, const void* Lq = nullptr,
+                        const int32_t* Re = nullptr);
 
 // a6 for split-bf16: float32 g(R_e,q) [ne][qc][nm*nb*nb] -> four bf16 planes
 // [4][qc*nm*nbp*nbp][kpad] (R_e contiguous), scaled by sc and rotated by e_q.
 void launch_mode_rotate_bf16(int ne, int qc, int nm, int nb, int nbp, int kpad, const void* in, const void* evec,
-                             const double* sc, void* out, hipStream_t stream, const int32_t* ndeg_fold = nullptr);
+                             const double* sc, void* out, hipStream_t stream, const int32_t* ndeg_fold = nullptr,
+                             const void* Lq = nullptr, const int32_t* Re = nullptr);
+
+// Polar long-range factor L_nu(q) (k_polar.hip): the per-q Gaussian-damped
+// sum over G of Sec. 4, for a chunk of q points.
+struct PolarDev {
+    int nat, gmax;
+    double B[3][3];          // reciprocal vectors (rows, Cartesian)
+    double tau[EPW_MAX_ATOMS][3];
+    double zstar[EPW_MAX_ATOMS][3][3];
+    double eps[3][3];
+    double rsm[EPW_MAX_ATOMS];   // 1/sqrt(M_kappa)
+    double prefactor, alpha, cutoff;
+};
+void launch_polar_factor(const PolarDev& P, int qc, int nm, const double* qfrac, const void* evec,
+                         const double* sc, void* L, hipStream_t stream);
 
 struct FusedArgs {
     int nk, ne, nb, nbp, nm;

@@ -109,8 +109,9 @@ def epw_interp_phonons(DR, R, ndeg, qfrac):
 class System:
     """Device-resident real-space system: WS sets, H(R_e), D(R_p), g(R_e,R_p)."""
 
-    def __init__(self, Re, ndeg_e, Rp, ndeg_p, HR, DR, gR, device="cuda"):
+    def __init__(self, Re, ndeg_e, Rp, ndeg_p, HR, DR, gR, device="cuda", polar=None):
         self.device = torch.device(device)
+        self.polar = None if polar is None else make_polar(**polar)
         d = self.device
         self.Re = _dev(Re, torch.int32, d)
         self.ndeg_e = _dev(ndeg_e, torch.int32, d)
@@ -127,9 +128,38 @@ class System:
         self.nmax_e = nmax if 1 <= nmax <= _lib.EPW_MAX_NMAX else 0
 
     def c_struct(self):
-        return _lib.EpwSystem(self.nb, self.nm, self.Re.shape[0], self.Rp.shape[0],
-                              _ptr(self.Re), _ptr(self.ndeg_e), _ptr(self.Rp), _ptr(self.ndeg_p),
-                              _ptr(self.HR), _ptr(self.DR), _ptr(self.gR), self.nmax_e, 0)
+        s = _lib.EpwSystem(self.nb, self.nm, self.Re.shape[0], self.Rp.shape[0],
+                           _ptr(self.Re), _ptr(self.ndeg_e), _ptr(self.Rp), _ptr(self.ndeg_p),
+                           _ptr(self.HR), _ptr(self.DR), _ptr(self.gR), self.nmax_e, 0)
+        if self.polar is not None:
+            s.polar = ctypes.cast(ctypes.pointer(self.polar), ctypes.c_void_p)
+        return s
+
+
+def make_polar(vectors, tau, zstar, eps_inf, masses, prefactor, alpha, cutoff):
+    """The long-range (polar) data of Sec. 4 as the host struct of the C ABI:
+    primitive vectors [3][3] (rows), positions tau [nat][3], Born charges
+    zstar [nat][3][3], eps_inf [3][3], masses [nat] (Cartesian, one length
+    unit), the overall factor C, the Gaussian parameter and the cutoff."""
+    tau = np.asarray(tau, dtype=np.float64)
+    nat = len(tau)
+    if not 1 <= nat <= _lib.EPW_MAX_ATOMS:
+        raise ValueError("polar: 1..%d atoms" % _lib.EPW_MAX_ATOMS)
+    p = _lib.EpwPolar()
+    p.nat = nat
+    p.vectors[:] = list(np.asarray(vectors, dtype=np.float64).reshape(9))
+    t = np.zeros((_lib.EPW_MAX_ATOMS, 3))
+    t[:nat] = tau
+    p.tau[:] = list(t.reshape(-1))
+    z = np.zeros((_lib.EPW_MAX_ATOMS, 3, 3))
+    z[:nat] = np.asarray(zstar, dtype=np.float64)
+    p.zstar[:] = list(z.reshape(-1))
+    p.eps_inf[:] = list(np.asarray(eps_inf, dtype=np.float64).reshape(9))
+    m = np.ones(_lib.EPW_MAX_ATOMS)
+    m[:nat] = np.asarray(masses, dtype=np.float64)
+    p.mass[:] = list(m)
+    p.prefactor, p.alpha, p.cutoff = float(prefactor), float(alpha), float(cutoff)
+    return p
 
 
 class Points:

@@ -1,0 +1,132 @@
+"""Polar long-range vertex (Sec. 4): HIP path against the FP64 oracle,
+through the C ABI.  The kernels add L_nu(q) delta_ij at R_e = 0 of the
+mode-rotated operand; the oracle adds L_nu(q) [U_k+q^dag U_k]_mn after the
+band rotation.  Tolerances as for Im Sigma: FP64 1e-10, FP32 1e-5,
+split-BF16 1e-4."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import interp, lattice, polar
+from paper_1604_03525_amd import epw
+from paper_1604_03525_amd import inputs as I
+from tests.helpers import realistic_case, rel_err
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "split_bf16": 1e-4}
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _case(nb=3, kg=(4, 4, 4), seed=3):
+    """Two-atom fcc (6 modes, acoustic sum rule holds on the 3^3 coarse set),
+    nb random bands, a kg grid whose smallest q carry a large long-range
+    term."""
+    R, nd = lattice.ws_vectors(I.FCC_METRIC, (3, 3, 3))
+    HR = I.random_hamiltonian(R, I.FCC_VECTORS, nb, seed=seed, scale=0.8)
+    DR = I.spring_dynmat(R, I.FCC_VECTORS, I.ATOMS_FCC2, shells=2, seed=seed + 1, scale=4e-4)
+    gR = I.random_vertex(R, R, I.FCC_VECTORS, 6, nb, seed=seed + 2, g0=0.05)
+    k = lattice.grid_points(*kg)
+    return dict(R=R, nd=nd, HR=HR, DR=DR, gR=gR, k=k, q=k, kq=lattice.kq_index(kg, kg), T=300.0, mu=0.1,
+                sigma=0.15, polar=I.polar_params())
+
+
+def _system(c, with_polar=True):
+    return epw.System(c["R"], c["nd"], c["R"], c["nd"], c["HR"], c["DR"], c["gR"], DEV,
+                      polar=c["polar"] if with_polar else None)
+
+
+def _params(c, **kw):
+    base = dict(T=c["T"], mu=c["mu"], sigma=c["sigma"])
+    base.update(kw)
+    return epw.make_params(**base)
+
+
+def _deg_groups(vals, tol):
+    g = [0]
+    for i in range(1, len(vals)):
+        g.append(g[-1] + (0 if abs(vals[i] - vals[i - 1]) < tol else 1))
+    return np.array(g)
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "split_bf16"])
+def test_interp_g_polar_gauge_invariant(dtype):
+    """|g^S + g^L|^2 summed over degenerate groups of m, n and nu matches the
+    oracle for every (k, q) of a 3^3 grid."""
+    c = _case(kg=(3, 3, 3))
+    g = epw.epw_interp_g(_system(c), epw.Points(c["k"], c["q"], c["kq"], device=DEV),
+                         _params(c, dtype=dtype)).cpu().numpy()
+    eps, _ = interp.bands(c["HR"], c["R"], c["nd"], c["k"])
+    worst = scale = 0.0
+    for ik, k in enumerate(c["k"]):
+        go, ek, ekq, om = polar.vertex_band(c["HR"], c["R"], c["nd"], c["DR"], c["R"], c["nd"], c["gR"], k,
+                                            c["q"], c["polar"])
+        for iq in range(len(c["q"])):
+            gn, gm, gv = _deg_groups(ek, 1e-6), _deg_groups(ekq[iq], 1e-6), _deg_groups(om[iq], 1e-9)
+            A, B = np.abs(g[ik, iq]) ** 2, np.abs(go[iq]) ** 2
+            for v in np.unique(gv):
+                for m in np.unique(gm):
+                    for n in np.unique(gn):
+                        a = A[gv == v][:, gm == m][:, :, gn == n].sum()
+                        b = B[gv == v][:, gm == m][:, :, gn == n].sum()
+                        worst = max(worst, abs(a - b))
+                        scale = max(scale, abs(b))
+    _say("polar interp_g", dtype, worst / scale)
+    assert worst <= TOL[dtype] * scale
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "split_bf16"])
+def test_imsigma_polar_grid(dtype):
+    """Im Sigma with the polar vertex on a 4^3 grid (ragged q chunks in FP64);
+    the long-range part changes the result (by ~0.35 % here, the grid's
+    smallest q being a quarter of the zone) far beyond the tolerance."""
+    c = _case()
+    ref = polar.imsigma(c["HR"], c["R"], c["nd"], c["DR"], c["R"], c["nd"], c["gR"], c["k"], c["q"], c["T"],
+                        c["mu"], c["sigma"], c["polar"])
+    pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
+    for chunk in ((0, 7) if dtype == "fp64" else (0,)):
+        got = epw.epw_imsigma(_system(c), pts, _params(c, dtype=dtype, chunk_q=chunk)).cpu().numpy()
+        _say("polar imsigma", dtype, chunk, rel_err(got, ref))
+        assert rel_err(got, ref) < TOL[dtype]
+    plain = epw.epw_imsigma(_system(c, False), pts, _params(c)).cpu().numpy()
+    assert rel_err(plain, ref) > 1e-3
+
+
+def test_imsigma_polar_offgrid():
+    """Random k and q without a k+q map: per-pair k+q states, same vertex."""
+    c = _case(nb=5)
+    c.update(k=I.random_points(12, 41), q=I.random_points(30, 42), kq=None)
+    ref = polar.imsigma(c["HR"], c["R"], c["nd"], c["DR"], c["R"], c["nd"], c["gR"], c["k"], c["q"], c["T"],
+                        c["mu"], c["sigma"], c["polar"])
+    got = epw.epw_imsigma(_system(c), epw.Points(c["k"], c["q"], None, device=DEV), _params(c)).cpu().numpy()
+    _say("polar offgrid", rel_err(got, ref))
+    assert rel_err(got, ref) < 1e-10
+
+
+def test_backward_refuses_polar():
+    c = _case(kg=(2, 2, 2))
+    pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
+    import torch
+    w = torch.ones((len(c["k"]), 3), dtype=torch.float64, device=DEV)
+    with pytest.raises(epw.EpwError) as e:
+        epw.epw_imsigma_backward(_system(c), pts, _params(c), w)
+    assert e.value.code == epw._lib.EPW_EINVAL
+
+
+def test_realistic_full_size_polar_sampled():
+    """The benchmark workload (fcc, 8 bands, 6 modes, 279 WS, 20^3 k x 20^3 q)
+    with the polar term in the benchmark's launch configuration, checked on
+    sampled k points against all 8000 q."""
+    c = realistic_case()
+    par = I.polar_params()
+    sysd = epw.System(c["R"], c["nd"], c["R"], c["nd"], c["HR"], c["DR"], c["gR"], DEV, polar=par)
+    got = epw.epw_imsigma(sysd, epw.Points(c["k"], c["q"], c["kq"], device=DEV), _params(c)).cpu().numpy()
+    kidx = np.array([0, 1, 4321, 7999])
+    ref = polar.imsigma(c["HR"], c["R"], c["nd"], c["DR"], c["R"], c["nd"], c["gR"], c["k"][kidx], c["q"],
+                        c["T"], c["mu"], c["sigma"], par)
+    _say("polar realistic", rel_err(got[kidx], ref))
+    assert rel_err(got[kidx], ref) < 1e-10

@@ -213,3 +213,26 @@ def test_selfenergy_omega_argument_errors_and_workspace():
                                      None) == _lib.EPW_EINVAL
     assert lib.epw_spectral_function(0, 2, 4, None, ctypes.c_double(0.0), None, None, None, None,
                                      None) == _lib.EPW_OK
+
+
+def test_polar_validation():
+    """The polar data is checked on the host: atom count against the modes,
+    a positive definite symmetric dielectric tensor, positive masses and a G
+    box that fits; a valid set sizes a workspace."""
+    lib = _lib.load()
+    par = epw.make_params()
+    s, p = _shape_only(nb=3, nm=6, ne=19, np_=19, nk=27, nq=8)
+    good = I.polar_params()
+    bad = [dict(good, tau=good["tau"][:1], zstar=good["zstar"][:1], masses=good["masses"][:1]),
+           dict(good, eps_inf=-good["eps_inf"]),
+           dict(good, eps_inf=good["eps_inf"] + np.triu(np.ones((3, 3)), 1)),
+           dict(good, masses=np.array([1.0, 0.0])),
+           dict(good, alpha=0.0),
+           dict(good, cutoff=1e6)]
+    for b in [good] + bad:
+        pol = epw.make_polar(**b)
+        s.polar = ctypes.cast(ctypes.pointer(pol), ctypes.c_void_p)
+        n = lib.epw_workspace_size(_lib.EPW_WS_IMSIGMA, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
+        assert (n > 0) == (b is good), lib.epw_last_error()
+        if b is not good:
+            assert b"polar" in lib.epw_last_error()
