@@ -27,6 +27,8 @@ spectral    Complex Sigma_nk(omega) of Sec. 3 Eq. (3) on a frequency grid
             and the spectral function A_nk(omega) of Sec. 3 Eq. (10).
 polar       Long-range (polar) vertex g^L of Sec. 4 added to the
             interpolated short-range vertex.
+transport   Band velocities, lambda_tr (Sec. 6 Eq. (55)), alpha^2 F
+            (Eqs. (12), (54)) and the Ziman resistivity integral (Eq. (53)).
 torch_ref   The same forward in plain torch CPU float64, differentiated by
             autograd: the reference gradient for the hand-written adjoint.
 
