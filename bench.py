@@ -242,8 +242,10 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--variants", default="fp32,split_bf16,backward,backward_fp32,phonon,resigma,polar,spectral",
-                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, resigma, polar, spectral, "
+    ap.add_argument("--variants",
+                    default="fp32,split_bf16,backward,backward_fp32,phonon,resigma,polar,transport,spectral",
+                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, resigma, polar, "
+                         "transport, spectral, "
                          "mobility (the last is "
                          "opt-in: one 4096-q shard of the mobility-scale system, ~2 min)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -338,6 +340,19 @@ def main():
                 variants[var] = {"value": pairs * args.steps / dtr, "ms_per_step": 1e3 * dtr / args.steps,
                                  "dtype": "fp64", "outputs": "Sigma'_nk on shell (Eq. 3) and Sigma~'_nk (Eq. 5)",
                                  "fused_tflops": achr, "fused_frac_of_peak": achr / PEAK_TFLOPS["fp64"] if achr else None}
+            elif var == "transport":
+                log("bench: transport coupling lambda_tr with lambda and Pi'' (fp64)")
+                from paper_1604_03525_amd import inputs as I
+                # eps_F 0.3 eV into the valence bands (the headline mu is mid-gap)
+                par = epw.make_params(T=model.T, mu=model.mu - 0.3, sigma=0.05)
+                dtt, stt = timed(lambda: epw.epw_transport_coupling(sysd, pts, par, I.FCC_VECTORS, want_pi=True,
+                                                                    workspace=ws), args.steps, args.warmup, torch)
+                fmst, fnt = stt["fused"]
+                acht = flops / (fmst * 1e-3) / 1e12 if fmst > 0 else None
+                variants[var] = {"value": pairs * args.steps / dtt, "ms_per_step": 1e3 * dtt / args.steps,
+                                 "dtype": "fp64", "outputs": "lambda_tr (Eq. 55), lambda (Eq. 11), Pi'' (Eq. 9)",
+                                 "mu_shift_eV": -0.3, "sigma_eV": 0.05,
+                                 "fused_tflops": acht, "fused_frac_of_peak": acht / PEAK_TFLOPS["fp64"] if acht else None}
             elif var == "polar":
                 log("bench: fp64 forward with the polar long-range term")
                 from paper_1604_03525_amd import inputs as I

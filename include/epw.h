@@ -292,6 +292,52 @@ size_t epw_workspace_size_omega(const epw_system* sys, const epw_points* pts, co
 int epw_spectral_function(int nk, int nb, int nw, const double* eps, double mu, const double* wgrid,
                           const void* sigma_w, const void* sigma0, double* A, void* stream);
 
+/* Band velocities for the transport coupling (Sec. 6; the analytic
+ * derivative of the interpolated bands, the Wannier route Sec. 7 names):
+ *   v_nk,a = Re [U_k^dag (dH/dk_a) U_k]_nn,
+ *   dH/dk_a = Hermitised sum_R i R_a exp(2 pi i k.R) H(R)/ndeg(R), R Cartesian
+ * (R_cart = R . vectors), averaged over bands whose sorted energies differ
+ * by < deg_tol (the trace over a degenerate subspace is basis independent).
+ *  vectors  host [3][3] double: primitive lattice vectors (rows, Cartesian)
+ *  eps, U   device out, as epw_interp_bands
+ *  vel      device [nk][nb][3] double out (energy x length)
+ * Errors: EPW_ESHAPE, EPW_EINVAL, EPW_EHIP. */
+int epw_band_velocities(int nb, int nR, const int32_t* R, const int32_t* ndeg, const void* HR,
+                        const double* vectors, int nk, const double* kfrac, double deg_tol, double* eps,
+                        void* U, double* vel, void* stream);
+
+/* Mode-resolved transport coupling strength, Sec. 6 Eq. (55):
+ *   lambda_tr,q,nu = 1 / (N(eps_F) omega_q,nu) (1/N_k) sum_k sum_mn |g_mn,nu(k,q)|^2
+ *       delta(eps_nk - eps_F) delta(eps_m,k+q - eps_F) (1 - v_nk . v_m,k+q / |v_nk|^2)
+ * with the velocities of epw_band_velocities (the factor is 1 where
+ * |v_nk|^2 <= 1e-18), N(eps_F), the deltas and the degenerate-mode average
+ * as for lambda_q,nu (epw_phonon_selfenergy), which comes out of the same
+ * pass together with Pi''.  Grid runs only (the k+q map is required).
+ *  vectors  host [3][3] double: primitive lattice vectors (rows, Cartesian)
+ *  lam_tr   device [nq][nm] double out; lam, pi_im device [nq][nm] or NULL
+ * Errors: as epw_phonon_selfenergy; EPW_EINVAL without a k+q map. */
+int epw_transport_coupling(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                           const double* vectors, double* lam_tr, double* lam, double* pi_im, void* ws,
+                           size_t ws_bytes, void* stream);
+
+/* Eliashberg function, Sec. 3 Eq. (12) (from lambda_q,nu) or its transport
+ * form Sec. 6 Eq. (54) (from lambda_tr,q,nu), on a frequency grid:
+ *   a2F(w_j) = (1/2) (1/nq_norm) sum_q,nu omega_q,nu lambda_q,nu delta_s(w_j - omega_q,nu)
+ * with the Gaussian delta_s(x) = exp(-x^2/s^2)/(s sqrt(pi)), s = sigma.
+ *  omega, lam  device [nq][nm] double; wgrid device [nw]; a2f device [nw] out
+ * Errors: EPW_ESHAPE, EPW_EINVAL, EPW_EHIP. */
+int epw_eliashberg_function(int nq, int nm, const double* omega, const double* lam, double nq_norm, int nw,
+                            const double* wgrid, double sigma, double* a2f, void* stream);
+
+/* Ziman resistivity, Sec. 6 Eq. (53), without its material prefactor:
+ *   out[i] = rho(T_i) n e^2 / m_e = (4 pi / (k_B T_i)) int dw w a2F_tr(w) n(w) [1 + n(w)]
+ * by the trapezoid rule over the grid (integrand 0 for w <= 0; out = 0 at
+ * T = 0); energies in eV, k_B in eV/K, hbar = 1.
+ *  wgrid, a2f_tr device [nw]; T device [nT] (K); out device [nT] out
+ * Errors: EPW_ESHAPE, EPW_EINVAL, EPW_EHIP. */
+int epw_ziman_resistivity(int nw, const double* wgrid, const double* a2f_tr, int nT, const double* T,
+                          double* out, void* stream);
+
 /* Phonon linewidth, Sec. 3 Eq. (9), on shell (omega = omega_q,nu), and the
  * mode-resolved electron-phonon coupling strength, Sec. 3 Eq. (11):
  *   Pi''_q,nu = (2 pi / N_k) sum_k sum_mn |g_mn,nu(k,q)|^2
@@ -333,7 +379,7 @@ int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw
                          void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for the call `which` (EPW_WS_INTERP_G, EPW_WS_IMSIGMA,
- * EPW_WS_IMSIGMA_BACKWARD, EPW_WS_PHONON, EPW_WS_RESIGMA) with these sizes and parameters; device pointers
+ * EPW_WS_IMSIGMA_BACKWARD, EPW_WS_PHONON, EPW_WS_RESIGMA, EPW_WS_TRANSPORT) with these sizes and parameters; device pointers
  * inside sys/pts are not dereferenced and may be NULL.  Returns 0 and sets
  * the error message on invalid arguments. */
 #define EPW_WS_INTERP_G          1
@@ -341,6 +387,7 @@ int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw
 #define EPW_WS_IMSIGMA_BACKWARD  3
 #define EPW_WS_PHONON            4
 #define EPW_WS_RESIGMA           5
+#define EPW_WS_TRANSPORT         6
 size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
                           const epw_params* par);
 

@@ -24,6 +24,7 @@ EPW_WS_IMSIGMA = 2
 EPW_WS_IMSIGMA_BACKWARD = 3
 EPW_WS_PHONON = 4
 EPW_WS_RESIGMA = 5
+EPW_WS_TRANSPORT = 6
 
 EPW_STAGE_EIGH = 0
 EPW_STAGE_GEMM_RP = 1
@@ -99,6 +100,14 @@ PROTOTYPES = {
     "epw_timing_read": (ctypes.c_int, [ctypes.c_int, _dp, _i64p]),
     "epw_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(EpwSystem),
                                              ctypes.POINTER(EpwPoints), ctypes.POINTER(EpwParams)]),
+    "epw_band_velocities": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, _vp, _vp, ctypes.c_int, _vp,
+                                           ctypes.c_double, _vp, _vp, _vp, _vp]),
+    "epw_transport_coupling": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
+                                              ctypes.POINTER(EpwParams), _vp, _vp, _vp, _vp, _vp, ctypes.c_size_t,
+                                              _vp]),
+    "epw_eliashberg_function": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_double, ctypes.c_int,
+                                               _vp, ctypes.c_double, _vp, _vp]),
+    "epw_ziman_resistivity": (ctypes.c_int, [ctypes.c_int, _vp, _vp, ctypes.c_int, _vp, _vp, _vp]),
     "epw_selfenergy_omega": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
                                             ctypes.POINTER(EpwParams), ctypes.c_int, _vp, _vp, _vp, _vp,
                                             ctypes.c_size_t, _vp]),

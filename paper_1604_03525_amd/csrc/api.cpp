@@ -152,7 +152,7 @@ struct PairScratch {
 };
 
 // what a forward pass produces
-enum class Out { IMSIGMA, STORE, PHONON, RESIGMA, OMEGA };
+enum class Out { IMSIGMA, STORE, PHONON, RESIGMA, OMEGA, TRANSPORT };
 
 struct Layout {
     Prec prec;
@@ -181,6 +181,7 @@ struct Layout {
     void* spart = nullptr;       // [S_w][nk][nb][nw + 1] c128 slice partials
     int Sw = 1;
     void* polar_L = nullptr;     // [Q][nm] c128 long-range factors (polar systems)
+    double* vel = nullptr;       // [nk][nb][3] band velocities (transport mode)
     // per pair states at k+q when no k+q map is given
     double* eps_pair = nullptr;
     void* U_pair = nullptr;
@@ -301,10 +302,12 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
         L.Sw = smax;
         L.spart = A.take(16 * (size_t)smax * nk * nb * ((size_t)nw + 1));
     }
-    if (out == Out::PHONON) {
-        L.part_ph = (double*)A.take(8 * 2 * (size_t)L.tiles_m * L.Q * nm);
+    if (out == Out::PHONON || out == Out::TRANSPORT) {
+        const int kinds = out == Out::TRANSPORT ? 3 : 2;
+        L.part_ph = (double*)A.take(8 * kinds * (size_t)L.tiles_m * L.Q * nm);
         L.dos_raw = (double*)A.take(8);
     }
+    if (out == Out::TRANSPORT) L.vel = (double*)A.take(8 * 3 * (size_t)nk * nb);
     take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair, L.ps);
 }
 
@@ -332,8 +335,9 @@ GemmDesc rp_desc(int qc, int ne, int np_, int ncol, const void* phi_q, const voi
 void run_forward(const epw_system* s, const epw_points* p, const epw_params* par, Layout& L,
                  double* imsig, void* gkq, hipStream_t st, double* pi_im = nullptr, double* lam = nullptr,
                  double* re_tilde = nullptr, const double* wgrid = nullptr, void* sig_w = nullptr,
-                 void* sig0 = nullptr) {
-    const bool phon = L.out == Out::PHONON;
+                 void* sig0 = nullptr, double* lam_tr = nullptr, const double* vectors9 = nullptr) {
+    const bool trans = L.out == Out::TRANSPORT;
+    const bool phon = L.out == Out::PHONON || trans;
     const bool omg = L.out == Out::OMEGA;
     const bool re = L.out == Out::RESIGMA;     // imsig then receives Sigma' on shell
     const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
@@ -347,6 +351,9 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
     }
     launch_fermi_table((size_t)nk * nb, L.eps, par->mu, par->T, L.ftab, st);
     if (phon) launch_dos_raw((size_t)nk * nb, L.eps, par->mu, par->sigma, L.dos_raw, st);
+    if (trans)
+        launch_velocities(nb, ne, s->Re, s->ndeg_e, s->HR, vectors9, nk, p->kfrac, L.eps, L.U, par->deg_tol, L.vel,
+                          st);
     const bool bf = prec == Prec::BF16X2;
     const Prec rprec = bf ? Prec::F32 : prec;      // precision of the R_p -> q step
     // Phases of the R_e -> k contraction: generated inside the fused kernel
@@ -436,6 +443,7 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp), SLICE_CUS);
         a.gkq = gkq;
         a.part_ph = phon ? L.part_ph : nullptr;
+        a.vel = trans ? L.vel : nullptr;
         a.part2 = re ? L.part2 : nullptr;
         a.rec = omg ? L.rec : nullptr;
         {
@@ -452,13 +460,15 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
             launch_sigma_omega_reduce(nk, nb, L.nw, sw, L.spart, L.eps, par->deg_tol, 1.0 / nqn,
                                       (c > 0 || par->accumulate) ? 1 : 0, sig_w, sig0, st);
         } else if (phon) {
-            double* pi_c = pi_im + (size_t)q0 * nm;
+            double* pi_c = pi_im ? pi_im + (size_t)q0 * nm : nullptr;
             double* lam_c = lam ? lam + (size_t)q0 * nm : nullptr;
+            double* ltr_c = (trans && lam_tr) ? lam_tr + (size_t)q0 * nm : nullptr;
             launch_phonon_finalize(qc, nm, L.tiles_m, L.part_ph, om, par->omega_cut, L.dos_raw, nk, par->sigma,
-                                   pi_c, lam_c, st);
+                                   pi_c, lam_c, st, ltr_c);
             // average over degenerate modes of each q
-            launch_degenerate_average(qc, nm, om, par->deg_tol, pi_c, st);
+            if (pi_c) launch_degenerate_average(qc, nm, om, par->deg_tol, pi_c, st);
             if (lam_c) launch_degenerate_average(qc, nm, om, par->deg_tol, lam_c, st);
+            if (ltr_c) launch_degenerate_average(qc, nm, om, par->deg_tol, ltr_c, st);
         } else if (re) {
             // Eq. (3) carries no pi: the BZ mean only
             const int acc = (c > 0 || par->accumulate) ? 1 : 0;
@@ -779,7 +789,7 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
                                      const epw_params* par) {
     clear_error();
     if (which != EPW_WS_INTERP_G && which != EPW_WS_IMSIGMA && which != EPW_WS_IMSIGMA_BACKWARD &&
-        which != EPW_WS_PHONON && which != EPW_WS_RESIGMA) {
+        which != EPW_WS_PHONON && which != EPW_WS_RESIGMA && which != EPW_WS_TRANSPORT) {
         fail(EPW_EINVAL, "epw_workspace_size: unknown call id %d", which);
         return 0;
     }
@@ -811,7 +821,8 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
         Layout L;
         const Out o = which == EPW_WS_INTERP_G ? Out::STORE
                       : which == EPW_WS_PHONON ? Out::PHONON
-                      : which == EPW_WS_RESIGMA ? Out::RESIGMA : Out::IMSIGMA;
+                      : which == EPW_WS_RESIGMA ? Out::RESIGMA
+                      : which == EPW_WS_TRANSPORT ? Out::TRANSPORT : Out::IMSIGMA;
         plan(&s, &p, par, o, A, L);
     }
     return A.used + 256;
@@ -954,6 +965,78 @@ extern "C" int epw_resigma(const epw_system* sys, const epw_points* pts, const e
         A.cap = ws_bytes;
         plan(sys, pts, par, Out::RESIGMA, A, L);
         run_forward(sys, pts, par, L, re_shell, nullptr, (hipStream_t)stream, nullptr, nullptr, re_tilde);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_transport_coupling(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                                      const double* vectors, double* lam_tr, double* lam, double* pi_im, void* ws,
+                                      size_t ws_bytes, void* stream) {
+    clear_error();
+    int rc = check_common(sys, pts, par, "epw_transport_coupling");
+    if (rc != EPW_OK) return rc;
+    if (pts->nq == 0) return EPW_OK;
+    if (!lam_tr || !vectors) return fail(EPW_EINVAL, "epw_transport_coupling: NULL output or lattice vectors");
+    if (pts->nk == 0) return fail(EPW_ESHAPE, "epw_transport_coupling: the k set is empty");
+    if (!pts->kq) return fail(EPW_EINVAL, "epw_transport_coupling: needs the k+q map (grid runs)");
+    for (int i = 0; i < 9; ++i)
+        if (!std::isfinite(vectors[i])) return fail(EPW_EINVAL, "epw_transport_coupling: lattice vectors not finite");
+    Arena dry;
+    dry.dry = true;
+    Layout L;
+    plan(sys, pts, par, Out::TRANSPORT, dry, L);
+    if (!ws || ws_bytes < dry.used + 256)
+        return fail(EPW_ENOMEM, "epw_transport_coupling: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
+    return guarded("epw_transport_coupling", [&]() {
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        plan(sys, pts, par, Out::TRANSPORT, A, L);
+        run_forward(sys, pts, par, L, nullptr, nullptr, (hipStream_t)stream, pi_im, lam, nullptr, nullptr, nullptr,
+                    nullptr, lam_tr, vectors);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_band_velocities(int nb, int nR, const int32_t* R, const int32_t* ndeg, const void* HR,
+                                   const double* vectors, int nk, const double* kfrac, double deg_tol, double* eps,
+                                   void* U, double* vel, void* stream) {
+    clear_error();
+    if (nb < 1 || nb > EPW_MAX_NB || nR < 1 || nk < 0)
+        return fail(EPW_ESHAPE, "epw_band_velocities: nb = %d, nR = %d, nk = %d", nb, nR, nk);
+    if (nk == 0) return EPW_OK;
+    if (!R || !ndeg || !HR || !vectors || !kfrac || !eps || !U || !vel)
+        return fail(EPW_EINVAL, "epw_band_velocities: NULL argument");
+    if (!(deg_tol >= 0.0)) return fail(EPW_EINVAL, "epw_band_velocities: deg_tol must be >= 0");
+    return guarded("epw_band_velocities", [&]() {
+        launch_interp_eigh(false, false, nb, nR, R, ndeg, (const double*)HR, nk, kfrac, eps, U, (hipStream_t)stream);
+        launch_velocities(nb, nR, R, ndeg, HR, vectors, nk, kfrac, eps, U, deg_tol, vel, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_eliashberg_function(int nq, int nm, const double* omega, const double* lam, double nq_norm,
+                                       int nw, const double* wgrid, double sigma, double* a2f, void* stream) {
+    clear_error();
+    if (nq < 0 || nm < 1 || nm > EPW_MAX_NM || nw < 0)
+        return fail(EPW_ESHAPE, "epw_eliashberg_function: nq = %d, nm = %d, nw = %d", nq, nm, nw);
+    if (!(sigma > 0.0) || !(nq_norm > 0.0)) return fail(EPW_EINVAL, "epw_eliashberg_function: sigma and nq_norm must be > 0");
+    if (nw == 0) return EPW_OK;
+    if (!wgrid || !a2f || (nq > 0 && (!omega || !lam))) return fail(EPW_EINVAL, "epw_eliashberg_function: NULL argument");
+    return guarded("epw_eliashberg_function", [&]() {
+        launch_eliashberg(nq, nm, omega, lam, nq_norm, nw, wgrid, sigma, a2f, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" int epw_ziman_resistivity(int nw, const double* wgrid, const double* a2f_tr, int nT, const double* T,
+                                     double* out, void* stream) {
+    clear_error();
+    if (nw < 0 || nT < 0) return fail(EPW_ESHAPE, "epw_ziman_resistivity: nw = %d, nT = %d", nw, nT);
+    if (nT == 0) return EPW_OK;
+    if (!T || !out || (nw > 0 && (!wgrid || !a2f_tr))) return fail(EPW_EINVAL, "epw_ziman_resistivity: NULL argument");
+    return guarded("epw_ziman_resistivity", [&]() {
+        launch_ziman(nw, wgrid, a2f_tr, nT, T, out, (hipStream_t)stream);
         return EPW_OK;
     });
 }

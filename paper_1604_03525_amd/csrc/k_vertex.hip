@@ -360,12 +360,15 @@ __device__ inline float2 cmulx(float2 a, float2 b) {
 // 4: one pole record of 4 + NBP doubles per (k, q, nu, m) for the
 // frequency-resolved Eq. (3): {xi_m - omega, xi_m + omega, n + f, n + 1 - f,
 // |g_mn|^2 for n < nb, 0 up to NBP}, with xi_m = eps_m,k+q - mu (the records
-// of modes below omega_cut carry zero weights).
+// of modes below omega_cut carry zero weights);
+// 5: mode 2 plus the transport coupling sum of Eq. (55) (the Eq. (11) weight
+// times 1 - v_nk . v_m,k+q / |v_nk|^2; grid runs, velocities of the k set).
 template <int MODE, int NBP, int KIND, bool GEN>
 __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
 {
     constexpr bool STORE = KIND == 1;
-    constexpr bool PH = KIND == 2;
+    constexpr bool TR = KIND == 5;
+    constexpr bool PH = KIND == 2 || TR;
     constexpr bool RE = KIND == 3;
     constexpr bool POLE = KIND == 4;
     typedef typename ModeTypes<MODE>::T T;
@@ -600,11 +603,12 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
         // phase 2: g_mn = sum_i conj(U_k+q[i][m]) V[i][n] for the thread's
         // items (b, m), all n; weights and |g|^2 accumulated per n (Im Sigma)
         // or per run (phonon sums)
-        double pp[NRUN], pl[NRUN];
+        double pp[NRUN], pl[NRUN], pt[TR ? NRUN : 1];
 #pragma unroll
         for (int rr = 0; rr < NRUN; ++rr) {
             pp[rr] = 0.0;
             pl[rr] = 0.0;
+            if constexpr (TR) pt[rr] = 0.0;
         }
         if (active_row) {
 #pragma unroll
@@ -621,6 +625,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 const double2* Uq;
                 const double* eq;
                 const double* fq;
+                const double* vq = nullptr;   // velocities at k+q (transport mode, grid runs)
                 if (a.kq) {
                     const int kq = a.kq[(size_t)k * a.nq_total + q];
                     if ((unsigned)kq >= (unsigned)a.nk) {           // invalid map entry: no access
@@ -636,6 +641,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     Uq = U + (size_t)kq * nb * nb;
                     eq = a.eps + (size_t)kq * nb;
                     fq = a.ftab + (size_t)kq * nb;
+                    if constexpr (TR) vq = a.vel + (size_t)kq * nb * 3;
                 } else {
                     const size_t pr = (size_t)k * a.qc + ql;
                     Uq = reinterpret_cast<const double2*>(a.U_pair) + pr * nb * nb;
@@ -646,6 +652,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 const double nB = a.nbose[(size_t)ql * nm + nu];
                 CE uq[RUN][NBP];
                 double em[RUN], fm[RUN], dm[RUN];
+                double vm[TR ? RUN : 1][3];
                 bool mv[RUN];
 #pragma unroll
                 for (int t = 0; t < RUN; ++t) {
@@ -656,6 +663,9 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     if constexpr (PH) {
                         const double ym = (em[t] - a.mu) * inv_sig;
                         dm[t] = mv[t] ? exp(-ym * ym) : 0.0;
+                    }
+                    if constexpr (TR) {
+                        for (int c = 0; c < 3; ++c) vm[t][c] = mv[t] ? vq[3 * m + c] : 0.0;
                     }
 #pragma unroll
                     for (int i = 0; i < NBP; ++i) {
@@ -669,7 +679,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     if (n >= nb) break;
                     double epsn;
                     if constexpr (HOIST) epsn = eps_h[n]; else epsn = a.eps[(size_t)k * nb + n];
-                    TE W[RUN], WL[RUN];
+                    TE W[RUN], WL[RUN], WT[TR ? RUN : 1];
                     bool need = STORE || POLE;
                     if constexpr (PH) {
                         // Eq. (9): [f_nk - f_m,k+q] exp(-((eps_nk - eps_m,k+q - omega)/sigma)^2);
@@ -677,15 +687,29 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                         const double fn = a.ftab[(size_t)k * nb + n];
                         const double yn = (epsn - a.mu) * inv_sig;
                         const double dn = exp(-yn * yn);
+                        // Eq. (55): 1 - v_nk . v_m,k+q / |v_nk|^2, 1 at a zero velocity
+                        double vn[3] = {0.0, 0.0, 0.0}, inv_vv = 0.0;
+                        if constexpr (TR) {
+                            for (int c = 0; c < 3; ++c) vn[c] = a.vel[((size_t)k * nb + n) * 3 + c];
+                            const double vv = vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2];
+                            inv_vv = vv > 1e-18 ? 1.0 / vv : 0.0;
+                        }
 #pragma unroll
                         for (int t = 0; t < RUN; ++t) {
                             W[t] = TE(0);
                             WL[t] = TE(0);
+                            if constexpr (TR) WT[t] = TE(0);
                             if (!mv[t]) continue;
                             const double y = (epsn - em[t] - w) * inv_sig;
                             const double s1 = y * y;
                             if (s1 < ylim) W[t] = (TE)(fn - fm[t]) * fexp((TE)(-s1));
                             WL[t] = (TE)(dn * dm[t]);
+                            if constexpr (TR) {
+                                const double fac = inv_vv > 0.0
+                                    ? 1.0 - (vn[0] * vm[t][0] + vn[1] * vm[t][1] + vn[2] * vm[t][2]) * inv_vv
+                                    : 1.0;
+                                WT[t] = (TE)(dn * dm[t] * fac);
+                            }
                             need = need || (s1 < ylim) || (WL[t] != TE(0));
                         }
                     } else if constexpr (RE) {
@@ -748,6 +772,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                             const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
                             pp[rr] += (double)(g2 * W[t]);
                             pl[rr] += (double)(g2 * WL[t]);
+                            if constexpr (TR) pt[rr] += (double)(g2 * WT[TR ? t : 0]);
                         } else if (RE) {
                             const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
                             acc[n] += (double)(g2 * W[t]);
@@ -784,12 +809,14 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
             const int jslot = x0 / RUN;
             const size_t ncb = (size_t)a.qc * nm;
 #pragma unroll
-            for (int kind = 0; kind < 2; ++kind) {
+            for (int kind = 0; kind < (TR ? 3 : 2); ++kind) {
                 __syncthreads();                            // V, or the previous pass, no longer read
 #pragma unroll
                 for (int rr = 0; rr < NRUN; ++rr) {
                     const int b = (sub * JI + rr * RUN) / NBP;
-                    red[((size_t)b * BM + r) * SPB + jslot] = kind == 0 ? pp[rr] : pl[rr];
+                    double val = kind == 0 ? pp[rr] : pl[rr];
+                    if constexpr (TR) val = kind == 2 ? pt[rr] : val;
+                    red[((size_t)b * BM + r) * SPB + jslot] = val;
                 }
                 __syncthreads();
                 for (int t = tid; t < NBLK * BM; t += 256) {
@@ -809,7 +836,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
         }
         __syncthreads();
     }
-    if constexpr (KIND == 1 || KIND == 2 || KIND == 4) return;
+    if constexpr (KIND == 1 || KIND == 2 || KIND == 4 || KIND == 5) return;
     // fixed-order reduction over the TPR threads of each row (real-part
     // mode: the on-shell sums, then the sums at eps_F)
     double* red = reinterpret_cast<double*>(smem);   // [BM][TPR][NBP]
@@ -990,25 +1017,26 @@ __global__ __launch_bounds__(256) void dos_raw_kernel(size_t n, const double* __
 __global__ void phonon_finalize_kernel(int qc, int nm, int tiles_m, const double* __restrict__ part_ph,
                                        const double* __restrict__ omega, double omega_cut,
                                        const double* __restrict__ raw_dos, int nk, double sigma,
-                                       double* __restrict__ pi_im, double* __restrict__ lam)
+                                       double* __restrict__ pi_im, double* __restrict__ lam,
+                                       double* __restrict__ lam_tr)
 {
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
     const int ncb = qc * nm;
     if (idx >= ncb) return;
-    double P = 0.0, L = 0.0;
+    double P = 0.0, L = 0.0, Lt = 0.0;
     for (int t = 0; t < tiles_m; ++t) {
         P += part_ph[(size_t)t * ncb + idx];
         L += part_ph[((size_t)tiles_m + t) * ncb + idx];
+        if (lam_tr) Lt += part_ph[((size_t)2 * tiles_m + t) * ncb + idx];
     }
     const double w = omega[idx];
     const bool keep = w >= omega_cut;
     constexpr double kPi = 3.141592653589793;
     const double gnorm = 1.0 / (sigma * sqrt(kPi));
-    pi_im[idx] = keep ? 2.0 * kPi * gnorm * P / (double)nk : 0.0;
-    if (lam) {
-        const double raw = raw_dos[0];
-        lam[idx] = (keep && raw > 0.0) ? gnorm * L / (raw * w) : 0.0;
-    }
+    if (pi_im) pi_im[idx] = keep ? 2.0 * kPi * gnorm * P / (double)nk : 0.0;
+    const double raw = raw_dos[0];
+    if (lam) lam[idx] = (keep && raw > 0.0) ? gnorm * L / (raw * w) : 0.0;
+    if (lam_tr) lam_tr[idx] = (keep && raw > 0.0) ? gnorm * Lt / (raw * w) : 0.0;
 }
 
 inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / bs); }
@@ -1038,6 +1066,7 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     };
     if (a.gkq) go(std::integral_constant<int, 1>());
     else if (a.rec) go(std::integral_constant<int, 4>());
+    else if (a.part_ph && a.vel) go(std::integral_constant<int, 5>());
     else if (a.part_ph) go(std::integral_constant<int, 2>());
     else if (a.part2) go(std::integral_constant<int, 3>());
     else go(std::integral_constant<int, 0>());
@@ -1133,11 +1162,11 @@ void launch_dos_raw(size_t n, const double* eps, double mu, double sigma, double
 
 void launch_phonon_finalize(int qc, int nm, int tiles_m, const double* part_ph, const double* omega,
                             double omega_cut, const double* raw_dos, int nk, double sigma, double* pi_im,
-                            double* lam, hipStream_t stream) {
+                            double* lam, hipStream_t stream, double* lam_tr) {
     const int n = qc * nm;
     if (n == 0) return;
     phonon_finalize_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(qc, nm, tiles_m, part_ph, omega, omega_cut,
-                                                                  raw_dos, nk, sigma, pi_im, lam);
+                                                                  raw_dos, nk, sigma, pi_im, lam, lam_tr);
     launch_check("phonon_finalize_kernel");
 }
 

@@ -110,6 +110,7 @@ struct FusedArgs {
     double* part2;     // [S][nk][nb] second partials (real-part mode: Sigma' at omega = 0; part
                        // then holds Sigma' on shell)
     double* rec;       // [nk][qc][nm][nb] pole records of 4 + nbp doubles (pole mode)
+    const double* vel; // [nk][nb][3] band velocities of the k set (transport mode, with part_ph)
 };
 // a7 + a8 + a9 (imsigma mode), a7 + a8 (store mode, gkq != nullptr),
 // a7 + a8 + the phonon-linewidth sums (phonon mode, part_ph != nullptr), or
@@ -124,7 +125,7 @@ void launch_dos_raw(size_t n, const double* eps, double mu, double sigma, double
 // lam[q][nu] = sum_t part[1][t][q][nu] / (sigma sqrt(pi) raw_dos omega) (0 for cut modes or raw_dos = 0)
 void launch_phonon_finalize(int qc, int nm, int tiles_m, const double* part_ph, const double* omega,
                             double omega_cut, const double* raw_dos, int nk, double sigma, double* pi_im,
-                            double* lam, hipStream_t stream);
+                            double* lam, hipStream_t stream, double* lam_tr = nullptr);
 
 // ---- k_gemm.hip ----
 // C(m, n) (+)= sum_k A(m, k) B(k, n), complex in `prec` (F64 or F32).
@@ -221,6 +222,17 @@ void launch_sigma_omega_reduce(int nk, int nb, int nw, int S, const void* part, 
                                double scale, int acc, void* out, void* out0, hipStream_t stream);
 void launch_spectral_function(int nk, int nb, int nw, const double* eps, double mu, const double* wgrid,
                               const void* sig, const void* sig0, double* A, hipStream_t stream);
+
+// Transport (k_transport.hip): band velocities v_nk = Re diag(U^dag dH/dk U),
+// averaged over degenerate bands, at np points (vectors: Cartesian primitive
+// rows); alpha^2 F on a frequency grid; the Ziman resistivity integral.
+void launch_velocities(int nb, int nR, const int32_t* R, const int32_t* ndeg, const void* HR, const double* vectors9,
+                       int np, const double* kfrac, const double* eps, const void* U, double deg_tol, double* vel,
+                       hipStream_t stream);
+void launch_eliashberg(int nq, int nm, const double* omega, const double* lam, double nq_norm, int nw,
+                       const double* wgrid, double sigma, double* a2f, hipStream_t stream);
+void launch_ziman(int nw, const double* wgrid, const double* a2f, int nT, const double* T, double* out,
+                  hipStream_t stream);
 void launch_degenerate_average(int nk, int nb, const double* eps, double tol, double* v,
                                hipStream_t stream);
 

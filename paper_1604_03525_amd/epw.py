@@ -12,7 +12,7 @@ import torch
 from . import _lib
 from ._lib import (EPW_FP32, EPW_FP64, EPW_SPLIT_BF16, EPW_WS_IMSIGMA,  # noqa: F401
                    EPW_WS_IMSIGMA_BACKWARD, EPW_WS_INTERP_G, EPW_WS_PHONON, EPW_WS_RESIGMA,
-                   EpwError)
+                   EPW_WS_TRANSPORT, EpwError)
 
 DTYPES = {"fp64": EPW_FP64, "fp32": EPW_FP32, "split_bf16": EPW_SPLIT_BF16}
 
@@ -301,6 +301,73 @@ def spectral_function(system, points, params, wgrid, workspace=None):
     sig, sig0 = epw_selfenergy_omega(system, points, params, wgrid, workspace=workspace)
     eps, _ = epw_interp_bands(system.HR, system.Re, system.ndeg_e, points.k)
     return epw_spectral_function(eps, params.mu, wgrid, sig, sig0), sig, sig0, eps
+
+
+def _host9(vectors):
+    v = np.ascontiguousarray(np.asarray(vectors, dtype=np.float64).reshape(9))
+    return v, v.ctypes.data_as(ctypes.c_void_p)
+
+
+def epw_band_velocities(HR, R, ndeg, vectors, kfrac, deg_tol=1e-6):
+    """(eps [nk][nb], U [nk][nb][nb], v [nk][nb][3]) on the device of HR."""
+    lib = _lib.load()
+    dev = HR.device
+    HR = _dev(HR, torch.complex128, dev)
+    R = _dev(R, torch.int32, dev)
+    ndeg = _dev(ndeg, torch.int32, dev)
+    k = _dev(kfrac, torch.float64, dev)
+    nb, nk = HR.shape[-1], k.shape[0]
+    eps = torch.empty((nk, nb), dtype=torch.float64, device=dev)
+    U = torch.empty((nk, nb, nb), dtype=torch.complex128, device=dev)
+    v = torch.empty((nk, nb, 3), dtype=torch.float64, device=dev)
+    keep, vp = _host9(vectors)
+    _lib.check(lib.epw_band_velocities(nb, R.shape[0], _ptr(R), _ptr(ndeg), _ptr(HR), vp, nk, _ptr(k),
+                                       float(deg_tol), _ptr(eps), _ptr(U), _ptr(v), _stream(dev)))
+    return eps, U, v
+
+
+def epw_transport_coupling(system, points, params, vectors, want_lambda=True, want_pi=False, workspace=None):
+    """(lambda_tr [nq][nm], lambda or None, Pi'' or None), Sec. 6 Eq. (55)."""
+    lib = _lib.load()
+    ws = workspace or Workspace(system.device)
+    nbytes = epw_workspace_size(EPW_WS_TRANSPORT, system, points, params)
+    buf = ws.get(nbytes)
+    d = system.device
+    shape = (points.q.shape[0], system.nm)
+    ltr = torch.empty(shape, dtype=torch.float64, device=d)
+    lam = torch.empty(shape, dtype=torch.float64, device=d) if want_lambda else None
+    pi = torch.empty(shape, dtype=torch.float64, device=d) if want_pi else None
+    keep, vp = _host9(vectors)
+    s, p = system.c_struct(), points.c_struct()
+    _lib.check(lib.epw_transport_coupling(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), vp, _ptr(ltr),
+                                          _ptr(lam), _ptr(pi), _ptr(buf), buf.numel(), _stream(d)))
+    return ltr, lam, pi
+
+
+def epw_eliashberg_function(omega, lam, wgrid, sigma, nq_norm=None):
+    """alpha^2 F on the grid (Eq. (12), or Eq. (54) from lambda_tr)."""
+    lib = _lib.load()
+    d = lam.device
+    om = _dev(omega, torch.float64, d)
+    lam = _dev(lam, torch.float64, d)
+    w = _dev(wgrid, torch.float64, d)
+    nq, nm = om.shape
+    out = torch.empty(w.shape[0], dtype=torch.float64, device=d)
+    _lib.check(lib.epw_eliashberg_function(nq, nm, _ptr(om), _ptr(lam), float(nq if nq_norm is None else nq_norm),
+                                           w.shape[0], _ptr(w), float(sigma), _ptr(out), _stream(d)))
+    return out
+
+
+def epw_ziman_resistivity(wgrid, a2f_tr, temperatures):
+    """rho(T) n e^2 / m_e of Eq. (53) for each temperature (K)."""
+    lib = _lib.load()
+    d = a2f_tr.device
+    w = _dev(wgrid, torch.float64, d)
+    a = _dev(a2f_tr, torch.float64, d)
+    T = _dev(temperatures, torch.float64, d)
+    out = torch.empty(T.shape[0], dtype=torch.float64, device=d)
+    _lib.check(lib.epw_ziman_resistivity(w.shape[0], _ptr(w), _ptr(a), T.shape[0], _ptr(T), _ptr(out), _stream(d)))
+    return out
 
 
 def epw_phonon_selfenergy(system, points, params, want_lambda=True, workspace=None):

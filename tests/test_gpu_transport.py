@@ -1,0 +1,131 @@
+"""Transport coupling (Sec. 6 Eqs. (53)-(55)) and band velocities: HIP path
+against the FP64 oracle, through the C ABI.  Tolerances: FP64 1e-10
+(velocities, lambda_tr), FP32 1e-5, split-BF16 1e-4, 1e-12 for the
+Eliashberg function and the resistivity integral of given inputs."""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import phonon as ph
+from oracle import transport as tr
+from paper_1604_03525_amd import epw
+from paper_1604_03525_amd import inputs as I
+from tests.helpers import fcc_small_case, realistic_case, rel_err, toy_case
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+TOL = {"fp64": 1e-10, "fp32": 1e-5, "split_bf16": 1e-4}
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _system(c):
+    return epw.System(c["R"], c["nd"], c["R"], c["nd"], c["HR"], c["DR"], c["gR"], DEV)
+
+
+def _params(c, **kw):
+    base = dict(T=c["T"], mu=c["mu"], sigma=c["sigma"])
+    base.update(kw)
+    return epw.make_params(**base)
+
+
+def test_velocities_parity():
+    """Toy band against its closed form and the oracle; 8-band fcc at random
+    points and on a grid (band crossings at symmetric points are averaged)."""
+    c = toy_case()
+    k = I.random_points(200, 4)
+    _, _, v = epw.epw_band_velocities(torch.as_tensor(c["HR"]).to(DEV), c["R"], c["nd"], I.SC_VECTORS, k)
+    v = v.cpu().numpy()
+    assert np.max(np.abs(v[:, 0, :] - 2 * np.sin(2 * np.pi * k))) < 1e-12
+    f = fcc_small_case(nb=8, kg=(4, 4, 4), seed=8)
+    for pts in (I.random_points(300, 5), f["k"]):
+        _, _, v = epw.epw_band_velocities(torch.as_tensor(f["HR"]).to(DEV), f["R"], f["nd"], I.FCC_VECTORS, pts)
+        ref = tr.velocities(f["HR"], f["R"], f["nd"], I.FCC_VECTORS, pts)
+        _say("velocities", rel_err(v.cpu().numpy(), ref))
+        assert rel_err(v.cpu().numpy(), ref) < 1e-10
+
+
+def _ref(c, vectors, qidx=None):
+    q = c["q"] if qidx is None else c["q"][qidx]
+    ltr = tr.lambda_tr(c["HR"], c["R"], c["nd"], c["DR"], c["R"], c["nd"], c["gR"], c["k"], q, c["mu"], c["sigma"],
+                       vectors)
+    pi, lam = ph.phonon_selfenergy(c["HR"], c["R"], c["nd"], c["DR"], c["R"], c["nd"], c["gR"], c["k"], q, c["T"],
+                                   c["mu"], c["sigma"], loop="q")
+    return ltr, lam, pi
+
+
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "split_bf16"])
+def test_toy_complete(dtype):
+    """The 8^3 toy, broad and hot (sigma = 0.3 eV, mu = 0.5 eV), every q."""
+    c = toy_case()
+    c.update(T=2000.0, mu=0.5, sigma=0.3)
+    ltr, lam, pi = epw.epw_transport_coupling(_system(c), epw.Points(c["k"], c["q"], c["kq"], device=DEV),
+                                              _params(c, dtype=dtype), I.SC_VECTORS, want_pi=True)
+    rl, rlam, rpi = _ref(c, I.SC_VECTORS)
+    errs = (rel_err(ltr.cpu().numpy(), rl), rel_err(lam.cpu().numpy(), rlam), rel_err(pi.cpu().numpy(), rpi))
+    _say("transport toy", dtype, errs)
+    assert np.abs(rl).max() > 0
+    assert max(errs) < TOL[dtype]
+
+
+@pytest.mark.parametrize("nb", [2, 5, 8])
+def test_fcc_band_counts(nb):
+    """Padded band blocks and ragged q chunks, FP64; lambda_tr also agrees
+    with the phonon call's lambda where the two differ only by the factor."""
+    c = fcc_small_case(nb=nb, kg=(3, 3, 3), seed=nb)
+    rl, rlam, _ = _ref(c, I.FCC_VECTORS)
+    pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
+    for chunk in (0, 7):
+        ltr, lam, _ = epw.epw_transport_coupling(_system(c), pts, _params(c, chunk_q=chunk), I.FCC_VECTORS)
+        _say("transport fcc nb", nb, chunk, rel_err(ltr.cpu().numpy(), rl), rel_err(lam.cpu().numpy(), rlam))
+        assert rel_err(ltr.cpu().numpy(), rl) < 1e-10
+        assert rel_err(lam.cpu().numpy(), rlam) < 1e-10
+    _, lam2 = epw.epw_phonon_selfenergy(_system(c), pts, _params(c))
+    assert rel_err(lam.cpu().numpy(), lam2.cpu().numpy()) < 1e-13
+
+
+def test_eliashberg_and_resistivity():
+    """alpha_tr^2 F from the GPU lambda_tr and the Ziman integral against the
+    oracle's formulas on the same inputs."""
+    c = fcc_small_case(nb=5, kg=(4, 4, 4), seed=3)
+    pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
+    ltr, _, _ = epw.epw_transport_coupling(_system(c), pts, _params(c), I.FCC_VECTORS, want_lambda=False)
+    om, _ = epw.epw_interp_phonons(torch.as_tensor(c["DR"]).to(DEV), c["R"], c["nd"], c["q"])
+    w = np.linspace(0.0, 0.08, 801)
+    a2f = epw.epw_eliashberg_function(om, ltr, w, 0.002)
+    ref = tr.eliashberg_function(om.cpu().numpy(), ltr.cpu().numpy(), w, 0.002)
+    assert rel_err(a2f.cpu().numpy(), ref) < 1e-12
+    T = np.array([0.0, 50.0, 300.0, 1000.0])
+    rho = epw.epw_ziman_resistivity(w, a2f, T).cpu().numpy()
+    want = np.array([tr.ziman_integral(w, ref, t) for t in T])
+    _say("ziman", rho, want)
+    assert rho[0] == 0.0
+    assert rel_err(rho, want) < 1e-12
+
+
+def test_requires_grid_map():
+    c = fcc_small_case(nb=3, kg=(2, 2, 2), seed=2)
+    with pytest.raises(epw.EpwError) as e:
+        epw.epw_transport_coupling(_system(c), epw.Points(c["k"], c["q"], None, device=DEV), _params(c),
+                                   I.FCC_VECTORS)
+    assert e.value.code == epw._lib.EPW_EINVAL
+
+
+def test_realistic_full_size_sampled_q():
+    """The benchmark system at full size (20^3 x 20^3), FP64, with eps_F moved
+    0.3 eV into the valence bands and sigma = 50 meV so that states sit at the
+    Fermi level; the oracle evaluates three q points against all 8000 k."""
+    c = realistic_case()
+    c.update(mu=c["mu"] - 0.3, sigma=0.05)
+    ltr, lam, _ = epw.epw_transport_coupling(_system(c), epw.Points(c["k"], c["q"], c["kq"], device=DEV),
+                                             _params(c), I.FCC_VECTORS)
+    qidx = np.array([1, 2345, 7777])
+    rl, rlam, _ = _ref(c, I.FCC_VECTORS, qidx)
+    _say("transport realistic", rel_err(ltr.cpu().numpy()[qidx], rl), rel_err(lam.cpu().numpy()[qidx], rlam))
+    assert np.abs(rl).max() > 0
+    assert rel_err(ltr.cpu().numpy()[qidx], rl) < 1e-10
+    assert rel_err(lam.cpu().numpy()[qidx], rlam) < 1e-10
