@@ -177,7 +177,7 @@ struct Layout {
     double* part_ph = nullptr;   // [2][tiles_m][Q nm] (phonon mode)
     double* dos_raw = nullptr;   // [1] (phonon mode)
     int nw = 0;                  // frequency-grid mode: grid size,
-    double* rec = nullptr;       // [nk][Q][nm][nb] pole records of 4 + nbp doubles (+ 1),
+    double* rec = nullptr;       // [nk][Q][nm][nb] pole records of 4 + nbp doubles (+ 2),
     void* spart = nullptr;       // [S_w][nk][nb][nw + 1] c128 slice partials
     int Sw = 1;
     void* polar_L = nullptr;     // [Q][nm] c128 long-range factors (polar systems)
@@ -290,8 +290,8 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     if (out == Out::RESIGMA) L.part2 = (double*)A.take(8 * (size_t)L.S * nk * nb);
     if (omg) {
         L.nw = nw;
-        // one record of padding: the frequency kernel reads one record ahead
-        L.rec = (double*)A.take(8 * ((size_t)nk * L.Q * nm * nb + 1) * (4 + L.nbp));
+        // two records of padding: the frequency kernel reads two records ahead
+        L.rec = (double*)A.take(8 * ((size_t)nk * L.Q * nm * nb + 2) * (4 + L.nbp));
         // slice count of the largest chunk bounds every chunk's
         int smax = 1;
         for (int qc : {L.Q, nq % L.Q}) {

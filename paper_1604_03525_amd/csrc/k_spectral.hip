@@ -55,30 +55,45 @@ __global__ __launch_bounds__(64) void sigma_omega_kernel(int nk, int nb, long np
         are[n] = 0.0;
         aim[n] = 0.0;
     }
-    // records at wave-uniform addresses, one record read ahead (the buffer
-    // holds one record of padding past the last)
+    // records at wave-uniform addresses, two at a time, the next two read
+    // ahead (the buffer holds two records of padding past the last)
     const double* r = rec + ((size_t)k * npole + p0) * RS;
-    double cur[RS];
-#pragma unroll
-    for (int i = 0; i < RS; ++i) cur[i] = r[i];
-    for (long p = p0; p < p1; ++p) {
-        r += RS;
-        double nxt[RS];
-#pragma unroll
-        for (int i = 0; i < RS; ++i) nxt[i] = r[i];
-        const double x1 = w - cur[0], x2 = w - cur[1];
-        const double t1 = cur[2] * recip_pos(fma(x1, x1, d2));
-        const double t2 = cur[3] * recip_pos(fma(x2, x2, d2));
+    auto pole = [&](const double* c) {
+        const double x1 = w - c[0], x2 = w - c[1];
+        const double t1 = c[2] * recip_pos(fma(x1, x1, d2));
+        const double t2 = c[3] * recip_pos(fma(x2, x2, d2));
         const double wre = fma(t1, x1, t2 * x2);       // real part of the braces
         const double wim = t1 + t2;                    // imaginary part is -d wim
 #pragma unroll
         for (int n = 0; n < NBT; ++n) {
-            are[n] = fma(cur[4 + n], wre, are[n]);
-            aim[n] = fma(cur[4 + n], wim, aim[n]);
+            are[n] = fma(c[4 + n], wre, are[n]);
+            aim[n] = fma(c[4 + n], wim, aim[n]);
         }
+    };
+    double c0[RS], c1[RS];
 #pragma unroll
-        for (int i = 0; i < RS; ++i) cur[i] = nxt[i];
+    for (int i = 0; i < RS; ++i) {
+        c0[i] = r[i];
+        c1[i] = r[RS + i];
     }
+    long p = p0;
+    for (; p + 1 < p1; p += 2) {
+        r += 2 * RS;
+        double n0[RS], n1[RS];
+#pragma unroll
+        for (int i = 0; i < RS; ++i) {
+            n0[i] = r[i];
+            n1[i] = r[RS + i];
+        }
+        pole(c0);
+        pole(c1);
+#pragma unroll
+        for (int i = 0; i < RS; ++i) {
+            c0[i] = n0[i];
+            c1[i] = n1[i];
+        }
+    }
+    if (p < p1) pole(c0);
     if (j > nw) return;
     const size_t ld = (size_t)nw + 1;
 #pragma unroll
