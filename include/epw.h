@@ -211,8 +211,17 @@ typedef struct {
     int32_t dtype;         /* EPW_FP64 / EPW_FP32 / EPW_SPLIT_BF16               */
     int32_t chunk_q;       /* q points per chunk (0 = choose from the workspace) */
     int32_t accumulate;    /* 0: overwrite the output, 1: add to it              */
-    int32_t reserved;
+    int32_t order;         /* contraction order of epw_selfenergy_omega (other
+                              calls ignore it): EPW_ORDER_AUTO, EPW_ORDER_K_INNER
+                              (per q chunk R_p -> q, then R_e -> k fused with the
+                              rotation) or EPW_ORDER_K_OUTER (R_e -> k once for
+                              all k, then R_p -> q per chunk and a per-pair
+                              rotation; cheaper when n_k is small against N_e) */
 } epw_params;
+
+#define EPW_ORDER_AUTO     0   /* k-outer when 4 n_k <= N_e */
+#define EPW_ORDER_K_INNER  1
+#define EPW_ORDER_K_OUTER  2
 
 /* Electron-phonon vertex in the band/mode basis (Sec. 3 Eq. (2)):
  *   g_mn,nu(k,q) = [U_{k+q}^dag (sum_ka g_ka(k,q) e_ka,nu(q)) U_k]_mn / sqrt(2 omega_q,nu)

@@ -25,6 +25,9 @@ EPW_WS_IMSIGMA_BACKWARD = 3
 EPW_WS_PHONON = 4
 EPW_WS_RESIGMA = 5
 EPW_WS_TRANSPORT = 6
+EPW_ORDER_AUTO = 0
+EPW_ORDER_K_INNER = 1
+EPW_ORDER_K_OUTER = 2
 
 EPW_STAGE_EIGH = 0
 EPW_STAGE_GEMM_RP = 1
@@ -71,7 +74,7 @@ class EpwParams(ctypes.Structure):
                 ("omega_cut", ctypes.c_double), ("deg_tol", ctypes.c_double),
                 ("nq_norm", ctypes.c_double), ("dtype", ctypes.c_int32),
                 ("chunk_q", ctypes.c_int32), ("accumulate", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("order", ctypes.c_int32)]
 
 
 # name -> (restype, argtypes); every symbol include/epw.h declares

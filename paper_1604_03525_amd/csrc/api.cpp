@@ -119,6 +119,8 @@ int check_common(const epw_system* s, const epw_points* p, const epw_params* par
     if (!(par->nq_norm >= 0.0)) return fail(EPW_EINVAL, "%s: nq_norm must be >= 0", fn);
     if (!std::isfinite(par->omega_cut)) return fail(EPW_EINVAL, "%s: omega_cut not finite", fn);
     if (par->chunk_q < 0) return fail(EPW_EINVAL, "%s: chunk_q < 0", fn);
+    if (par->order < EPW_ORDER_AUTO || par->order > EPW_ORDER_K_OUTER)
+        return fail(EPW_EINVAL, "%s: unknown contraction order %d", fn, par->order);
     if (s->nmax_e < 0 || s->nmax_e > EPW_MAX_NMAX)
         return fail(EPW_EINVAL, "%s: nmax_e = %d not in 0..%d", fn, s->nmax_e, EPW_MAX_NMAX);
     if (s->polar) {
@@ -182,6 +184,11 @@ struct Layout {
     int Sw = 1;
     void* polar_L = nullptr;     // [Q][nm] c128 long-range factors (polar systems)
     double* vel = nullptr;       // [nk][nb][3] band velocities (transport mode)
+    // k-outer order (frequency-grid mode): R_e -> k once, R_p -> q per chunk
+    bool kouter = false;
+    void* phi_e = nullptr;       // [nk][N_e] phases with 1/ndeg_e
+    void* Gk = nullptr;          // [N_p][nk][nm nb nb] g(k, R_p)
+    void* Cq = nullptr;          // [nk][Q][nm nb nb] g(k, q), Wannier basis
     // per pair states at k+q when no k+q map is given
     double* eps_pair = nullptr;
     void* U_pair = nullptr;
@@ -260,10 +267,12 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     const bool bf = L.prec == Prec::BF16X2;
     L.kpad = (ne + 31) / 32 * 32;
     const size_t bcol_bytes = bf ? 8 * (size_t)L.kpad : cb * (size_t)ne;   // B bytes per column
+    const size_t X = (size_t)nm * nb * nb;
+    L.kouter = omg && (par->order == EPW_ORDER_K_OUTER || (par->order == EPW_ORDER_AUTO && 4L * nk <= ne));
     // chunk size
-    const size_t per_q = cb * ((size_t)ne * nm * nb * nb + np_) + bcol_bytes * nm * L.nbp * L.nbp +
-                         (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm +
-                         pair_bytes_per_q(s, p) + (omg ? 8 * (size_t)nk * nm * nb * (4 + L.nbp) : 0);
+    const size_t per_q = cb * np_ + (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm +
+                         pair_bytes_per_q(s, p) + (omg ? 8 * (size_t)nk * nm * nb * (4 + L.nbp) : 0) +
+                         (L.kouter ? cb * (size_t)nk * X : cb * (size_t)ne * X + bcol_bytes * nm * L.nbp * L.nbp);
     long Q = par->chunk_q > 0 ? par->chunk_q : (long)(AUTO_CHUNK_BYTES / per_q);
     if (Q < 1) Q = 1;
     if (Q > nq) Q = nq > 0 ? nq : 1;
@@ -273,7 +282,7 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     L.eps = (double*)A.take(8 * (size_t)nk * nb);
     L.U = A.take(16 * (size_t)nk * nb * nb);
     L.ftab = (double*)A.take(8 * (size_t)nk * nb);
-    L.phi_k = A.take(bf ? 8 * (size_t)nk * L.kpad : cb * (size_t)nk * ne);
+    if (!L.kouter) L.phi_k = A.take(bf ? 8 * (size_t)nk * L.kpad : cb * (size_t)nk * ne);
     if (L.prec != Prec::F64) L.gR_t = A.take(cb * (size_t)ne * np_ * nm * nb * nb);
     if (!given) {
         L.omega_c = (double*)A.take(8 * (size_t)L.Q * nm);
@@ -282,8 +291,14 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     L.sc = (double*)A.take(8 * (size_t)L.Q * nm);
     L.nbose = (double*)A.take(8 * (size_t)L.Q * nm);
     L.phi_q = A.take(cb * (size_t)L.Q * np_);
-    L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
-    L.Bnu = A.take(bcol_bytes * L.Q * nm * L.nbp * L.nbp);
+    if (L.kouter) {
+        L.phi_e = A.take(cb * (size_t)nk * ne);
+        L.Gk = A.take(cb * (size_t)np_ * nk * X);
+        L.Cq = A.take(cb * (size_t)nk * L.Q * X);
+    } else {
+        L.gq = A.take(cb * (size_t)ne * L.Q * X);
+        L.Bnu = A.take(bcol_bytes * L.Q * nm * L.nbp * L.nbp);
+    }
     if (s->polar) L.polar_L = A.take(16 * (size_t)L.Q * nm);
     L.tiles_m = (nk + fused_tile_rows(L.nbp) - 1) / fused_tile_rows(L.nbp);
     if (out == Out::IMSIGMA || out == Out::RESIGMA) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
@@ -363,11 +378,32 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
     // R_e offsets of a tile in LDS, hence the bound on ne.  The 1/ndeg weights
     // of R_e are folded into the B operand (mode rotation) in both cases.
     const bool gen = prec != Prec::F64 && s->nmax_e > 0 && ne <= 4096;
-    if (!gen) launch_phase_table(prec, nk, p->kfrac, ne, s->Re, nullptr, bf ? L.kpad : ne, L.phi_k, st);
+    if (!gen && !L.kouter) launch_phase_table(prec, nk, p->kfrac, ne, s->Re, nullptr, bf ? L.kpad : ne, L.phi_k, st);
     const void* gsrc = s->gR;
     if (prec != Prec::F64) {
         launch_c128_to_c64((size_t)ne * np_ * nm * nb * nb, s->gR, L.gR_t, st);
         gsrc = L.gR_t;
+    }
+    const int X = nm * nb * nb;
+    if (L.kouter) {
+        // k-outer: g(k, R_p)[p][k][x] = sum_e Phi_k[k][e] g(R_e, R_p)[e][p][x], once for all chunks
+        StageTimer t(EPW_STAGE_GEMM_RP, st);
+        const Prec kp = prec == Prec::BF16X2 ? Prec::F32 : prec;
+        launch_phase_table(kp, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_e, st);
+        GemmDesc d;
+        d.M = nk;
+        d.N = np_ * X;
+        d.K = ne;
+        d.A = L.phi_e;
+        d.lda = ne;
+        d.B = gsrc;
+        d.ncb = X;
+        d.sBe = X;
+        d.sBk = (long)np_ * X;
+        d.C = L.Gk;
+        d.sCe = (long)nk * X;
+        d.sCm = X;
+        launch_cgemm(kp, d, st);
     }
     const double nqn = par->nq_norm > 0.0 ? par->nq_norm : (double)nq;
     const double scale = M_PI / (nqn * par->sigma * std::sqrt(M_PI));
@@ -395,6 +431,63 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         }
         pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, L.ps, st);
         launch_phase_table(rprec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
+        if (L.kouter) {
+            {
+                // g(k, q)[k][q][x] = sum_p Phi_q[q][p] g(k, R_p)[p][k][x]
+                StageTimer t(EPW_STAGE_GEMM_RP, st);
+                GemmDesc d;
+                d.M = qc;
+                d.N = nk * X;
+                d.K = np_;
+                d.A = L.phi_q;
+                d.lda = np_;
+                d.B = L.Gk;
+                d.ncb = X;
+                d.sBe = X;
+                d.sBk = (long)nk * X;
+                d.C = L.Cq;
+                d.sCe = (long)qc * X;
+                d.sCm = X;
+                launch_cgemm(rprec, d, st);
+            }
+            {
+                StageTimer t(EPW_STAGE_FUSED, st);
+                PairPoleArgs pa;
+                pa.nk = nk;
+                pa.nb = nb;
+                pa.nbp = L.nbp;
+                pa.nm = nm;
+                pa.qc = qc;
+                pa.q0 = q0;
+                pa.nq_total = nq;
+                pa.C = L.Cq;
+                pa.c64 = rprec == Prec::F64 ? 0 : 1;
+                pa.U = L.U;
+                pa.kq = p->kq;
+                pa.eps = L.eps;
+                pa.ftab = L.ftab;
+                pa.eps_pair = L.eps_pair;
+                pa.f_pair = L.f_pair;
+                pa.U_pair = L.U_pair;
+                pa.omega = om;
+                pa.nbose = L.nbose;
+                pa.sc = L.sc;
+                pa.evec = ev;
+                pa.Lq = L.polar_L;
+                pa.mu = par->mu;
+                pa.rec = L.rec;
+                launch_pair_pole(pa, st);
+            }
+            const long npole = (long)qc * nm * nb;
+            const int sw = sigma_omega_slices(nk, L.nw, npole);
+            {
+                StageTimer t(EPW_STAGE_SPECTRAL, st);
+                launch_sigma_omega(nk, nb, npole, L.nw, wgrid, par->sigma, L.rec, sw, L.spart, st);
+            }
+            launch_sigma_omega_reduce(nk, nb, L.nw, sw, L.spart, L.eps, par->deg_tol, 1.0 / nqn,
+                                      (c > 0 || par->accumulate) ? 1 : 0, sig_w, sig0, st);
+            continue;
+        }
         {
             StageTimer t(EPW_STAGE_GEMM_RP, st);
             launch_cgemm(rprec, rp_desc(qc, ne, np_, nm * nb * nb, L.phi_q, gsrc, L.gq), st);

@@ -182,7 +182,118 @@ __global__ void spectral_function_kernel(int nk, int nb, int nw, const double* _
     A[idx] = im / (M_PI * (x * x + im * im));
 }
 
+// One block (one wave) per (k, q) pair: for each mode nu, the Wannier-basis
+// g_nu[i][j] = sc_nu sum_a C[a][i][j] e[a][nu] (+ L_nu delta_ij), then
+// T = g_nu U_k and h = U_k+q^dag T, written as the pole records of (k, q, nu, m).
+template <typename CT>
+__global__ __launch_bounds__(64) void pair_pole_kernel(PairPoleArgs a)
+{
+    __shared__ double2 Uk[EPW_MAX_NB * EPW_MAX_NB], Uq[EPW_MAX_NB * EPW_MAX_NB];
+    __shared__ double2 Gv[EPW_MAX_NB * EPW_MAX_NB], Tm[EPW_MAX_NB * EPW_MAX_NB];
+    __shared__ double emq[EPW_MAX_NB], fmq[EPW_MAX_NB];
+    const long pr = blockIdx.x;                      // k * qc + ql
+    const int k = (int)(pr / a.qc), ql = (int)(pr % a.qc);
+    const int tid = threadIdx.x;
+    const int nb = a.nb, nb2 = nb * nb, nm = a.nm, RS = 4 + a.nbp;
+    double* rec0 = a.rec + (size_t)pr * nm * nb * RS;
+    const double2* Uqs;
+    const double* eq;
+    const double* fq;
+    if (a.kq) {
+        const int kq = a.kq[(size_t)k * a.nq_total + a.q0 + ql];
+        if ((unsigned)kq >= (unsigned)a.nk) {        // invalid map entry: zero records
+            for (int t = tid; t < nm * nb * RS; t += 64) rec0[t] = 0.0;
+            return;
+        }
+        Uqs = reinterpret_cast<const double2*>(a.U) + (size_t)kq * nb2;
+        eq = a.eps + (size_t)kq * nb;
+        fq = a.ftab + (size_t)kq * nb;
+    } else {
+        Uqs = reinterpret_cast<const double2*>(a.U_pair) + (size_t)pr * nb2;
+        eq = a.eps_pair + (size_t)pr * nb;
+        fq = a.f_pair + (size_t)pr * nb;
+    }
+    const double2* Uks = reinterpret_cast<const double2*>(a.U) + (size_t)k * nb2;
+    for (int t = tid; t < nb2; t += 64) {
+        Uk[t] = Uks[t];
+        Uq[t] = Uqs[t];
+    }
+    if (tid < nb) {
+        emq[tid] = eq[tid];
+        fmq[tid] = fq[tid];
+    }
+    const CT* C = reinterpret_cast<const CT*>(a.C) + (size_t)pr * nm * nb2;
+    const double2* ev = reinterpret_cast<const double2*>(a.evec) + (size_t)ql * nm * nm;
+    for (int nu = 0; nu < nm; ++nu) {
+        const double s = a.sc[(size_t)ql * nm + nu];
+        __syncthreads();                             // Gv, Tm of the previous mode no longer read
+        for (int t = tid; t < nb2; t += 64) {
+            double gr = 0.0, gi = 0.0;
+            if (s != 0.0) {
+                for (int m = 0; m < nm; ++m) {
+                    const CT c = C[(size_t)m * nb2 + t];
+                    const double2 e = ev[(size_t)m * nm + nu];
+                    gr += (double)c.x * e.x - (double)c.y * e.y;
+                    gi += (double)c.x * e.y + (double)c.y * e.x;
+                }
+                gr *= s;
+                gi *= s;
+            }
+            if (a.Lq && t / nb == t % nb) {
+                const double2 l = reinterpret_cast<const double2*>(a.Lq)[(size_t)ql * nm + nu];
+                gr += l.x;
+                gi += l.y;
+            }
+            Gv[t] = make_double2(gr, gi);
+        }
+        __syncthreads();
+        for (int t = tid; t < nb2; t += 64) {        // T[i][n] = sum_j Gv[i][j] Uk[j][n]
+            const int i = t / nb, n = t % nb;
+            double tr = 0.0, ti = 0.0;
+            for (int j = 0; j < nb; ++j) {
+                const double2 g = Gv[i * nb + j], u = Uk[j * nb + n];
+                tr += g.x * u.x - g.y * u.y;
+                ti += g.x * u.y + g.y * u.x;
+            }
+            Tm[t] = make_double2(tr, ti);
+        }
+        __syncthreads();
+        const double w = a.omega[(size_t)ql * nm + nu];
+        const double nB = a.nbose[(size_t)ql * nm + nu];
+        for (int t = tid; t < nb2; t += 64) {        // h[m][n] = sum_i conj(Uq[i][m]) T[i][n]
+            const int m = t / nb, n = t % nb;
+            double hr = 0.0, hi = 0.0;
+            for (int i = 0; i < nb; ++i) {
+                const double2 u = Uq[i * nb + m], x = Tm[i * nb + n];
+                hr += u.x * x.x + u.y * x.y;
+                hi += u.x * x.y - u.y * x.x;
+            }
+            double* rec = rec0 + ((size_t)nu * nb + m) * RS;
+            rec[4 + n] = hr * hr + hi * hi;
+            if (n == 0) {
+                const double xi = emq[m] - a.mu;
+                const bool kept = s != 0.0;
+                rec[0] = xi - w;
+                rec[1] = xi + w;
+                rec[2] = kept ? nB + fmq[m] : 0.0;
+                rec[3] = kept ? nB + 1.0 - fmq[m] : 0.0;
+                for (int j = nb; j < a.nbp; ++j) rec[4 + j] = 0.0;
+            }
+        }
+    }
+}
+
 }  // namespace
+
+void launch_pair_pole(const PairPoleArgs& a, hipStream_t stream) {
+    const long pairs = (long)a.nk * a.qc;
+    if (pairs == 0) return;
+    if (a.c64)
+        pair_pole_kernel<float2><<<(unsigned)pairs, 64, 0, stream>>>(a);
+    else
+        pair_pole_kernel<double2><<<(unsigned)pairs, 64, 0, stream>>>(a);
+    launch_check("pair_pole_kernel");
+}
 
 int sigma_omega_slices(int nk, int nw, long npole) {
     const long waves = (long)nk * ((nw + 1 + 63) / 64);

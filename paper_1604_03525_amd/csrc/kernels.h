@@ -223,6 +223,31 @@ void launch_sigma_omega_reduce(int nk, int nb, int nw, int S, const void* part, 
 void launch_spectral_function(int nk, int nb, int nw, const double* eps, double mu, const double* wgrid,
                               const void* sig, const void* sig0, double* A, hipStream_t stream);
 
+// k-outer pole records: from the Wannier-basis vertex C[k][q][nm][nb][nb]
+// (complex, float64 or float32), the mode rotation (with 1/sqrt(2 omega) and
+// the polar term), the band rotation and the record layout of the fused
+// kernel's pole mode (4 + nbp doubles per (k, q, nu, m)).
+struct PairPoleArgs {
+    int nk, nb, nbp, nm, qc, q0, nq_total;
+    const void* C;
+    int c64;
+    const void* U;              // [nk][nb][nb] c128
+    const int32_t* kq;          // [nk][nq_total] or NULL (then the pair states)
+    const double* eps;          // [nk][nb]
+    const double* ftab;         // [nk][nb]
+    const double* eps_pair;     // [nk][qc][nb]
+    const double* f_pair;       // [nk][qc][nb]
+    const void* U_pair;         // [nk][qc][nb][nb] c128
+    const double* omega;        // [qc][nm]
+    const double* nbose;        // [qc][nm]
+    const double* sc;           // [qc][nm]
+    const void* evec;           // [qc][nm][nm] c128
+    const void* Lq;             // [qc][nm] c128 or NULL
+    double mu;
+    double* rec;
+};
+void launch_pair_pole(const PairPoleArgs& a, hipStream_t stream);
+
 // Transport (k_transport.hip): band velocities v_nk = Re diag(U^dag dH/dk U),
 // averaged over degenerate bands, at np points (vectors: Cartesian primitive
 // rows); alpha^2 F on a frequency grid; the Ziman resistivity integral.

@@ -179,11 +179,14 @@ class Points:
                               _ptr(self.kq), _ptr(self.omega), _ptr(self.evec))
 
 
+ORDERS = {"auto": 0, "k_inner": 1, "k_outer": 2}
+
+
 def make_params(T=300.0, mu=0.0, sigma=0.05, omega_cut=1e-3, deg_tol=1e-6, nq_norm=0.0,
-                dtype="fp64", chunk_q=0, accumulate=False):
+                dtype="fp64", chunk_q=0, accumulate=False, order="auto"):
     return _lib.EpwParams(float(T), float(mu), float(sigma), float(omega_cut), float(deg_tol),
                           float(nq_norm), DTYPES[dtype] if isinstance(dtype, str) else int(dtype),
-                          int(chunk_q), int(bool(accumulate)), 0)
+                          int(chunk_q), int(bool(accumulate)), ORDERS[order] if isinstance(order, str) else int(order))
 
 
 def epw_workspace_size(which, system, points, params):

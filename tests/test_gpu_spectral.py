@@ -108,16 +108,64 @@ def test_offgrid_mobility_shape(dtype):
     _check(("omega offgrid", dtype), _gpu(c, w, kq=False, dtype=dtype), _oracle(c, w), c, w, TOL[dtype])
 
 
-def test_spectral_workload_full_size_sampled():
+@pytest.mark.parametrize("dtype", ["fp64", "fp32", "split_bf16"])
+def test_k_outer_order(dtype):
+    """The k-outer contraction order (R_e -> k once, R_p -> q per chunk, a
+    per-pair rotation) on the toy, a 5-band fcc case with ragged chunks and
+    the off-grid shape, against the same oracle."""
+    cases = [("toy", toy_case(), True, np.linspace(-1.5, 1.5, 70)),
+             ("fcc5", fcc_small_case(nb=5, kg=(3, 3, 3), seed=5), True, np.linspace(-1.0, 1.0, 65)),
+             ("offgrid", mobility_small_case(), False, np.linspace(-0.5, 0.5, 40))]
+    for name, c, kq, w in cases:
+        ref = _oracle(c, w)
+        for chunk in ((0, 7) if dtype == "fp64" else (0,)):
+            _check(("omega k-outer", name, dtype, chunk), _gpu(c, w, kq=kq, dtype=dtype, chunk_q=chunk,
+                                                                order="k_outer"), ref, c, w, TOL[dtype])
+
+
+@pytest.mark.parametrize("order", ["k_inner", "k_outer"])
+def test_polar_both_orders(order):
+    """With the polar long-range term: the oracle's polar vertex summed with
+    the frequency-resolved weights, both contraction orders."""
+    from oracle import interp, lattice, polar
+    from oracle.selfenergy import degenerate_average
+    R, nd = lattice.ws_vectors(I.FCC_METRIC, (3, 3, 3))
+    HR = I.random_hamiltonian(R, I.FCC_VECTORS, 4, seed=9, scale=0.8)
+    DR = I.spring_dynmat(R, I.FCC_VECTORS, I.ATOMS_FCC2, shells=2, seed=10, scale=4e-4)
+    gR = I.random_vertex(R, R, I.FCC_VECTORS, 6, 4, seed=11, g0=0.05)
+    k = lattice.grid_points(3, 3, 3)
+    par = I.polar_params()
+    T, mu, d = 300.0, 0.1, 0.15
+    w = np.linspace(-1.0, 1.0, 33)
+    wall = np.concatenate([w, [0.0]])
+    sig = np.zeros((len(k), 4, len(wall)), dtype=np.complex128)
+    for ik, kk in enumerate(k):
+        g, ek, ekq, om = polar.vertex_band(HR, R, nd, DR, R, nd, gR, kk, k, par)
+        sig[ik] = sp.sigma_from_states(g, ekq, om, mu, T, d, wall, len(k))
+    eps = interp.bands(HR, R, nd, k)[0]
+    for iw in range(len(wall)):
+        sig[:, :, iw] = (degenerate_average(eps, sig[:, :, iw].real, 1e-6)
+                         + 1j * degenerate_average(eps, sig[:, :, iw].imag, 1e-6))
+    sysd = epw.System(R, nd, R, nd, HR, DR, gR, DEV, polar=par)
+    pts = epw.Points(k, k, lattice.kq_index((3, 3, 3), (3, 3, 3)), device=DEV)
+    got, got0 = epw.epw_selfenergy_omega(sysd, pts, epw.make_params(T=T, mu=mu, sigma=d, order=order), w)
+    e1, e0 = rel_err(got.cpu().numpy(), sig[:, :, :-1]), rel_err(got0.cpu().numpy(), sig[:, :, -1])
+    _say("omega polar", order, e1, e0)
+    assert max(e1, e0) < 1e-10
+
+
+@pytest.mark.parametrize("order", ["auto", "k_inner"])
+def test_spectral_workload_full_size_sampled(order):
     """The spectral-function workload of the benchmark (realistic fcc system,
     64 k on Gamma-X, 10^5 random q, 512 frequencies, FP64) in its launch
-    configuration; the oracle evaluates two k points against all q at eight
-    sampled frequencies and omega = 0, in q blocks."""
+    configuration (auto: the k-outer order) and in the k-inner order; the
+    oracle evaluates two k points against all q at eight sampled frequencies
+    and omega = 0, in q blocks."""
     c = realistic_case()
     wl = I.spectral_workload()
     c.update(k=wl["k"], q=wl["q"], kq=None)
     w = wl["wgrid"]
-    A, sig, sig0, eps = _gpu(c, w, kq=False)
+    A, sig, sig0, eps = _gpu(c, w, kq=False, order=order)
     kidx = np.array([5, 40])
     jw = np.array([0, 77, 200, 255, 256, 300, 449, 511])
     nq = len(c["q"])
@@ -129,6 +177,6 @@ def test_spectral_workload_full_size_sampled():
         r0 += s0_
     rA = sp.spectral_function(reps, c["mu"], w[jw], rs, r0)
     errs = (rel_err(sig[kidx][:, :, jw], rs), rel_err(sig0[kidx], r0), rel_err(A[kidx][:, :, jw], rA))
-    _say("omega spectral workload sigma(w) %.2e sigma(0) %.2e A %.2e" % errs)
+    _say("omega spectral workload", order, "sigma(w) %.2e sigma(0) %.2e A %.2e" % errs)
     assert max(errs) < 1e-10
     assert np.all(A >= 0) and np.all(np.isfinite(A))

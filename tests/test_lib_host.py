@@ -85,7 +85,7 @@ def test_workspace_size_and_parameter_errors():
     n32 = lib.epw_workspace_size(_lib.EPW_WS_IMSIGMA, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par32))
     assert n64 > 0 and n32 > 0
     bad = [epw.make_params(sigma=0.0), epw.make_params(T=-1.0), epw.make_params(dtype=7),
-           epw.make_params(deg_tol=-1.0), epw.make_params(chunk_q=-3)]
+           epw.make_params(deg_tol=-1.0), epw.make_params(chunk_q=-3), epw.make_params(order=3)]
     for b in bad:
         assert lib.epw_workspace_size(_lib.EPW_WS_IMSIGMA, ctypes.byref(s), ctypes.byref(p), ctypes.byref(b)) == 0
         assert lib.epw_last_error() != b""
@@ -236,3 +236,17 @@ def test_polar_validation():
         assert (n > 0) == (b is good), lib.epw_last_error()
         if b is not good:
             assert b"polar" in lib.epw_last_error()
+
+
+def test_k_outer_workspace():
+    """The k-outer order needs no R_p -> q or mode-rotated operand per q, so
+    with few k its chunks are larger for the same budget: the forced orders
+    give different workspace sizes and auto picks k-outer for 4 nk <= N_e."""
+    lib = _lib.load()
+    s, p = _shape_only(nb=8, nm=6, ne=279, np_=279, nk=64, nq=2000)
+    sizes = {}
+    for order in ("auto", "k_inner", "k_outer"):
+        par = epw.make_params(order=order, chunk_q=100)
+        sizes[order] = lib.epw_workspace_size_omega(ctypes.byref(s), ctypes.byref(p), ctypes.byref(par), 512)
+        assert sizes[order] > 0
+    assert sizes["auto"] == sizes["k_outer"] != sizes["k_inner"]
