@@ -201,8 +201,6 @@ def spectral_run(sysd, model, dev, steps, warmup, torch):
     sms, sn = st["spectral"]
     fl = spectral_flops(nk, nq, nw, sysd.nm, sysd.nb) * steps
     ach = fl / (sms * 1e-3) / 1e12 if sms > 0 else None
-    fms, _ = st["fused"]
-    fa = fused_flops(nk, nq, sysd.Re.shape[0], sysd.nm, sysd.nb) * steps / (fms * 1e-3) / 1e12 if fms > 0 else None
     return {"value": nk * nq * steps / dt, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dt / steps,
             "dtype": "fp64", "workload": "realistic fcc system, %d k on Gamma-X x %d random q (off-grid k+q), "
                                          "%d frequencies on [-1, 1] eV, delta = 20 meV" % (nk, nq, nw),
@@ -211,7 +209,6 @@ def spectral_run(sysd, model, dev, steps, warmup, torch):
                                 "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
                                 "frac": ach / PEAK_TFLOPS["fp64"] if ach else None,
                                 "launches": sn, "avg_launch_ms": sms / sn if sn else None},
-            "fused_tflops": fa,
             "stages_ms_per_step": {s_: v[0] / steps for s_, v in st.items()}}
 
 
