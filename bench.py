@@ -172,6 +172,15 @@ def mobility_shard(dev, dtypes, steps, warmup, torch):
         out[dt] = {"value": pairs * steps / dtv, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dtv / steps,
                    "fused_tflops": ach, "fused_frac_of_peak": ach / PEAK_TFLOPS[dt] if ach else None,
                    "stages_ms_per_step": {s_: v[0] / steps for s_, v in stv.items()}}
+    # the adjoint of the same shard in FP32 (dL/dg and dL/domega; dL/dH needs a k+q map)
+    log("bench: mobility shard fp32 backward")
+    par = epw.make_params(T=m.T, mu=mu, sigma=m.sigma, nq_norm=float(x["nq"]), dtype="fp32")
+    w = torch.rand((len(k), m.nb), dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
+    dtb, stb = timed(lambda: epw.epw_imsigma_backward(sysd, pts, par, w, want=("gR", "omega"), workspace=ws),
+                     1, 0, torch)
+    out["backward_fp32"] = {"value": pairs / dtb, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dtb,
+                            "outputs": "dL/dg(R_e,R_p), dL/domega",
+                            "stages_ms_per_step": {s_: v[0] for s_, v in stb.items()}}
     return out
 
 
