@@ -321,10 +321,11 @@ int epw_band_velocities(int nb, int nR, const int32_t* R, const int32_t* ndeg, c
  * with the velocities of epw_band_velocities (the factor is 1 where
  * |v_nk|^2 <= 1e-18), N(eps_F), the deltas and the degenerate-mode average
  * as for lambda_q,nu (epw_phonon_selfenergy), which comes out of the same
- * pass together with Pi''.  Grid runs only (the k+q map is required).
+ * pass together with Pi''.  Without a k+q map the velocities at k+q are
+ * formed per pair, from dH/dk at k+q summed like H(k+q).
  *  vectors  host [3][3] double: primitive lattice vectors (rows, Cartesian)
  *  lam_tr   device [nq][nm] double out; lam, pi_im device [nq][nm] or NULL
- * Errors: as epw_phonon_selfenergy; EPW_EINVAL without a k+q map. */
+ * Errors: as epw_phonon_selfenergy. */
 int epw_transport_coupling(const epw_system* sys, const epw_points* pts, const epw_params* par,
                            const double* vectors, double* lam_tr, double* lam, double* pi_im, void* ws,
                            size_t ws_bytes, void* stream);

@@ -151,6 +151,12 @@ struct PairScratch {
     void* phi_q = nullptr;   // [Q][N_e] c128
     void* H = nullptr;       // [batch][n_b][n_b] c128
     long batch = 0;
+    // band velocities at k+q (transport mode): i R_a H(R) for a = x, y, z,
+    // their Fourier sums for one batch, and the velocities of every pair
+    void* dHR3 = nullptr;    // [3][N_e][n_b][n_b] c128
+    void* dH3 = nullptr;     // [3][batch][n_b][n_b] c128
+    double* vel_pair = nullptr;  // [N_k][Q][n_b][3]
+    const double* vectors9 = nullptr;
 };
 
 // what a forward pass produces
@@ -202,17 +208,28 @@ size_t pair_bytes_per_q(const epw_system* s, const epw_points* p) {
     return (size_t)p->nk * (16 * (size_t)s->nb + 16 * (size_t)s->nb * s->nb) + 16 * (size_t)s->nRe;
 }
 
+// extra bytes per q point of the k+q velocities (off-grid transport runs)
+size_t pair_vel_bytes_per_q(const epw_system* s, const epw_points* p) {
+    return p->kq ? 0 : (size_t)p->nk * 24 * (size_t)s->nb;
+}
+
 void take_pair_states(const epw_system* s, const epw_points* p, int Q, Arena& A, double*& eps_pair, void*& U_pair,
-                      double*& f_pair, PairScratch& ps) {
+                      double*& f_pair, PairScratch& ps, bool velocities = false) {
     if (p->kq) return;
     const size_t n = (size_t)p->nk * Q;
+    const size_t nbb = (size_t)s->nb * s->nb;
     eps_pair = (double*)A.take(8 * n * s->nb);
-    U_pair = A.take(16 * n * s->nb * s->nb);
+    U_pair = A.take(16 * n * nbb);
     f_pair = (double*)A.take(8 * n * s->nb);
     ps.phi_k = A.take(16 * (size_t)p->nk * s->nRe);
     ps.phi_q = A.take(16 * (size_t)Q * s->nRe);
     ps.batch = std::min<long>(PAIR_BATCH, (long)n);
-    ps.H = A.take(16 * (size_t)ps.batch * s->nb * s->nb);
+    ps.H = A.take(16 * (size_t)ps.batch * nbb);
+    if (velocities) {
+        ps.dHR3 = A.take(16 * 3 * (size_t)s->nRe * nbb);
+        ps.dH3 = A.take(16 * 3 * (size_t)ps.batch * nbb);
+        ps.vel_pair = (double*)A.take(8 * 3 * n * s->nb);
+    }
 }
 
 // eps, U and f at k+q for every (k, q) of a chunk (off-grid runs); pair
@@ -223,6 +240,7 @@ void pair_states(const epw_system* s, const epw_points* p, const epw_params* par
     StageTimer t(EPW_STAGE_EIGH, st);
     const int nb = s->nb, ne = s->nRe, nbb = nb * nb;
     if (q0 == 0) launch_phase_table(Prec::F64, p->nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, ps.phi_k, st);
+    if (q0 == 0 && ps.dHR3) launch_velocity_operands(nb, ne, s->Re, s->HR, ps.vectors9, ps.dHR3, st);
     launch_phase_table(Prec::F64, qc, p->qfrac + 3 * (size_t)q0, ne, s->Re, nullptr, ne, ps.phi_q, st);
     const long npair = (long)p->nk * qc;
     for (long b0 = 0; b0 < npair; b0 += ps.batch) {
@@ -243,6 +261,17 @@ void pair_states(const epw_system* s, const epw_points* p, const epw_params* par
         d.sCm = nbb;
         launch_cgemm(Prec::F64, d, st);
         launch_eigh_given(nb, nbt, ps.H, eps_pair + (size_t)b0 * nb, (char*)U_pair + 16 * (size_t)b0 * nbb, st);
+        if (ps.vel_pair) {
+            // dH/dk_a(k+q) = sum_R Phi_k Phi_q (i R_a H(R)), then the band velocities
+            for (int a = 0; a < 3; ++a) {
+                GemmDesc dv = d;
+                dv.B = (const char*)ps.dHR3 + 16 * (size_t)a * ne * nbb;
+                dv.C = (char*)ps.dH3 + 16 * (size_t)a * ps.batch * nbb;
+                launch_cgemm(Prec::F64, dv, st);
+            }
+            launch_pair_velocities(nb, nbt, ps.batch, ps.dH3, (const char*)U_pair + 16 * (size_t)b0 * nbb,
+                                   eps_pair + (size_t)b0 * nb, par->deg_tol, ps.vel_pair + 3 * (size_t)b0 * nb, st);
+        }
     }
     launch_fermi_table((size_t)p->nk * qc * nb, eps_pair, par->mu, par->T, f_pair, st);
 }
@@ -272,6 +301,7 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     // chunk size
     const size_t per_q = cb * np_ + (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm +
                          pair_bytes_per_q(s, p) + (omg ? 8 * (size_t)nk * nm * nb * (4 + L.nbp) : 0) +
+                         (out == Out::TRANSPORT ? pair_vel_bytes_per_q(s, p) : 0) +
                          (L.kouter ? cb * (size_t)nk * X : cb * (size_t)ne * X + bcol_bytes * nm * L.nbp * L.nbp);
     long Q = par->chunk_q > 0 ? par->chunk_q : (long)(AUTO_CHUNK_BYTES / per_q);
     if (Q < 1) Q = 1;
@@ -323,7 +353,7 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
         L.dos_raw = (double*)A.take(8);
     }
     if (out == Out::TRANSPORT) L.vel = (double*)A.take(8 * 3 * (size_t)nk * nb);
-    take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair, L.ps);
+    take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair, L.ps, out == Out::TRANSPORT);
 }
 
 // a5 as a strided GEMM: out[e][q][c] = sum_p phi_q[q][p] gR[e][p][c]
@@ -366,9 +396,11 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
     }
     launch_fermi_table((size_t)nk * nb, L.eps, par->mu, par->T, L.ftab, st);
     if (phon) launch_dos_raw((size_t)nk * nb, L.eps, par->mu, par->sigma, L.dos_raw, st);
-    if (trans)
+    if (trans) {
         launch_velocities(nb, ne, s->Re, s->ndeg_e, s->HR, vectors9, nk, p->kfrac, L.eps, L.U, par->deg_tol, L.vel,
                           st);
+        L.ps.vectors9 = vectors9;
+    }
     const bool bf = prec == Prec::BF16X2;
     const Prec rprec = bf ? Prec::F32 : prec;      // precision of the R_p -> q step
     // Phases of the R_e -> k contraction: generated inside the fused kernel
@@ -537,6 +569,7 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.gkq = gkq;
         a.part_ph = phon ? L.part_ph : nullptr;
         a.vel = trans ? L.vel : nullptr;
+        a.vel_pair = trans ? L.ps.vel_pair : nullptr;
         a.part2 = re ? L.part2 : nullptr;
         a.rec = omg ? L.rec : nullptr;
         {
@@ -1071,7 +1104,6 @@ extern "C" int epw_transport_coupling(const epw_system* sys, const epw_points* p
     if (pts->nq == 0) return EPW_OK;
     if (!lam_tr || !vectors) return fail(EPW_EINVAL, "epw_transport_coupling: NULL output or lattice vectors");
     if (pts->nk == 0) return fail(EPW_ESHAPE, "epw_transport_coupling: the k set is empty");
-    if (!pts->kq) return fail(EPW_EINVAL, "epw_transport_coupling: needs the k+q map (grid runs)");
     for (int i = 0; i < 9; ++i)
         if (!std::isfinite(vectors[i])) return fail(EPW_EINVAL, "epw_transport_coupling: lattice vectors not finite");
     Arena dry;

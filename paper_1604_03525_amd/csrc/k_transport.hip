@@ -123,6 +123,66 @@ __global__ __launch_bounds__(VEL_THREADS) void velocity_kernel(int nb, int nR, c
     }
 }
 
+// dHR3[a][r][ij] = i R_a(r) H(R)[ij], R Cartesian
+__global__ void velocity_operands_kernel(int nb2, int nR, const int32_t* __restrict__ R,
+                                         const double2* __restrict__ HR, Vectors V, double2* __restrict__ out)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t per = (size_t)nR * nb2;
+    if (idx >= 3 * per) return;
+    const int a = (int)(idx / per);
+    const size_t rij = idx % per;
+    const int r = (int)(rij / nb2);
+    const double Ra = R[3 * r] * V.a[0][a] + R[3 * r + 1] * V.a[1][a] + R[3 * r + 2] * V.a[2][a];
+    const double2 h = HR[rij];
+    out[idx] = make_double2(-Ra * h.y, Ra * h.x);
+}
+
+// One wave per pair: v_m,a = Re [U^dag ((dH_a + dH_a^dag)/2) U]_mm, then the
+// average over degenerate bands.
+__global__ __launch_bounds__(64) void pair_velocity_kernel(int nb, long ld, const double2* __restrict__ dH3,
+                                                           const double2* __restrict__ U,
+                                                           const double* __restrict__ eps, double deg_tol,
+                                                           double* __restrict__ vel)
+{
+    __shared__ double d[3][EPW_MAX_NB];
+    const long p = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int nb2 = nb * nb;
+    if (tid < 3 * nb) {
+        const int a = tid / nb, m = tid % nb;
+        const double2* h = dH3 + ((size_t)a * ld + p) * nb2;
+        const double2* u = U + (size_t)p * nb2;
+        double acc = 0.0;
+        for (int i = 0; i < nb; ++i) {
+            const double2 ui = u[i * nb + m];
+            for (int j = 0; j < nb; ++j) {
+                const double2 uj = u[j * nb + m];
+                const double2 x = h[i * nb + j], y = h[j * nb + i];
+                const double hr = 0.5 * (x.x + y.x), hi = 0.5 * (x.y - y.y);
+                const double tr = hr * uj.x - hi * uj.y, ti = hr * uj.y + hi * uj.x;
+                acc += ui.x * tr + ui.y * ti;
+            }
+        }
+        d[a][m] = acc;
+    }
+    __syncthreads();
+    if (tid < 3) {
+        const int a = tid;
+        const double* e = eps + (size_t)p * nb;
+        int start = 0;
+        while (start < nb) {
+            int stop = start + 1;
+            while (stop < nb && fabs(e[stop] - e[stop - 1]) < deg_tol) ++stop;
+            double t = 0.0;
+            for (int n = start; n < stop; ++n) t += d[a][n];
+            t /= (double)(stop - start);
+            for (int n = start; n < stop; ++n) vel[((size_t)p * nb + n) * 3 + a] = t;
+            start = stop;
+        }
+    }
+}
+
 __global__ void eliashberg_kernel(int ncb, const double* __restrict__ omega, const double* __restrict__ lam,
                                   double inv_nq, int nw, const double* __restrict__ wgrid, double sigma,
                                   double* __restrict__ a2f)
@@ -177,6 +237,26 @@ void launch_velocities(int nb, int nR, const int32_t* R, const int32_t* ndeg, co
     velocity_kernel<<<np, VEL_THREADS, 0, stream>>>(nb, nR, R, ndeg, (const double2*)HR, V, kfrac, eps,
                                                     (const double2*)U, deg_tol, vel);
     launch_check("velocity_kernel");
+}
+
+void launch_velocity_operands(int nb, int nR, const int32_t* R, const void* HR, const double* vectors9, void* dHR3,
+                              hipStream_t stream) {
+    const size_t n = 3 * (size_t)nR * nb * nb;
+    if (n == 0) return;
+    Vectors V;
+    for (int i = 0; i < 3; ++i)
+        for (int a = 0; a < 3; ++a) V.a[i][a] = vectors9[3 * i + a];
+    velocity_operands_kernel<<<(unsigned)((n + 255) / 256), 256, 0, stream>>>(nb * nb, nR, R, (const double2*)HR, V,
+                                                                             (double2*)dHR3);
+    launch_check("velocity_operands_kernel");
+}
+
+void launch_pair_velocities(int nb, int np, long ld, const void* dH3, const void* U, const double* eps, double deg_tol,
+                            double* vel, hipStream_t stream) {
+    if (np == 0) return;
+    pair_velocity_kernel<<<(unsigned)np, 64, 0, stream>>>(nb, ld, (const double2*)dH3, (const double2*)U, eps,
+                                                         deg_tol, vel);
+    launch_check("pair_velocity_kernel");
 }
 
 void launch_eliashberg(int nq, int nm, const double* omega, const double* lam, double nq_norm, int nw,

@@ -362,7 +362,8 @@ __device__ inline float2 cmulx(float2 a, float2 b) {
 // |g_mn|^2 for n < nb, 0 up to NBP}, with xi_m = eps_m,k+q - mu (the records
 // of modes below omega_cut carry zero weights);
 // 5: mode 2 plus the transport coupling sum of Eq. (55) (the Eq. (11) weight
-// times 1 - v_nk . v_m,k+q / |v_nk|^2; grid runs, velocities of the k set).
+// times 1 - v_nk . v_m,k+q / |v_nk|^2; velocities of the k set, and per pair
+// at k+q for off-grid runs).
 template <int MODE, int NBP, int KIND, bool GEN>
 __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
 {
@@ -647,6 +648,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     Uq = reinterpret_cast<const double2*>(a.U_pair) + pr * nb * nb;
                     eq = a.eps_pair + pr * nb;
                     fq = a.f_pair + pr * nb;
+                    if constexpr (TR) vq = a.vel_pair + pr * nb * 3;
                 }
                 const double w = a.omega[(size_t)ql * nm + nu];
                 const double nB = a.nbose[(size_t)ql * nm + nu];

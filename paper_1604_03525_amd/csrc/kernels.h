@@ -111,6 +111,7 @@ struct FusedArgs {
                        // then holds Sigma' on shell)
     double* rec;       // [nk][qc][nm][nb] pole records of 4 + nbp doubles (pole mode)
     const double* vel; // [nk][nb][3] band velocities of the k set (transport mode, with part_ph)
+    const double* vel_pair;  // [nk][qc][nb][3] velocities at k+q per pair (transport mode, off-grid)
 };
 // a7 + a8 + a9 (imsigma mode), a7 + a8 (store mode, gkq != nullptr),
 // a7 + a8 + the phonon-linewidth sums (phonon mode, part_ph != nullptr), or
@@ -254,6 +255,13 @@ void launch_pair_pole(const PairPoleArgs& a, hipStream_t stream);
 void launch_velocities(int nb, int nR, const int32_t* R, const int32_t* ndeg, const void* HR, const double* vectors9,
                        int np, const double* kfrac, const double* eps, const void* U, double deg_tol, double* vel,
                        hipStream_t stream);
+// i R_a H(R) for a = x, y, z (R Cartesian): [3][nR][nb][nb] c128
+void launch_velocity_operands(int nb, int nR, const int32_t* R, const void* HR, const double* vectors9, void* dHR3,
+                              hipStream_t stream);
+// velocities of np pairs from dH/dk_a [3][ld][nb][nb] (ld = batch stride),
+// eigenvectors U [np][nb][nb] and energies eps [np][nb] (degenerate average)
+void launch_pair_velocities(int nb, int np, long ld, const void* dH3, const void* U, const double* eps, double deg_tol,
+                            double* vel, hipStream_t stream);
 void launch_eliashberg(int nq, int nm, const double* omega, const double* lam, double nq_norm, int nw,
                        const double* wgrid, double sigma, double* a2f, hipStream_t stream);
 void launch_ziman(int nw, const double* wgrid, const double* a2f, int nT, const double* T, double* out,

@@ -107,12 +107,19 @@ def test_eliashberg_and_resistivity():
     assert rel_err(rho, want) < 1e-12
 
 
-def test_requires_grid_map():
-    c = fcc_small_case(nb=3, kg=(2, 2, 2), seed=2)
-    with pytest.raises(epw.EpwError) as e:
-        epw.epw_transport_coupling(_system(c), epw.Points(c["k"], c["q"], None, device=DEV), _params(c),
-                                   I.FCC_VECTORS)
-    assert e.value.code == epw._lib.EPW_EINVAL
+@pytest.mark.parametrize("dtype", ["fp64", "fp32"])
+def test_offgrid_pairs(dtype):
+    """Random k and q without a k+q map (5 bands, 6 modes, two atoms): the
+    velocities at k+q come per pair from dH/dk summed like H(k+q)."""
+    c = fcc_small_case(nb=5, kg=(2, 2, 2), seed=4)
+    c.update(k=I.random_points(20, 31), q=I.random_points(24, 32), kq=None, mu=0.3, sigma=0.3)
+    rl, rlam, _ = _ref(c, I.FCC_VECTORS)
+    ltr, lam, _ = epw.epw_transport_coupling(_system(c), epw.Points(c["k"], c["q"], None, device=DEV),
+                                             _params(c, dtype=dtype, chunk_q=7), I.FCC_VECTORS)
+    _say("transport offgrid", dtype, rel_err(ltr.cpu().numpy(), rl), rel_err(lam.cpu().numpy(), rlam))
+    assert np.abs(rl).max() > 0
+    assert rel_err(ltr.cpu().numpy(), rl) < TOL[dtype]
+    assert rel_err(lam.cpu().numpy(), rlam) < TOL[dtype]
 
 
 def test_realistic_full_size_sampled_q():

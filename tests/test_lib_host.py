@@ -120,10 +120,14 @@ def test_workspace_size_counts_per_pair_states():
     kq = (ctypes.c_int32 * 1)()
     p_grid = _lib.EpwPoints(24, 40, None, None, ctypes.cast(kq, ctypes.c_void_p), None, None)
     for which in (_lib.EPW_WS_INTERP_G, _lib.EPW_WS_IMSIGMA, _lib.EPW_WS_IMSIGMA_BACKWARD, _lib.EPW_WS_PHONON,
-                  _lib.EPW_WS_RESIGMA):
+                  _lib.EPW_WS_RESIGMA, _lib.EPW_WS_TRANSPORT):
         off = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
         on = lib.epw_workspace_size(which, ctypes.byref(s), ctypes.byref(p_grid), ctypes.byref(par))
         assert off >= on + 24 * 16 * (16 * 16 * 16 + 16 * 16)
+    # transport adds the velocity operands i R_a H(R), one batch of dH/dk and the pair velocities
+    ph = lib.epw_workspace_size(_lib.EPW_WS_PHONON, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
+    tr = lib.epw_workspace_size(_lib.EPW_WS_TRANSPORT, ctypes.byref(s), ctypes.byref(p), ctypes.byref(par))
+    assert tr >= ph + 16 * 3 * 89 * 256 + 8 * 3 * 24 * 16 * 16
 
 
 def test_phonon_selfenergy_argument_errors():
