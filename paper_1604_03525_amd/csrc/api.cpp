@@ -377,10 +377,32 @@ GemmDesc rp_desc(int qc, int ne, int np_, int ncol, const void* phi_q, const voi
 // Shared forward pipeline: store mode writes g_mn,nu(k,q) to gkq, phonon
 // mode writes Pi''_q,nu and lambda_q,nu to pi_im / lam, otherwise Im Sigma
 // goes to imsig.
-void run_forward(const epw_system* s, const epw_points* p, const epw_params* par, Layout& L,
-                 double* imsig, void* gkq, hipStream_t st, double* pi_im = nullptr, double* lam = nullptr,
-                 double* re_tilde = nullptr, const double* wgrid = nullptr, void* sig_w = nullptr,
-                 void* sig0 = nullptr, double* lam_tr = nullptr, const double* vectors9 = nullptr) {
+// What a forward call writes (unused members stay NULL).
+struct Outputs {
+    double* imsig = nullptr;            // Im Sigma, or Sigma' on shell (real-part mode)
+    void* gkq = nullptr;                // g_mn,nu(k,q) (store mode)
+    double* pi_im = nullptr;            // Pi'' (phonon and transport modes)
+    double* lam = nullptr;              // lambda
+    double* re_tilde = nullptr;         // Sigma~' (real-part mode)
+    const double* wgrid = nullptr;      // frequencies (frequency-grid mode)
+    void* sig_w = nullptr;              // Sigma(omega)
+    void* sig0 = nullptr;               // Sigma(0)
+    double* lam_tr = nullptr;           // lambda_tr (transport mode)
+    const double* vectors9 = nullptr;   // lattice vectors (transport mode)
+};
+
+void run_forward(const epw_system* s, const epw_points* p, const epw_params* par, Layout& L, const Outputs& o,
+                 hipStream_t st) {
+    double* imsig = o.imsig;
+    void* gkq = o.gkq;
+    double* pi_im = o.pi_im;
+    double* lam = o.lam;
+    double* re_tilde = o.re_tilde;
+    const double* wgrid = o.wgrid;
+    void* sig_w = o.sig_w;
+    void* sig0 = o.sig0;
+    double* lam_tr = o.lam_tr;
+    const double* vectors9 = o.vectors9;
     const bool trans = L.out == Out::TRANSPORT;
     const bool phon = L.out == Out::PHONON || trans;
     const bool omg = L.out == Out::OMEGA;
@@ -911,21 +933,13 @@ extern "C" int epw_interp_phonons(int nm, int nR, const int32_t* R, const int32_
     });
 }
 
-extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
-                                     const epw_params* par) {
-    clear_error();
-    if (which != EPW_WS_INTERP_G && which != EPW_WS_IMSIGMA && which != EPW_WS_IMSIGMA_BACKWARD &&
-        which != EPW_WS_PHONON && which != EPW_WS_RESIGMA && which != EPW_WS_TRANSPORT) {
-        fail(EPW_EINVAL, "epw_workspace_size: unknown call id %d", which);
-        return 0;
-    }
-    if (!sys || !pts || !par) {
-        fail(EPW_EINVAL, "epw_workspace_size: NULL argument");
-        return 0;
-    }
-    epw_points p = *pts;
-    epw_system s = *sys;
-    // sizes only: pretend pointers are present so the shape checks run
+// Size queries run the shape checks on copies of the structs whose missing
+// pointers are replaced by placeholders (never dereferenced).
+int size_query_checks(const epw_system* sys, const epw_points* pts, const epw_params* par, const char* fn,
+                      epw_system& s, epw_points& p) {
+    if (!sys || !pts || !par) return fail(EPW_EINVAL, "%s: NULL argument", fn);
+    p = *pts;
+    s = *sys;
     static const int32_t dummy_i = 0;
     static const double dummy_d = 0.0;
     if (!p.kfrac) p.kfrac = &dummy_d;
@@ -937,7 +951,40 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
     if (!s.HR) s.HR = &dummy_d;
     if (!s.gR) s.gR = &dummy_d;
     if (!s.DR && !(p.omega && p.evec)) s.DR = &dummy_d;
-    if (check_common(&s, &p, par, "epw_workspace_size") != EPW_OK) return 0;
+    return check_common(&s, &p, par, fn);
+}
+
+// Shared tail of the forward entry points: size the workspace, carve it and
+// run the pipeline, with HIP failures turned into status codes.
+int planned_forward(const char* fn, const epw_system* sys, const epw_points* pts, const epw_params* par, Out out,
+                    int nw, void* ws, size_t ws_bytes, void* stream, const Outputs& o) {
+    Arena dry;
+    dry.dry = true;
+    Layout L;
+    plan(sys, pts, par, out, dry, L, nw);
+    if (!ws || ws_bytes < dry.used + 256)
+        return fail(EPW_ENOMEM, "%s: workspace %zu bytes, need %zu", fn, ws_bytes, dry.used + 256);
+    return guarded(fn, [&]() {
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        plan(sys, pts, par, out, A, L, nw);
+        run_forward(sys, pts, par, L, o, (hipStream_t)stream);
+        return EPW_OK;
+    });
+}
+
+extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
+                                     const epw_params* par) {
+    clear_error();
+    if (which != EPW_WS_INTERP_G && which != EPW_WS_IMSIGMA && which != EPW_WS_IMSIGMA_BACKWARD &&
+        which != EPW_WS_PHONON && which != EPW_WS_RESIGMA && which != EPW_WS_TRANSPORT) {
+        fail(EPW_EINVAL, "epw_workspace_size: unknown call id %d", which);
+        return 0;
+    }
+    epw_system s;
+    epw_points p;
+    if (size_query_checks(sys, pts, par, "epw_workspace_size", s, p) != EPW_OK) return 0;
     Arena A;
     A.dry = true;
     if (which == EPW_WS_IMSIGMA_BACKWARD) {
@@ -961,20 +1008,9 @@ extern "C" int epw_interp_g(const epw_system* sys, const epw_points* pts, const 
     if (rc != EPW_OK) return rc;
     if (pts->nk == 0 || pts->nq == 0) return EPW_OK;
     if (!gkq) return fail(EPW_EINVAL, "epw_interp_g: NULL output");
-    Arena dry;
-    dry.dry = true;
-    Layout L;
-    plan(sys, pts, par, Out::STORE, dry, L);
-    if (!ws || ws_bytes < dry.used + 256)
-        return fail(EPW_ENOMEM, "epw_interp_g: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
-    return guarded("epw_interp_g", [&]() {
-        Arena A;
-        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        A.cap = ws_bytes;
-        plan(sys, pts, par, Out::STORE, A, L);
-        run_forward(sys, pts, par, L, nullptr, gkq, (hipStream_t)stream);
-        return EPW_OK;
-    });
+    Outputs o;
+    o.gkq = gkq;
+    return planned_forward("epw_interp_g", sys, pts, par, Out::STORE, 0, ws, ws_bytes, stream, o);
 }
 
 extern "C" int epw_imsigma(const epw_system* sys, const epw_points* pts, const epw_params* par, double* imsig,
@@ -984,47 +1020,21 @@ extern "C" int epw_imsigma(const epw_system* sys, const epw_points* pts, const e
     if (rc != EPW_OK) return rc;
     if (pts->nk == 0) return EPW_OK;
     if (!imsig) return fail(EPW_EINVAL, "epw_imsigma: NULL output");
-    Arena dry;
-    dry.dry = true;
-    Layout L;
-    plan(sys, pts, par, Out::IMSIGMA, dry, L);
-    if (!ws || ws_bytes < dry.used + 256)
-        return fail(EPW_ENOMEM, "epw_imsigma: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
-    return guarded("epw_imsigma", [&]() {
-        Arena A;
-        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        A.cap = ws_bytes;
-        plan(sys, pts, par, Out::IMSIGMA, A, L);
-        run_forward(sys, pts, par, L, imsig, nullptr, (hipStream_t)stream);
-        return EPW_OK;
-    });
+    Outputs o;
+    o.imsig = imsig;
+    return planned_forward("epw_imsigma", sys, pts, par, Out::IMSIGMA, 0, ws, ws_bytes, stream, o);
 }
 
 extern "C" size_t epw_workspace_size_omega(const epw_system* sys, const epw_points* pts, const epw_params* par,
                                            int nw) {
     clear_error();
-    if (!sys || !pts || !par) {
-        fail(EPW_EINVAL, "epw_workspace_size_omega: NULL argument");
-        return 0;
-    }
     if (nw < 0 || nw > EPW_MAX_NW) {
         fail(EPW_ESHAPE, "epw_workspace_size_omega: nw = %d not in 0..%d", nw, EPW_MAX_NW);
         return 0;
     }
-    epw_points p = *pts;
-    epw_system s = *sys;
-    static const int32_t dummy_i = 0;
-    static const double dummy_d = 0.0;
-    if (!p.kfrac) p.kfrac = &dummy_d;
-    if (!p.qfrac) p.qfrac = &dummy_d;
-    if (!s.Re) s.Re = &dummy_i;
-    if (!s.Rp) s.Rp = &dummy_i;
-    if (!s.ndeg_e) s.ndeg_e = &dummy_i;
-    if (!s.ndeg_p) s.ndeg_p = &dummy_i;
-    if (!s.HR) s.HR = &dummy_d;
-    if (!s.gR) s.gR = &dummy_d;
-    if (!s.DR && !(p.omega && p.evec)) s.DR = &dummy_d;
-    if (check_common(&s, &p, par, "epw_workspace_size_omega") != EPW_OK) return 0;
+    epw_system s;
+    epw_points p;
+    if (size_query_checks(sys, pts, par, "epw_workspace_size_omega", s, p) != EPW_OK) return 0;
     Arena A;
     A.dry = true;
     Layout L;
@@ -1041,21 +1051,11 @@ extern "C" int epw_selfenergy_omega(const epw_system* sys, const epw_points* pts
     if (rc != EPW_OK) return rc;
     if (pts->nk == 0) return EPW_OK;
     if (!sigma0 || (nw > 0 && (!sigma_w || !wgrid))) return fail(EPW_EINVAL, "epw_selfenergy_omega: NULL output or grid");
-    Arena dry;
-    dry.dry = true;
-    Layout L;
-    plan(sys, pts, par, Out::OMEGA, dry, L, nw);
-    if (!ws || ws_bytes < dry.used + 256)
-        return fail(EPW_ENOMEM, "epw_selfenergy_omega: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
-    return guarded("epw_selfenergy_omega", [&]() {
-        Arena A;
-        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        A.cap = ws_bytes;
-        plan(sys, pts, par, Out::OMEGA, A, L, nw);
-        run_forward(sys, pts, par, L, nullptr, nullptr, (hipStream_t)stream, nullptr, nullptr, nullptr, wgrid,
-                    sigma_w, sigma0);
-        return EPW_OK;
-    });
+    Outputs o;
+    o.wgrid = wgrid;
+    o.sig_w = sigma_w;
+    o.sig0 = sigma0;
+    return planned_forward("epw_selfenergy_omega", sys, pts, par, Out::OMEGA, nw, ws, ws_bytes, stream, o);
 }
 
 extern "C" int epw_spectral_function(int nk, int nb, int nw, const double* eps, double mu, const double* wgrid,
@@ -1079,20 +1079,10 @@ extern "C" int epw_resigma(const epw_system* sys, const epw_points* pts, const e
     if (rc != EPW_OK) return rc;
     if (pts->nk == 0) return EPW_OK;
     if (!re_shell) return fail(EPW_EINVAL, "epw_resigma: NULL output");
-    Arena dry;
-    dry.dry = true;
-    Layout L;
-    plan(sys, pts, par, Out::RESIGMA, dry, L);
-    if (!ws || ws_bytes < dry.used + 256)
-        return fail(EPW_ENOMEM, "epw_resigma: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
-    return guarded("epw_resigma", [&]() {
-        Arena A;
-        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        A.cap = ws_bytes;
-        plan(sys, pts, par, Out::RESIGMA, A, L);
-        run_forward(sys, pts, par, L, re_shell, nullptr, (hipStream_t)stream, nullptr, nullptr, re_tilde);
-        return EPW_OK;
-    });
+    Outputs o;
+    o.imsig = re_shell;
+    o.re_tilde = re_tilde;
+    return planned_forward("epw_resigma", sys, pts, par, Out::RESIGMA, 0, ws, ws_bytes, stream, o);
 }
 
 extern "C" int epw_transport_coupling(const epw_system* sys, const epw_points* pts, const epw_params* par,
@@ -1106,21 +1096,12 @@ extern "C" int epw_transport_coupling(const epw_system* sys, const epw_points* p
     if (pts->nk == 0) return fail(EPW_ESHAPE, "epw_transport_coupling: the k set is empty");
     for (int i = 0; i < 9; ++i)
         if (!std::isfinite(vectors[i])) return fail(EPW_EINVAL, "epw_transport_coupling: lattice vectors not finite");
-    Arena dry;
-    dry.dry = true;
-    Layout L;
-    plan(sys, pts, par, Out::TRANSPORT, dry, L);
-    if (!ws || ws_bytes < dry.used + 256)
-        return fail(EPW_ENOMEM, "epw_transport_coupling: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
-    return guarded("epw_transport_coupling", [&]() {
-        Arena A;
-        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        A.cap = ws_bytes;
-        plan(sys, pts, par, Out::TRANSPORT, A, L);
-        run_forward(sys, pts, par, L, nullptr, nullptr, (hipStream_t)stream, pi_im, lam, nullptr, nullptr, nullptr,
-                    nullptr, lam_tr, vectors);
-        return EPW_OK;
-    });
+    Outputs o;
+    o.pi_im = pi_im;
+    o.lam = lam;
+    o.lam_tr = lam_tr;
+    o.vectors9 = vectors;
+    return planned_forward("epw_transport_coupling", sys, pts, par, Out::TRANSPORT, 0, ws, ws_bytes, stream, o);
 }
 
 extern "C" int epw_band_velocities(int nb, int nR, const int32_t* R, const int32_t* ndeg, const void* HR,
@@ -1174,20 +1155,10 @@ extern "C" int epw_phonon_selfenergy(const epw_system* sys, const epw_points* pt
     if (pts->nq == 0) return EPW_OK;
     if (!pi_im) return fail(EPW_EINVAL, "epw_phonon_selfenergy: NULL output");
     if (pts->nk == 0) return fail(EPW_ESHAPE, "epw_phonon_selfenergy: the k set is empty");
-    Arena dry;
-    dry.dry = true;
-    Layout L;
-    plan(sys, pts, par, Out::PHONON, dry, L);
-    if (!ws || ws_bytes < dry.used + 256)
-        return fail(EPW_ENOMEM, "epw_phonon_selfenergy: workspace %zu bytes, need %zu", ws_bytes, dry.used + 256);
-    return guarded("epw_phonon_selfenergy", [&]() {
-        Arena A;
-        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-        A.cap = ws_bytes;
-        plan(sys, pts, par, Out::PHONON, A, L);
-        run_forward(sys, pts, par, L, nullptr, nullptr, (hipStream_t)stream, pi_im, lam);
-        return EPW_OK;
-    });
+    Outputs o;
+    o.pi_im = pi_im;
+    o.lam = lam;
+    return planned_forward("epw_phonon_selfenergy", sys, pts, par, Out::PHONON, 0, ws, ws_bytes, stream, o);
 }
 
 extern "C" int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw_params* par,
