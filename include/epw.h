@@ -177,9 +177,8 @@ typedef struct {
                               streamed from a table; 0 = use the table.  A value
                               smaller than the true maximum gives wrong results. */
     int32_t reserved;
-    const epw_polar* polar;  /* optional long-range term, NULL = none.  Used by
-                              every forward call; epw_imsigma_backward refuses
-                              it (EPW_EINVAL).                                  */
+    const epw_polar* polar;  /* optional long-range term, NULL = none: used by
+                              every forward call and by the adjoint             */
 } epw_system;
 
 #define EPW_MAX_NMAX 8

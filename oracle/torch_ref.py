@@ -33,12 +33,15 @@ def _phases(points, R, ndeg):
 
 
 def imsigma_torch(gR, HR, omega, evec, Re, ndeg_e, Rp, ndeg_p, kpoints, qpoints,
-                  kq, T, mu, sigma, omega_cut=1e-3, deg_tol=1e-6, nq_norm=None):
+                  kq, T, mu, sigma, omega_cut=1e-3, deg_tol=1e-6, nq_norm=None, polar_lr=None):
     """Im Sigma [Nk][nb] as a differentiable torch function.
 
     gR [Ne][Np][nm][nb][nb] complex128, HR [Ne][nb][nb] complex128,
     omega [Nq][nm] float64, evec [Nq][nm][nm] complex128 (constant),
-    kq [Nk][Nq] int: index of k+q in the k list (grid runs only)."""
+    kq [Nk][Nq] int: index of k+q in the k list (grid runs only).
+    polar_lr [Nq][nm] complex (constant), optional: the long-range factor of
+    Sec. 4 without its 1/sqrt(2 omega); the vertex then gains
+    (polar_lr / sqrt(2 omega)) [U_k+q^dag U_k]_mn."""
     nq_norm = len(qpoints) if nq_norm is None else nq_norm
     ph_q = _phases(qpoints, Rp, ndeg_p)                        # [Q][Np]
     ph_k = _phases(kpoints, Re, ndeg_e)                        # [K][Ne]
@@ -72,6 +75,10 @@ def imsigma_torch(gR, HR, omega, evec, Re, ndeg_e, Rp, ndeg_p, kpoints, qpoints,
         eps_kq = e2.reshape(len(kpoints), len(qpoints), nb)
         U_kq = U2.reshape(len(kpoints), len(qpoints), nb, nb)
     gb = torch.einsum("kqim,kqvij,kjn->kqvmn", U_kq.conj(), gk, U)
+    if polar_lr is not None:
+        ov = torch.einsum("kqim,kin->kqmn", U_kq.conj(), U)
+        lr = torch.as_tensor(np.asarray(polar_lr, dtype=np.complex128)) * scale
+        gb = gb + lr[None, :, :, None, None] * ov[:, :, None, :, :]
     # weights of Eq. (8)
     if T == 0.0:
         nB = torch.zeros_like(safe)

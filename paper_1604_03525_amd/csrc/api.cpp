@@ -677,6 +677,7 @@ struct BwdLayout {
     void* gR_t = nullptr;
     void* dgR_t = nullptr;
     void* phi_k64 = nullptr;
+    void* polar_L = nullptr; // [Q][nm] c128 long-range factors (polar systems)
     int kparts = 1;          // split-K slices of the sum over k (conjugate-transposed GEMM)
     void* kpart = nullptr;   // [kparts][N_e][Q n_m NBP^2] partial products
 };
@@ -716,6 +717,7 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     L.phi_q = A.take(cb * (size_t)L.Q * np_);
     L.gq = A.take(cb * (size_t)ne * L.Q * nm * nb * nb);
     L.Bnu = A.take(cb * (size_t)ne * L.Q * nm * nbp2);
+    if (s->polar) L.polar_L = A.take(16 * (size_t)L.Q * nm);
     L.G = A.take(cb * (size_t)nk * L.Q * nm * nbp2);
     L.ek_c = (double*)A.take(8 * (size_t)nk * L.Q * nb);
     L.ekq_c = (double*)A.take(8 * (size_t)nk * L.Q * nb);
@@ -779,12 +781,20 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             ev = L.evec_c;
         }
         launch_phonon_factors(qc, nm, om, par->omega_cut, par->T, L.sc, L.nbose, st);
+        if (s->polar) {
+            // the long-range part is proportional to 1/sqrt(2 omega) like the rest of g, so
+            // the per-pair omega adjoint (|g|^2 ~ 1/omega) covers it; it depends on g(R_e,R_p)
+            // and H(R_e) only through the rotations
+            PolarDev P;
+            polar_device(s->polar, nm, P);
+            launch_polar_factor(P, qc, nm, p->qfrac + 3 * (size_t)q0, ev, L.sc, L.polar_L, st);
+        }
         launch_phase_table(prec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
         pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, L.ps, st);
         const long ncols = (long)qc * nm * L.nbp * L.nbp;
         StageTimer tb(EPW_STAGE_BACKWARD, st);
         launch_cgemm(prec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, gsrc, L.gq), st);
-        launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st);
+        launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, nullptr, L.polar_L, s->Re);
         {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
             GemmDesc d;
             d.M = nk;
@@ -1167,7 +1177,6 @@ extern "C" int epw_imsigma_backward(const epw_system* sys, const epw_points* pts
     clear_error();
     int rc = check_common(sys, pts, par, "epw_imsigma_backward");
     if (rc != EPW_OK) return rc;
-    if (sys->polar) return fail(EPW_EINVAL, "epw_imsigma_backward: the polar long-range term has no adjoint here");
     if (pts->nk == 0) return EPW_OK;
     if (!w) return fail(EPW_EINVAL, "epw_imsigma_backward: NULL weights");
     if (dHR && !pts->kq)

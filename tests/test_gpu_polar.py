@@ -107,14 +107,36 @@ def test_imsigma_polar_offgrid():
     assert rel_err(got, ref) < 1e-10
 
 
-def test_backward_refuses_polar():
-    c = _case(kg=(2, 2, 2))
-    pts = epw.Points(c["k"], c["q"], c["kq"], device=DEV)
+@pytest.mark.parametrize("dtype,tol", [("fp64", 1e-6), ("fp32", 1e-4)])
+def test_backward_polar_reference_gradient(dtype, tol):
+    """The adjoint with the long-range term against the torch-CPU-FP64
+    reference gradient of the same polar forward (dL/dg, dL/dH, dL/domega at
+    fixed phonon eigenvectors): the long-range part is proportional to
+    1/sqrt(2 omega) and enters only through the rotations."""
     import torch
-    w = torch.ones((len(c["k"]), 3), dtype=torch.float64, device=DEV)
-    with pytest.raises(epw.EpwError) as e:
-        epw.epw_imsigma_backward(_system(c), pts, _params(c), w)
-    assert e.value.code == epw._lib.EPW_EINVAL
+    from oracle import torch_ref
+    from paper_1604_03525_amd import autograd
+    c = _case(kg=(3, 3, 3))
+    om, ev = interp.phonons(c["DR"], c["R"], c["nd"], c["q"])
+    L = polar.long_range_factor(c["q"], om, ev, **c["polar"])
+    keep = om >= 1e-3
+    lt = np.where(keep, L * np.sqrt(2.0 * np.where(keep, om, 1.0)), 0.0)
+    w = I.loss_weights(len(c["k"]), 3, 1)
+    kw = dict(Re=c["R"], ndeg_e=c["nd"], Rp=c["R"], ndeg_p=c["nd"], kpoints=c["k"], qpoints=c["q"], kq=c["kq"],
+              T=c["T"], mu=c["mu"], sigma=c["sigma"])
+    L_ref, _, dg_ref, dh_ref, dom_ref = torch_ref.loss_and_grads(c["gR"], c["HR"], om, ev, w, polar_lr=lt, **kw)
+    g = torch.tensor(c["gR"], device=DEV, requires_grad=True)
+    h = torch.tensor(c["HR"], device=DEV, requires_grad=True)
+    o = torch.tensor(om, device=DEV, requires_grad=True)
+    ims = autograd.imsigma(g, h, o, torch.as_tensor(ev).to(DEV), c["R"], c["nd"], c["R"], c["nd"], c["k"], c["q"],
+                           c["kq"], T=c["T"], mu=c["mu"], sigma=c["sigma"], dtype=dtype, polar=c["polar"])
+    loss = torch.sum(torch.as_tensor(w, device=DEV) * ims)
+    loss.backward()
+    errs = (rel_err(g.grad.cpu().numpy(), dg_ref), rel_err(h.grad.cpu().numpy(), dh_ref),
+            rel_err(o.grad.cpu().numpy(), dom_ref))
+    _say("polar backward", dtype, float(loss), L_ref, errs)
+    assert abs(float(loss) - L_ref) < (1e-10 if dtype == "fp64" else 1e-5) * abs(L_ref)
+    assert max(errs) < tol
 
 
 def test_realistic_full_size_polar_sampled():

@@ -138,3 +138,27 @@ def test_vertex_overlap_at_lattice_translation_and_zero_field():
     assert np.max(np.abs(a - b)) < 1e-13 * np.abs(b).max()
     c = polar.imsigma(HR, R, nd, DR, R, nd, gR, kk, kk, 300.0, 0.1, 0.15, par)
     assert np.max(np.abs(c - b)) > 3e-4 * np.abs(b).max()
+
+
+def test_torch_reference_with_polar_matches_numpy():
+    """The torch reference forward with the long-range factor (used for the
+    reference gradient) equals the NumPy polar oracle; L / (1/sqrt(2 omega))
+    is the factor it takes."""
+    import torch  # noqa: F401
+    from oracle import torch_ref
+    R, nd, DR = _fcc2(seed=2)
+    HR = I.random_hamiltonian(R, I.FCC_VECTORS, 3, seed=7, scale=0.8)
+    gR = I.random_vertex(R, R, I.FCC_VECTORS, 6, 3, seed=8, g0=0.05)
+    kg = (3, 3, 3)
+    k = lattice.grid_points(*kg)
+    par = I.polar_params()
+    om, ev = interp.phonons(DR, R, nd, k)
+    L = polar.long_range_factor(k, om, ev, **par)
+    keep = om >= 1e-3
+    lt = np.where(keep, L * np.sqrt(2.0 * np.where(keep, om, 1.0)), 0.0)
+    w = I.loss_weights(len(k), 3, 1)
+    _, ims, *_ = torch_ref.loss_and_grads(gR, HR, om, ev, w, Re=R, ndeg_e=nd, Rp=R, ndeg_p=nd, kpoints=k,
+                                          qpoints=k, kq=lattice.kq_index(kg, kg), T=300.0, mu=0.1, sigma=0.15,
+                                          polar_lr=lt)
+    ref = polar.imsigma(HR, R, nd, DR, R, nd, gR, k, k, 300.0, 0.1, 0.15, par)
+    assert np.max(np.abs(ims - ref)) < 1e-11 * np.abs(ref).max()
