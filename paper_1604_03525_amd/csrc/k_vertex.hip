@@ -549,6 +549,10 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 }
         }
         __syncthreads();
+        // The band loops of both phases stop at nb for up to 8 padded bands; at
+        // 16 they run over the zero padding (G, U_k and the k+q columns are
+        // zero there), so they unroll completely and their arrays stay in
+        // registers instead of scratch.
         // phase 1: V = G U_k for the thread's items (b, n), all rows i of V,
         // written over G in LDS.  With JI >= NBP a thread owns whole band
         // blocks; otherwise the TPR threads of a row share the single block
@@ -575,10 +579,10 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 if (active_row) {
 #pragma unroll
                     for (int i = 0; i < NBP; ++i) {
-                        if (i >= nb) break;
+                        if (NBP < 16 && i >= nb) break;
 #pragma unroll
                         for (int jj = 0; jj < NBP; ++jj) {
-                            if (jj >= nb) break;
+                            if (NBP < 16 && jj >= nb) break;
                             const CT g = Gt[i * NBP + jj];
                             const TE gx = (TE)g.x, gy = (TE)g.y;
 #pragma unroll
@@ -598,7 +602,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                         if (n >= nb) break;
 #pragma unroll
                         for (int i = 0; i < NBP; ++i) {
-                            if (i >= nb) break;
+                            if (NBP < 16 && i >= nb) break;
                             CT o;
                             o.x = (T)v[t][i].x;
                             o.y = (T)v[t][i].y;
@@ -761,7 +765,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     }
 #pragma unroll
                     for (int i = 0; i < NBP; ++i) {
-                        if (i >= nb) break;
+                        if (NBP < 16 && i >= nb) break;
                         const CT vv = Vt[i * NBP + n];
                         const TE vx = (TE)vv.x, vy = (TE)vv.y;
 #pragma unroll
