@@ -116,6 +116,28 @@ def copy_calibration(torch):
     print(json.dumps({"copy_calibration_bytes": x.numel() * 4}), flush=True)
 
 
+def peak_gemm(torch, n=8192, reps=10):
+    """Library GEMM rates (torch.matmul, n x n x n) in FP64, FP32 and BF16: a
+    check of the datasheet MFMA peaks used as roofline denominators."""
+    out = {}
+    for name, dt in (("fp64", torch.float64), ("fp32", torch.float32), ("bf16", torch.bfloat16)):
+        a = torch.randn(n, n, device="cuda:0").to(dt)
+        b = torch.randn(n, n, device="cuda:0").to(dt)
+        c = a @ b
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            c = a @ b
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name] = {"ms": ms, "tflops": 2.0 * n ** 3 / (ms * 1e-3) / 1e12}
+        log("bench: peak gemm %s %.2f TFLOP/s" % (name, out[name]["tflops"]))
+        del a, b, c
+    print(json.dumps({"peak_gemm": out, "n": n}), flush=True)
+
+
 def mobility_shard(dev, dtypes, steps, warmup, torch):
     """One 4096-q chunk of the mobility-scale system, i.e. the per-GPU shard of
     a q-sharded run: fcc, 3 atoms, 16 bands, 9 modes, 617 + 617 WS vectors,
@@ -238,8 +260,23 @@ def cpu_baseline(host, model, seconds_target=15.0):
         nk_s += 1
     dt = time.perf_counter() - t0
     pairs = nk_s * len(k)
+    # the same oracle on one BLAS thread, one k point against all q
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t1 = time.perf_counter()
+        selfenergy.imsigma(HR, R, nd, DR, R, nd, gR, k[idx[:1]], k, model.T, model.mu, model.sigma)
+        dt1 = time.perf_counter() - t1
+    cpu = "unknown CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": pairs / dt, "unit": "k·q pairs/s", "cores": int(threads), "kind": "oracle",
-            "sample": "%d k points x all %d q of the same workload (%.1f s, FP64 NumPy)" % (nk_s, len(k), dt)}
+            "sample": "%d k points x all %d q of the same workload (%.1f s, FP64 NumPy, %s, %d CPUs visible)"
+                      % (nk_s, len(k), dt, cpu, os.cpu_count() or 0),
+            "single_thread": {"value": len(k) / dt1, "unit": "k·q pairs/s", "cores": 1,
+                              "sample": "1 k point x all %d q (%.1f s)" % (len(k), dt1)}}
 
 
 def main():
@@ -256,6 +293,8 @@ def main():
                          "opt-in: one 4096-q shard of the mobility-scale system, ~2 min)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--peak-gemm", action="store_true",
+                    help="only time library GEMMs (8192^3, FP64 / FP32 / BF16) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -268,6 +307,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(torch)
+        return
+    if args.peak_gemm:
+        peak_gemm(torch)
         return
     dev = torch.device("cuda:0")
     model, sysd, pts, host = setup(dev)
