@@ -22,17 +22,35 @@ constexpr int MAXN = 16;
 constexpr int LDA = MAXN + 1;     // padded leading dimension in LDS
 constexpr int RBLK = 256;         // R vectors staged per pass
 constexpr int MAX_SWEEPS = 24;
+// work items of the rotation updates are decoded with shifts over the fixed
+// MAXN x MAXN layout (no division by the runtime size)
+constexpr int LOGN = 4;
+static_assert((1 << LOGN) == MAXN, "MAXN is a power of two");
 
 __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
+// pair i of round r of the round-robin schedule on n2 (even) indices:
+// index n2 - 1 stays fixed, the others rotate (r < n2 - 1, i < n2 / 2, so
+// one conditional subtraction does the reduction mod n2 - 1)
 __device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
     const int m = n2 - 1;
-    const int a = (r + i) % m;
-    const int b = (i == 0) ? m : (r - i + m) % m;
+    int a = r + i;
+    if (a >= m) a -= m;
+    int b = r - i + m;
+    if (b >= m) b -= m;
+    if (i == 0) b = m;
     p = a < b ? a : b;
     q = a < b ? b : a;
+}
+
+// sum over the 64 lanes of the wave; every lane receives the same value
+// (each butterfly step adds the same two operands in every lane)
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    return v;
 }
 
 // REAL_IN: X(R) is real (dynamical matrix); else complex interleaved.
@@ -52,7 +70,6 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     __shared__ double2 red[64];
     __shared__ double rot[MAXN / 2][4];
     __shared__ int rpq[MAXN / 2][2];
-    __shared__ double sred[64];
 
     const int lane = threadIdx.x;
     const int p = blockIdx.x;
@@ -172,24 +189,15 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
         // convergence: off-diagonal mass against the whole matrix
         double off = 0.0, dia = 0.0;
-        for (int e = lane; e < n * n; e += 64) {
-            const int i = e / n, j = e % n;
+        for (int e = lane; e < MAXN * MAXN; e += 64) {
+            const int i = e >> LOGN, j = e & (MAXN - 1);
+            if (i >= n || j >= n) continue;
             const double2 a = A[i][j];
             const double m2 = a.x * a.x + a.y * a.y;
             if (i == j) dia += m2; else off += m2;
         }
-        sred[lane] = off;
-        red[lane].x = dia;
-        __syncthreads();
-        if (lane == 0) {
-            double so = 0.0, sd = 0.0;
-            for (int l = 0; l < 64; ++l) { so += sred[l]; sd += red[l].x; }
-            sred[0] = (so <= 1e-30 * (so + sd)) ? 1.0 : 0.0;
-        }
-        __syncthreads();
-        const bool done = sred[0] != 0.0;
-        __syncthreads();
-        if (done) break;
+        const double so = wave_sum(off), sd = wave_sum(dia);
+        if (so <= 1e-30 * (so + sd)) break;   // the same decision in every lane
         for (int r = 0; r < n2 - 1; ++r) {
             if (lane < npair) {
                 int pp, qq;
@@ -220,10 +228,10 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
             __syncthreads();
             // columns of A and V: col_p' = c col_p - s e^{-i phi} col_q,
             //                     col_q' = s col_p + c e^{-i phi} col_q
-            for (int item = lane; item < 2 * npair * n; item += 64) {
-                const int which = item / (npair * n);
-                const int rem = item % (npair * n);
-                const int pr = rem / n, i = rem % n;
+            for (int item = lane; item < 2 * (MAXN / 2) * MAXN; item += 64) {
+                const int which = item >> (2 * LOGN - 1);
+                const int pr = (item >> LOGN) & (MAXN / 2 - 1), i = item & (MAXN - 1);
+                if (pr >= npair || i >= n) continue;
                 const int pp = rpq[pr][0], qq = rpq[pr][1];
                 if (qq < 0) continue;
                 const double c = rot[pr][0], s = rot[pr][1];
@@ -236,8 +244,9 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
             }
             __syncthreads();
             // rows of A: row_p' = c row_p - s e^{i phi} row_q, row_q' = s row_p + c e^{i phi} row_q
-            for (int item = lane; item < npair * n; item += 64) {
-                const int pr = item / n, j = item % n;
+            for (int item = lane; item < (MAXN / 2) * MAXN; item += 64) {
+                const int pr = item >> LOGN, j = item & (MAXN - 1);
+                if (pr >= npair || j >= n) continue;
                 const int pp = rpq[pr][0], qq = rpq[pr][1];
                 if (qq < 0) continue;
                 const double c = rot[pr][0], s = rot[pr][1];
