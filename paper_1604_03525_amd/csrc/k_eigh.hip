@@ -6,8 +6,11 @@
 // are reduced in a fixed order (bit-reproducible).  The matrix is then
 // Hermitised and diagonalised by the cyclic complex Jacobi method with the
 // round-robin (tournament) ordering: every round applies n/2 disjoint plane
-// rotations at once, columns then rows, so the LDS updates of one round
-// never collide.  Jacobi is used because it reaches full float64 accuracy
+// rotations at once.  The two-sided update J^H A J of a round is block-wise:
+// the 2 x 2 block of rows of one pair and columns of another depends only
+// on itself, so each lane updates one block in a single step (no barrier
+// between the column and the row rotations) and no two lanes touch the same
+// entry.  Jacobi is used because it reaches full float64 accuracy
 // for eigenvalues and eigenvectors at these sizes (n <= 16) and maps onto a
 // single wave without serial Householder steps.
 #include <hip/hip_runtime.h>
@@ -199,6 +202,9 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
         const double so = wave_sum(off), sd = wave_sum(dia);
         if (so <= 1e-30 * (so + sd)) break;   // the same decision in every lane
         for (int r = 0; r < n2 - 1; ++r) {
+            // rotation of pair `lane`: J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on
+            // indices (p, q), which zeroes A[p][q] = |b| e^{i phi} of J^H A J.
+            // An inactive pair (q is the padding index of odd n) keeps J = 1.
             if (lane < npair) {
                 int pp, qq;
                 rr_pair(n2, r, lane, pp, qq);
@@ -206,17 +212,23 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                 if (qq < n) {
                     const double app = A[pp][pp].x, aqq = A[qq][qq].x;
                     const double2 b = A[pp][qq];
-                    const double ab = hypot(b.x, b.y);
-                    if (ab > 0.0) {
-                        cph = b.x / ab;
-                        sph = b.y / ab;
-                        const double tau = (aqq - app) / (2.0 * ab);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + hypot(1.0, tau));
+                    // b = |b| e^{i phi} with b scaled by max(|Re b|, |Im b|) first, so that the
+                    // phase keeps unit modulus down to the smallest normal numbers; a coupling
+                    // below 1e-300 is taken as zero (no rotation)
+                    const double mb = fmax(fabs(b.x), fabs(b.y));
+                    if (mb > 1e-300) {
+                        const double im = 1.0 / mb;
+                        const double bx = b.x * im, by = b.y * im;
+                        const double ir = 1.0 / sqrt(bx * bx + by * by);
+                        cph = bx * ir;
+                        sph = by * ir;
+                        // tau = (a_qq - a_pp) / (2 |b|); the smaller root t of t^2 + 2 tau t = 1
+                        // (tau^2 overflowing gives t = 0, a rotation by less than the rounding of |b|)
+                        const double tau = 0.5 * (aqq - app) * im * ir;
+                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
                         c = 1.0 / sqrt(1.0 + t * t);
                         s = t * c;
                     }
-                } else {
-                    qq = -1;   // inactive (dummy index)
                 }
                 rot[lane][0] = c;
                 rot[lane][1] = s;
@@ -226,43 +238,58 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                 rpq[lane][1] = qq;
             }
             __syncthreads();
-            // columns of A and V: col_p' = c col_p - s e^{-i phi} col_q,
-            //                     col_q' = s col_p + c e^{-i phi} col_q
-            for (int item = lane; item < 2 * (MAXN / 2) * MAXN; item += 64) {
-                const int which = item >> (2 * LOGN - 1);
-                const int pr = (item >> LOGN) & (MAXN / 2 - 1), i = item & (MAXN - 1);
+            // A <- J^H A J in one step: lane (P1, P2) owns the 2 x 2 block of rows
+            // (p1, q1) and columns (p2, q2), which depends on no other block.
+            // Columns first: col_p' = c col_p - s e^{-i phi} col_q,
+            //                col_q' = s col_p + c e^{-i phi} col_q (pair P2);
+            // then rows:     row_p' = c row_p - s e^{i phi} row_q,
+            //                row_q' = s row_p + c e^{i phi} row_q (pair P1).
+            {
+                const int P1 = lane >> (LOGN - 1), P2 = lane & (MAXN / 2 - 1);
+                if (P1 < npair && P2 < npair) {
+                    const int p1 = rpq[P1][0], q1 = rpq[P1][1], p2 = rpq[P2][0], q2 = rpq[P2][1];
+                    const double c1 = rot[P1][0], s1 = rot[P1][1];
+                    const double2 e1 = make_double2(rot[P1][2], rot[P1][3]);
+                    const double c2 = rot[P2][0], s2 = rot[P2][1];
+                    const double2 e2 = make_double2(rot[P2][2], -rot[P2][3]);
+                    const double2 xpp = A[p1][p2], xpq = A[p1][q2], xqp = A[q1][p2], xqq = A[q1][q2];
+                    // columns (pair P2) on rows p1 and q1
+                    const double2 wp = cmul(xpq, e2), wq = cmul(xqq, e2);
+                    const double2 ypp = make_double2(c2 * xpp.x - s2 * wp.x, c2 * xpp.y - s2 * wp.y);
+                    const double2 ypq = make_double2(s2 * xpp.x + c2 * wp.x, s2 * xpp.y + c2 * wp.y);
+                    const double2 yqp = make_double2(c2 * xqp.x - s2 * wq.x, c2 * xqp.y - s2 * wq.y);
+                    const double2 yqq = make_double2(s2 * xqp.x + c2 * wq.x, s2 * xqp.y + c2 * wq.y);
+                    // rows (pair P1) on columns p2 and q2
+                    const double2 up = cmul(yqp, e1), uq = cmul(yqq, e1);
+                    double2 zpp = make_double2(c1 * ypp.x - s1 * up.x, c1 * ypp.y - s1 * up.y);
+                    double2 zqp = make_double2(s1 * ypp.x + c1 * up.x, s1 * ypp.y + c1 * up.y);
+                    double2 zpq = make_double2(c1 * ypq.x - s1 * uq.x, c1 * ypq.y - s1 * uq.y);
+                    double2 zqq = make_double2(s1 * ypq.x + c1 * uq.x, s1 * ypq.y + c1 * uq.y);
+                    if (P1 == P2 && q1 < n) {
+                        // the rotated pair: exact zeros off the diagonal, a real diagonal
+                        zpq = make_double2(0.0, 0.0);
+                        zqp = make_double2(0.0, 0.0);
+                        zpp.y = 0.0;
+                        zqq.y = 0.0;
+                    }
+                    A[p1][p2] = zpp;
+                    A[p1][q2] = zpq;
+                    A[q1][p2] = zqp;
+                    A[q1][q2] = zqq;
+                }
+            }
+            // V <- V J: columns (p, q) of the active pairs, rows i < n
+            for (int item = lane; item < (MAXN / 2) * MAXN; item += 64) {
+                const int pr = item >> LOGN, i = item & (MAXN - 1);
                 if (pr >= npair || i >= n) continue;
                 const int pp = rpq[pr][0], qq = rpq[pr][1];
-                if (qq < 0) continue;
+                if (qq >= n) continue;
                 const double c = rot[pr][0], s = rot[pr][1];
                 const double2 emi = make_double2(rot[pr][2], -rot[pr][3]);
-                double2 (*M)[LDA] = which ? V : A;
-                const double2 xp = M[i][pp];
-                const double2 w = cmul(M[i][qq], emi);
-                M[i][pp] = make_double2(c * xp.x - s * w.x, c * xp.y - s * w.y);
-                M[i][qq] = make_double2(s * xp.x + c * w.x, s * xp.y + c * w.y);
-            }
-            __syncthreads();
-            // rows of A: row_p' = c row_p - s e^{i phi} row_q, row_q' = s row_p + c e^{i phi} row_q
-            for (int item = lane; item < (MAXN / 2) * MAXN; item += 64) {
-                const int pr = item >> LOGN, j = item & (MAXN - 1);
-                if (pr >= npair || j >= n) continue;
-                const int pp = rpq[pr][0], qq = rpq[pr][1];
-                if (qq < 0) continue;
-                const double c = rot[pr][0], s = rot[pr][1];
-                const double2 epi = make_double2(rot[pr][2], rot[pr][3]);
-                const double2 xp = A[pp][j];
-                const double2 w = cmul(A[qq][j], epi);
-                A[pp][j] = make_double2(c * xp.x - s * w.x, c * xp.y - s * w.y);
-                A[qq][j] = make_double2(s * xp.x + c * w.x, s * xp.y + c * w.y);
-            }
-            __syncthreads();
-            if (lane < npair && rpq[lane][1] >= 0) {
-                const int pp = rpq[lane][0], qq = rpq[lane][1];
-                A[pp][qq] = make_double2(0.0, 0.0);
-                A[qq][pp] = make_double2(0.0, 0.0);
-                A[pp][pp].y = 0.0;
-                A[qq][qq].y = 0.0;
+                const double2 xp = V[i][pp];
+                const double2 w = cmul(V[i][qq], emi);
+                V[i][pp] = make_double2(c * xp.x - s * w.x, c * xp.y - s * w.y);
+                V[i][qq] = make_double2(s * xp.x + c * w.x, s * xp.y + c * w.y);
             }
             __syncthreads();
         }
