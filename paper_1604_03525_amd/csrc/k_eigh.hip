@@ -48,6 +48,23 @@ __device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
     q = a < b ? b : a;
 }
 
+// 1/x and 1/sqrt(x) for positive normal x: the hardware estimates (relative
+// error near 5e-8) refined by two Newton-Raphson steps, each of which squares
+// the relative error, so the results are within a few units in the last
+// place, like the correctly rounded division and square root they replace
+// (which cost several times more issue cycles).
+__device__ __forceinline__ double rcp_pos(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsqrt_pos(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) y = fma(0.5 * y, fma(-x * y, y, 1.0), y);   // y (3 - x y^2) / 2
+    return y;
+}
+
 // sum over the 64 lanes of the wave; every lane receives the same value
 // (each butterfly step adds the same two operands in every lane)
 __device__ inline double wave_sum(double v) {
@@ -217,16 +234,25 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                     // below 1e-300 is taken as zero (no rotation)
                     const double mb = fmax(fabs(b.x), fabs(b.y));
                     if (mb > 1e-300) {
-                        const double im = 1.0 / mb;
+                        const double im = rcp_pos(mb);
                         const double bx = b.x * im, by = b.y * im;
-                        const double ir = 1.0 / sqrt(bx * bx + by * by);
+                        const double ir = rsqrt_pos(fma(bx, bx, by * by));
                         cph = bx * ir;
                         sph = by * ir;
-                        // tau = (a_qq - a_pp) / (2 |b|); the smaller root t of t^2 + 2 tau t = 1
-                        // (tau^2 overflowing gives t = 0, a rotation by less than the rounding of |b|)
+                        // tau = (a_qq - a_pp) / (2 |b|); the smaller root t of t^2 + 2 tau t = 1,
+                        // t = sign(tau) / (|tau| + sqrt(1 + tau^2)); beyond |tau| = 1e150 the
+                        // denominator is 2 |tau| to rounding
                         const double tau = 0.5 * (aqq - app) * im * ir;
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        c = 1.0 / sqrt(1.0 + t * t);
+                        const double at = fabs(tau);
+                        double t;
+                        if (at < 1e150) {
+                            const double u = fma(at, at, 1.0);
+                            t = rcp_pos(at + u * rsqrt_pos(u));
+                        } else {
+                            t = 0.5 * rcp_pos(at);
+                        }
+                        if (tau < 0.0) t = -t;
+                        c = rsqrt_pos(fma(t, t, 1.0));
                         s = t * c;
                     }
                 }
