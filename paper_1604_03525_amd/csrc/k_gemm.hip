@@ -35,6 +35,26 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
     const CT* A = reinterpret_cast<const CT*>(d.A);
     const CT* B = reinterpret_cast<const CT*>(d.B);
     CT* C = reinterpret_cast<CT*>(d.C) + (size_t)blockIdx.z * d.sCz;
+    // Index arithmetic that does not change along K is done once per tile, so
+    // that the K loop has no integer division.  Row-major A: the AE elements
+    // a thread fetches per K step lie in one row (AE divides BK), whose two
+    // phase rows the pair operand needs.  B: the thread fetches BE consecutive
+    // columns from nbase on; the slab index and offset of the first one are
+    // kept, the others are at most one slab boundary further.
+    constexpr int AE = BM * BK / 256, BE = BK * BN / 256;
+    static_assert(BK % AE == 0 && BN < 256 && BN % BE == 0, "fetch order of the 64 x 64 tile");
+    const CT* arow1 = A;
+    const CT* arow2 = reinterpret_cast<const CT*>(d.A2);
+    if (!CONJ_TRANS_A && d.A2) {
+        const int my_row = min(m0 + (int)threadIdx.x * AE / BK, d.M - 1);
+        const long r = d.row0 + my_row;
+        arow1 = A + (size_t)(r / d.n2) * d.lda;
+        arow2 += (size_t)(r % d.n2) * d.lda;
+    }
+    const int nbase = (int)(threadIdx.x * BE) % BN;
+    const long colbase = n0 + nbase;
+    const long e_base = colbase / d.ncb;
+    const int c_base = (int)(colbase % d.ncb);
     auto afetch = [&](int m, int kl) -> CT {
         const int row = m0 + m, k = kb + kl;
         if (row < d.M && kl < Kz) {
@@ -44,9 +64,8 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
                 return v;
             }
             if (d.A2) {
-                const long r = d.row0 + row;
-                const CT x = A[(size_t)(r / d.n2) * d.lda + k];
-                const CT y = reinterpret_cast<const CT*>(d.A2)[(size_t)(r % d.n2) * d.lda + k];
+                const CT x = arow1[k];
+                const CT y = arow2[k];
                 CT v;
                 v.x = x.x * y.x - x.y * y.y;
                 v.y = x.x * y.y + x.y * y.x;
@@ -59,7 +78,12 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
     auto bfetch = [&](int kl, int n) -> CT {
         const long col = n0 + n;
         if (kl < Kz && col < d.N) {
-            const long e = col / d.ncb, c = col % d.ncb;
+            long e = e_base;
+            int c = c_base + (n - nbase);      // n - nbase < BE
+            while (c >= d.ncb) {
+                c -= d.ncb;
+                ++e;
+            }
             return B[(size_t)e * d.sBe + (size_t)(kb + kl) * d.sBk + c];
         }
         return cz<T>();
@@ -152,6 +176,8 @@ void launch_cgemm_splitk(Prec prec, const GemmDesc& d, int parts, void* scratch,
 
 void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream, int kparts) {
     if (d.M <= 0 || d.N <= 0) return;
+    // the kernel walks column slabs of width ncb and splits pair rows by n2
+    if (d.ncb < 1 || d.n2 < 1) throw HipFailure{(int)hipErrorInvalidValue, "cgemm descriptor (ncb, n2)", __FILE__, __LINE__};
     const long tiles = (long)((d.N + 63) / 64) * ((d.M + 63) / 64);
     dim3 grid((unsigned)tiles, 1, (unsigned)(kparts > 1 ? kparts : 1));
     if (prec == Prec::F64) {
