@@ -297,8 +297,9 @@ def main():
                     help="only time library GEMMs (8192^3, FP64 / FP32 / BF16) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the q-sharded design is described in DESIGN.md); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (a sharded run "
+              "would give each GPU whole q chunks and sum the partial Im Sigma once); run with --gpus 1",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_1604_03525_amd import epw
