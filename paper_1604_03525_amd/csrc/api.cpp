@@ -149,7 +149,8 @@ constexpr long PAIR_BATCH = 65536;
 struct PairScratch {
     void* phi_k = nullptr;   // [N_k][N_e] c128, 1/ndeg_e included
     void* phi_q = nullptr;   // [Q][N_e] c128
-    void* H = nullptr;       // [batch][n_b][n_b] c128
+    void* H = nullptr;       // [batch][n_b (n_b + 1) / 2] c128: upper triangles of H(k+q)
+    void* HRu = nullptr;     // [N_e][n_b (n_b + 1) / 2] c128: upper triangles of H(R_e)
     long batch = 0;
     // band velocities at k+q (transport mode): i R_a H(R) for a = x, y, z,
     // their Fourier sums for one batch, and the velocities of every pair
@@ -225,6 +226,7 @@ void take_pair_states(const epw_system* s, const epw_points* p, int Q, Arena& A,
     ps.phi_q = A.take(16 * (size_t)Q * s->nRe);
     ps.batch = std::min<long>(PAIR_BATCH, (long)n);
     ps.H = A.take(16 * (size_t)ps.batch * nbb);
+    ps.HRu = A.take(16 * (size_t)s->nRe * (s->nb * (s->nb + 1) / 2));
     if (velocities) {
         ps.dHR3 = A.take(16 * 3 * (size_t)s->nRe * nbb);
         ps.dH3 = A.take(16 * 3 * (size_t)ps.batch * nbb);
@@ -239,32 +241,40 @@ void pair_states(const epw_system* s, const epw_points* p, const epw_params* par
     if (p->kq) return;
     StageTimer t(EPW_STAGE_EIGH, st);
     const int nb = s->nb, ne = s->nRe, nbb = nb * nb;
+    // H(k+q) is Hermitian: only its upper triangle is formed (from that of H(R_e))
+    const int ntri = nb * (nb + 1) / 2;
     if (q0 == 0) launch_phase_table(Prec::F64, p->nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, ps.phi_k, st);
+    if (q0 == 0) launch_pack_upper(nb, ne, s->HR, ps.HRu, st);
     if (q0 == 0 && ps.dHR3) launch_velocity_operands(nb, ne, s->Re, s->HR, ps.vectors9, ps.dHR3, st);
     launch_phase_table(Prec::F64, qc, p->qfrac + 3 * (size_t)q0, ne, s->Re, nullptr, ne, ps.phi_q, st);
     const long npair = (long)p->nk * qc;
     for (long b0 = 0; b0 < npair; b0 += ps.batch) {
         const int nbt = (int)std::min(ps.batch, npair - b0);
-        GemmDesc d;   // H(k+q)[pair][ij] = sum_R Phi_k[k][R] Phi_q[q][R] H(R)[ij]
+        GemmDesc d;   // H(k+q)[pair][i <= j] = sum_R Phi_k[k][R] Phi_q[q][R] H(R)[i <= j]
         d.M = nbt;
-        d.N = nbb;
+        d.N = ntri;
         d.K = ne;
         d.A = ps.phi_k;
         d.lda = ne;
         d.A2 = ps.phi_q;
         d.n2 = qc;
         d.row0 = b0;
-        d.B = s->HR;
-        d.ncb = nbb;
-        d.sBk = nbb;
+        d.B = ps.HRu;
+        d.ncb = ntri;
+        d.sBk = ntri;
         d.C = ps.H;
-        d.sCm = nbb;
+        d.sCm = ntri;
         launch_cgemm(Prec::F64, d, st);
-        launch_eigh_given(nb, nbt, ps.H, eps_pair + (size_t)b0 * nb, (char*)U_pair + 16 * (size_t)b0 * nbb, st);
+        launch_eigh_given(nb, nbt, ps.H, eps_pair + (size_t)b0 * nb, (char*)U_pair + 16 * (size_t)b0 * nbb, st,
+                          true);
         if (ps.vel_pair) {
-            // dH/dk_a(k+q) = sum_R Phi_k Phi_q (i R_a H(R)), then the band velocities
+            // dH/dk_a(k+q) = sum_R Phi_k Phi_q (i R_a H(R)), then the band velocities (full matrices)
             for (int a = 0; a < 3; ++a) {
                 GemmDesc dv = d;
+                dv.N = nbb;
+                dv.ncb = nbb;
+                dv.sBk = nbb;
+                dv.sCm = nbb;
                 dv.B = (const char*)ps.dHR3 + 16 * (size_t)a * ne * nbb;
                 dv.C = (char*)ps.dH3 + 16 * (size_t)a * ps.batch * nbb;
                 launch_cgemm(Prec::F64, dv, st);

@@ -76,8 +76,10 @@ __device__ inline double wave_sum(double v) {
 // REAL_IN: X(R) is real (dynamical matrix); else complex interleaved.
 // SQRT_OUT: write omega = sign(l) sqrt|l| instead of the eigenvalue l.
 // Pair mode (pts2 != nullptr): point p is pts[p / npts2] + pts2[p % npts2].
-// GIVEN: the matrices are given ([np][n][n] complex at XR), no Fourier sum.
-template <bool REAL_IN, bool SQRT_OUT, bool GIVEN = false>
+// GIVEN: the matrices are given ([np][n][n] complex at XR), no Fourier sum;
+// with PACKED only their upper triangles ([np][n(n+1)/2], rows i with columns
+// j >= i in turn), the lower triangle being the conjugate.
+template <bool REAL_IN, bool SQRT_OUT, bool GIVEN = false, bool PACKED = false>
 __global__ __launch_bounds__(64) void interp_eigh_kernel(
     int n, int nR, const int32_t* __restrict__ R, const int32_t* __restrict__ ndeg,
     const double* __restrict__ XR, int np, const double* __restrict__ pts,
@@ -94,7 +96,16 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     const int lane = threadIdx.x;
     const int p = blockIdx.x;
     if (p >= np) return;
-    if constexpr (GIVEN) {
+    if constexpr (GIVEN && PACKED) {
+        const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * (n * (n + 1) / 2);
+        for (int e = lane; e < n * n; e += 64) {
+            const int i = e / n, j = e % n;
+            if (i > j) continue;
+            const double2 x = X[i * n - i * (i - 1) / 2 + (j - i)];
+            V[i][j] = x;
+            if (i < j) V[j][i] = make_double2(x.x, -x.y);
+        }
+    } else if constexpr (GIVEN) {
         const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * n * n;
         for (int e = lane; e < n * n; e += 64) V[e / n][e % n] = X[e];
     } else {
@@ -338,12 +349,37 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
 
 }  // namespace
 
-void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream) {
+void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream, bool packed) {
     if (np <= 0) return;
-    interp_eigh_kernel<false, false, true><<<dim3(np), dim3(64), 0, stream>>>(
-        n, 0, nullptr, nullptr, reinterpret_cast<const double*>(X), np, nullptr, nullptr, 1, evals,
-        reinterpret_cast<double2*>(evecs));
+    if (packed)
+        interp_eigh_kernel<false, false, true, true><<<dim3(np), dim3(64), 0, stream>>>(
+            n, 0, nullptr, nullptr, reinterpret_cast<const double*>(X), np, nullptr, nullptr, 1, evals,
+            reinterpret_cast<double2*>(evecs));
+    else
+        interp_eigh_kernel<false, false, true><<<dim3(np), dim3(64), 0, stream>>>(
+            n, 0, nullptr, nullptr, reinterpret_cast<const double*>(X), np, nullptr, nullptr, 1, evals,
+            reinterpret_cast<double2*>(evecs));
     launch_check("interp_eigh_kernel (given)");
+}
+
+// upper triangles of nR complex n x n matrices, rows i with columns j >= i in turn
+__global__ void pack_upper_kernel(int n, int nR, const double2* __restrict__ X, double2* __restrict__ P) {
+    const int nt = n * (n + 1) / 2;
+    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (long)nR * n * n) return;
+    const int e = (int)(idx % (n * n));
+    const long r = idx / (n * n);
+    const int i = e / n, j = e % n;
+    if (i > j) return;
+    P[r * nt + i * n - i * (i - 1) / 2 + (j - i)] = X[idx];
+}
+
+void launch_pack_upper(int n, int nR, const void* X, void* P, hipStream_t stream) {
+    const long total = (long)nR * n * n;
+    if (total <= 0) return;
+    pack_upper_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream>>>(
+        n, nR, reinterpret_cast<const double2*>(X), reinterpret_cast<double2*>(P));
+    launch_check("pack_upper_kernel");
 }
 
 void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_t* R,

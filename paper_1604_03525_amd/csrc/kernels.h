@@ -21,7 +21,11 @@ void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_
 
 // Eigendecomposition (float64, Hermitised first) of np given n x n complex
 // matrices X [np][n][n]; evals ascending [np][n], evecs [np][n][n] c128.
-void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream);
+// packed: X holds only the upper triangles ([np][n(n+1)/2], row by row from the diagonal)
+void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream,
+                       bool packed = false);
+// P[r] = upper triangle of X[r] in the packed order above (nR matrices, n x n complex)
+void launch_pack_upper(int n, int nR, const void* X, void* P, hipStream_t stream);
 
 // ---- k_vertex.hip ----
 enum class Prec { F64 = 0, F32 = 1, BF16X2 = 2 };
