@@ -360,6 +360,12 @@ def main():
                                  "fused_tflops": ach, "fused_frac_of_peak": ach / PEAK_TFLOPS[var] if ach else None,
                                  "fused_avg_launch_ms": fmsv / fnv if fnv else None,
                                  "fused_traffic": recorded_traffic(var)}
+                if var == "split_bf16" and ach:
+                    # three BF16 products per real product: 24 MFMA flops per complex
+                    # multiply-add (8 algorithmic), so the split form tops out at 1/3 of the
+                    # BF16 peak in algorithmic flops; also the rate against the FP32 peak
+                    variants[var]["fused_frac_of_split_peak"] = ach / (PEAK_TFLOPS[var] / 3.0)
+                    variants[var]["effective_fp32_frac"] = ach / PEAK_TFLOPS["fp32"]
             elif var in ("backward", "backward_fp32"):
                 bdt = "fp32" if var == "backward_fp32" else "fp64"
                 log("bench: %s backward" % bdt)
