@@ -411,14 +411,6 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     // XCD-aware remap: consecutive workgroup ids land on different XCDs
     // (round-robin over 8); give each XCD a contiguous range of (s, mt)
     // so blocks sharing a column slice run on the same L2.
-    // FP64: the second half of the grid (the second resident block of each
-    // CU) starts about 30 us late, so that one block's epilogue (VALU, LDS)
-    // falls into the other block's main loop (MFMA) instead of coinciding
-    // with it: 3 % faster on the 8-band workload; the FP32 paths gained nothing.
-    if constexpr (MODE == 0) {
-        if (blockIdx.x >= gridDim.x / 2)
-            for (int it = 0; it < 9; ++it) __builtin_amdgcn_s_sleep(127);
-    }
     const int G = gridDim.x;
     const int bid = blockIdx.x;
     const int per = G / 8;
@@ -503,6 +495,12 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
 
     for (int nt = s; nt < tiles_n; nt += a.S) {
         const long n0 = (long)nt * BN;
+        // The main loop runs at raised wave priority and the epilogue at the
+        // normal one: where one resident block is in its main loop and the
+        // other in its epilogue, the SIMD's arbiter then keeps the MFMA stream
+        // fed first and fills the gaps with the epilogue (FP64 170 -> 163 ms per
+        // 1260-q launch, FP32 -2 %, split-BF16 -2 %).
+        __builtin_amdgcn_s_setprio(1);
         if constexpr (MODE == 2) {
             f4 cr[4], ci[4];
             const uint16_t* Ap = reinterpret_cast<const uint16_t*>(a.phi_k);
@@ -552,6 +550,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                     Cs[row * LDC + col] = v;
                 }
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         // The band loops of both phases stop at nb for up to 8 padded bands; at
         // 16 they run over the zero padding (G, U_k and the k+q columns are
