@@ -42,6 +42,24 @@ def test_offgrid_forward_parity(case, dtype, tol):
     assert rel_err(got, ref) < tol
 
 
+@pytest.mark.parametrize("nb", [2, 3, 5, 7, 11, 13, 16])
+def test_offgrid_band_counts(nb):
+    """Per-pair k+q states at band counts of every parity and padding: the
+    pair GEMM forms only the upper triangle of H(k+q) (n(n+1)/2 packed
+    columns), which the eigensolver mirrors; FP64 against the oracle, two
+    ragged q chunks."""
+    c = mobility_small_case(nk=10, nq=13, nb=nb, seed=30 + nb)
+    sysd = epw.System(c["R"], c["nd"], c["R"], c["nd"], c["HR"], c["DR"], c["gR"], DEV)
+    pts = epw.Points(c["k"], c["q"], None, device=DEV)
+    par = epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"], chunk_q=7)
+    got = epw.epw_imsigma(sysd, pts, par).cpu().numpy()
+    ref = se.imsigma(c["HR"], c["R"], c["nd"], c["DR"], c["R"], c["nd"], c["gR"], c["k"], c["q"],
+                     c["T"], c["mu"], c["sigma"])
+    _say("offgrid nb", nb, "rel err", rel_err(got, ref))
+    assert np.abs(ref).max() > 0
+    assert rel_err(got, ref) < 1e-10
+
+
 def test_offgrid_backward_matches_reference():
     """dL/dgR and dL/domega off-grid (dL/dH needs the k+q states in the k
     set and is rejected with EPW_ESHAPE)."""
