@@ -7,10 +7,12 @@
 //   a8  g_mn,nu(k,q)  = [U_{k+q}^dag g_nu(k,q) U_k]_mn              fused epilogue
 //   a9  Im Sigma_nk  += |g_mn,nu|^2 {(n+f) d(x+w) + (n+1-f) d(x-w)}  fused epilogue
 //
-// Phi tables already carry the 1/ndeg weights.  Complex products use four
-// real MFMAs (re.re, -im.im into the real accumulator, re.im, im.re into the
-// imaginary one); the four are interleaved over the wave's four C blocks so
-// consecutive MFMAs never depend on each other.
+// The 1/ndeg weights of R_e are folded into the B operand by a6.  Complex
+// products in float64 / float32 use Gauss's three-multiplication form (three
+// real MFMAs per complex block product, cgemm.h); the split-bf16 path uses
+// four real products of three split terms each.  The MFMAs of one K step are
+// interleaved over the wave's C blocks so consecutive ones never depend on
+// each other.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 

@@ -275,3 +275,65 @@ def test_reference_gradient_euler_and_finite_differences():
         omm = om.copy(); omm[idx] -= hstep
         fd = (loss(o=op) - loss(o=omm)) / (2 * hstep)
         assert abs(fd - dom[idx]) < 1e-6 * np.abs(dom).max()
+
+
+def test_reference_offgrid_forward_and_gradient():
+    """The reference gradient's off-grid branch (no k+q map: H diagonalised at
+    every unfolded k+q, as for the random point sets of Sec. 10.2) against the
+    NumPy oracle: forward to 1e-12, Euler identity, and central differences
+    (h = 1e-6) of the NumPy forward for dL/dg, dL/dH and dL/domega.  A wrong
+    pairing of k+q states with (k, q) fails the forward check; a wrong
+    Hermitisation or conjugation fails the dL/dH differences."""
+    R, nd = lattice.ws_vectors(I.FCC_METRIC, (2, 2, 2))
+    nb, nm = 3, 6
+    HR = I.random_hamiltonian(R, I.FCC_VECTORS, nb, seed=41, scale=0.8)
+    DR = I.spring_dynmat(R, I.FCC_VECTORS, I.ATOMS_FCC2, shells=2, seed=42, scale=4e-4)
+    gR = I.random_vertex(R, R, I.FCC_VECTORS, nm, nb, seed=43, g0=0.05)
+    k = I.random_points(4, 3)
+    q = I.random_points(5, 2)
+    T, mu, sig = 300.0, 0.1, 0.3
+    om, e = interp.phonons(DR, R, nd, q)
+    w = I.loss_weights(len(k), nb, 1)
+    kw = dict(Re=R, ndeg_e=nd, Rp=R, ndeg_p=nd, kpoints=k, qpoints=q, kq=None, T=T, mu=mu, sigma=sig)
+    L, ims, dg, dh, dom = torch_ref.loss_and_grads(gR, HR, om, e, w, **kw)
+
+    def fwd(g=gR, h=HR, o=om):
+        return se.imsigma(h, R, nd, None, R, nd, g, k, q, T, mu, sig, phonon_states=(o, e))
+
+    ref = fwd()
+    assert ref.max() > 0
+    assert np.max(np.abs(ims - ref)) < 1e-12 * ref.max()
+    # the k+q states really are per pair: pairing k with the k+q states of
+    # another k changes the result far beyond the tolerance
+    shuffled = se.imsigma(HR, R, nd, None, R, nd, gR, k, q, T, mu, sig, phonon_states=(om, e),
+                          kq_points=(k[::-1][:, None, :] + q[None, :, :]))
+    assert np.max(np.abs(shuffled - ref)) > 1e-3 * ref.max()
+    assert abs(np.sum(np.real(np.conj(dg) * gR)) - 2 * L) < 1e-10 * abs(L)
+
+    def loss(**a):
+        return np.sum(w * fwd(**a))
+    rng = np.random.default_rng(4)
+    hstep = 1e-6
+    for _ in range(3):
+        idx = tuple(rng.integers(0, s) for s in gR.shape)
+        for unit in (1.0, 1j):
+            gp = gR.copy(); gp[idx] += hstep * unit
+            gm = gR.copy(); gm[idx] -= hstep * unit
+            fd = (loss(g=gp) - loss(g=gm)) / (2 * hstep)
+            an = dg[idx].real if unit == 1.0 else dg[idx].imag
+            assert abs(fd - an) < 1e-6 * np.abs(dg).max()
+        for _h in range(2):
+            idx = tuple(rng.integers(0, s) for s in HR.shape)
+            for unit in (1.0, 1j):
+                hp = HR.copy(); hp[idx] += hstep * unit
+                hm = HR.copy(); hm[idx] -= hstep * unit
+                fd = (loss(h=hp) - loss(h=hm)) / (2 * hstep)
+                an = dh[idx].real if unit == 1.0 else dh[idx].imag
+                assert abs(fd - an) < 1e-6 * np.abs(dh).max()
+        idx = (int(rng.integers(0, om.shape[0])), int(rng.integers(0, om.shape[1])))
+        if om[idx] < 2e-3:
+            continue
+        op = om.copy(); op[idx] += hstep
+        omm = om.copy(); omm[idx] -= hstep
+        fd = (loss(o=op) - loss(o=omm)) / (2 * hstep)
+        assert abs(fd - dom[idx]) < 1e-6 * np.abs(dom).max()
