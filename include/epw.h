@@ -21,7 +21,8 @@
  *  - The library allocates no device memory.  Calls that need scratch take
  *    a caller-allocated device workspace (ws, ws_bytes); its size comes
  *    from epw_workspace_size().  Concurrent calls must use distinct
- *    workspaces.
+ *    workspaces.  (epw_imsigma_noalloc instead uses a static device array
+ *    of the library, see there.)
  *  - Units: energies in eV, temperature in K, hbar = 1.  Points are in
  *    fractional (reciprocal-lattice) coordinates, real-space vectors in
  *    integer lattice coordinates.
@@ -247,6 +248,27 @@ int epw_interp_g(const epw_system* sys, const epw_points* pts, const epw_params*
  * Errors: EPW_EINVAL, EPW_ESHAPE, EPW_EDTYPE, EPW_ENOMEM, EPW_EHIP. */
 int epw_imsigma(const epw_system* sys, const epw_points* pts, const epw_params* par,
                 double* imsig, void* ws, size_t ws_bytes, void* stream);
+
+/* Im Sigma exactly as epw_imsigma, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): there is no workspace argument and the call allocates nothing.
+ * Its scratch is a library-owned device array of EPW_NOALLOC_SCRATCH_BYTES
+ * on each GPU, held from the first call on that GPU until the process ends.
+ *  - The array of the current device (hipGetDevice) is used: the stream and
+ *    every pointer must belong to that device.
+ *  - par->chunk_q = 0 takes the largest q chunk whose scratch fits the array;
+ *    a given chunk_q must fit as it is.  Sizes that do not fit (even one q
+ *    point at a time, or the given chunk) fail with EPW_ENOMEM before any
+ *    device work.
+ *  - Every call on one GPU shares that GPU's array, which keeps the last
+ *    call's contents (nothing in it is assumed to start at zero).  Calls
+ *    ordered on one stream are safe; calls that overlap on one GPU (other
+ *    streams, or host threads with no ordering between them) race on the
+ *    array and give wrong results.
+ * Errors: as epw_imsigma. */
+#define EPW_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int epw_imsigma_noalloc(const epw_system* sys, const epw_points* pts, const epw_params* par,
+                        double* imsig, void* stream);
 
 /* Real part of the electron self-energy, Sec. 3 Eq. (3), on shell, and its
  * Fermi-level-referenced form, Sec. 3 Eq. (5):

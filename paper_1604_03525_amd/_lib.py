@@ -40,6 +40,7 @@ EPW_MAX_NB = 16
 EPW_MAX_NM = 16
 EPW_MAX_NMAX = 8
 EPW_MAX_ATOMS = 5
+EPW_NOALLOC_SCRATCH_BYTES = 256 << 20
 
 _vp = ctypes.c_void_p
 _i32p = ctypes.POINTER(ctypes.c_int32)
@@ -92,6 +93,8 @@ PROTOTYPES = {
                                     ctypes.POINTER(EpwParams), _vp, _vp, ctypes.c_size_t, _vp]),
     "epw_imsigma": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
                                    ctypes.POINTER(EpwParams), _vp, _vp, ctypes.c_size_t, _vp]),
+    "epw_imsigma_noalloc": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
+                                           ctypes.POINTER(EpwParams), _vp, _vp]),
     "epw_resigma": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
                                    ctypes.POINTER(EpwParams), _vp, _vp, _vp, ctypes.c_size_t, _vp]),
     "epw_phonon_selfenergy": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),

@@ -997,6 +997,59 @@ int planned_forward(const char* fn, const epw_system* sys, const epw_points* pts
     });
 }
 
+namespace epw {
+
+// Im Sigma in a fixed device buffer of `cap` bytes (the no-allocation entry
+// point).  With par->chunk_q = 0 the largest q chunk whose workspace fits is
+// taken; a given chunk_q must fit as it is.  Argument and size checks run
+// before anything touches the device; `base` is asked for only once they
+// have passed.
+int imsigma_in_buffer(const char* fn, const epw_system* sys, const epw_points* pts, const epw_params* par,
+                      double* imsig, size_t cap, void* (*base)(int* rc), void* stream) {
+    int rc = check_common(sys, pts, par, fn);
+    if (rc != EPW_OK) return rc;
+    if (pts->nk == 0) return EPW_OK;
+    if (!imsig) return fail(EPW_EINVAL, "%s: NULL output", fn);
+    auto need = [&](int q) {
+        epw_params t = *par;
+        t.chunk_q = q;
+        Arena dry;
+        dry.dry = true;
+        Layout L;
+        plan(sys, pts, &t, Out::IMSIGMA, dry, L);
+        return dry.used + 256;
+    };
+    epw_params fitted = *par;
+    if (par->chunk_q > 0) {
+        const size_t n = need(par->chunk_q);
+        if (n > cap)
+            return fail(EPW_ENOMEM, "%s: chunk_q = %d needs %zu bytes of scratch, the library's buffer holds %zu", fn,
+                        par->chunk_q, n, cap);
+    } else {
+        const size_t n1 = need(1);
+        if (n1 > cap)
+            return fail(EPW_ENOMEM, "%s: these sizes need %zu bytes of scratch even one q point at a time, the "
+                        "library's buffer holds %zu", fn, n1, cap);
+        // the workspace grows with the chunk; take the largest chunk that fits
+        int lo = 1, hi = pts->nq > 1 ? pts->nq : 1;
+        while (lo < hi) {
+            const int mid = lo + (hi - lo + 1) / 2;
+            if (need(mid) <= cap) lo = mid;
+            else hi = mid - 1;
+        }
+        while (lo > 1 && need(lo) > cap) --lo;
+        fitted.chunk_q = lo;
+    }
+    int brc = EPW_OK;
+    void* ws = base(&brc);
+    if (brc != EPW_OK) return brc;
+    Outputs o;
+    o.imsig = imsig;
+    return planned_forward(fn, sys, pts, &fitted, Out::IMSIGMA, 0, ws, cap, stream, o);
+}
+
+}  // namespace epw
+
 extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
                                      const epw_params* par) {
     clear_error();

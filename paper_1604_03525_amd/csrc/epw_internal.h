@@ -50,6 +50,13 @@ struct Arena {
     }
 };
 
+// Im Sigma (epw_imsigma) with its workspace in a fixed device buffer of cap
+// bytes: checks the arguments, picks the largest q chunk that fits (or
+// checks the given one) and only then calls base() for the buffer's device
+// address (base sets *rc and returns nullptr on failure).
+int imsigma_in_buffer(const char* fn, const epw_system* sys, const epw_points* pts, const epw_params* par,
+                      double* imsig, size_t cap, void* (*base)(int* rc), void* stream);
+
 // smallest power of two >= n (n >= 1)
 inline int pow2_at_least(int n) {
     int p = 1;

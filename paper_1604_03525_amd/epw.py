@@ -242,6 +242,18 @@ def epw_imsigma(system, points, params, out=None, workspace=None):
     return out
 
 
+def epw_imsigma_noalloc(system, points, params, out=None):
+    """Im Sigma_nk [nk][nb] float64 as epw_imsigma, with the library's own
+    static device scratch instead of a workspace (no allocation in the call)."""
+    lib = _lib.load()
+    if out is None:
+        out = torch.empty((points.k.shape[0], system.nb), dtype=torch.float64, device=system.device)
+    s, p = system.c_struct(), points.c_struct()
+    _lib.check(lib.epw_imsigma_noalloc(ctypes.byref(s), ctypes.byref(p), ctypes.byref(params), _ptr(out),
+                                       _stream(system.device)))
+    return out
+
+
 def epw_resigma(system, points, params, want_tilde=True, workspace=None):
     """(Sigma'_nk on shell, Sigma~'_nk or None) [nk][nb] float64: the real part
     of Sec. 3 Eq. (3) at omega = eps_nk - eps_F and its Eq. (5) form."""
