@@ -64,7 +64,7 @@ def timed(fn, steps, warmup, torch):
     dt = time.perf_counter() - t0
     stages = {}
     for name, sid in (("eigh", 0), ("gemm_rp", 1), ("moderot", 2), ("fused", 3), ("backward", 4),
-                      ("spectral", 5)):
+                      ("spectral", 5), ("pair_gemm", 6), ("pair_eigh", 7)):
         ms, n = epw.epw_timing_read(sid)
         stages[name] = (ms, n)
     epw.epw_timing_enable(False)
@@ -76,6 +76,7 @@ def timed(fn, steps, warmup, torch):
 # device copy, see --copy-calibration).  It describes the kernel sources whose
 # hash it records: once those change, the figure is reported as null.
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "fused_k_kernel_fcc20.md")
+MOBILITY_PROFILE = os.path.join(ROOT, "profiles", "fused_k_kernel_mobility_shard.md")
 TRAFFIC_SOURCES = ["paper_1604_03525_amd/csrc/k_vertex.hip", "paper_1604_03525_amd/csrc/cgemm.h",
                    "paper_1604_03525_amd/csrc/api.cpp"]
 
@@ -89,11 +90,11 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def recorded_traffic(dtype):
+def recorded_traffic(dtype, profile=TRAFFIC_PROFILE):
     """Bytes per launch of the fused kernel for `dtype`, or None when the
     profile is missing or was taken on other kernel sources."""
     try:
-        with open(TRAFFIC_PROFILE) as f:
+        with open(profile) as f:
             for line in f:
                 if line.startswith("traffic-record: "):
                     rec = json.loads(line[len("traffic-record: "):])
@@ -138,43 +139,38 @@ def peak_gemm(torch, n=8192, reps=10):
     print(json.dumps({"peak_gemm": out, "n": n}), flush=True)
 
 
-def mobility_shard(dev, dtypes, steps, warmup, torch):
+def pair_eigh_flops(n):
+    """Arithmetic of one n x n complex Jacobi sweep as the eigensolver runs it
+    (one-sided count, flops = real additions and multiplications): each of the
+    n(n-1)/2 rotations of a sweep rewrites two rows and two columns of A
+    (4n complex entries, each 2 complex-by-real products, one complex phase
+    product and one complex addition: 14 flops) and two columns of V (2n
+    entries, 14 flops each)."""
+    return n * (n - 1) / 2 * (4 * n + 2 * n) * 14.0
+
+
+def mobility_shard(dev, dtypes, bwd_dtypes, steps, warmup, torch):
     """One 4096-q chunk of the mobility-scale system, i.e. the per-GPU shard of
     a q-sharded run: fcc, 3 atoms, 16 bands, 9 modes, 617 + 617 WS vectors,
     8000 k in the 0.3 eV window above the conduction band minimum x the first
     4096 of 125,000 random q, off-grid k+q (H interpolated and diagonalised per
-    pair), normalised by N_q = 125,000.  H and D are rescaled on the coarse
-    grid to a 12 eV bandwidth and a 65 meV top phonon; mu is mid-gap on a 40^3
-    grid.  g(R_e,R_p) (14 GB) is drawn on the device."""
+    pair), normalised by N_q = 125,000.  H and D carry the scale constants of
+    the model (12 eV bandwidth and a 65 meV top phonon on the coarse grid; mu
+    mid-gap on a 40^3 grid).  g(R_e,R_p) (14 GB) is drawn on the device."""
     import numpy as np
     from paper_1604_03525_amd import epw
     from paper_1604_03525_amd import inputs as I
     m = I.mobility_model()
     x = m.extra
     R, nd = epw.epw_ws_vectors(m.metric, m.coarse)
-    H0, D0 = I.mobility_unscaled(R)
+    H0, D0 = I.mobility_arrays(R)
     Ht = torch.as_tensor(H0, device=dev)
     Dt = torch.as_tensor(D0, device=dev)
-    coarse = epw.epw_grid_points(m.coarse)
-    e0, _ = epw.epw_interp_bands(Ht, R, nd, coarse)
-    Ht *= x["bandwidth"] / float(e0.max() - e0.min())
-    w0, _ = epw.epw_interp_phonons(Dt, R, nd, coarse)
-    Dt *= (x["omega_max"] / float(w0.max())) ** 2
-    e40, _ = epw.epw_interp_bands(Ht, R, nd, epw.epw_grid_points((40, 40, 40)))
-    nv = m.nb // 2
-    vbm, cbm = float(e40[:, nv - 1].max()), float(e40[:, nv].min())
-    mu = 0.5 * (vbm + cbm)
-    rng = np.random.default_rng(x["seed_k"])
-    kept, total = [], 0
-    for _ in range(200):
-        cand = rng.random((65536, 3))
-        e, _ = epw.epw_interp_bands(Ht, R, nd, cand)
-        mask = ((e >= cbm) & (e <= cbm + x["window"])).any(dim=1).cpu().numpy()
-        kept.append(cand[mask])
-        total += int(mask.sum())
-        if total >= x["nk"]:
-            break
-    k = np.concatenate(kept)[: x["nk"]]
+    cbm, mu = I.C5_CBM, I.C5_MU
+    cand = I.mobility_k_candidates(65536, x["seed_k"])
+    e, _ = epw.epw_interp_bands(Ht, R, nd, cand)
+    mask = ((e >= cbm) & (e <= cbm + x["window"])).any(dim=1).cpu().numpy()
+    k = cand[mask][: x["nk"]]
     q = I.random_points(x["nq"], x["seed_q"])[: x["chunk"]]
     gR = I.random_vertex_device(R, R, m.vectors, m.nm, m.nb, seed=x["seed_g"], g0=0.05, decay=1.0, device=dev)
     sysd = epw.System(R, nd, R, nd, Ht, Dt, gR, dev)
@@ -182,27 +178,46 @@ def mobility_shard(dev, dtypes, steps, warmup, torch):
     pts = epw.Points(k, q, None, device=dev)
     ws = epw.Workspace(dev)
     pairs = len(k) * len(q)
-    out = {"workload": "fcc 3 atoms, nb=16, nm=9, WS 617+617, %d window k x %d random q (one chunk of %d), "
-                       "off-grid k+q, T=300 K, sigma=10 meV" % (len(k), len(q), x["nq"]),
-           "mu_eV": mu, "cbm_eV": cbm}
+    out = {"workload": "mobility-scale shard: fcc 3 atoms, nb=16, nm=9, WS 617+617, %d window k x %d random q "
+                       "(the first chunk of %d), off-grid k+q, T=300 K, sigma=10 meV" % (len(k), len(q), x["nq"]),
+           "nk": len(k), "nq": len(q), "pairs": pairs, "mu_eV": mu, "cbm_eV": cbm}
+    ff = fused_flops(len(k), len(q), len(R), m.nm, m.nb)
     for dt in dtypes:
-        log("bench: mobility shard %s" % dt)
+        log("bench: mobility shard %s forward" % dt)
         par = epw.make_params(T=m.T, mu=mu, sigma=m.sigma, nq_norm=float(x["nq"]), dtype=dt)
         dtv, stv = timed(lambda: epw.epw_imsigma(sysd, pts, par, workspace=ws), steps, warmup, torch)
         fms, fnn = stv["fused"]
-        ach = fused_flops(len(k), len(q), len(R), m.nm, m.nb) * steps / (fms * 1e-3) / 1e12 if fms > 0 else None
-        out[dt] = {"value": pairs * steps / dtv, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dtv / steps,
-                   "fused_tflops": ach, "fused_frac_of_peak": ach / PEAK_TFLOPS[dt] if ach else None,
-                   "stages_ms_per_step": {s_: v[0] / steps for s_, v in stv.items()}}
-    # the adjoint of the same shard in FP32 (dL/dg and dL/domega; dL/dH needs a k+q map)
-    log("bench: mobility shard fp32 backward")
-    par = epw.make_params(T=m.T, mu=mu, sigma=m.sigma, nq_norm=float(x["nq"]), dtype="fp32")
+        ach = ff * steps / (fms * 1e-3) / 1e12 if fms > 0 else None
+        gms, gn = stv["pair_gemm"]
+        ems, en = stv["pair_eigh"]
+        eig_tf = pairs * steps * 7.0 * pair_eigh_flops(m.nb) / (ems * 1e-3) / 1e12 if ems > 0 else None
+        rec = {"value": pairs * steps / dtv, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dtv / steps,
+               "roofline": {"bound": "mfma", "kernel": "fused_k_kernel", "achieved": ach,
+                            "peak": PEAK_TFLOPS[dt], "unit": "TFLOP/s",
+                            "frac": ach / PEAK_TFLOPS[dt] if ach else None,
+                            "traffic": recorded_traffic(dt, MOBILITY_PROFILE),
+                            "launches": fnn, "avg_launch_ms": fms / fnn if fnn else None},
+               "pair_states_ms_per_step": {"h_kq_gemm": gms / steps, "eigh": ems / steps},
+               "pair_eigh_fp64_valu": {"achieved": eig_tf, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                                       "frac": eig_tf / PEAK_TFLOPS["fp64"] if eig_tf else None,
+                                       "count": "7 Jacobi sweeps of pair_eigh_flops(16) per pair"},
+               "stages_ms_per_step": {s_: v[0] / steps for s_, v in stv.items()}}
+        if dt == "split_bf16" and ach:
+            rec["roofline"]["frac_of_split_peak"] = ach / (PEAK_TFLOPS[dt] / 3.0)
+        out[dt] = rec
     w = torch.rand((len(k), m.nb), dtype=torch.float64, device=dev, generator=torch.Generator(device=dev).manual_seed(1))
-    dtb, stb = timed(lambda: epw.epw_imsigma_backward(sysd, pts, par, w, want=("gR", "omega"), workspace=ws),
-                     1, 0, torch)
-    out["backward_fp32"] = {"value": pairs / dtb, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dtb,
-                            "outputs": "dL/dg(R_e,R_p), dL/domega",
-                            "stages_ms_per_step": {s_: v[0] for s_, v in stb.items()}}
+    for dt in bwd_dtypes:
+        log("bench: mobility shard %s backward" % dt)
+        par = epw.make_params(T=m.T, mu=mu, sigma=m.sigma, nq_norm=float(x["nq"]), dtype=dt)
+        dtb, stb = timed(lambda: epw.epw_imsigma_backward(sysd, pts, par, w, workspace=ws), 1, 0, torch)
+        out["backward_" + dt] = {"value": pairs / dtb, "unit": "k·q pairs/s", "ms_per_step": 1e3 * dtb,
+                                 "outputs": "dL/dg(R_e,R_p), dL/dH(R_e), dL/domega",
+                                 "stages_ms_per_step": {s_: v[0] for s_, v in stb.items()}}
+    for s_ in ("fp32", "split_bf16"):
+        if s_ in out and "fp64" in out:
+            out[s_]["speedup_vs_fp64"] = out[s_]["value"] / out["fp64"]["value"]
+    del sysd
+    torch.cuda.empty_cache()
     return out
 
 
@@ -286,11 +301,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--variants",
-                    default="fp32,split_bf16,backward,backward_fp32,phonon,resigma,polar,transport,spectral",
-                    help="comma list of fp32, split_bf16, backward, backward_fp32, phonon, resigma, polar, "
-                         "transport, spectral, "
-                         "mobility (the last is "
-                         "opt-in: one 4096-q shard of the mobility-scale system, ~2 min)")
+                    default="fp32,split_bf16,backward,backward_fp32,backward_split_bf16,mobility,phonon,resigma,"
+                            "polar,transport,spectral",
+                    help="comma list of fp32, split_bf16, backward, backward_fp32, backward_split_bf16, mobility "
+                         "(one 4096-q shard of the mobility-scale system), phonon, resigma, polar, transport, "
+                         "spectral")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--peak-gemm", action="store_true",
@@ -348,6 +363,11 @@ def main():
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
     }
     variants = {}
+    # secondary variants (everything but the precisions of the headline
+    # forward) take at most 3 timed steps after at most 1 warm-up, so the
+    # default run stays within a few minutes
+    ksteps, kwarm = min(args.steps, 3), min(args.warmup, 1)
+    kflops = fused_flops(nk, nq, ne, nm, nb) * ksteps
     for var in [v for v in args.variants.split(",") if v]:
         try:
             if var in ("fp32", "split_bf16"):
@@ -366,33 +386,36 @@ def main():
                     # BF16 peak in algorithmic flops; also the rate against the FP32 peak
                     variants[var]["fused_frac_of_split_peak"] = ach / (PEAK_TFLOPS[var] / 3.0)
                     variants[var]["effective_fp32_frac"] = ach / PEAK_TFLOPS["fp32"]
-            elif var in ("backward", "backward_fp32"):
-                bdt = "fp32" if var == "backward_fp32" else "fp64"
+            elif var in ("backward", "backward_fp32", "backward_split_bf16"):
+                bdt = {"backward": "fp64", "backward_fp32": "fp32", "backward_split_bf16": "split_bf16"}[var]
                 log("bench: %s backward" % bdt)
                 par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma, dtype=bdt)
                 w = torch.rand((nk, nb), dtype=torch.float64, device=dev)
-                dtb, _ = timed(lambda: epw.epw_imsigma_backward(sysd, pts, par, w, workspace=ws),
-                               args.steps, args.warmup, torch)
-                variants[var] = {"value": pairs * args.steps / dtb, "ms_per_step": 1e3 * dtb / args.steps,
-                                 "dtype": bdt, "outputs": "dL/dg(R_e,R_p), dL/dH(R_e), dL/domega"}
+                dtb, stb = timed(lambda: epw.epw_imsigma_backward(sysd, pts, par, w, workspace=ws),
+                                 ksteps, kwarm, torch)
+                variants[var] = {"value": pairs * ksteps / dtb, "ms_per_step": 1e3 * dtb / ksteps,
+                                 "steps": ksteps, "dtype": bdt,
+                                 "outputs": "dL/dg(R_e,R_p), dL/dH(R_e), dL/domega",
+                                 "ratio_to_forward": (1e3 * dtb / ksteps) / ms_step if bdt == "fp64" else None,
+                                 "stages_ms_per_step": {s_: v[0] / ksteps for s_, v in stb.items()}}
             elif var == "phonon":
                 log("bench: phonon linewidth and lambda (fp64)")
                 par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
                 dtp, stp = timed(lambda: epw.epw_phonon_selfenergy(sysd, pts, par, workspace=ws),
-                                 args.steps, args.warmup, torch)
+                                 ksteps, kwarm, torch)
                 fmsp, fnp = stp["fused"]
-                achp = flops / (fmsp * 1e-3) / 1e12 if fmsp > 0 else None
-                variants[var] = {"value": pairs * args.steps / dtp, "ms_per_step": 1e3 * dtp / args.steps,
+                achp = kflops / (fmsp * 1e-3) / 1e12 if fmsp > 0 else None
+                variants[var] = {"value": pairs * ksteps / dtp, "ms_per_step": 1e3 * dtp / ksteps,
                                  "dtype": "fp64", "outputs": "Pi''_q,nu (Eq. 9) and lambda_q,nu (Eq. 11)",
                                  "fused_tflops": achp, "fused_frac_of_peak": achp / PEAK_TFLOPS["fp64"] if achp else None}
             elif var == "resigma":
                 log("bench: on-shell Re Sigma and Sigma~' (fp64)")
                 par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
                 dtr, str_ = timed(lambda: epw.epw_resigma(sysd, pts, par, workspace=ws),
-                                  args.steps, args.warmup, torch)
+                                  ksteps, kwarm, torch)
                 fmsr, fnr = str_["fused"]
-                achr = flops / (fmsr * 1e-3) / 1e12 if fmsr > 0 else None
-                variants[var] = {"value": pairs * args.steps / dtr, "ms_per_step": 1e3 * dtr / args.steps,
+                achr = kflops / (fmsr * 1e-3) / 1e12 if fmsr > 0 else None
+                variants[var] = {"value": pairs * ksteps / dtr, "ms_per_step": 1e3 * dtr / ksteps,
                                  "dtype": "fp64", "outputs": "Sigma'_nk on shell (Eq. 3) and Sigma~'_nk (Eq. 5)",
                                  "fused_tflops": achr, "fused_frac_of_peak": achr / PEAK_TFLOPS["fp64"] if achr else None}
             elif var == "transport":
@@ -401,10 +424,10 @@ def main():
                 # eps_F 0.3 eV into the valence bands (the headline mu is mid-gap)
                 par = epw.make_params(T=model.T, mu=model.mu - 0.3, sigma=0.05)
                 dtt, stt = timed(lambda: epw.epw_transport_coupling(sysd, pts, par, I.FCC_VECTORS, want_pi=True,
-                                                                    workspace=ws), args.steps, args.warmup, torch)
+                                                                    workspace=ws), ksteps, kwarm, torch)
                 fmst, fnt = stt["fused"]
-                acht = flops / (fmst * 1e-3) / 1e12 if fmst > 0 else None
-                variants[var] = {"value": pairs * args.steps / dtt, "ms_per_step": 1e3 * dtt / args.steps,
+                acht = kflops / (fmst * 1e-3) / 1e12 if fmst > 0 else None
+                variants[var] = {"value": pairs * ksteps / dtt, "ms_per_step": 1e3 * dtt / ksteps,
                                  "dtype": "fp64", "outputs": "lambda_tr (Eq. 55), lambda (Eq. 11), Pi'' (Eq. 9)",
                                  "mu_shift_eV": -0.3, "sigma_eV": 0.05,
                                  "fused_tflops": acht, "fused_frac_of_peak": acht / PEAK_TFLOPS["fp64"] if acht else None}
@@ -415,16 +438,17 @@ def main():
                 sysp = epw.System(R_, nd_, R_, nd_, HR_, DR_, gR_, dev, polar=I.polar_params())
                 par = epw.make_params(T=model.T, mu=model.mu, sigma=model.sigma)
                 outp = torch.empty((nk, nb), dtype=torch.float64, device=dev)
-                dtq, stq = timed(lambda: epw.epw_imsigma(sysp, pts, par, out=outp, workspace=ws), args.steps,
-                                 args.warmup, torch)
-                variants[var] = {"value": pairs * args.steps / dtq, "ms_per_step": 1e3 * dtq / args.steps,
+                dtq, stq = timed(lambda: epw.epw_imsigma(sysp, pts, par, out=outp, workspace=ws), ksteps,
+                                 kwarm, torch)
+                variants[var] = {"value": pairs * ksteps / dtq, "ms_per_step": 1e3 * dtq / ksteps,
                                  "dtype": "fp64", "outputs": "Im Sigma_nk with g = g^S + g^L (Sec. 4)",
-                                 "stages_ms_per_step": {s_: v[0] / args.steps for s_, v in stq.items()}}
+                                 "stages_ms_per_step": {s_: v[0] / ksteps for s_, v in stq.items()}}
                 del sysp
             elif var == "spectral":
-                variants[var] = spectral_run(sysd, model, dev, args.steps, args.warmup, torch)
+                variants[var] = spectral_run(sysd, model, dev, ksteps, kwarm, torch)
             elif var == "mobility":
-                variants[var] = mobility_shard(dev, ("fp32", "split_bf16"), min(args.steps, 2), 1, torch)
+                variants[var] = mobility_shard(dev, ("fp64", "fp32", "split_bf16"), ("fp32", "split_bf16"), 1, 0,
+                                               torch)
         except epw.EpwError as e:
             variants[var] = {"unavailable": str(e)}
     result["variants"] = variants

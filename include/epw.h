@@ -45,6 +45,7 @@ extern "C" {
 #define EPW_EINVAL   -1   /* NULL pointer or invalid scalar parameter            */
 #define EPW_ESHAPE   -2   /* unsupported or inconsistent sizes                   */
 #define EPW_EDTYPE   -3   /* unknown precision selector                          */
+#define EPW_ENOTHERM -4   /* H(-R) != H(R)^dag or D(-R) != D(R)^T beyond tolerance */
 #define EPW_ENOMEM   -5   /* workspace (or host capacity) too small              */
 #define EPW_EHIP     -6   /* the HIP runtime reported an error                   */
 
@@ -410,7 +411,8 @@ int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw
                          void* ws, size_t ws_bytes, void* stream);
 
 /* Workspace bytes for the call `which` (EPW_WS_INTERP_G, EPW_WS_IMSIGMA,
- * EPW_WS_IMSIGMA_BACKWARD, EPW_WS_PHONON, EPW_WS_RESIGMA, EPW_WS_TRANSPORT) with these sizes and parameters; device pointers
+ * EPW_WS_IMSIGMA_BACKWARD, EPW_WS_PHONON, EPW_WS_RESIGMA, EPW_WS_TRANSPORT,
+ * EPW_WS_CHECK for epw_check_inputs) with these sizes and parameters; device pointers
  * inside sys/pts are not dereferenced and may be NULL.  Returns 0 and sets
  * the error message on invalid arguments. */
 #define EPW_WS_INTERP_G          1
@@ -419,8 +421,35 @@ int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw
 #define EPW_WS_PHONON            4
 #define EPW_WS_RESIGMA           5
 #define EPW_WS_TRANSPORT         6
+#define EPW_WS_CHECK             7
 size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pts,
                           const epw_params* par);
+
+/* Validation of a system and point set, meant to run once before the calls
+ * above, which check sizes and scalar parameters only and take the arrays
+ * as they are.  Synchronous: the check kernels run on `stream` and the call
+ * waits for them.  The first failed check, in this order, is returned:
+ *  1. every entry of H(R_e), D(R_p) (when given), g(R_e,R_p), the k and q
+ *     points and given omega / evec is finite                 -> EPW_EINVAL
+ *  2. ndeg >= 1 in both WS sets, and nmax_e (when set) >= every |component|
+ *     of R_e (the in-kernel phase generation relies on it)    -> EPW_EINVAL
+ *  3. both WS sets are closed under R -> -R (off-grid runs need it for R_e;
+ *     epw_ws_vectors always returns such sets)                 -> EPW_ESHAPE
+ *  4. max |H(-R) - H(R)^dag| <= herm_tol max |H| and
+ *     max |D(-R) - D(R)^T| <= herm_tol max |D| over all R and entries: the
+ *     interpolated H(k) and D(q) are then Hermitian before their
+ *     symmetrisation (the Wannier Hamiltonian and force constants of a real
+ *     crystal are; every call Hermitises the interpolated matrices, so a
+ *     violation is a symptom of bad input, not a failure)    -> EPW_ENOTHERM
+ *  5. the k+q map (when given): every entry in [0, nk), and for every q the
+ *     map k -> kq[k][q] is one-to-one (as on a full grid)     -> EPW_EINVAL
+ *  herm_tol  >= 0 (1e-12 suits float64 inputs built with the symmetry)
+ *  ws        device workspace of epw_workspace_size(EPW_WS_CHECK, ...) bytes
+ *            (the params of the size query are only checked for validity)
+ * Errors: as listed, plus EPW_EINVAL (NULL, bad herm_tol), EPW_ESHAPE,
+ * EPW_ENOMEM (workspace), EPW_EHIP. */
+int epw_check_inputs(const epw_system* sys, const epw_points* pts, double herm_tol, void* ws, size_t ws_bytes,
+                     void* stream);
 
 /* ======================================================================
  * Stage timing (diagnostics)
@@ -429,13 +458,16 @@ size_t epw_workspace_size(int which, const epw_system* sys, const epw_points* pt
 /* When enabled, every launch of the kernels of a stage is bracketed by a
  * pair of HIP events recorded on the launch's own stream.  The library's
  * only process-wide state; guarded by a mutex.  Stages: */
-#define EPW_STAGE_EIGH      0   /* interpolation + eigensolve of H(k), D(q)      */
+#define EPW_STAGE_EIGH      0   /* interpolation + eigensolve of H(k), D(q),
+                                   phase tables of the off-grid pairs            */
 #define EPW_STAGE_GEMM_RP   1   /* R_p -> q contraction                          */
 #define EPW_STAGE_MODEROT   2   /* mode rotation and 1/sqrt(2 omega)             */
 #define EPW_STAGE_FUSED     3   /* R_e -> k contraction + rotation + reduction   */
 #define EPW_STAGE_BACKWARD  4   /* adjoint kernels                               */
 #define EPW_STAGE_SPECTRAL  5   /* frequency-resolved sum over pole records      */
-#define EPW_NUM_STAGES      6
+#define EPW_STAGE_PAIR_GEMM 6   /* off-grid: H(k+q) of every pair (phase GEMM)   */
+#define EPW_STAGE_PAIR_EIGH 7   /* off-grid: eigensolve of every H(k+q)          */
+#define EPW_NUM_STAGES      8
 
 /* enable != 0 starts recording (and discards earlier records); 0 stops. */
 int epw_timing_enable(int enable);

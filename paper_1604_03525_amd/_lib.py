@@ -12,6 +12,7 @@ EPW_OK = 0
 EPW_EINVAL = -1
 EPW_ESHAPE = -2
 EPW_EDTYPE = -3
+EPW_ENOTHERM = -4
 EPW_ENOMEM = -5
 EPW_EHIP = -6
 
@@ -25,6 +26,7 @@ EPW_WS_IMSIGMA_BACKWARD = 3
 EPW_WS_PHONON = 4
 EPW_WS_RESIGMA = 5
 EPW_WS_TRANSPORT = 6
+EPW_WS_CHECK = 7
 EPW_ORDER_AUTO = 0
 EPW_ORDER_K_INNER = 1
 EPW_ORDER_K_OUTER = 2
@@ -35,6 +37,8 @@ EPW_STAGE_MODEROT = 2
 EPW_STAGE_FUSED = 3
 EPW_STAGE_BACKWARD = 4
 EPW_STAGE_SPECTRAL = 5
+EPW_STAGE_PAIR_GEMM = 6
+EPW_STAGE_PAIR_EIGH = 7
 
 EPW_MAX_NB = 16
 EPW_MAX_NM = 16
@@ -102,6 +106,8 @@ PROTOTYPES = {
     "epw_imsigma_backward": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints),
                                             ctypes.POINTER(EpwParams), _vp, _vp, _vp, _vp, _vp,
                                             ctypes.c_size_t, _vp]),
+    "epw_check_inputs": (ctypes.c_int, [ctypes.POINTER(EpwSystem), ctypes.POINTER(EpwPoints), ctypes.c_double,
+                                        _vp, ctypes.c_size_t, _vp]),
     "epw_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "epw_timing_read": (ctypes.c_int, [ctypes.c_int, _dp, _i64p]),
     "epw_workspace_size": (ctypes.c_size_t, [ctypes.c_int, ctypes.POINTER(EpwSystem),

@@ -19,7 +19,7 @@ ARCH = os.environ.get("EPW_OFFLOAD_ARCH", "gfx950")
 
 SOURCES = ["errors.cpp", "host_lattice.cpp", "timing.cpp", "api.cpp", "k_eigh.hip", "k_vertex.hip",
            "k_gemm.hip", "k_backward.hip", "k_spectral.hip", "k_polar.hip", "k_transport.hip",
-           "noalloc.hip"]
+           "k_check.hip", "noalloc.hip"]
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,

@@ -150,7 +150,8 @@ struct PairScratch {
     void* phi_k = nullptr;   // [N_k][N_e] c128, 1/ndeg_e included
     void* phi_q = nullptr;   // [Q][N_e] c128
     void* H = nullptr;       // [batch][n_b (n_b + 1) / 2] c128: upper triangles of H(k+q)
-    void* HRu = nullptr;     // [N_e][n_b (n_b + 1) / 2] c128: upper triangles of H(R_e)
+    void* HRu = nullptr;     // [N_e][n_b (n_b + 1) / 2] c128: upper triangles of the Hermitian part of H(R_e)
+    int32_t* negR = nullptr; // [N_e] index of -R_e
     long batch = 0;
     // band velocities at k+q (transport mode): i R_a H(R) for a = x, y, z,
     // their Fourier sums for one batch, and the velocities of every pair
@@ -227,6 +228,7 @@ void take_pair_states(const epw_system* s, const epw_points* p, int Q, Arena& A,
     ps.batch = std::min<long>(PAIR_BATCH, (long)n);
     ps.H = A.take(16 * (size_t)ps.batch * nbb);
     ps.HRu = A.take(16 * (size_t)s->nRe * (s->nb * (s->nb + 1) / 2));
+    ps.negR = (int32_t*)A.take(4 * (size_t)s->nRe);
     if (velocities) {
         ps.dHR3 = A.take(16 * 3 * (size_t)s->nRe * nbb);
         ps.dH3 = A.take(16 * 3 * (size_t)ps.batch * nbb);
@@ -239,14 +241,17 @@ void take_pair_states(const epw_system* s, const epw_points* p, int Q, Arena& A,
 void pair_states(const epw_system* s, const epw_points* p, const epw_params* par, int q0, int qc, double* eps_pair,
                  void* U_pair, double* f_pair, const PairScratch& ps, hipStream_t st) {
     if (p->kq) return;
-    StageTimer t(EPW_STAGE_EIGH, st);
     const int nb = s->nb, ne = s->nRe, nbb = nb * nb;
-    // H(k+q) is Hermitian: only its upper triangle is formed (from that of H(R_e))
+    // H(k+q) is Hermitian: only its upper triangle is formed, from the upper
+    // triangles of the Hermitian part of H(R_e) (exact for any H(R_e))
     const int ntri = nb * (nb + 1) / 2;
-    if (q0 == 0) launch_phase_table(Prec::F64, p->nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, ps.phi_k, st);
-    if (q0 == 0) launch_pack_upper(nb, ne, s->HR, ps.HRu, st);
-    if (q0 == 0 && ps.dHR3) launch_velocity_operands(nb, ne, s->Re, s->HR, ps.vectors9, ps.dHR3, st);
-    launch_phase_table(Prec::F64, qc, p->qfrac + 3 * (size_t)q0, ne, s->Re, nullptr, ne, ps.phi_q, st);
+    {
+        StageTimer t(EPW_STAGE_EIGH, st);
+        if (q0 == 0) launch_phase_table(Prec::F64, p->nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, ps.phi_k, st);
+        if (q0 == 0) launch_pack_upper(nb, ne, s->Re, s->ndeg_e, s->HR, ps.negR, ps.HRu, st);
+        if (q0 == 0 && ps.dHR3) launch_velocity_operands(nb, ne, s->Re, s->HR, ps.vectors9, ps.dHR3, st);
+        launch_phase_table(Prec::F64, qc, p->qfrac + 3 * (size_t)q0, ne, s->Re, nullptr, ne, ps.phi_q, st);
+    }
     const long npair = (long)p->nk * qc;
     for (long b0 = 0; b0 < npair; b0 += ps.batch) {
         const int nbt = (int)std::min(ps.batch, npair - b0);
@@ -264,10 +269,17 @@ void pair_states(const epw_system* s, const epw_points* p, const epw_params* par
         d.sBk = ntri;
         d.C = ps.H;
         d.sCm = ntri;
-        launch_cgemm(Prec::F64, d, st);
-        launch_eigh_given(nb, nbt, ps.H, eps_pair + (size_t)b0 * nb, (char*)U_pair + 16 * (size_t)b0 * nbb, st,
-                          true);
+        {
+            StageTimer t(EPW_STAGE_PAIR_GEMM, st);
+            launch_cgemm(Prec::F64, d, st);
+        }
+        {
+            StageTimer t(EPW_STAGE_PAIR_EIGH, st);
+            launch_eigh_given(nb, nbt, ps.H, eps_pair + (size_t)b0 * nb, (char*)U_pair + 16 * (size_t)b0 * nbb, st,
+                              true);
+        }
         if (ps.vel_pair) {
+            StageTimer t(EPW_STAGE_PAIR_GEMM, st);
             // dH/dk_a(k+q) = sum_R Phi_k Phi_q (i R_a H(R)), then the band velocities (full matrices)
             for (int a = 0; a < 3; ++a) {
                 GemmDesc dv = d;
@@ -690,9 +702,21 @@ struct BwdLayout {
     void* gR_t = nullptr;
     void* dgR_t = nullptr;
     void* phi_k64 = nullptr;
+    // split-bf16 runs: the R_e <-> k contractions on bf16 planes (K contiguous)
+    int kpad = 0;            // N_e padded to a multiple of 32
+    int nkpad = 0;           // N_k padded to a multiple of 32
+    void* Bpl = nullptr;     // [4][Q n_m NBP^2][kpad] mode-rotated vertex (recompute B)
+    void* phiT = nullptr;    // [4][N_e][nkpad] conj phases (adjoint A)
+    void* Gt = nullptr;      // [4][Q n_m NBP^2][nkpad] adjoint Gbar, transposed (adjoint B)
     void* polar_L = nullptr; // [Q][nm] c128 long-range factors (polar systems)
     int kparts = 1;          // split-K slices of the sum over k (conjugate-transposed GEMM)
     void* kpart = nullptr;   // [kparts][N_e][Q n_m NBP^2] partial products
+    // off-grid dL/dH(R_e): per-pair eigen-adjoints of one batch, their sum
+    // over pairs (split over pairs, then reduced), and the running total
+    void* Xbar_pair = nullptr;   // [batch][n_b][n_b] c128
+    int hparts = 1;
+    void* hpart = nullptr;       // [hparts][N_e][n_b n_b] c128
+    double* dHR_pair = nullptr;  // [N_e][n_b][n_b] c128
 };
 
 constexpr size_t AUTO_BWD_CHUNK_BYTES = (size_t)4 << 30;
@@ -703,8 +727,12 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     const size_t cb = cbytes(L.prec);
     const int nk = p->nk, nq = p->nq, nb = s->nb, nm = s->nm, ne = s->nRe, np_ = s->nRp;
     const bool given = p->omega && p->evec;
+    const bool bf = L.prec == Prec::BF16X2;
     const size_t nbp2 = (size_t)L.nbp * L.nbp;
+    L.kpad = (ne + 31) / 32 * 32;
+    L.nkpad = (nk + 31) / 32 * 32;
     const size_t per_q = cb * ((size_t)nk * nm * nbp2 + 6 * (size_t)ne * nm * nbp2 + np_) +
+                         (bf ? 8 * ((size_t)L.kpad + L.nkpad) * nm * nbp2 : 0) +
                          (size_t)nk * (16 * nb + 32 * (size_t)nb * nb + 8 * nm + 4) +
                          (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm +
                          pair_bytes_per_q(s, p);
@@ -717,7 +745,7 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     L.U = A.take(16 * (size_t)nk * nb * nb);
     L.ftab = (double*)A.take(8 * (size_t)nk * nb);
     L.wbar = (double*)A.take(8 * (size_t)nk * nb);
-    L.phi_k = A.take(cb * (size_t)nk * ne);
+    L.phi_k = A.take(bf ? 8 * (size_t)nk * L.kpad : cb * (size_t)nk * ne);
     L.ebar = (double*)A.take(8 * (size_t)nk * nb);
     L.Ubar = A.take(16 * (size_t)nk * nb * nb);
     L.Xbar = A.take(16 * (size_t)nk * nb * nb);
@@ -739,13 +767,26 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     L.om_c = (double*)A.take(8 * (size_t)nk * L.Q * nm);
     L.inv = (int32_t*)A.take(4 * (size_t)nk * L.Q);
     take_pair_states(s, p, L.Q, A, L.eps_pair, L.U_pair, L.f_pair, L.ps);
-    L.kparts = splitk_parts(ne, (int)((size_t)L.Q * nm * nbp2), nk);
+    if (!p->kq) {
+        const size_t nbb = (size_t)nb * nb;
+        L.Xbar_pair = A.take(16 * (size_t)L.ps.batch * nbb);
+        L.hparts = splitk_parts_wide(ne, (int)nbb, (int)L.ps.batch, 32);
+        if (L.hparts > 1) L.hpart = A.take(16 * (size_t)L.hparts * ne * nbb);
+        L.dHR_pair = (double*)A.take(16 * (size_t)ne * nbb);
+    }
+    L.kparts = bf ? 1 : splitk_parts(ne, (int)((size_t)L.Q * nm * nbp2), nk);
     if (L.kparts > 1) L.kpart = A.take(cb * (size_t)L.kparts * ne * L.Q * nm * nbp2);
-    if (L.prec == Prec::F32) {
+    if (L.prec != Prec::F64) {
         const size_t ng = (size_t)ne * np_ * nm * nb * nb;
         L.gR_t = A.take(8 * ng);
         L.dgR_t = A.take(8 * ng);
         L.phi_k64 = A.take(16 * (size_t)nk * ne);
+    }
+    if (bf) {
+        const size_t cols = (size_t)L.Q * nm * nbp2;
+        L.Bpl = A.take(8 * cols * L.kpad);
+        L.phiT = A.take(8 * (size_t)ne * L.nkpad);
+        L.Gt = A.take(8 * cols * L.nkpad);
     }
 }
 
@@ -764,15 +805,26 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
     launch_fermi_table((size_t)nk * nb, L.eps, par->mu, par->T, L.ftab, st);
     EPW_HIP(hipMemcpyAsync(L.wbar, w, 8 * (size_t)nk * nb, hipMemcpyDeviceToDevice, st));
     launch_degenerate_average(nk, nb, L.eps, par->deg_tol, L.wbar, st);
-    launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_k, st);
+    const bool bf = prec == Prec::BF16X2;
+    // contraction precision of everything but the R_e <-> k sums (split-bf16
+    // runs those on bf16 planes and the rest in float32, as the forward does)
+    const Prec cprec = bf ? Prec::F32 : prec;
+    if (bf) {
+        launch_phase_table(Prec::BF16X2, nk, p->kfrac, ne, s->Re, s->ndeg_e, L.kpad, L.phi_k, st);
+        launch_phase_planes_t(nk, p->kfrac, ne, s->Re, s->ndeg_e, L.nkpad, L.phiT, st);
+    } else {
+        launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_k, st);
+    }
     launch_fill((size_t)nk * nb, 0.0, L.ebar, st);
     launch_fill(2 * (size_t)nk * nb * nb, 0.0, (double*)L.Ubar, st);
     if (dgR && (L.nchunks == 0) && !acc0)
         launch_fill(2 * (size_t)ne * np_ * ncol_g, 0.0, (double*)dgR, st);
+    const bool offgrid = !p->kq;
+    if (dHR && offgrid) launch_fill(2 * (size_t)ne * nb * nb, 0.0, L.dHR_pair, st);
     const double nqn = par->nq_norm > 0.0 ? par->nq_norm : (double)nq;
     const double C = M_PI / (nqn * par->sigma * std::sqrt(M_PI));
     const double kT = 8.617333262e-5 * par->T;
-    const bool f32 = prec == Prec::F32;
+    const bool f32 = prec != Prec::F64;    // float32 storage of g, dL/dg and the vertex
     const void* gsrc = s->gR;
     if (f32) {
         launch_c128_to_c64((size_t)ne * np_ * ncol_g, s->gR, L.gR_t, st);
@@ -802,13 +854,32 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             polar_device(s->polar, nm, P);
             launch_polar_factor(P, qc, nm, p->qfrac + 3 * (size_t)q0, ev, L.sc, L.polar_L, st);
         }
-        launch_phase_table(prec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
+        launch_phase_table(cprec, qc, p->qfrac + 3 * (size_t)q0, np_, s->Rp, s->ndeg_p, np_, L.phi_q, st);
         pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, L.ps, st);
         const long ncols = (long)qc * nm * L.nbp * L.nbp;
         StageTimer tb(EPW_STAGE_BACKWARD, st);
-        launch_cgemm(prec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, gsrc, L.gq), st);
-        launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, nullptr, L.polar_L, s->Re);
-        {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
+        launch_cgemm(cprec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, gsrc, L.gq), st);
+        if (bf) {
+            // recompute G = Phi_k B on bf16 planes (the forward's R_e -> k arithmetic)
+            launch_mode_rotate_bf16(ne, qc, nm, nb, L.nbp, L.kpad, L.gq, ev, L.sc, L.Bpl, st, nullptr, L.polar_L,
+                                    s->Re);
+            Bf16GemmDesc d;
+            d.M = nk;
+            d.N = ncols;
+            d.Kpad = L.kpad;
+            d.A = (const uint16_t*)L.phi_k;
+            d.lda = L.kpad;
+            d.aplane = (long)nk * L.kpad;
+            d.B = (const uint16_t*)L.Bpl;
+            d.ldb = L.kpad;
+            d.bplane = ncols * L.kpad;
+            d.C = (float2*)L.G;
+            d.ldc = ncols;
+            launch_bf16_gemm(d, st);
+        } else {
+            launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, nullptr, L.polar_L, s->Re);
+        }
+        if (!bf) {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
             GemmDesc d;
             d.M = nk;
             d.N = (int)ncols;
@@ -850,13 +921,60 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
         a.ekq_c = L.ekq_c;
         a.Ukq_c = L.Ukq_c;
         a.om_c = L.om_c;
-        launch_pair_bwd(prec, a, st);
-        if (dHR) {
+        launch_pair_bwd(cprec, a, st);
+        if (dHR && !offgrid) {
             launch_kq_inverse(nk, qc, q0, nq, p->kq, L.inv, st);
             launch_gather_state_adjoint(nk, nb, qc, L.inv, L.ek_c, L.Uk_c, L.ekq_c, L.Ukq_c, L.ebar, L.Ubar, st);
+        } else if (dHR) {
+            // k side summed over the chunk's q; the k+q side stays per pair: the
+            // eigen-adjoint of every H(k+q), contracted back to R_e through the
+            // conjugate of the pair phases e^{2 pi i (k+q).R}/ndeg that formed it
+            launch_gather_state_adjoint(nk, nb, qc, nullptr, L.ek_c, L.Uk_c, nullptr, nullptr, L.ebar, L.Ubar, st);
+            const long npair = (long)nk * qc;
+            const size_t nbb = (size_t)nb * nb;
+            for (long b0 = 0; b0 < npair; b0 += L.ps.batch) {
+                const int nbt = (int)std::min(L.ps.batch, npair - b0);
+                launch_eigh_adjoint(nbt, nb, L.eps_pair + (size_t)b0 * nb, (const char*)L.U_pair + 16 * (size_t)b0 * nbb,
+                                    L.ekq_c + (size_t)b0 * nb, (const char*)L.Ukq_c + 16 * (size_t)b0 * nbb,
+                                    par->deg_tol, L.Xbar_pair, st);
+                GemmDesc d;   // dHR_pair[e][ij] += sum_pair conj(Phi_k[k][e] Phi_q[q][e]) Xbar[pair][ij]
+                d.M = ne;
+                d.N = (int)nbb;
+                d.K = nbt;
+                d.A = L.ps.phi_k;
+                d.lda = ne;
+                d.A2 = L.ps.phi_q;
+                d.n2 = qc;
+                d.row0 = b0;
+                d.conj_trans_a = 1;
+                d.B = L.Xbar_pair;
+                d.ncb = (int)nbb;
+                d.sBk = (long)nbb;
+                d.C = L.dHR_pair;
+                d.sCm = (long)nbb;
+                d.accumulate = 1;
+                launch_cgemm_splitk(Prec::F64, d, std::min(L.hparts, splitk_parts_wide(ne, (int)nbb, nbt, 32)),
+                                    L.hpart, st);
+            }
         }
         if (domega) launch_reduce_omega(nk, qc, nm, L.om_c, acc0, domega + (size_t)q0 * nm, st);
-        if (dgR) {
+        if (dgR && bf) {
+            // gbar_nu(R_e, q) = sum_k conj(Phi_k[k][R_e]) Gbar[k][col] on bf16 planes
+            launch_split_transpose(nk, ncols, L.G, L.nkpad, L.Gt, st);
+            Bf16GemmDesc d;
+            d.M = ne;
+            d.N = ncols;
+            d.Kpad = L.nkpad;
+            d.A = (const uint16_t*)L.phiT;
+            d.lda = L.nkpad;
+            d.aplane = (long)ne * L.nkpad;
+            d.B = (const uint16_t*)L.Gt;
+            d.ldb = L.nkpad;
+            d.bplane = ncols * L.nkpad;
+            d.C = (float2*)L.Bnu;
+            d.ldc = ncols;
+            launch_bf16_gemm(d, st);
+        } else if (dgR) {
             GemmDesc d;   // gbar_nu(R_e, q) = sum_k conj(Phi_k[k][R_e]) Gbar[k][col]
             d.M = ne;
             d.N = (int)ncols;
@@ -871,7 +989,9 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.sCm = ncols;
             // K = N_k is long and M = N_e short: split the sum over k so the grid fills the chip
             launch_cgemm_splitk(prec, d, std::min(splitk_parts(d.M, d.N, d.K), L.kparts), L.kpart, st);
-            launch_mode_rotate_adjoint(prec, ne, qc, nm, nb, L.nbp, L.Bnu, ev, L.sc, L.gq, st);
+        }
+        if (dgR) {
+            launch_mode_rotate_adjoint(cprec, ne, qc, nm, nb, L.nbp, L.Bnu, ev, L.sc, L.gq, st);
             GemmDesc e;   // dgR[e][p][c] (+)= sum_q conj(Phi_q[q][p]) gbar_a[e][q][c]
             e.M = np_;
             e.N = (int)(ne * ncol_g);
@@ -888,7 +1008,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             e.sCe = (long)np_ * ncol_g;
             e.sCm = (long)ncol_g;
             e.accumulate = (c > 0 || (acc0 && !f32)) ? 1 : 0;
-            launch_cgemm(prec, e, st);
+            launch_cgemm(cprec, e, st);
         }
     }
     if (dgR && f32 && L.nchunks > 0) launch_c64_to_c128((size_t)ne * np_ * ncol_g, L.dgR_t, acc0, dgR, st);
@@ -909,6 +1029,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
         d.sCm = nb * nb;
         d.accumulate = acc0;
         launch_cgemm(Prec::F64, d, st);
+        if (offgrid) launch_add_f64(2 * (size_t)ne * nb * nb, L.dHR_pair, (double*)dHR, st);
     }
 }
 
@@ -998,6 +1119,38 @@ int planned_forward(const char* fn, const epw_system* sys, const epw_points* pts
 }
 
 namespace epw {
+namespace {
+
+// q points per pass of the k+q map check (its inverse map is [nk][Qc] int32)
+int check_kq_chunk(const epw_points* p) {
+    if (!p->kq || p->nk <= 0 || p->nq <= 0) return 0;
+    const long q = std::max<long>(1, (4L << 20) / p->nk);
+    return (int)std::min<long>(q, p->nq);
+}
+
+size_t check_ws_bytes(const epw_system* s, const epw_points* p) {
+    Arena A;
+    A.dry = true;
+    A.take(sizeof(CheckRecord));
+    A.take(4 * (size_t)s->nRe);
+    A.take(4 * (size_t)s->nRp);
+    A.take(4 * (size_t)std::max(p->nk, 0) * check_kq_chunk(p));
+    return A.used + 256;
+}
+
+// parameters that pass check_common (epw_check_inputs has none of its own)
+epw_params neutral_params() {
+    epw_params q;
+    std::memset(&q, 0, sizeof(q));
+    q.sigma = 1.0;
+    q.dtype = EPW_FP64;
+    return q;
+}
+
+}  // namespace
+}  // namespace epw
+
+namespace epw {
 
 // Im Sigma in a fixed device buffer of `cap` bytes (the no-allocation entry
 // point).  With par->chunk_q = 0 the largest q chunk whose workspace fits is
@@ -1054,13 +1207,14 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
                                      const epw_params* par) {
     clear_error();
     if (which != EPW_WS_INTERP_G && which != EPW_WS_IMSIGMA && which != EPW_WS_IMSIGMA_BACKWARD &&
-        which != EPW_WS_PHONON && which != EPW_WS_RESIGMA && which != EPW_WS_TRANSPORT) {
+        which != EPW_WS_PHONON && which != EPW_WS_RESIGMA && which != EPW_WS_TRANSPORT && which != EPW_WS_CHECK) {
         fail(EPW_EINVAL, "epw_workspace_size: unknown call id %d", which);
         return 0;
     }
     epw_system s;
     epw_points p;
     if (size_query_checks(sys, pts, par, "epw_workspace_size", s, p) != EPW_OK) return 0;
+    if (which == EPW_WS_CHECK) return check_ws_bytes(&s, &p);
     Arena A;
     A.dry = true;
     if (which == EPW_WS_IMSIGMA_BACKWARD) {
@@ -1075,6 +1229,79 @@ extern "C" size_t epw_workspace_size(int which, const epw_system* sys, const epw
         plan(&s, &p, par, o, A, L);
     }
     return A.used + 256;
+}
+
+extern "C" int epw_check_inputs(const epw_system* sys, const epw_points* pts, double herm_tol, void* ws,
+                                size_t ws_bytes, void* stream) {
+    clear_error();
+    const char* fn = "epw_check_inputs";
+    const epw_params np0 = neutral_params();
+    int rc = check_common(sys, pts, &np0, fn);
+    if (rc != EPW_OK) return rc;
+    if (!(herm_tol >= 0.0) || !std::isfinite(herm_tol)) return fail(EPW_EINVAL, "%s: herm_tol must be >= 0", fn);
+    if (!sys->Re || !sys->ndeg_e || !sys->Rp || !sys->ndeg_p || !sys->HR || !sys->gR)
+        return fail(EPW_EINVAL, "%s: NULL pointer in epw_system", fn);
+    if ((pts->nk > 0 && !pts->kfrac) || (pts->nq > 0 && !pts->qfrac)) return fail(EPW_EINVAL, "%s: NULL point array", fn);
+    const size_t need = check_ws_bytes(sys, pts);
+    if (!ws || ws_bytes < need) return fail(EPW_ENOMEM, "%s: workspace %zu bytes, need %zu", fn, ws_bytes, need);
+    CheckRecord h;
+    rc = guarded(fn, [&]() {
+        hipStream_t st = (hipStream_t)stream;
+        Arena A;
+        A.base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+        A.cap = ws_bytes;
+        CheckRecord* rec = (CheckRecord*)A.take(sizeof(CheckRecord));
+        int32_t* negE = (int32_t*)A.take(4 * (size_t)sys->nRe);
+        int32_t* negP = (int32_t*)A.take(4 * (size_t)sys->nRp);
+        const int qck = check_kq_chunk(pts);
+        int32_t* inv = (int32_t*)A.take(4 * (size_t)std::max(pts->nk, 0) * qck);
+        const size_t nb = sys->nb, nm = sys->nm, ne = sys->nRe, np_ = sys->nRp;
+        launch_check_clear(rec, st);
+        launch_check_finite(2 * ne * nb * nb, (const double*)sys->HR, 1, rec, st);
+        if (sys->DR) launch_check_finite(np_ * nm * nm, sys->DR, 2, rec, st);
+        launch_check_finite(2 * ne * np_ * nm * nb * nb, (const double*)sys->gR, 4, rec, st);
+        launch_check_finite(3 * (size_t)pts->nk, pts->kfrac, 8, rec, st);
+        launch_check_finite(3 * (size_t)pts->nq, pts->qfrac, 8, rec, st);
+        if (pts->omega) launch_check_finite((size_t)pts->nq * nm, pts->omega, 16, rec, st);
+        if (pts->evec) launch_check_finite(2 * (size_t)pts->nq * nm * nm, (const double*)pts->evec, 16, rec, st);
+        launch_check_ws(sys->nRe, sys->Re, sys->ndeg_e, sys->nmax_e, 1, negE, rec, st);
+        launch_check_ws(sys->nRp, sys->Rp, sys->ndeg_p, 0, 2, negP, rec, st);
+        launch_check_herm(true, sys->nb, sys->nRe, (const double*)sys->HR, negE, &rec->h_dev, &rec->h_max, st);
+        if (sys->DR) launch_check_herm(false, sys->nm, sys->nRp, sys->DR, negP, &rec->d_dev, &rec->d_max, st);
+        for (int q0 = 0; qck > 0 && q0 < pts->nq; q0 += qck) {
+            const int qc = std::min(qck, pts->nq - q0);
+            launch_check_kq(pts->nk, qc, q0, pts->nq, pts->kq, inv, rec, st);
+        }
+        EPW_HIP(hipMemcpyAsync(&h, rec, sizeof(h), hipMemcpyDeviceToHost, st));
+        EPW_HIP(hipStreamSynchronize(st));
+        return EPW_OK;
+    });
+    if (rc != EPW_OK) return rc;
+    auto bits = [](unsigned long long b) {
+        double v;
+        std::memcpy(&v, &b, sizeof(v));
+        return v;
+    };
+    static const char* const what[] = {"H(R_e)", "D(R_p)", "g(R_e,R_p)", "the k or q points",
+                                       "the given phonon frequencies or modes"};
+    for (int b = 0; b < 5; ++b)
+        if (h.nonfinite & (1 << b)) return fail(EPW_EINVAL, "%s: non-finite entries in %s", fn, what[b]);
+    if (h.ndeg_bad) return fail(EPW_EINVAL, "%s: a WS degeneracy of %s is < 1", fn, (h.ndeg_bad & 1) ? "R_e" : "R_p");
+    if (h.nmax_bad)
+        return fail(EPW_EINVAL, "%s: nmax_e = %d is smaller than a component of R_e", fn, sys->nmax_e);
+    if (h.not_closed)
+        return fail(EPW_ESHAPE, "%s: the WS set %s is not closed under R -> -R", fn,
+                    (h.not_closed & 1) ? "R_e" : "R_p");
+    const double hd = bits(h.h_dev), hm = bits(h.h_max), dd = bits(h.d_dev), dm = bits(h.d_max);
+    if (hd > herm_tol * hm)
+        return fail(EPW_ENOTHERM, "%s: max |H(-R) - H(R)^dag| = %.3e exceeds %.3e x max |H| = %.3e", fn, hd,
+                    herm_tol, hm);
+    if (dd > herm_tol * dm)
+        return fail(EPW_ENOTHERM, "%s: max |D(-R) - D(R)^T| = %.3e exceeds %.3e x max |D| = %.3e", fn, dd, herm_tol,
+                    dm);
+    if (h.kq_range) return fail(EPW_EINVAL, "%s: a kq entry lies outside [0, nk)", fn);
+    if (h.kq_not_bijective) return fail(EPW_EINVAL, "%s: for some q the map k -> kq[k][q] is not one-to-one", fn);
+    return EPW_OK;
 }
 
 extern "C" int epw_interp_g(const epw_system* sys, const epw_points* pts, const epw_params* par, void* gkq,
@@ -1245,10 +1472,6 @@ extern "C" int epw_imsigma_backward(const epw_system* sys, const epw_points* pts
     if (rc != EPW_OK) return rc;
     if (pts->nk == 0) return EPW_OK;
     if (!w) return fail(EPW_EINVAL, "epw_imsigma_backward: NULL weights");
-    if (dHR && !pts->kq)
-        return fail(EPW_ESHAPE, "epw_imsigma_backward: dL/dH(R) needs the k+q states in the k set (a kq map)");
-    if (par->dtype != EPW_FP64 && par->dtype != EPW_FP32)
-        return fail(EPW_EDTYPE, "epw_imsigma_backward: EPW_FP64 or EPW_FP32 (the split-bf16 adjoint is not built)");
     Arena dry;
     dry.dry = true;
     BwdLayout L;

@@ -1,5 +1,6 @@
 // Adjoint of L = sum_nk w_nk Im Sigma_nk (Sec. 3 Eq. (8)) with respect to
-// g(R_e,R_p), H(R_e) and omega_q,nu, for grid runs (k+q in the k set).
+// g(R_e,R_p), H(R_e) and omega_q,nu; the k+q states are members of the k set
+// (grid runs) or per pair (off-grid runs).
 //
 // Per (k, q) pair and mode nu, with X = g_nu(k,q) in the Wannier basis
 // (recomputed by the R_e -> k GEMM), T = X U_k, g' = U_{k+q}^dag T:
@@ -238,7 +239,7 @@ __global__ void gather_state_adjoint_kernel(int nk, int nb, int qc, const int32_
         double s = 0.0;
         for (int j = 0; j < qc; ++j) {
             s += ek_c[((size_t)k * qc + j) * nb + e];
-            const int src = inv[(size_t)k * qc + j];
+            const int src = inv ? inv[(size_t)k * qc + j] : -1;
             if (src >= 0) s += ekq_c[((size_t)src * qc + j) * nb + e];
         }
         ebar[(size_t)k * nb + e] += s;
@@ -249,7 +250,7 @@ __global__ void gather_state_adjoint_kernel(int nk, int nb, int qc, const int32_
             const double2 v = Uk_c[((size_t)k * qc + j) * nb2 + f];
             s.x += v.x;
             s.y += v.y;
-            const int src = inv[(size_t)k * qc + j];
+            const int src = inv ? inv[(size_t)k * qc + j] : -1;
             if (src >= 0) {
                 const double2 u = Ukq_c[((size_t)src * qc + j) * nb2 + f];
                 s.x += u.x;
@@ -368,6 +369,11 @@ __global__ __launch_bounds__(64) void eigh_adjoint_kernel(int nk, int nb, const 
     }
 }
 
+__global__ void add_f64_kernel(size_t n, const double* __restrict__ src, double* __restrict__ dst) {
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] += src[i];
+}
+
 __global__ void c64_to_c128_kernel(size_t n, const float2* __restrict__ in, int acc, double2* __restrict__ out) {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
@@ -453,6 +459,12 @@ void launch_fill(size_t n, double v, double* p, hipStream_t stream) {
     if (n == 0) return;
     fill_f64_kernel<<<nblk(n, 256), 256, 0, stream>>>(n, v, p);
     launch_check("fill_f64_kernel");
+}
+
+void launch_add_f64(size_t n, const double* src, double* dst, hipStream_t stream) {
+    if (n == 0) return;
+    add_f64_kernel<<<nblk(n, 256), 256, 0, stream>>>(n, src, dst);
+    launch_check("add_f64_kernel");
 }
 
 void launch_c64_to_c128(size_t n, const void* in, int accumulate, void* out, hipStream_t stream) {

@@ -362,8 +362,29 @@ void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs,
     launch_check("interp_eigh_kernel (given)");
 }
 
-// upper triangles of nR complex n x n matrices, rows i with columns j >= i in turn
-__global__ void pack_upper_kernel(int n, int nR, const double2* __restrict__ X, double2* __restrict__ P) {
+// neg[r] = index of -R[r] in the set, or -1 when the set has no such vector
+__global__ void neg_index_kernel(int nR, const int32_t* __restrict__ R, int32_t* __restrict__ neg) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nR) return;
+    const int a = -R[3 * r], b = -R[3 * r + 1], c = -R[3 * r + 2];
+    int found = -1;
+    for (int t = 0; t < nR; ++t)
+        if (R[3 * t] == a && R[3 * t + 1] == b && R[3 * t + 2] == c) {
+            found = t;
+            break;
+        }
+    neg[r] = found;
+}
+
+// Upper triangles (rows i with columns j >= i in turn) of the Hermitian part
+// of the interpolation: with Phi_R = exp(2 pi i p.R)/ndeg(R) and the set
+// closed under R -> -R,
+//   ((S + S^dag)/2)_ij = sum_R Phi_R (X_ij(R) + ndeg(R)/ndeg(-R) conj(X_ji(-R)))/2,
+// so a sum over these triangles gives the Hermitised matrix exactly, whatever
+// X(-R) is.  A vector whose negative is missing makes its entries NaN (the
+// triangle cannot represent the sum; the results then show it).
+__global__ void pack_upper_kernel(int n, int nR, const double2* __restrict__ X, const int32_t* __restrict__ ndeg,
+                                  const int32_t* __restrict__ neg, double2* __restrict__ P) {
     const int nt = n * (n + 1) / 2;
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (long)nR * n * n) return;
@@ -371,14 +392,27 @@ __global__ void pack_upper_kernel(int n, int nR, const double2* __restrict__ X, 
     const long r = idx / (n * n);
     const int i = e / n, j = e % n;
     if (i > j) return;
-    P[r * nt + i * n - i * (i - 1) / 2 + (j - i)] = X[idx];
+    const int t = neg[r];
+    double2 v;
+    if (t >= 0) {
+        const double2 x = X[idx];
+        const double2 y = X[(long)t * n * n + j * n + i];
+        const double w = (double)ndeg[r] / (double)ndeg[t];
+        v = make_double2(0.5 * (x.x + w * y.x), 0.5 * (x.y - w * y.y));
+    } else {
+        v = make_double2(__builtin_nan(""), __builtin_nan(""));
+    }
+    P[r * nt + i * n - i * (i - 1) / 2 + (j - i)] = v;
 }
 
-void launch_pack_upper(int n, int nR, const void* X, void* P, hipStream_t stream) {
+void launch_pack_upper(int n, int nR, const int32_t* R, const int32_t* ndeg, const void* X, int32_t* neg, void* P,
+                       hipStream_t stream) {
     const long total = (long)nR * n * n;
     if (total <= 0) return;
+    neg_index_kernel<<<dim3((unsigned)((nR + 255) / 256)), dim3(256), 0, stream>>>(nR, R, neg);
+    launch_check("neg_index_kernel");
     pack_upper_kernel<<<dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream>>>(
-        n, nR, reinterpret_cast<const double2*>(X), reinterpret_cast<double2*>(P));
+        n, nR, reinterpret_cast<const double2*>(X), ndeg, neg, reinterpret_cast<double2*>(P));
     launch_check("pack_upper_kernel");
 }
 

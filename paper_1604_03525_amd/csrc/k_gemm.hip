@@ -59,7 +59,18 @@ __global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
         const int row = m0 + m, k = kb + kl;
         if (row < d.M && kl < Kz) {
             if (CONJ_TRANS_A) {
-                CT v = A[(size_t)k * d.lda + row];
+                CT v;
+                if (d.A2) {
+                    // conj of the pair operand: GEMM index k is the pair row0 + k
+                    const unsigned r = (unsigned)(d.row0 + k);
+                    const unsigned i1 = r / (unsigned)d.n2, i2 = r - i1 * (unsigned)d.n2;
+                    const CT x = A[(size_t)i1 * d.lda + row];
+                    const CT y = reinterpret_cast<const CT*>(d.A2)[(size_t)i2 * d.lda + row];
+                    v.x = x.x * y.x - x.y * y.y;
+                    v.y = x.x * y.y + x.y * y.x;
+                } else {
+                    v = A[(size_t)k * d.lda + row];
+                }
                 v.y = -v.y;
                 return v;
             }
@@ -136,6 +147,17 @@ __global__ void splitk_reduce_kernel(int M, int N, int parts, const CT* __restri
 }
 
 }  // namespace
+
+int splitk_parts_wide(int M, int N, int K, int max_parts) {
+    // about four rounds of two resident blocks per CU on 256 CUs, at least
+    // 512 K values per part
+    const long blocks = (long)((N + 63) / 64) * ((M + 63) / 64);
+    long parts = blocks > 0 ? (2048 + blocks - 1) / blocks : 1;
+    const long kmax = K / 512;
+    if (parts > kmax) parts = kmax;
+    if (parts > max_parts) parts = max_parts;
+    return parts < 1 ? 1 : (int)parts;
+}
 
 int splitk_parts(int M, int N, int K) {
     // enough blocks for ~8 rounds of two resident blocks per CU on 256 CUs,

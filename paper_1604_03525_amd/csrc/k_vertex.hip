@@ -1215,6 +1215,157 @@ void launch_degenerate_average(int nk, int nb, const double* eps, double tol, do
 }  // namespace epw
 
 namespace epw {
+namespace {
+
+// ------------------------------------------------------------ split-bf16 GEMM
+// C[m][n] (+)= sum_k A[m][k] B[n][k] (complex), both operands four bf16
+// planes with K contiguous and zero-padded to Kpad (a multiple of 32); float32
+// accumulation on MFMA 16x16x32, the product form of the fused kernel's main
+// loop; C is complex64.  Used by the split-bf16 adjoint for the R_e <-> k
+// contractions.
+__global__ __launch_bounds__(256) void bf16_gemm_kernel(Bf16GemmDesc d)
+{
+    __shared__ BfStage<64, 64> st;
+    const int tiles_m = (d.M + 63) / 64;
+    const long tiles_n = (d.N + 63) / 64;
+    const long bx = blockIdx.x;
+    const int mt = tiles_m <= 8 ? (int)(bx % tiles_m) : (int)(bx / tiles_n);
+    const long nt = tiles_m <= 8 ? bx / tiles_m : bx % tiles_n;
+    const int m0 = mt * 64;
+    const long n0 = nt * 64;
+    f4 cr[4], ci[4];
+    auto nogen = [](int, int) { return make_float2(0.f, 0.f); };
+    bf16_mainloop<64, 64, false>(st, d.A, d.lda, d.aplane, d.M, m0, d.B, d.ldb, d.bplane, d.N, n0, d.Kpad, nogen, cr,
+                                 ci);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = 0; c < 4; ++c) {
+        const long col = n0 + c * 16 + (lane & 15);
+        if (col >= d.N) continue;
+        for (int i = 0; i < 4; ++i) {
+            const int row = m0 + wave * 16 + 4 * (lane >> 4) + i;
+            if (row >= d.M) continue;
+            float2* dst = d.C + (size_t)row * d.ldc + col;
+            float2 v = make_float2(cr[c][i], ci[c][i]);
+            if (d.accumulate) {
+                const float2 o = *dst;
+                v.x += o.x;
+                v.y += o.y;
+            }
+            *dst = v;
+        }
+    }
+}
+
+__device__ inline void split_bf(float x, uint16_t& h, uint16_t& l) {
+    const __hip_bfloat16 xh = __float2bfloat16(x);
+    const __hip_bfloat16 xl = __float2bfloat16(x - __bfloat162float(xh));
+    h = __builtin_bit_cast(uint16_t, xh);
+    l = __builtin_bit_cast(uint16_t, xl);
+}
+
+// conj(exp(2 pi i p.R_r) / ndeg_r) as planes [4][nR][ld] (point index p
+// contiguous, zero for p >= np): the A operand of a sum over points
+__global__ void phase_planes_t_kernel(int np, const double* __restrict__ pts, int nR, const int32_t* __restrict__ R,
+                                      const int32_t* __restrict__ ndeg, int ld, uint16_t* __restrict__ out)
+{
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t total = (size_t)nR * ld;
+    if (idx >= total) return;
+    const int r = (int)(idx / ld), p = (int)(idx % ld);
+    float c = 0.f, sn = 0.f;
+    if (p < np) {
+        double x = pts[3 * (size_t)p] * (double)R[3 * r] + pts[3 * (size_t)p + 1] * (double)R[3 * r + 1] +
+                   pts[3 * (size_t)p + 2] * (double)R[3 * r + 2];
+        x -= rint(x);
+        double s, cc;
+        sincospi(2.0 * x, &s, &cc);
+        const double w = ndeg ? 1.0 / (double)ndeg[r] : 1.0;
+        c = (float)(cc * w);
+        sn = (float)(-s * w);
+    }
+    uint16_t h, l;
+    split_bf(c, h, l);
+    out[idx] = h;
+    out[total + idx] = l;
+    split_bf(sn, h, l);
+    out[2 * total + idx] = h;
+    out[3 * total + idx] = l;
+}
+
+// complex64 X [K][N] -> planes [4][N][Kpad] (K contiguous, zero for k >= K),
+// transposed through LDS in 64 x 64 tiles
+__global__ __launch_bounds__(256) void split_transpose_kernel(int K, long N, const float2* __restrict__ X, int Kpad,
+                                                              uint16_t* __restrict__ out)
+{
+    __shared__ float2 tile[64][65];
+    const long n0 = (long)blockIdx.x * 64;
+    const int k0 = blockIdx.y * 64;
+    const int tid = threadIdx.x;
+    for (int it = tid; it < 64 * 64; it += 256) {
+        const int kl = it / 64, nl = it % 64;
+        const int k = k0 + kl;
+        const long n = n0 + nl;
+        tile[nl][kl] = (k < K && n < N) ? X[(size_t)k * N + n] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    const long plane = N * (long)Kpad;
+    for (int it = tid; it < 64 * 8; it += 256) {
+        const int nl = it / 8, part = it % 8;
+        const long n = n0 + nl;
+        const int kb = k0 + part * 8;
+        if (n >= N || kb >= Kpad) continue;
+        uint32_t hr[4] = {0u, 0u, 0u, 0u}, lr[4] = {0u, 0u, 0u, 0u}, hi[4] = {0u, 0u, 0u, 0u},
+                 li[4] = {0u, 0u, 0u, 0u};
+        for (int t = 0; t < 8; ++t) {
+            const float2 v = tile[nl][part * 8 + t];
+            uint16_t a, b, c2, d2;
+            split_bf(v.x, a, b);
+            split_bf(v.y, c2, d2);
+            const int sh = 16 * (t & 1);
+            hr[t >> 1] |= (uint32_t)a << sh;
+            lr[t >> 1] |= (uint32_t)b << sh;
+            hi[t >> 1] |= (uint32_t)c2 << sh;
+            li[t >> 1] |= (uint32_t)d2 << sh;
+        }
+        uint16_t* o = out + (size_t)n * Kpad + kb;
+        *reinterpret_cast<uint4*>(o) = make_uint4(hr[0], hr[1], hr[2], hr[3]);
+        *reinterpret_cast<uint4*>(o + plane) = make_uint4(lr[0], lr[1], lr[2], lr[3]);
+        *reinterpret_cast<uint4*>(o + 2 * plane) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        *reinterpret_cast<uint4*>(o + 3 * plane) = make_uint4(li[0], li[1], li[2], li[3]);
+    }
+}
+
+}  // namespace
+
+void launch_bf16_gemm(const Bf16GemmDesc& d, hipStream_t stream) {
+    if (d.M <= 0 || d.N <= 0) return;
+    if (d.Kpad % 32 != 0 || d.lda % 8 != 0 || d.ldb % 8 != 0 || d.aplane % 8 != 0 || d.bplane % 8 != 0)
+        throw HipFailure{(int)hipErrorInvalidValue, "bf16 GEMM descriptor (K padding / 16-byte rows)", __FILE__,
+                         __LINE__};
+    const long tiles = (long)((d.N + 63) / 64) * ((d.M + 63) / 64);
+    bf16_gemm_kernel<<<dim3((unsigned)tiles), 256, 0, stream>>>(d);
+    launch_check("bf16_gemm_kernel");
+}
+
+void launch_phase_planes_t(int np, const double* pts, int nR, const int32_t* R, const int32_t* ndeg, int ld,
+                           void* out, hipStream_t stream) {
+    const size_t total = (size_t)nR * ld;
+    if (total == 0) return;
+    phase_planes_t_kernel<<<(unsigned)((total + 255) / 256), 256, 0, stream>>>(np, pts, nR, R, ndeg, ld,
+                                                                              (uint16_t*)out);
+    launch_check("phase_planes_t_kernel");
+}
+
+void launch_split_transpose(int K, long N, const void* X, int Kpad, void* out, hipStream_t stream) {
+    if (N <= 0 || Kpad <= 0) return;
+    dim3 grid((unsigned)((N + 63) / 64), (unsigned)((Kpad + 63) / 64));
+    split_transpose_kernel<<<grid, 256, 0, stream>>>(K, N, (const float2*)X, Kpad, (uint16_t*)out);
+    launch_check("split_transpose_kernel");
+}
+
+}  // namespace epw
+
+namespace epw {
 void launch_mode_rotate_bf16(int ne, int qc, int nm, int nb, int nbp, int kpad, const void* in, const void* evec,
                              const double* sc, void* out, hipStream_t stream, const int32_t* ndeg_fold,
                              const void* Lq, const int32_t* Re) {

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "epw.h"
@@ -24,8 +25,13 @@ void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_
 // packed: X holds only the upper triangles ([np][n(n+1)/2], row by row from the diagonal)
 void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream,
                        bool packed = false);
-// P[r] = upper triangle of X[r] in the packed order above (nR matrices, n x n complex)
-void launch_pack_upper(int n, int nR, const void* X, void* P, hipStream_t stream);
+// P[r] = upper triangle, in the packed order above, of the Hermitian part
+// (X(R) + ndeg(R)/ndeg(-R) X(-R)^dag)/2 of nR complex n x n matrices on a WS set
+// closed under R -> -R (a sum of these over R gives the Hermitised interpolated
+// matrix); neg [nR] int32 scratch receives the index of -R (entries of a vector
+// whose negative is missing become NaN)
+void launch_pack_upper(int n, int nR, const int32_t* R, const int32_t* ndeg, const void* X, int32_t* neg, void* P,
+                       hipStream_t stream);
 
 // ---- k_vertex.hip ----
 enum class Prec { F64 = 0, F32 = 1, BF16X2 = 2 };
@@ -64,6 +70,30 @@ void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, cons
 void launch_mode_rotate_bf16(int ne, int qc, int nm, int nb, int nbp, int kpad, const void* in, const void* evec,
                              const double* sc, void* out, hipStream_t stream, const int32_t* ndeg_fold = nullptr,
                              const void* Lq = nullptr, const int32_t* Re = nullptr);
+
+// Split-bf16 complex GEMM C[m][n] (+)= sum_k A[m][k] B[n][k]: both operands
+// as four bf16 planes (re_hi, re_lo, im_hi, im_lo) with K contiguous and
+// zero-padded to Kpad (a multiple of 32); A plane p row m at A + p*aplane +
+// m*lda (likewise B); C complex64 with row stride ldc.
+struct Bf16GemmDesc {
+    int M = 0;
+    long N = 0;
+    int Kpad = 0;
+    const uint16_t* A = nullptr;
+    long lda = 0, aplane = 0;
+    const uint16_t* B = nullptr;
+    long ldb = 0, bplane = 0;
+    float2* C = nullptr;
+    long ldc = 0;
+    int accumulate = 0;
+};
+void launch_bf16_gemm(const Bf16GemmDesc& d, hipStream_t stream);
+// conj(exp(2 pi i p.R)/ndeg(R)) split into four bf16 planes [4][nR][ld], the
+// point index contiguous (zero for p >= np)
+void launch_phase_planes_t(int np, const double* pts, int nR, const int32_t* R, const int32_t* ndeg, int ld,
+                           void* out, hipStream_t stream);
+// complex64 X [K][N] -> four bf16 planes [4][N][Kpad] (K contiguous, zero-padded)
+void launch_split_transpose(int K, long N, const void* X, int Kpad, void* out, hipStream_t stream);
 
 // Polar long-range factor L_nu(q) (k_polar.hip): the per-q Gaussian-damped
 // sum over G of Sec. 4, for a chunk of q points.
@@ -147,8 +177,9 @@ struct GemmDesc {
     void* C = nullptr;
     long sCe = 0, sCm = 0;
     int accumulate = 0;
-    // pair operand (A2 != nullptr, not with conj_trans_a): A(m, k) = A[(r / n2) * lda + k] * A2[(r % n2) * lda + k]
-    // with r = row0 + m -- the phases of the sum k + q of a point pair
+    // pair operand (A2 != nullptr): A(m, k) = A[(r / n2) * lda + k] * A2[(r % n2) * lda + k] with
+    // r = row0 + m -- the phases of the sum k + q of a point pair; with conj_trans_a,
+    // A(m, k) = conj(A[(r / n2) * lda + m] * A2[(r % n2) * lda + m]) with r = row0 + k
     const void* A2 = nullptr;
     int n2 = 1;
     long row0 = 0;
@@ -159,6 +190,8 @@ struct GemmDesc {
 void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream, int kparts = 1);
 // number of K slices launch_cgemm_splitk uses for an M x N x K product
 int splitk_parts(int M, int N, int K);
+// the same for products with very few output tiles (up to max_parts slices)
+int splitk_parts_wide(int M, int N, int K, int max_parts);
 // C (+)= A B as `parts` K slices into scratch ([parts][M][N] complex in prec),
 // summed in fixed order into C; needs a single column slab (d.ncb == d.N)
 void launch_cgemm_splitk(Prec prec, const GemmDesc& d, int parts, void* scratch, hipStream_t stream);
@@ -191,7 +224,8 @@ void launch_pair_bwd(Prec prec, const PairBwdArgs& a, hipStream_t stream);
 // inv[k'][j] = k with kq[k][q0+j] = k', else -1   (j < qc)
 void launch_kq_inverse(int nk, int qc, int q0, int nq_total, const int32_t* kq, int32_t* inv,
                        hipStream_t stream);
-// ebar[k] += sum_j ek_c[k][j] + ekq_c[inv[k][j]][j];  Ubar likewise (fixed order)
+// ebar[k] += sum_j ek_c[k][j] + ekq_c[inv[k][j]][j];  Ubar likewise (fixed order);
+// inv == nullptr: the k side only (off-grid runs, whose k+q states are per pair)
 void launch_gather_state_adjoint(int nk, int nb, int qc, const int32_t* inv, const double* ek_c,
                                  const void* Uk_c, const double* ekq_c, const void* Ukq_c,
                                  double* ebar, void* Ubar, hipStream_t stream);
@@ -206,6 +240,8 @@ void launch_eigh_adjoint(int nk, int nb, const double* eps, const void* U, const
                          const void* Ubar, double deg_tol, void* Xbar, hipStream_t stream);
 // f64 fill
 void launch_fill(size_t n, double v, double* p, hipStream_t stream);
+// dst[i] += src[i] (n doubles)
+void launch_add_f64(size_t n, const double* src, double* dst, hipStream_t stream);
 // convert c64 -> c128 with optional accumulate
 void launch_c64_to_c128(size_t n, const void* in, int accumulate, void* out, hipStream_t stream);
 
@@ -272,5 +308,24 @@ void launch_ziman(int nw, const double* wgrid, const double* a2f, int nT, const 
                   hipStream_t stream);
 void launch_degenerate_average(int nk, int nb, const double* eps, double tol, double* v,
                                hipStream_t stream);
+
+// ---- k_check.hip (epw_check_inputs) ----
+struct CheckRecord {
+    int32_t nonfinite;          // bits: 1 H, 2 D, 4 g, 8 points, 16 given phonon states
+    int32_t ndeg_bad;           // bits: 1 R_e, 2 R_p (ndeg < 1)
+    int32_t nmax_bad;           // 1: a component of R_e exceeds nmax_e
+    int32_t not_closed;         // bits: 1 R_e, 2 R_p (-R missing)
+    int32_t kq_range;           // 1: a kq entry outside [0, nk)
+    int32_t kq_not_bijective;   // 1: for some q, k -> kq[k][q] is not one-to-one
+    unsigned long long h_dev, h_max, d_dev, d_max;   // bit patterns of non-negative doubles
+};
+void launch_check_clear(CheckRecord* rec, hipStream_t st);
+void launch_check_finite(size_t n, const double* x, int bit, CheckRecord* rec, hipStream_t st);
+void launch_check_ws(int nR, const int32_t* R, const int32_t* ndeg, int nmax, int bit, int32_t* neg,
+                     CheckRecord* rec, hipStream_t st);
+void launch_check_herm(bool cplx, int n, int nR, const double* X, const int32_t* neg, unsigned long long* dev_slot,
+                       unsigned long long* max_slot, hipStream_t st);
+void launch_check_kq(int nk, int qc, int q0, int nq_total, const int32_t* kq, int32_t* inv, CheckRecord* rec,
+                     hipStream_t st);
 
 }  // namespace epw

@@ -10,7 +10,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import (EPW_FP32, EPW_FP64, EPW_SPLIT_BF16, EPW_WS_IMSIGMA,  # noqa: F401
+from ._lib import (EPW_FP32, EPW_FP64, EPW_SPLIT_BF16, EPW_WS_CHECK, EPW_WS_IMSIGMA,  # noqa: F401
                    EPW_WS_IMSIGMA_BACKWARD, EPW_WS_INTERP_G, EPW_WS_PHONON, EPW_WS_RESIGMA,
                    EPW_WS_TRANSPORT, EpwError)
 
@@ -211,6 +211,17 @@ class Workspace:
             self.buf = None
             self.buf = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
         return self.buf
+
+
+def epw_check_inputs(system, points, herm_tol=1e-12, workspace=None):
+    """Validate the device arrays of a system and point set (synchronous);
+    raises EpwError with the code of the first failed check."""
+    lib = _lib.load()
+    ws = workspace or Workspace(system.device)
+    buf = ws.get(epw_workspace_size(EPW_WS_CHECK, system, points, make_params()))
+    s, p = system.c_struct(), points.c_struct()
+    _lib.check(lib.epw_check_inputs(ctypes.byref(s), ctypes.byref(p), float(herm_tol), _ptr(buf), buf.numel(),
+                                    _stream(system.device)))
 
 
 def epw_interp_g(system, points, params, workspace=None):

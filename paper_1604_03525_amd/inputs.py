@@ -134,16 +134,24 @@ def einstein_dynmat(R, nm, omega_e):
 
 # --------------------------------------------------------------- vertex
 
-def random_vertex(Re, Rp, vectors, nm, nb, seed, g0, decay=1.0):
+def random_vertex(Re, Rp, vectors, nm, nb, seed, g0, decay=1.0, rows_per_block=None):
     """g(R_e,R_p) [Ne][Np][nm][nb][nb] c128 with modulus
     g0 exp(-(|R_e| + |R_p|)/decay) and a uniform random phase, the phases
-    drawn in (R_e, R_p, mode, m, n) C order."""
+    drawn in (R_e, R_p, mode, m, n) C order.  Drawn a block of R_e rows at a
+    time (the same stream as one draw of the whole array), so the largest
+    systems need no temporaries beyond the output."""
     rng = np.random.default_rng(seed)
-    phi = 2.0 * np.pi * rng.random((len(Re), len(Rp), nm, nb, nb))
     de = np.linalg.norm(cartesian(Re, vectors), axis=1)
     dp = np.linalg.norm(cartesian(Rp, vectors), axis=1)
-    mod = g0 * np.exp(-(de[:, None] + dp[None, :]) / decay)
-    return mod[:, :, None, None, None] * np.exp(1j * phi)
+    out = np.empty((len(Re), len(Rp), nm, nb, nb), dtype=np.complex128)
+    per_row = len(Rp) * nm * nb * nb
+    step = rows_per_block or max(1, (1 << 24) // max(per_row, 1))
+    for e0 in range(0, len(Re), step):
+        e1 = min(len(Re), e0 + step)
+        phi = 2.0 * np.pi * rng.random((e1 - e0, len(Rp), nm, nb, nb))
+        mod = g0 * np.exp(-(de[e0:e1, None] + dp[None, :]) / decay)
+        out[e0:e1] = mod[:, :, None, None, None] * np.exp(1j * phi)
+    return out
 
 
 def random_vertex_device(Re, Rp, vectors, nm, nb, seed, g0, decay=1.0, device="cuda"):
@@ -194,6 +202,14 @@ def loss_weights(nk, nb, seed):
 # tests/test_inputs.py recomputes each one and checks it.
 #   realistic fcc model: bandwidth 12 eV and max omega 65 meV on the 6^3
 #   coarse grid, mu = (max eps_4 + min eps_5)/2 + 0.1 eV on the 20^3 grid.
+#   mobility-scale fcc model (8^3 coarse grid): bandwidth 12 eV and max
+#   omega 65 meV on the coarse grid, band edges of bands 8 and 9 (1-based)
+#   on the 40^3 grid, mu at their midpoint.
+C5_H_SCALE = 0.16710290699251684
+C5_D_SCALE = 0.0005428255495717735
+C5_VBM = 0.8533556552525289
+C5_CBM = -0.6980924543090177
+C5_MU = 0.0776316004717556
 C2_H_SCALE = 0.26863436263417284
 C2_D_SCALE = 0.00038095141752211273
 C2_MU = 0.020638396418062227
@@ -294,6 +310,23 @@ def mobility_unscaled(R):
     HR = random_hamiltonian(R, FCC_VECTORS, 16, seed=20, decay=1.5, scale=1.0)
     DR = spring_dynmat(R, FCC_VECTORS, ATOMS_FCC3, shells=2, seed=21, scale=1.0)
     return HR, DR
+
+
+def mobility_arrays(R):
+    """(HR, DR) of the mobility-scale system, rescaled by the constants above."""
+    HR, DR = mobility_unscaled(R)
+    return HR * C5_H_SCALE, DR * C5_D_SCALE
+
+
+def mobility_vertex(R):
+    """g(R_e,R_p) of the mobility-scale system on the host (seed 22; 14 GB at
+    617 WS vectors)."""
+    return random_vertex(R, R, FCC_VECTORS, 9, 16, seed=22, g0=0.05, decay=1.0)
+
+
+def mobility_k_candidates(n, seed=3):
+    """The uniform stream from which the 0.3 eV window keeps its k points."""
+    return random_points(n, seed)
 
 
 def realistic_arrays(Re, Rp, h_scale=None, d_scale=None):

@@ -2,6 +2,7 @@
 gradient (torch autograd of the oracle forward) and central finite
 differences of the HIP forward; tolerance 1e-6 relative (infinity norm over
 all entries for the reference, over the checked entries for FD)."""
+import ctypes
 import sys
 
 import numpy as np
@@ -9,7 +10,7 @@ import pytest
 import torch
 
 from oracle import interp, lattice, torch_ref
-from paper_1604_03525_amd import autograd, epw
+from paper_1604_03525_amd import _lib, autograd, epw
 from paper_1604_03525_amd import inputs as I
 from tests.helpers import fcc_small_case, rel_err, toy_case
 
@@ -148,10 +149,31 @@ def test_adjoint_fp32_matches_reference_gradient(case):
     assert rel_err(dom, dom_ref) < 1e-4
 
 
-def test_adjoint_fp32_chunking_accumulate_and_bf16_refused():
-    """float32: chunks of 5 q give the result of one chunk (to float32
-    rounding), accumulate adds onto the outputs, and the split-bf16 adjoint
-    is refused with EPW_EDTYPE."""
+@pytest.mark.parametrize("case", ["toy12", "fcc3"])
+def test_adjoint_split_bf16_matches_reference_gradient(case):
+    """The split-bf16 adjoint (the R_e <-> k contractions, recompute and
+    adjoint, on bf16 hi + lo planes with float32 accumulation; everything
+    else as the float32 adjoint) against the FP64 reference gradient.
+    Tolerance 1e-4 relative, the bar of the split-bf16 forward: dropping
+    lo.lo leaves about 2^-16 = 1.5e-5 relative per product, which the float32
+    sums over N_e and N_k terms and the forward's own error (it sets every
+    weight of the adjoint) grow by a small factor."""
+    if case == "toy12":
+        c = toy_case((12, 12, 12))
+    else:
+        c = fcc_small_case(nb=3, kg=(3, 3, 3))
+    om, ev, w, kw = _setup(c, None)
+    L_ref, ims_ref, dg_ref, dh_ref, dom_ref = torch_ref.loss_and_grads(c["gR"], c["HR"], om, ev, w, **kw)
+    L, dg, dh, dom = _hip_grads(c, om, ev, w, dtype="split_bf16")
+    errs = (abs(L - L_ref) / abs(L_ref), rel_err(dg, dg_ref), rel_err(dh, dh_ref), rel_err(dom, dom_ref))
+    _say("split-bf16 gradients", case, "rel errs L/g/h/omega", *errs)
+    assert errs[0] < 1e-4
+    assert max(errs[1:]) < 1e-4
+
+
+def test_adjoint_fp32_chunking_accumulate():
+    """float32 and split-bf16: chunks of 5 q give the result of one chunk (to
+    float32 rounding), accumulate adds onto the outputs."""
     c = fcc_small_case(nb=2, kg=(3, 3, 3), seed=5)
     om, ev, w, kw = _setup(c, None)
     sysd = epw.System(c["R"], c["nd"], c["R"], c["nd"], c["HR"], None, c["gR"], DEV)
@@ -164,7 +186,23 @@ def test_adjoint_fp32_chunking_accumulate_and_bf16_refused():
     ref = epw.epw_imsigma_backward(sysd, pts, epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"]), w)
     for x, y in zip(a, ref):
         assert rel_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-4
-    with pytest.raises(epw.EpwError) as ei:
-        epw.epw_imsigma_backward(sysd, pts, epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"],
-                                                            dtype="split_bf16"), w)
-    assert ei.value.code == -3
+    mb = lambda **kw2: epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"], dtype="split_bf16", **kw2)
+    a = epw.epw_imsigma_backward(sysd, pts, mb(), w)
+    b = epw.epw_imsigma_backward(sysd, pts, mb(chunk_q=5), w)
+    for x, y in zip(a, b):
+        assert rel_err(y.cpu().numpy(), x.cpu().numpy()) < 1e-5
+    for x, y in zip(a, ref):
+        assert rel_err(x.cpu().numpy(), y.cpu().numpy()) < 1e-4
+    acc = epw.make_params(T=c["T"], mu=c["mu"], sigma=c["sigma"], dtype="split_bf16", accumulate=True)
+    lib = _lib.load()
+    outs = [t.clone() for t in a]
+    s_, p_ = sysd.c_struct(), pts.c_struct()
+    ws = epw.Workspace(DEV)
+    buf = ws.get(epw.epw_workspace_size(epw.EPW_WS_IMSIGMA_BACKWARD, sysd, pts, acc))
+    wt = torch.as_tensor(w, device=DEV)
+    _lib.check(lib.epw_imsigma_backward(ctypes.byref(s_), ctypes.byref(p_), ctypes.byref(acc), ctypes.c_void_p(
+        wt.data_ptr()), ctypes.c_void_p(outs[0].data_ptr()), ctypes.c_void_p(outs[1].data_ptr()),
+        ctypes.c_void_p(outs[2].data_ptr()), ctypes.c_void_p(buf.data_ptr()), buf.numel(),
+        ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)))
+    for x, y in zip(outs, a):
+        assert rel_err(x.cpu().numpy(), 2 * y.cpu().numpy()) < 1e-6

@@ -18,6 +18,30 @@ def test_realistic_constants_reproduce():
     assert abs(mu - I.C2_MU) < 1e-12
 
 
+def test_mobility_constants_reproduce():
+    import importlib.util, os
+    path = os.path.join(os.path.dirname(__file__), "golden", "calibrate_models.py")
+    spec = importlib.util.spec_from_file_location("calibrate_models", path)
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    h, d, vbm, cbm, mu = mod.mobility_constants()
+    assert abs(h - I.C5_H_SCALE) < 1e-12 * h
+    assert abs(d - I.C5_D_SCALE) < 1e-12 * d
+    assert abs(vbm - I.C5_VBM) < 1e-12 and abs(cbm - I.C5_CBM) < 1e-12 and abs(mu - I.C5_MU) < 1e-12
+
+
+def test_random_vertex_blocks_reproduce_one_draw():
+    """The vertex drawn a block of R_e rows at a time is the one-draw array."""
+    R, nd = lattice.ws_vectors(I.FCC_METRIC, (3, 3, 3))
+    g = I.random_vertex(R, R, I.FCC_VECTORS, 9, 16, seed=22, g0=0.05, rows_per_block=5)
+    assert np.array_equal(g, I.random_vertex(R, R, I.FCC_VECTORS, 9, 16, seed=22, g0=0.05))
+    rng = np.random.default_rng(22)
+    phi = 2.0 * np.pi * rng.random(g.shape)
+    de = np.linalg.norm(I.cartesian(R, I.FCC_VECTORS), axis=1)
+    mod = 0.05 * np.exp(-(de[:, None] + de[None, :]))
+    assert np.array_equal(g, mod[:, :, None, None, None] * np.exp(1j * phi))
+
+
 def test_model_symmetries():
     R, nd = lattice.ws_vectors(I.FCC_METRIC, (6, 6, 6))
     HR, DR, gR = I.realistic_arrays(R, R)
