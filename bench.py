@@ -64,7 +64,7 @@ def timed(fn, steps, warmup, torch):
     dt = time.perf_counter() - t0
     stages = {}
     for name, sid in (("eigh", 0), ("gemm_rp", 1), ("moderot", 2), ("fused", 3), ("backward", 4),
-                      ("spectral", 5), ("pair_gemm", 6), ("pair_eigh", 7)):
+                      ("spectral", 5), ("pair_gemm", 6), ("pair_eigh", 7), ("bwd_gemm", 8)):
         ms, n = epw.epw_timing_read(sid)
         stages[name] = (ms, n)
     epw.epw_timing_enable(False)
@@ -137,6 +137,16 @@ def peak_gemm(torch, n=8192, reps=10):
         log("bench: peak gemm %s %.2f TFLOP/s" % (name, out[name]["tflops"]))
         del a, b, c
     print(json.dumps({"peak_gemm": out, "n": n}), flush=True)
+
+
+def backward_gemm_flops(nk, nq, ne, np_, nm, nb):
+    """Algorithmic flops of the adjoint's contractions (8 per complex
+    multiply-add): the recomputed R_p -> q and R_e -> k products, their two
+    conjugate-transposed sums (over k for dL/dg_nu(R_e,q), over q for
+    dL/dg(R_e,R_p)) and the k-set sum of dL/dH(R_e)."""
+    a5 = 8.0 * nq * np_ * ne * nm * nb * nb
+    a7 = 8.0 * nk * nq * ne * nm * nb * nb
+    return 2.0 * (a5 + a7) + 8.0 * ne * nk * nb * nb
 
 
 def pair_eigh_flops(n):
@@ -393,10 +403,22 @@ def main():
                 w = torch.rand((nk, nb), dtype=torch.float64, device=dev)
                 dtb, stb = timed(lambda: epw.epw_imsigma_backward(sysd, pts, par, w, workspace=ws),
                                  ksteps, kwarm, torch)
+                bms, bn = stb["bwd_gemm"]
+                bfl = backward_gemm_flops(nk, nq, ne, ne, nm, nb) * ksteps
+                bach = bfl / (bms * 1e-3) / 1e12 if bms > 0 else None
+                bpeak = PEAK_TFLOPS["fp64" if bdt == "fp64" else "fp32"]
                 variants[var] = {"value": pairs * ksteps / dtb, "ms_per_step": 1e3 * dtb / ksteps,
                                  "steps": ksteps, "dtype": bdt,
                                  "outputs": "dL/dg(R_e,R_p), dL/dH(R_e), dL/domega",
                                  "ratio_to_forward": (1e3 * dtb / ksteps) / ms_step if bdt == "fp64" else None,
+                                 "roofline": {"bound": "mfma", "kernel": "adjoint contractions (cgemm_generic_kernel%s)"
+                                              % (", bf16_gemm_kernel" if bdt == "split_bf16" else ""),
+                                              "achieved": bach, "peak": bpeak, "unit": "TFLOP/s",
+                                              "frac": bach / bpeak if bach else None, "traffic": None,
+                                              "launches": bn, "gemm_ms_per_step": bms / ksteps,
+                                              "peak_note": "split-bf16 runs its R_p <-> q sums in float32: "
+                                                           "rated against the float32 peak" if bdt == "split_bf16"
+                                              else None},
                                  "stages_ms_per_step": {s_: v[0] / ksteps for s_, v in stb.items()}}
             elif var == "phonon":
                 log("bench: phonon linewidth and lambda (fp64)")

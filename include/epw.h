@@ -467,7 +467,9 @@ int epw_check_inputs(const epw_system* sys, const epw_points* pts, double herm_t
 #define EPW_STAGE_SPECTRAL  5   /* frequency-resolved sum over pole records      */
 #define EPW_STAGE_PAIR_GEMM 6   /* off-grid: H(k+q) of every pair (phase GEMM)   */
 #define EPW_STAGE_PAIR_EIGH 7   /* off-grid: eigensolve of every H(k+q)          */
-#define EPW_NUM_STAGES      8
+#define EPW_STAGE_BWD_GEMM  8   /* adjoint: recomputed and transposed contractions
+                                   (also counted in EPW_STAGE_BACKWARD)          */
+#define EPW_NUM_STAGES      9
 
 /* enable != 0 starts recording (and discards earlier records); 0 stops. */
 int epw_timing_enable(int enable);

@@ -39,6 +39,7 @@ EPW_STAGE_BACKWARD = 4
 EPW_STAGE_SPECTRAL = 5
 EPW_STAGE_PAIR_GEMM = 6
 EPW_STAGE_PAIR_EIGH = 7
+EPW_STAGE_BWD_GEMM = 8
 
 EPW_MAX_NB = 16
 EPW_MAX_NM = 16

@@ -14,7 +14,17 @@ namespace epw {
 namespace {
 
 constexpr int SLICE_CUS = 256;          // column-slice count is sized for 256 CUs
-constexpr size_t AUTO_CHUNK_BYTES = (size_t)4 << 30;
+constexpr size_t AUTO_CHUNK_BYTES = (size_t)8 << 30;
+
+// Automatic q chunk: as many q as the per-q scratch budget allows, then
+// evened out over the chunks that takes, so no launch runs a small tail.
+long auto_chunk(long nq, size_t budget, size_t per_q) {
+    long Q = (long)(budget / (per_q > 0 ? per_q : 1));
+    if (Q < 1) Q = 1;
+    if (nq <= Q) return nq > 0 ? nq : 1;
+    const long nchunks = (nq + Q - 1) / Q;
+    return (nq + nchunks - 1) / nchunks;
+}
 
 size_t cbytes(Prec p) { return p == Prec::F64 ? 16 : 8; }
 
@@ -298,9 +308,9 @@ void pair_states(const epw_system* s, const epw_points* p, const epw_params* par
     launch_fermi_table((size_t)p->nk * qc * nb, eps_pair, par->mu, par->T, f_pair, st);
 }
 
-int tiles_n_for(int qc, int nm, int nbp) {
+int tiles_n_for(int qc, int nm, int nbp, Prec prec) {
     const long ncols = (long)qc * nm * nbp * nbp;
-    const int BN = nbp * nbp >= 64 ? nbp * nbp : 64;
+    const int BN = fused_tile_cols(nbp, prec);
     return (int)((ncols + BN - 1) / BN);
 }
 
@@ -325,12 +335,12 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
                          pair_bytes_per_q(s, p) + (omg ? 8 * (size_t)nk * nm * nb * (4 + L.nbp) : 0) +
                          (out == Out::TRANSPORT ? pair_vel_bytes_per_q(s, p) : 0) +
                          (L.kouter ? cb * (size_t)nk * X : cb * (size_t)ne * X + bcol_bytes * nm * L.nbp * L.nbp);
-    long Q = par->chunk_q > 0 ? par->chunk_q : (long)(AUTO_CHUNK_BYTES / per_q);
+    long Q = par->chunk_q > 0 ? par->chunk_q : auto_chunk(nq, AUTO_CHUNK_BYTES, per_q);
     if (Q < 1) Q = 1;
     if (Q > nq) Q = nq > 0 ? nq : 1;
     L.Q = (int)Q;
     L.nchunks = nq > 0 ? (int)((nq + Q - 1) / Q) : 0;
-    L.S = (store || omg) ? 0 : fused_slices(nk, L.nbp, tiles_n_for(L.Q, nm, L.nbp), SLICE_CUS);
+    L.S = (store || omg) ? 0 : fused_slices(nk, L.nbp, tiles_n_for(L.Q, nm, L.nbp, L.prec), SLICE_CUS, L.prec);
     L.eps = (double*)A.take(8 * (size_t)nk * nb);
     L.U = A.take(16 * (size_t)nk * nb * nb);
     L.ftab = (double*)A.take(8 * (size_t)nk * nb);
@@ -352,7 +362,7 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
         L.Bnu = A.take(bcol_bytes * L.Q * nm * L.nbp * L.nbp);
     }
     if (s->polar) L.polar_L = A.take(16 * (size_t)L.Q * nm);
-    L.tiles_m = (nk + fused_tile_rows(L.nbp) - 1) / fused_tile_rows(L.nbp);
+    L.tiles_m = (nk + fused_tile_rows(L.nbp, L.prec) - 1) / fused_tile_rows(L.nbp, L.prec);
     if (out == Out::IMSIGMA || out == Out::RESIGMA) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
     if (out == Out::RESIGMA) L.part2 = (double*)A.take(8 * (size_t)L.S * nk * nb);
     if (omg) {
@@ -612,7 +622,7 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.mu = par->mu;
         a.part = L.part;
         // (pole mode: the slices only spread the column tiles over blocks)
-        a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp), SLICE_CUS);
+        a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp, prec), SLICE_CUS, prec);
         a.gkq = gkq;
         a.part_ph = phon ? L.part_ph : nullptr;
         a.vel = trans ? L.vel : nullptr;
@@ -719,7 +729,7 @@ struct BwdLayout {
     double* dHR_pair = nullptr;  // [N_e][n_b][n_b] c128
 };
 
-constexpr size_t AUTO_BWD_CHUNK_BYTES = (size_t)4 << 30;
+constexpr size_t AUTO_BWD_CHUNK_BYTES = (size_t)16 << 30;
 
 void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, Arena& A, BwdLayout& L) {
     L.prec = (Prec)par->dtype;
@@ -736,7 +746,7 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
                          (size_t)nk * (16 * nb + 32 * (size_t)nb * nb + 8 * nm + 4) +
                          (given ? 0 : 8 * (size_t)nm + 16 * (size_t)nm * nm) + 16 * (size_t)nm +
                          pair_bytes_per_q(s, p);
-    long Q = par->chunk_q > 0 ? par->chunk_q : (long)(AUTO_BWD_CHUNK_BYTES / per_q);
+    long Q = par->chunk_q > 0 ? par->chunk_q : auto_chunk(nq, AUTO_BWD_CHUNK_BYTES, per_q);
     if (Q < 1) Q = 1;
     if (Q > nq) Q = nq > 0 ? nq : 1;
     L.Q = (int)Q;
@@ -858,7 +868,10 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
         pair_states(s, p, par, q0, qc, L.eps_pair, L.U_pair, L.f_pair, L.ps, st);
         const long ncols = (long)qc * nm * L.nbp * L.nbp;
         StageTimer tb(EPW_STAGE_BACKWARD, st);
-        launch_cgemm(cprec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, gsrc, L.gq), st);
+        {
+            StageTimer tg(EPW_STAGE_BWD_GEMM, st);
+            launch_cgemm(cprec, rp_desc(qc, ne, np_, (int)ncol_g, L.phi_q, gsrc, L.gq), st);
+        }
         if (bf) {
             // recompute G = Phi_k B on bf16 planes (the forward's R_e -> k arithmetic)
             launch_mode_rotate_bf16(ne, qc, nm, nb, L.nbp, L.kpad, L.gq, ev, L.sc, L.Bpl, st, nullptr, L.polar_L,
@@ -875,6 +888,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.bplane = ncols * L.kpad;
             d.C = (float2*)L.G;
             d.ldc = ncols;
+            StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_bf16_gemm(d, st);
         } else {
             launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, nullptr, L.polar_L, s->Re);
@@ -891,6 +905,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.sBk = ncols;
             d.C = L.G;
             d.sCm = ncols;
+            StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_cgemm(prec, d, st);
         }
         PairBwdArgs a;
@@ -973,6 +988,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.bplane = ncols * L.nkpad;
             d.C = (float2*)L.Bnu;
             d.ldc = ncols;
+            StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_bf16_gemm(d, st);
         } else if (dgR) {
             GemmDesc d;   // gbar_nu(R_e, q) = sum_k conj(Phi_k[k][R_e]) Gbar[k][col]
@@ -988,6 +1004,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.C = L.Bnu;
             d.sCm = ncols;
             // K = N_k is long and M = N_e short: split the sum over k so the grid fills the chip
+            StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_cgemm_splitk(prec, d, std::min(splitk_parts(d.M, d.N, d.K), L.kparts), L.kpart, st);
         }
         if (dgR) {
@@ -1008,6 +1025,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             e.sCe = (long)np_ * ncol_g;
             e.sCm = (long)ncol_g;
             e.accumulate = (c > 0 || (acc0 && !f32)) ? 1 : 0;
+            StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_cgemm(cprec, e, st);
         }
     }

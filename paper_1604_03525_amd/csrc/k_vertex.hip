@@ -160,9 +160,14 @@ __global__ void mode_rotate_kernel(int ne, int nq, int nm, int nb, int nbp,
 // registers across all of the block's tiles and written once per block to
 // part[s][k][n]: the cross-block sum is a separate fixed-order reduction.
 
-template <int NBP> struct FusedShape {
+// 64 x 64 (4096 complex entries) up to 8 padded bands; at 16 bands one band
+// block is 256 columns wide: 16 x 256 in float64 / float32, 32 x 256 in
+// split-bf16, where a 16-row tile uses each B column for too few k rows to
+// keep its faster main loop fed (the mobility-scale shard's split-bf16 fused
+// stage 5.3 -> 3.7 s)
+template <int MODE, int NBP> struct FusedShape {
     static constexpr int BN = NBP * NBP >= 64 ? NBP * NBP : 64;
-    static constexpr int BM = 4096 / BN;          // 64 x 64 or 16 x 256
+    static constexpr int BM = (MODE == 2 && BN >= 256 ? 8192 : 4096) / BN;
 };
 
 // ---- split-bf16 tile: x = hi + lo (bf16 each), products hi.hi + hi.lo + lo.hi
@@ -207,19 +212,28 @@ __device__ inline void split_pack(float x0, float x1, uint32_t& hi, uint32_t& lo
 // wide, chunk e of thread t is chunk e * 256 + t, so that consecutive lanes
 // read consecutive chunks (18 % faster at 16 bands), narrower tiles keep BCH
 // consecutive chunks per thread (the other order was 6 % slower at 64 columns).
+// Waves: WN = BN/64 across the columns, 4/WN across the rows; each wave owns
+// RB row blocks of 16 x 64 (accumulator index rb * 4 + column block).
+template <int BM, int BN> struct BfWaves {
+    static constexpr int WN = BN / 64;
+    static constexpr int RB = BM * WN / 64;
+};
 template <int BM, int BN, bool GEN, class AG>
 __device__ inline void bf16_mainloop(BfStage<BM, BN>& st, const uint16_t* __restrict__ A, long lda, long aplane,
                                      int arows, int m0, const uint16_t* __restrict__ B, long ldb, long bplane,
-                                     long bcols, long n0, int Kpad, AG agen, f4 (&cr)[4], f4 (&ci)[4])
+                                     long bcols, long n0, int Kpad, AG agen, f4 (&cr)[4 * BfWaves<BM, BN>::RB],
+                                     f4 (&ci)[4 * BfWaves<BM, BN>::RB])
 {
-    constexpr int WN = BN / 64;
+    constexpr int WN = BfWaves<BM, BN>::WN;
+    constexpr int RB = BfWaves<BM, BN>::RB;
+    static_assert(RB >= 1 && 16 * RB * (4 / WN) == BM && 4 * BM <= 256, "split-bf16 wave layout");
     constexpr int ACH0 = 4 * BM * 4 / 256;         // 16-byte chunks per thread
     constexpr int ACH = GEN ? 4 : ACH0;
     constexpr int BCH = 4 * BN * 4 / 256;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
     uint4 ra[ACH], rb[BCH];
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 4 * RB; ++c)
         for (int i = 0; i < 4; ++i) {
             cr[c][i] = 0.f;
             ci[c][i] = 0.f;
@@ -287,45 +301,86 @@ __device__ inline void bf16_mainloop(BfStage<BM, BN>& st, const uint16_t* __rest
     for (int k0 = 0; k0 < Kpad; k0 += 32) {
         const bool more = k0 + 32 < Kpad;
         if (more) gload(k0 + 32);
-        const int arow = wm * 16 + (lane & 15);
-        const uint4 arh = *reinterpret_cast<const uint4*>(&st.a[0][arow][koff]);
-        const uint4 arl = *reinterpret_cast<const uint4*>(&st.a[1][arow][koff]);
-        const uint4 aih = *reinterpret_cast<const uint4*>(&st.a[2][arow][koff]);
-        const uint4 ail = *reinterpret_cast<const uint4*>(&st.a[3][arow][koff]);
-        const uint4 naih = neg_bf8(aih), nail = neg_bf8(ail);
-        uint4 brh[4], brl[4], bih[4], bil[4];
+        if constexpr (RB == 1) {
+            const int arow = wm * 16 + (lane & 15);
+            const uint4 arh = *reinterpret_cast<const uint4*>(&st.a[0][arow][koff]);
+            const uint4 arl = *reinterpret_cast<const uint4*>(&st.a[1][arow][koff]);
+            const uint4 aih = *reinterpret_cast<const uint4*>(&st.a[2][arow][koff]);
+            const uint4 ail = *reinterpret_cast<const uint4*>(&st.a[3][arow][koff]);
+            const uint4 naih = neg_bf8(aih), nail = neg_bf8(ail);
+            uint4 brh[4], brl[4], bih[4], bil[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int bcol = wn * 64 + c * 16 + (lane & 15);
-            brh[c] = *reinterpret_cast<const uint4*>(&st.b[0][bcol][koff]);
-            brl[c] = *reinterpret_cast<const uint4*>(&st.b[1][bcol][koff]);
-            bih[c] = *reinterpret_cast<const uint4*>(&st.b[2][bcol][koff]);
-            bil[c] = *reinterpret_cast<const uint4*>(&st.b[3][bcol][koff]);
+            for (int c = 0; c < 4; ++c) {
+                const int bcol = wn * 64 + c * 16 + (lane & 15);
+                brh[c] = *reinterpret_cast<const uint4*>(&st.b[0][bcol][koff]);
+                brl[c] = *reinterpret_cast<const uint4*>(&st.b[1][bcol][koff]);
+                bih[c] = *reinterpret_cast<const uint4*>(&st.b[2][bcol][koff]);
+                bil[c] = *reinterpret_cast<const uint4*>(&st.b[3][bcol][koff]);
+            }
+            // the four column blocks interleaved: consecutive MFMAs never share an accumulator
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arh, brh[c], cr[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arh, bih[c], ci[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arh, brl[c], cr[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arh, bil[c], ci[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arl, brh[c], cr[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arl, bih[c], ci[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(naih, bih[c], cr[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(aih, brh[c], ci[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(naih, bil[c], cr[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(aih, brl[c], ci[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(nail, bih[c], cr[c]);
+#pragma unroll
+            for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(ail, brh[c], ci[c]);
+        } else {
+            // RB row blocks share each B fragment; the A fragments of all row
+            // blocks stay in registers over the four column blocks, the B
+            // fragments of one column block at a time
+            uint4 arh[RB], arl[RB], aih[RB], ail[RB], naih[RB], nail[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                const int arow = wm * 16 * RB + q * 16 + (lane & 15);
+                arh[q] = *reinterpret_cast<const uint4*>(&st.a[0][arow][koff]);
+                arl[q] = *reinterpret_cast<const uint4*>(&st.a[1][arow][koff]);
+                aih[q] = *reinterpret_cast<const uint4*>(&st.a[2][arow][koff]);
+                ail[q] = *reinterpret_cast<const uint4*>(&st.a[3][arow][koff]);
+                naih[q] = neg_bf8(aih[q]);
+                nail[q] = neg_bf8(ail[q]);
+            }
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int bcol = wn * 64 + c * 16 + (lane & 15);
+                const uint4 brh = *reinterpret_cast<const uint4*>(&st.b[0][bcol][koff]);
+                const uint4 brl = *reinterpret_cast<const uint4*>(&st.b[1][bcol][koff]);
+                const uint4 bih = *reinterpret_cast<const uint4*>(&st.b[2][bcol][koff]);
+                const uint4 bil = *reinterpret_cast<const uint4*>(&st.b[3][bcol][koff]);
+                // real and imaginary accumulators of the RB row blocks taken in
+                // turn, so that consecutive MFMAs never share an accumulator
+                auto step = [&](const uint4 (&ar)[RB], uint4 br, const uint4 (&ai)[RB], uint4 bi) {
+#pragma unroll
+                    for (int q = 0; q < RB; ++q) {
+                        cr[q * 4 + c] = mfma_bf(ar[q], br, cr[q * 4 + c]);
+                        ci[q * 4 + c] = mfma_bf(ai[q], bi, ci[q * 4 + c]);
+                    }
+                };
+                step(arh, brh, arh, bih);
+                step(arh, brl, arh, bil);
+                step(arl, brh, arl, bih);
+                step(naih, bih, aih, brh);
+                step(naih, bil, aih, brl);
+                step(nail, bih, ail, brh);
+            }
         }
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arh, brh[c], cr[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arh, bih[c], ci[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arh, brl[c], cr[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arh, bil[c], ci[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(arl, brh[c], cr[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(arl, bih[c], ci[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(naih, bih[c], cr[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(aih, brh[c], ci[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(naih, bil[c], cr[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(aih, brl[c], ci[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) cr[c] = mfma_bf(nail, bih[c], cr[c]);
-#pragma unroll
-        for (int c = 0; c < 4; ++c) ci[c] = mfma_bf(ail, brh[c], ci[c]);
         __syncthreads();
         if (more) {
             sstore();
@@ -382,7 +437,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     typedef typename ModeTypes<MODE>::CT CT;
     typedef typename ModeTypes<MODE>::TE TE;
     typedef typename ModeTypes<MODE>::CE CE;
-    constexpr int BM = FusedShape<NBP>::BM, BN = FusedShape<NBP>::BN;
+    constexpr int BM = FusedShape<MODE, NBP>::BM, BN = FusedShape<MODE, NBP>::BN;
     constexpr int BK = 16;
     constexpr int NB2 = NBP * NBP;
     constexpr int TPR = 256 / BM;                  // threads per k row
@@ -392,6 +447,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     constexpr int JI = BN / (NBP * TPR);
     constexpr int RUN = JI < NBP ? JI : NBP;
     constexpr int NRUN = JI / RUN;
+    constexpr int RT = MODE == 2 ? 1 : RUN;        // bands of a run taken together in phase 2
     static_assert(JI * NBP * TPR == BN && JI % RUN == 0 && NBP % RUN == 0, "epilogue split");
     constexpr int LDC = BN + 1;                    // C tile row stride: rows start on different LDS banks
     typedef Stage<T, BM, BN, BK> St;
@@ -478,7 +534,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     // Per-row state kept over the block's tiles: the Im Sigma accumulators of
     // the row's bands and, in the float32 modes, eps_nk and the U_k columns
     // (the float64 mode reloads those per tile to stay within its registers).
-    constexpr bool HOIST = MODE != 0;
+    constexpr bool HOIST = MODE == 1 || (MODE == 2 && RUN * NBP <= 16);
     double acc[NBP], acc2[RE ? NBP : 1];
     double eps_h[HOIST ? NBP : 1];
     CE uk_h[HOIST ? RUN : 1][NBP];
@@ -504,7 +560,8 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
         // 1260-q launch, FP32 -2 %, split-BF16 -2 %).
         __builtin_amdgcn_s_setprio(1);
         if constexpr (MODE == 2) {
-            f4 cr[4], ci[4];
+            constexpr int RB = BfWaves<BM, BN>::RB;
+            f4 cr[4 * RB], ci[4 * RB];
             const uint16_t* Ap = reinterpret_cast<const uint16_t*>(a.phi_k);
             const uint16_t* Bp = reinterpret_cast<const uint16_t*>(a.B);
             auto agen = [&](int m, int kk) -> float2 { return phase(m, kk); };
@@ -513,12 +570,13 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
             const int lane = tid & 63, wave = tid >> 6;
             constexpr int WN = BN / 64;
             const int wm = wave / WN, wn = wave % WN;
-            for (int c = 0; c < 4; ++c)
-                for (int i = 0; i < 4; ++i) {
-                    const int row = wm * 16 + 4 * (lane >> 4) + i;
-                    const int col = wn * 64 + c * 16 + (lane & 15);
-                    Cs[row * LDC + col] = make_float2(cr[c][i], ci[c][i]);
-                }
+            for (int q = 0; q < RB; ++q)
+                for (int c = 0; c < 4; ++c)
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = wm * 16 * RB + q * 16 + 4 * (lane >> 4) + i;
+                        const int col = wn * 64 + c * 16 + (lane & 15);
+                        Cs[row * LDC + col] = make_float2(cr[q * 4 + c][i], ci[q * 4 + c][i]);
+                    }
         } else {
             const CT* phi = reinterpret_cast<const CT*>(a.phi_k);
             const CT* Bm = reinterpret_cast<const CT*>(a.B);
@@ -669,151 +727,156 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 }
                 const double w = a.omega[(size_t)ql * nm + nu];
                 const double nB = a.nbose[(size_t)ql * nm + nu];
-                CE uq[RUN][NBP];
-                double em[RUN], fm[RUN], dm[RUN];
-                double vm[TR ? RUN : 1][3];
-                bool mv[RUN];
+                // the run's bands in groups of RT: split-bf16 takes one band at a time so
+                // its k+q eigenvector column and sums fit beside the wider main loop's state
+#pragma unroll 1
+                for (int tb = 0; tb < RUN; tb += RT) {
+                    CE uq[RT][NBP];
+                    double em[RT], fm[RT], dm[RT];
+                    double vm[TR ? RT : 1][3];
+                    bool mv[RT];
 #pragma unroll
-                for (int t = 0; t < RUN; ++t) {
-                    const int m = x0 + t;
-                    mv[t] = m < nb;
-                    em[t] = mv[t] ? eq[m] : 0.0;
-                    fm[t] = mv[t] ? fq[m] : 0.0;
-                    if constexpr (PH) {
-                        const double ym = (em[t] - a.mu) * inv_sig;
-                        dm[t] = mv[t] ? exp(-ym * ym) : 0.0;
-                    }
-                    if constexpr (TR) {
-                        for (int c = 0; c < 3; ++c) vm[t][c] = mv[t] ? vq[3 * m + c] : 0.0;
-                    }
-#pragma unroll
-                    for (int i = 0; i < NBP; ++i) {
-                        const double2 u = (mv[t] && i < nb) ? Uq[i * nb + m] : make_double2(0.0, 0.0);
-                        uq[t][i] = mk2((TE)u.x, (TE)u.y);
-                    }
-                }
-                const CT* Vt = Cs + r * LDC + b * NB2;
-#pragma unroll
-                for (int n = 0; n < NBP; ++n) {
-                    if (n >= nb) break;
-                    double epsn;
-                    if constexpr (HOIST) epsn = eps_h[n]; else epsn = a.eps[(size_t)k * nb + n];
-                    TE W[RUN], WL[RUN], WT[TR ? RUN : 1];
-                    bool need = STORE || POLE;
-                    if constexpr (PH) {
-                        // Eq. (9): [f_nk - f_m,k+q] exp(-((eps_nk - eps_m,k+q - omega)/sigma)^2);
-                        // Eq. (11): exp(-((eps_nk - mu)/sigma)^2) exp(-((eps_m,k+q - mu)/sigma)^2)
-                        const double fn = a.ftab[(size_t)k * nb + n];
-                        const double yn = (epsn - a.mu) * inv_sig;
-                        const double dn = exp(-yn * yn);
-                        // Eq. (55): 1 - v_nk . v_m,k+q / |v_nk|^2, 1 at a zero velocity
-                        double vn[3] = {0.0, 0.0, 0.0}, inv_vv = 0.0;
+                    for (int t = 0; t < RT; ++t) {
+                        const int m = x0 + tb + t;
+                        mv[t] = m < nb;
+                        em[t] = mv[t] ? eq[m] : 0.0;
+                        fm[t] = mv[t] ? fq[m] : 0.0;
+                        if constexpr (PH) {
+                            const double ym = (em[t] - a.mu) * inv_sig;
+                            dm[t] = mv[t] ? exp(-ym * ym) : 0.0;
+                        }
                         if constexpr (TR) {
-                            for (int c = 0; c < 3; ++c) vn[c] = a.vel[((size_t)k * nb + n) * 3 + c];
-                            const double vv = vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2];
-                            inv_vv = vv > 1e-18 ? 1.0 / vv : 0.0;
+                            for (int c = 0; c < 3; ++c) vm[t][c] = mv[t] ? vq[3 * m + c] : 0.0;
                         }
 #pragma unroll
-                        for (int t = 0; t < RUN; ++t) {
-                            W[t] = TE(0);
-                            WL[t] = TE(0);
-                            if constexpr (TR) WT[t] = TE(0);
-                            if (!mv[t]) continue;
-                            const double y = (epsn - em[t] - w) * inv_sig;
-                            const double s1 = y * y;
-                            if (s1 < ylim) W[t] = (TE)(fn - fm[t]) * fexp((TE)(-s1));
-                            WL[t] = (TE)(dn * dm[t]);
+                        for (int i = 0; i < NBP; ++i) {
+                            const double2 u = (mv[t] && i < nb) ? Uq[i * nb + m] : make_double2(0.0, 0.0);
+                            uq[t][i] = mk2((TE)u.x, (TE)u.y);
+                        }
+                    }
+                    const CT* Vt = Cs + r * LDC + b * NB2;
+#pragma unroll
+                    for (int n = 0; n < NBP; ++n) {
+                        if (n >= nb) break;
+                        double epsn;
+                        if constexpr (HOIST) epsn = eps_h[n]; else epsn = a.eps[(size_t)k * nb + n];
+                        TE W[RT], WL[RT], WT[TR ? RT : 1];
+                        bool need = STORE || POLE;
+                        if constexpr (PH) {
+                            // Eq. (9): [f_nk - f_m,k+q] exp(-((eps_nk - eps_m,k+q - omega)/sigma)^2);
+                            // Eq. (11): exp(-((eps_nk - mu)/sigma)^2) exp(-((eps_m,k+q - mu)/sigma)^2)
+                            const double fn = a.ftab[(size_t)k * nb + n];
+                            const double yn = (epsn - a.mu) * inv_sig;
+                            const double dn = exp(-yn * yn);
+                            // Eq. (55): 1 - v_nk . v_m,k+q / |v_nk|^2, 1 at a zero velocity
+                            double vn[3] = {0.0, 0.0, 0.0}, inv_vv = 0.0;
                             if constexpr (TR) {
-                                const double fac = inv_vv > 0.0
-                                    ? 1.0 - (vn[0] * vm[t][0] + vn[1] * vm[t][1] + vn[2] * vm[t][2]) * inv_vv
-                                    : 1.0;
-                                WT[t] = (TE)(dn * dm[t] * fac);
+                                for (int c = 0; c < 3; ++c) vn[c] = a.vel[((size_t)k * nb + n) * 3 + c];
+                                const double vv = vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2];
+                                inv_vv = vv > 1e-18 ? 1.0 / vv : 0.0;
                             }
-                            need = need || (s1 < ylim) || (WL[t] != TE(0));
-                        }
-                    } else if constexpr (RE) {
-                        // Eq. (3), Re 1/(x + i delta) = x/(x^2 + delta^2), delta = sigma:
-                        // on shell x = eps_nk - eps_m,k+q +- omega; at eps_F x = mu - eps_m,k+q +- omega
-                        const double d2 = a.sigma * a.sigma;
-                        need = true;
 #pragma unroll
-                        for (int t = 0; t < RUN; ++t) {
-                            W[t] = TE(0);
-                            WL[t] = TE(0);
-                            if (!mv[t]) continue;
-                            const double A1 = nB + fm[t], A2 = nB + 1.0 - fm[t];
-                            const double x1 = epsn - em[t] + w, x2 = epsn - em[t] - w;
-                            const double y1 = a.mu - em[t] + w, y2 = a.mu - em[t] - w;
-                            W[t] = (TE)(A1 * x1 / (x1 * x1 + d2) + A2 * x2 / (x2 * x2 + d2));
-                            WL[t] = (TE)(A1 * y1 / (y1 * y1 + d2) + A2 * y2 / (y2 * y2 + d2));
-                        }
-                    } else {
+                            for (int t = 0; t < RT; ++t) {
+                                W[t] = TE(0);
+                                WL[t] = TE(0);
+                                if constexpr (TR) WT[t] = TE(0);
+                                if (!mv[t]) continue;
+                                const double y = (epsn - em[t] - w) * inv_sig;
+                                const double s1 = y * y;
+                                if (s1 < ylim) W[t] = (TE)(fn - fm[t]) * fexp((TE)(-s1));
+                                WL[t] = (TE)(dn * dm[t]);
+                                if constexpr (TR) {
+                                    const double fac = inv_vv > 0.0
+                                        ? 1.0 - (vn[0] * vm[t][0] + vn[1] * vm[t][1] + vn[2] * vm[t][2]) * inv_vv
+                                        : 1.0;
+                                    WT[t] = (TE)(dn * dm[t] * fac);
+                                }
+                                need = need || (s1 < ylim) || (WL[t] != TE(0));
+                            }
+                        } else if constexpr (RE) {
+                            // Eq. (3), Re 1/(x + i delta) = x/(x^2 + delta^2), delta = sigma:
+                            // on shell x = eps_nk - eps_m,k+q +- omega; at eps_F x = mu - eps_m,k+q +- omega
+                            const double d2 = a.sigma * a.sigma;
+                            need = true;
 #pragma unroll
-                        for (int t = 0; t < RUN; ++t) {
-                            W[t] = TE(0);
-                            WL[t] = TE(0);
-                            if (STORE || POLE || !mv[t]) continue;
-                            const double x = epsn - em[t];
-                            const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
-                            const double s1 = y1 * y1, s2 = y2 * y2;
-                            if (s1 < ylim) W[t] += (TE)(nB + fm[t]) * fexp((TE)(-s1));
-                            if (s2 < ylim) W[t] += (TE)(nB + 1.0 - fm[t]) * fexp((TE)(-s2));
-                            need = need || (s1 < ylim) || (s2 < ylim);
-                        }
-                    }
-                    if (!need) continue;
-                    TE gr[RUN], gi[RUN];
-#pragma unroll
-                    for (int t = 0; t < RUN; ++t) {
-                        gr[t] = TE(0);
-                        gi[t] = TE(0);
-                    }
-#pragma unroll
-                    for (int i = 0; i < NBP; ++i) {
-                        if (NBP < 16 && i >= nb) break;
-                        const CT vv = Vt[i * NBP + n];
-                        const TE vx = (TE)vv.x, vy = (TE)vv.y;
-#pragma unroll
-                        for (int t = 0; t < RUN; ++t) {
-                            // conj(u) * v
-                            gr[t] += uq[t][i].x * vx + uq[t][i].y * vy;
-                            gi[t] += uq[t][i].x * vy - uq[t][i].y * vx;
-                        }
-                    }
-#pragma unroll
-                    for (int t = 0; t < RUN; ++t) {
-                        if (!mv[t]) continue;
-                        if (STORE) {
-                            reinterpret_cast<double2*>(a.gkq)
-                                [((((size_t)k * a.nq_total + q) * nm + nu) * nb + x0 + t) * nb + n] =
-                                make_double2((double)gr[t], (double)gi[t]);
-                        } else if (PH) {
-                            const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
-                            pp[rr] += (double)(g2 * W[t]);
-                            pl[rr] += (double)(g2 * WL[t]);
-                            if constexpr (TR) pt[rr] += (double)(g2 * WT[TR ? t : 0]);
-                        } else if (RE) {
-                            const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
-                            acc[n] += (double)(g2 * W[t]);
-                            acc2[n] += (double)(g2 * WL[t]);
-                        } else if (POLE) {
-                            double* rec = a.rec + ((((size_t)k * a.qc + ql) * nm + nu) * nb + x0 + t) * (4 + NBP);
-                            rec[4 + n] = (double)(gr[t] * gr[t] + gi[t] * gi[t]);
-                            if (n == 0) {
-                                const double xi = em[t] - a.mu;
-                                const bool kept = scv != 0.0;
-                                rec[0] = xi - w;
-                                rec[1] = xi + w;
-                                rec[2] = kept ? nB + fm[t] : 0.0;
-                                rec[3] = kept ? nB + 1.0 - fm[t] : 0.0;
-                                for (int j = nb; j < NBP; ++j) rec[4 + j] = 0.0;   // padded bands
+                            for (int t = 0; t < RT; ++t) {
+                                W[t] = TE(0);
+                                WL[t] = TE(0);
+                                if (!mv[t]) continue;
+                                const double A1 = nB + fm[t], A2 = nB + 1.0 - fm[t];
+                                const double x1 = epsn - em[t] + w, x2 = epsn - em[t] - w;
+                                const double y1 = a.mu - em[t] + w, y2 = a.mu - em[t] - w;
+                                W[t] = (TE)(A1 * x1 / (x1 * x1 + d2) + A2 * x2 / (x2 * x2 + d2));
+                                WL[t] = (TE)(A1 * y1 / (y1 * y1 + d2) + A2 * y2 / (y2 * y2 + d2));
                             }
                         } else {
-                            acc[n] += (double)((gr[t] * gr[t] + gi[t] * gi[t]) * W[t]);
+#pragma unroll
+                            for (int t = 0; t < RT; ++t) {
+                                W[t] = TE(0);
+                                WL[t] = TE(0);
+                                if (STORE || POLE || !mv[t]) continue;
+                                const double x = epsn - em[t];
+                                const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
+                                const double s1 = y1 * y1, s2 = y2 * y2;
+                                if (s1 < ylim) W[t] += (TE)(nB + fm[t]) * fexp((TE)(-s1));
+                                if (s2 < ylim) W[t] += (TE)(nB + 1.0 - fm[t]) * fexp((TE)(-s2));
+                                need = need || (s1 < ylim) || (s2 < ylim);
+                            }
                         }
+                        if (!need) continue;
+                        TE gr[RT], gi[RT];
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) {
+                            gr[t] = TE(0);
+                            gi[t] = TE(0);
+                        }
+#pragma unroll
+                        for (int i = 0; i < NBP; ++i) {
+                            if (NBP < 16 && i >= nb) break;
+                            const CT vv = Vt[i * NBP + n];
+                            const TE vx = (TE)vv.x, vy = (TE)vv.y;
+#pragma unroll
+                            for (int t = 0; t < RT; ++t) {
+                                // conj(u) * v
+                                gr[t] += uq[t][i].x * vx + uq[t][i].y * vy;
+                                gi[t] += uq[t][i].x * vy - uq[t][i].y * vx;
+                            }
+                        }
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) {
+                            if (!mv[t]) continue;
+                            if (STORE) {
+                                reinterpret_cast<double2*>(a.gkq)
+                                    [((((size_t)k * a.nq_total + q) * nm + nu) * nb + x0 + tb + t) * nb + n] =
+                                    make_double2((double)gr[t], (double)gi[t]);
+                            } else if (PH) {
+                                const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
+                                pp[rr] += (double)(g2 * W[t]);
+                                pl[rr] += (double)(g2 * WL[t]);
+                                if constexpr (TR) pt[rr] += (double)(g2 * WT[TR ? t : 0]);
+                            } else if (RE) {
+                                const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
+                                acc[n] += (double)(g2 * W[t]);
+                                acc2[n] += (double)(g2 * WL[t]);
+                            } else if (POLE) {
+                                double* rec = a.rec + ((((size_t)k * a.qc + ql) * nm + nu) * nb + x0 + tb + t) * (4 + NBP);
+                                rec[4 + n] = (double)(gr[t] * gr[t] + gi[t] * gi[t]);
+                                if (n == 0) {
+                                    const double xi = em[t] - a.mu;
+                                    const bool kept = scv != 0.0;
+                                    rec[0] = xi - w;
+                                    rec[1] = xi + w;
+                                    rec[2] = kept ? nB + fm[t] : 0.0;
+                                    rec[3] = kept ? nB + 1.0 - fm[t] : 0.0;
+                                    for (int j = nb; j < NBP; ++j) rec[4 + j] = 0.0;   // padded bands
+                                }
+                            } else {
+                                acc[n] += (double)((gr[t] * gr[t] + gi[t] * gi[t]) * W[t]);
+                            }
+                        }
+                        // keep the scheduler from overlapping band iterations (register pressure)
+                        __builtin_amdgcn_sched_barrier(0);
                     }
-                    // keep the scheduler from overlapping band iterations (register pressure)
-                    __builtin_amdgcn_sched_barrier(0);
                 }
             }
         }
@@ -1062,7 +1125,8 @@ inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / 
 
 template <int MODE, int NBP>
 void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
-    constexpr int BM = FusedShape<NBP>::BM, BN = FusedShape<NBP>::BN;
+    constexpr int BM = FusedShape<MODE, NBP>::BM, BN = FusedShape<MODE, NBP>::BN;
+    static_assert(BM == fused_tile_rows_c(NBP, MODE == 2), "tile rows known to the host code");
     const int tiles_m = (a.nk + BM - 1) / BM;
     const long ncols = (long)a.qc * a.nm * NBP * NBP;
     const int tiles_n = (int)((ncols + BN - 1) / BN);
@@ -1151,8 +1215,8 @@ void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, cons
     launch_check("mode_rotate_kernel");
 }
 
-int fused_slices(int nk, int nbp, int tiles_n, int num_cu) {
-    const int BM = (nbp * nbp >= 64) ? 4096 / (nbp * nbp) : 64;
+int fused_slices(int nk, int nbp, int tiles_n, int num_cu, Prec prec) {
+    const int BM = fused_tile_rows(nbp, prec);
     const int tiles_m = (nk + BM - 1) / BM;
     if (tiles_m <= 0 || tiles_n <= 0) return 1;
     // one round of resident blocks (two per CU): every block gets the same

@@ -151,9 +151,16 @@ struct FusedArgs {
 // a7 + a8 + the phonon-linewidth sums (phonon mode, part_ph != nullptr), or
 // a7 + a8 + the real-part sums of Eq. (3) (real-part mode, part2 != nullptr)
 void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t stream);
-int fused_slices(int nk, int nbp, int ncols_tiles, int num_cu);
-// k rows per tile of the fused kernel for a padded band count
-inline int fused_tile_rows(int nbp) { return nbp * nbp >= 64 ? 4096 / (nbp * nbp) : 64; }
+int fused_slices(int nk, int nbp, int ncols_tiles, int num_cu, Prec prec);
+// columns and k rows per tile of the fused kernel for a padded band count:
+// whole band blocks, at least 64 columns; 4096 complex entries, 8192 for
+// split-bf16 at 16 bands (32 x 256)
+constexpr int fused_tile_cols_c(int nbp, bool bf) { return nbp * nbp >= 64 ? nbp * nbp : 64; }
+constexpr int fused_tile_rows_c(int nbp, bool bf) {
+    return (bf && fused_tile_cols_c(nbp, bf) >= 256 ? 8192 : 4096) / fused_tile_cols_c(nbp, bf);
+}
+inline int fused_tile_cols(int nbp, Prec prec) { return fused_tile_cols_c(nbp, prec == Prec::BF16X2); }
+inline int fused_tile_rows(int nbp, Prec prec) { return fused_tile_rows_c(nbp, prec == Prec::BF16X2); }
 // raw[0] = sum_i exp(-((eps_i - mu)/sigma)^2) over n values (fixed order)
 void launch_dos_raw(size_t n, const double* eps, double mu, double sigma, double* raw, hipStream_t stream);
 // Pi''[q][nu] = 2 pi / (N_k sigma sqrt pi) sum_t part[0][t][q][nu];
