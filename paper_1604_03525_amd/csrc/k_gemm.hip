@@ -15,7 +15,7 @@ namespace epw {
 namespace {
 
 template <typename T, bool CONJ_TRANS_A>
-__global__ __launch_bounds__(256) void cgemm_generic_kernel(GemmDesc d)
+__global__ __launch_bounds__(256, 2) void cgemm_generic_kernel(GemmDesc d)
 {
     typedef typename Cx<T>::type CT;
     constexpr int BM = 64, BN = 64, BK = 16;
