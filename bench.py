@@ -44,6 +44,17 @@ def setup(device):
     return m, sysd, pts, (R, nd, HR, DR, gR, k)
 
 
+def mfma_issue_rate(nk, nq, ne, nm, nb, ms, bk):
+    """TFLOP/s the matrix units execute in the fused kernel's R_e -> k sum:
+    three real products per complex product (6 MFMA flops per 8 algorithmic
+    ones) over K = N_e padded to the K step bk, on the padded band blocks."""
+    nbp = 1
+    while nbp < nb:
+        nbp *= 2
+    kp = (ne + bk - 1) // bk * bk
+    return 6.0 * nk * nq * kp * nm * nbp * nbp / (ms * 1e-3) / 1e12
+
+
 def fused_flops(nk, nq, ne, nm, nb):
     """Algorithmic flops of the dominant kernel over all its launches:
     the R_e -> k contraction (8 flops per complex multiply-add) plus the
@@ -369,7 +380,13 @@ def main():
                      "achieved": achieved, "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_TFLOPS["fp64"]) if achieved else None,
                      "traffic": recorded_traffic("fp64"),
-                     "launches": fn, "avg_launch_ms": fms / fn if fn else None},
+                     "launches": fn, "avg_launch_ms": fms / fn if fn else None,
+                     "convention": "achieved = algorithmic flops (8 per complex multiply-add of the R_e->k sum, "
+                                   "plus the two band rotations) per second; the kernel forms each complex "
+                                   "product with three real MFMAs (6 flops per 8 algorithmic), so frac can "
+                                   "reach 4/3; mfma_issue_frac is the matrix units' own rate",
+                     "mfma_issue_frac": mfma_issue_rate(nk, nq, ne, nm, nb, fms / args.steps, 16)
+                     / PEAK_TFLOPS["fp64"] if fms > 0 else None},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
     }
     variants = {}

@@ -893,7 +893,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
         } else {
             launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, nullptr, L.polar_L, s->Re);
         }
-        if (!bf) {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
+        if (!bf && L.nbp >= 16) {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
             GemmDesc d;
             d.M = nk;
             d.N = (int)ncols;
@@ -907,6 +907,51 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.sCm = ncols;
             StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_cgemm(prec, d, st);
+        } else if (!bf) {
+            // recompute G on the forward's R_e -> k tiling (64 x 64 up to 8
+            // padded bands), without its epilogue (the 16 x 256 tiles of 16
+            // bands are slower than the generic GEMM's 64 x 64)
+            FusedArgs a;
+            a.nk = nk;
+            a.ne = ne;
+            a.nb = nb;
+            a.nbp = L.nbp;
+            a.nm = nm;
+            a.qc = qc;
+            a.q0 = q0;
+            a.nq_total = nq;
+            a.phi_k = L.phi_k;
+            a.ldk = ne;
+            a.nmax = 0;
+            a.Re = s->Re;
+            a.ndeg_e = s->ndeg_e;
+            a.kfrac = p->kfrac;
+            a.ldk_b = ne;
+            a.kpad = ne;
+            a.B = L.Bnu;
+            a.eps = L.eps;
+            a.U = L.U;
+            a.ftab = L.ftab;
+            a.kq = p->kq;
+            a.eps_pair = L.eps_pair;
+            a.U_pair = L.U_pair;
+            a.f_pair = L.f_pair;
+            a.omega = om;
+            a.nbose = L.nbose;
+            a.sc = L.sc;
+            a.sigma = par->sigma;
+            a.mu = par->mu;
+            a.part = nullptr;
+            a.S = fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp, prec), SLICE_CUS, prec);
+            a.gkq = nullptr;
+            a.part_ph = nullptr;
+            a.part2 = nullptr;
+            a.rec = nullptr;
+            a.vel = nullptr;
+            a.vel_pair = nullptr;
+            a.gout = L.G;
+            StageTimer tg(EPW_STAGE_BWD_GEMM, st);
+            launch_fused_k(prec, a, SLICE_CUS, st);
         }
         PairBwdArgs a;
         a.nk = nk;

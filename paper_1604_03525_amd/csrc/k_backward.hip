@@ -40,30 +40,49 @@ template <typename CT> __device__ inline CT from_d2(double2 v);
 template <> __device__ inline double2 from_d2<double2>(double2 v) { return v; }
 template <> __device__ inline float2 from_d2<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
-// One block per (k, q) pair (64 threads, or one per matrix element for
-// P = 16); the per-pair matrices live in LDS sized for the padded band count
-// P, so small band counts keep many blocks resident per CU.
+// One block per (k, q) pair; thread e owns matrix element (e / P, e % P) of
+// every per-pair matrix (P = padded band count: 64 threads for P <= 8, one
+// wave, or P^2 = 256 for P = 16).  The per-pair matrices live in LDS; the
+// accumulated adjoints of U_k and U_k+q stay in the registers of the element's
+// thread, and the sums over a row or a column of the band-pair weights are
+// lane butterflies inside the wave (LDS tree sums for P = 16), so no thread
+// walks a row of LDS values one dependent load at a time.
+template <int P> __device__ inline double sum_rows_of_column(double v) {   // over e / P, same e % P
+#pragma unroll
+    for (int m = P; m < P * P; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+template <int P> __device__ inline double sum_columns_of_row(double v) {   // over e % P, same e / P
+#pragma unroll
+    for (int m = 1; m < P; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+template <int P> __device__ inline double sum_all(double v) {
+#pragma unroll
+    for (int m = 1; m < P * P; m <<= 1) v += __shfl_xor(v, m, 64);
+    return v;
+}
+
 template <typename CT, int P>
 __global__ __launch_bounds__(P * P > 64 ? P * P : 64) void pair_bwd_kernel(PairBwdArgs a)
 {
-    constexpr int PMAX = P;
-    constexpr int NT = P * P > 64 ? P * P : 64;       // threads: at least one per matrix element
-    __shared__ double2 Uk[PMAX][PMAX + 1];
-    __shared__ double2 Uq[PMAX][PMAX + 1];
-    __shared__ double2 X[PMAX][PMAX + 1];
-    __shared__ double2 Tm[PMAX][PMAX + 1];
-    __shared__ double2 gb[PMAX][PMAX + 1];
-    __shared__ double2 Y[PMAX][PMAX + 1];
-    __shared__ double2 UkA[PMAX][PMAX + 1];
-    __shared__ double2 UqA[PMAX][PMAX + 1];
-    __shared__ double S1[PMAX][PMAX + 1], S2[PMAX][PMAX + 1], S3[PMAX][PMAX + 1];
-    __shared__ double ekA[PMAX], eqA[PMAX];
+    constexpr bool WAVE = P * P <= 64;             // every element in one wave
+    __shared__ double2 Uk[P][P + 1];
+    __shared__ double2 Uq[P][P + 1];
+    __shared__ double2 X[P][P + 1];
+    __shared__ double2 Tm[P][P + 1];
+    __shared__ double2 gb[P][P + 1];
+    __shared__ double2 Y[P][P + 1];
+    __shared__ double red[WAVE ? 1 : 3][P][P + 1];  // row / column / total sums (P = 16)
 
     const int lane = threadIdx.x;
+    const int r = lane / P, c = lane % P;
     const int ql = blockIdx.x;
     const int k = blockIdx.y;
     const int nb = a.nb, nm = a.nm, nbp = a.nbp;
     const int nb2 = nb * nb;
+    const bool act = lane < P * P;                        // lanes beyond P^2 (P < 8) hold no element
+    const bool el = act && r < nb && c < nb;              // a true element (not padding)
     const int q = a.q0 + ql;
     const size_t pair = (size_t)k * a.qc + ql;
     const double2* U = reinterpret_cast<const double2*>(a.U);
@@ -75,18 +94,20 @@ __global__ __launch_bounds__(P * P > 64 ? P * P : 64) void pair_bwd_kernel(PairB
     const double* fqs = a.kq ? a.ftab + (size_t)kq * nb : a.f_pair + pair * nb;
     CT* G = reinterpret_cast<CT*>(a.G);
     const size_t ncols = (size_t)a.qc * nm * nbp * nbp;
+    const double2 zero = make_double2(0.0, 0.0);
 
-    for (int e = lane; e < nb2; e += NT) {
-        const int r = e / nb, c = e % nb;
-        Uk[r][c] = valid ? U[((size_t)k * nb + r) * nb + c] : make_double2(0.0, 0.0);
-        Uq[r][c] = valid ? Uqs[r * nb + c] : make_double2(0.0, 0.0);
-        UkA[r][c] = make_double2(0.0, 0.0);
-        UqA[r][c] = make_double2(0.0, 0.0);
+    if (act) {
+        Uk[r][c] = (el && valid) ? U[((size_t)k * nb + r) * nb + c] : zero;
+        Uq[r][c] = (el && valid) ? Uqs[r * nb + c] : zero;
     }
-    if (lane < nb) {
-        ekA[lane] = 0.0;
-        eqA[lane] = 0.0;
-    }
+    // this thread's band energies and occupation (element (m, n) = (r, c))
+    const double en = el ? a.eps[(size_t)k * nb + c] : 0.0;
+    const double em = el && valid ? eqs[r] : 0.0;
+    const double f = el && valid ? fqs[r] : 0.0;
+    const double wb = el ? a.wbar[(size_t)k * nb + c] : 0.0;
+    const double fp = a.kT > 0.0 ? -f * (1.0 - f) / a.kT : 0.0;
+    double2 ukA = zero, uqA = zero;       // dL/dU_k[r][c], dL/dU_k+q[r][c]
+    double ekA = 0.0, eqA = 0.0;          // dL/deps_k[c] (held where r == 0), dL/deps_k+q[r] (where c == 0)
     __syncthreads();
     const double inv_s2 = 1.0 / (a.sigma * a.sigma);
     for (int nu = 0; nu < nm; ++nu) {
@@ -94,38 +115,36 @@ __global__ __launch_bounds__(P * P > 64 ? P * P : 64) void pair_bwd_kernel(PairB
         const double scv = a.sc[(size_t)ql * nm + nu];
         if (!valid || scv == 0.0) {
             // no contribution: the adjoint of this block is zero
-            for (int e = lane; e < nb2; e += NT) Gb[(e / nb) * nbp + e % nb] = from_d2<CT>(make_double2(0.0, 0.0));
+            if (el) Gb[r * nbp + c] = from_d2<CT>(zero);
             if (lane == 0) a.om_c[pair * nm + nu] = 0.0;
             continue;
         }
-        for (int e = lane; e < nb2; e += NT) X[e / nb][e % nb] = to_d2(Gb[(e / nb) * nbp + e % nb]);
+        if (act) X[r][c] = el ? to_d2(Gb[r * nbp + c]) : zero;
         __syncthreads();
-        for (int e = lane; e < nb2; e += NT) {          // T = X U_k
-            const int i = e / nb, n = e % nb;
-            double2 t = make_double2(0.0, 0.0);
-            for (int j = 0; j < nb; ++j) {
-                const double2 p = cmul(X[i][j], Uk[j][n]);
-                t.x += p.x;
-                t.y += p.y;
-            }
-            Tm[i][n] = t;
+        double2 t = zero;                  // T = X U_k
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if (!act) break;
+            const double2 p = cmul(X[r][j], Uk[j][c]);
+            t.x += p.x;
+            t.y += p.y;
         }
+        if (act) Tm[r][c] = t;
         __syncthreads();
         const double w = a.omega[(size_t)ql * nm + nu];
         const double nB = a.nbose[(size_t)ql * nm + nu];
         const double dnB = a.kT > 0.0 ? -nB * (nB + 1.0) / a.kT : 0.0;
-        for (int e = lane; e < nb2; e += NT) {          // g' = U_kq^dag T, weights
-            const int m = e / nb, n = e % nb;
-            double2 g = make_double2(0.0, 0.0);
-            for (int i = 0; i < nb; ++i) {
-                const double2 p = cmulc(Uq[i][m], Tm[i][n]);
-                g.x += p.x;
-                g.y += p.y;
-            }
-            const double en = a.eps[(size_t)k * nb + n];
-            const double em = eqs[m];
-            const double f = fqs[m];
-            const double fp = a.kT > 0.0 ? -f * (1.0 - f) / a.kT : 0.0;
+        double2 g = zero;                  // g' = U_kq^dag T, element (m, n) = (r, c)
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            if (!act) break;
+            const double2 p = cmulc(Uq[i][r], Tm[i][c]);
+            g.x += p.x;
+            g.y += p.y;
+        }
+        double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        double2 gbv = zero;
+        if (el) {
             const double x = en - em;
             const double e1 = exp(-(x + w) * (x + w) * inv_s2);
             const double e2 = exp(-(x - w) * (x - w) * inv_s2);
@@ -133,79 +152,97 @@ __global__ __launch_bounds__(P * P > 64 ? P * P : 64) void pair_bwd_kernel(PairB
             const double Wv = A1 * e1 + A2 * e2;
             const double dWdx = -2.0 * inv_s2 * (A1 * (x + w) * e1 + A2 * (x - w) * e2);
             const double dWdw = dnB * (e1 + e2) - 2.0 * inv_s2 * (A1 * (x + w) * e1 - A2 * (x - w) * e2);
-            const double cw = a.C * a.wbar[(size_t)k * nb + n];
+            const double cw = a.C * wb;
             const double amp = g.x * g.x + g.y * g.y;
-            gb[m][n] = make_double2(2.0 * cw * Wv * g.x, 2.0 * cw * Wv * g.y);
-            S1[m][n] = cw * amp * dWdx;
-            S2[m][n] = cw * amp * (-dWdx + (e1 - e2) * fp);
-            S3[m][n] = cw * amp * (dWdw - Wv / w);
+            gbv = make_double2(2.0 * cw * Wv * g.x, 2.0 * cw * Wv * g.y);
+            s1 = cw * amp * dWdx;
+            s2 = cw * amp * (-dWdx + (e1 - e2) * fp);
+            s3 = cw * amp * (dWdw - Wv / w);
+        }
+        if (act) gb[r][c] = gbv;
+        // eps_k[n] gets the column sums over m, eps_k+q[m] the row sums over n,
+        // omega the total (fixed order: lane butterflies, or LDS sums for P = 16)
+        double colsum, rowsum, total;
+        if constexpr (WAVE) {
+            colsum = sum_rows_of_column<P>(s1);
+            rowsum = sum_columns_of_row<P>(s2);
+            total = sum_all<P>(s3);
+        } else {
+            red[0][r][c] = s1;
+            red[1][r][c] = s2;
+            red[2][r][c] = s3;
         }
         __syncthreads();
-        for (int e = lane; e < nb2; e += NT) {          // Y = U_kq gbar'; Ubar_kq += T gbar'^dag
-            const int i = e / nb, c = e % nb;
-            double2 y = make_double2(0.0, 0.0), u = make_double2(0.0, 0.0);
-            for (int m = 0; m < nb; ++m) {
-                const double2 p = cmul(Uq[i][m], gb[m][c]);
-                y.x += p.x;
-                y.y += p.y;
+        if constexpr (!WAVE) {
+            colsum = 0.0;
+            rowsum = 0.0;
+            total = 0.0;
+            if (r == 0) {
+                for (int m = 0; m < P; ++m) colsum += red[0][m][c];
             }
-            for (int n = 0; n < nb; ++n) {
-                const double2 p = cmul_bc(Tm[i][n], gb[c][n]);
-                u.x += p.x;
-                u.y += p.y;
+            if (c == 0) {
+                for (int n = 0; n < P; ++n) rowsum += red[1][r][n];
+                red[2][r][P] = 0.0;
+                double t3 = 0.0;
+                for (int n = 0; n < P; ++n) t3 += red[2][r][n];
+                red[2][r][P] = t3;
             }
-            Y[i][c] = y;
-            UqA[i][c].x += u.x;
-            UqA[i][c].y += u.y;
         }
-        if (lane < nb) {                                 // fixed-order scalar sums
-            double s1 = 0.0, s2 = 0.0;
-            for (int m = 0; m < nb; ++m) s1 += S1[m][lane];
-            for (int n = 0; n < nb; ++n) s2 += S2[lane][n];
-            ekA[lane] += s1;
-            eqA[lane] += s2;
+        if (r == 0) ekA += colsum;
+        if (c == 0) eqA += rowsum;
+        double2 y = zero, u = zero;        // Y = U_kq gbar'; dL/dU_kq += T gbar'^dag
+#pragma unroll
+        for (int m = 0; m < P; ++m) {
+            if (!act) break;
+            const double2 p = cmul(Uq[r][m], gb[m][c]);
+            y.x += p.x;
+            y.y += p.y;
         }
+#pragma unroll
+        for (int n = 0; n < P; ++n) {
+            if (!act) break;
+            const double2 p = cmul_bc(Tm[r][n], gb[c][n]);
+            u.x += p.x;
+            u.y += p.y;
+        }
+        uqA.x += u.x;
+        uqA.y += u.y;
+        if (act) Y[r][c] = y;
         __syncthreads();
-        if (lane < nb) {                                 // row sums of S3, then their sum (fixed order)
-            double r3 = 0.0;
-            for (int n = 0; n < nb; ++n) r3 += S3[lane][n];
-            S3[lane][PMAX] = r3;
-        }
-        __syncthreads();
-        if (lane == 0) {
-            double s3 = 0.0;
-            for (int m = 0; m < nb; ++m) s3 += S3[m][PMAX];
-            a.om_c[pair * nm + nu] = s3;
-        }
-        for (int e = lane; e < nb2; e += NT) {          // Ubar_k += X^dag Y; Gbar = Y U_k^dag
-            const int r = e / nb, c = e % nb;
-            double2 u = make_double2(0.0, 0.0), gbar = make_double2(0.0, 0.0);
-            for (int i = 0; i < nb; ++i) {
-                const double2 p = cmulc(X[i][r], Y[i][c]);
-                u.x += p.x;
-                u.y += p.y;
+        if constexpr (!WAVE) {
+            if (lane == 0) {
+                for (int m = 0; m < P; ++m) total += red[2][m][P];
             }
-            for (int n = 0; n < nb; ++n) {
-                const double2 p = cmul_bc(Y[r][n], Uk[c][n]);
-                gbar.x += p.x;
-                gbar.y += p.y;
-            }
-            UkA[r][c].x += u.x;
-            UkA[r][c].y += u.y;
-            Gb[r * nbp + c] = from_d2<CT>(gbar);
         }
-        __syncthreads();
+        if (lane == 0) a.om_c[pair * nm + nu] = total;
+        double2 uk = zero, gbar = zero;    // dL/dU_k += X^dag Y; Gbar = Y U_k^dag
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            if (!act) break;
+            const double2 p = cmulc(X[i][r], Y[i][c]);
+            uk.x += p.x;
+            uk.y += p.y;
+        }
+#pragma unroll
+        for (int n = 0; n < P; ++n) {
+            if (!act) break;
+            const double2 p = cmul_bc(Y[r][n], Uk[c][n]);
+            gbar.x += p.x;
+            gbar.y += p.y;
+        }
+        ukA.x += uk.x;
+        ukA.y += uk.y;
+        if (el) Gb[r * nbp + c] = from_d2<CT>(gbar);
+        __syncthreads();                   // X, Tm, gb, Y are rewritten by the next mode
     }
     double2* Ukc = reinterpret_cast<double2*>(a.Uk_c);
     double2* Uqc = reinterpret_cast<double2*>(a.Ukq_c);
-    for (int e = lane; e < nb2; e += NT) {
-        Ukc[pair * nb2 + e] = UkA[e / nb][e % nb];
-        Uqc[pair * nb2 + e] = UqA[e / nb][e % nb];
+    if (el) {
+        Ukc[pair * nb2 + r * nb + c] = ukA;
+        Uqc[pair * nb2 + r * nb + c] = uqA;
     }
-    if (lane < nb) {
-        a.ek_c[pair * nb + lane] = ekA[lane];
-        a.ekq_c[pair * nb + lane] = eqA[lane];
-    }
+    if (r == 0 && c < nb) a.ek_c[pair * nb + c] = ekA;
+    if (c == 0 && r < nb) a.ekq_c[pair * nb + r] = eqA;
 }
 
 __global__ void fill_i32_kernel(size_t n, int32_t v, int32_t* p) {

@@ -429,6 +429,8 @@ template <int MODE, int NBP, int KIND, bool GEN>
 __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_m, int tiles_n)
 {
     constexpr bool STORE = KIND == 1;
+    constexpr bool WSTORE = KIND == 6;
+    static_assert(!WSTORE || MODE != 2, "the Wannier-basis store runs in float64 / float32");
     constexpr bool TR = KIND == 5;
     constexpr bool PH = KIND == 2 || TR;
     constexpr bool RE = KIND == 3;
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     // Per-row state kept over the block's tiles: the Im Sigma accumulators of
     // the row's bands and, in the float32 modes, eps_nk and the U_k columns
     // (the float64 mode reloads those per tile to stay within its registers).
-    constexpr bool HOIST = MODE == 1 || (MODE == 2 && RUN * NBP <= 16);
+    constexpr bool HOIST = (MODE == 1 && NBP < 16) || (MODE == 2 && RUN * NBP <= 16);
     double acc[NBP], acc2[RE ? NBP : 1];
     double eps_h[HOIST ? NBP : 1];
     CE uk_h[HOIST ? RUN : 1][NBP];
@@ -600,6 +602,24 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
             const int lane = tid & 63, wave = tid >> 6;
             constexpr int WN = BN / 64;
             const int wm = wave / WN, wn = wave % WN;
+            if constexpr (WSTORE) {
+                // the Wannier-basis tile itself, straight to memory (the main
+                // loop's last barrier has released the LDS stage)
+                CT* G = reinterpret_cast<CT*>(a.gout);
+                for (int c = 0; c < 4; ++c) {
+                    const long col = n0 + wn * 64 + c * 16 + (lane & 15);
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = m0 + wm * 16 + crow<T>(lane, i);
+                        if (row >= a.nk || col >= ncols) continue;
+                        CT v;
+                        v.x = cr[c][i];
+                        v.y = ci[c][i];
+                        G[(size_t)row * ncols + col] = v;
+                    }
+                }
+                __builtin_amdgcn_s_setprio(0);
+                continue;
+            }
             for (int c = 0; c < 4; ++c)
                 for (int i = 0; i < 4; ++i) {
                     const int row = wm * 16 + crow<T>(lane, i);
@@ -918,7 +938,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
         }
         __syncthreads();
     }
-    if constexpr (KIND == 1 || KIND == 2 || KIND == 4 || KIND == 5) return;
+    if constexpr (KIND == 1 || KIND == 2 || KIND == 4 || KIND == 5 || KIND == 6) return;
     // fixed-order reduction over the TPR threads of each row (real-part
     // mode: the on-shell sums, then the sums at eps_F)
     double* red = reinterpret_cast<double*>(smem);   // [BM][TPR][NBP]
@@ -1147,6 +1167,13 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
         else
             fused_k_kernel<MODE, NBP, K, false><<<grid, block, 0, stream>>>(a, tiles_m, tiles_n);
     };
+    if constexpr (MODE != 2) {
+        if (a.gout) {
+            go(std::integral_constant<int, 6>());
+            launch_check("fused_k_kernel");
+            return;
+        }
+    }
     if (a.gkq) go(std::integral_constant<int, 1>());
     else if (a.rec) go(std::integral_constant<int, 4>());
     else if (a.part_ph && a.vel) go(std::integral_constant<int, 5>());

@@ -146,8 +146,10 @@ struct FusedArgs {
     double* rec;       // [nk][qc][nm][nb] pole records of 4 + nbp doubles (pole mode)
     const double* vel; // [nk][nb][3] band velocities of the k set (transport mode, with part_ph)
     const double* vel_pair;  // [nk][qc][nb][3] velocities at k+q per pair (transport mode, off-grid)
+    void* gout = nullptr;    // [nk][qc*nm*nbp*nbp] complex in prec: the Wannier-basis g_nu(k,q)
+                             // itself (no rotation or reduction; float64 / float32, phase table)
 };
-// a7 + a8 + a9 (imsigma mode), a7 + a8 (store mode, gkq != nullptr),
+// a7 alone (gout != nullptr: the adjoint's recomputed vertex), a7 + a8 + a9 (imsigma mode), a7 + a8 (store mode, gkq != nullptr),
 // a7 + a8 + the phonon-linewidth sums (phonon mode, part_ph != nullptr), or
 // a7 + a8 + the real-part sums of Eq. (3) (real-part mode, part2 != nullptr)
 void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t stream);
