@@ -458,15 +458,15 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
     const bool bf = prec == Prec::BF16X2;
     const Prec rprec = bf ? Prec::F32 : prec;      // precision of the R_p -> q step
     // Phases of the R_e -> k contraction: generated inside the fused kernel
-    // from per-axis factors for the FP32 / split-BF16 paths (saves the table
-    // traffic there), read from a table for FP64, where the extra VALU work of
-    // generating them costs more than the table reads, and for FP32 at 16
-    // padded bands, where a tile has only 16 k rows, so the table is small per
-    // tile and generating costs more (the mobility-shaped shard's fused stage
-    // 5.7 -> 5.2 s).  Generation needs the R_e offsets of a tile in LDS, hence
-    // the bound on ne.  The 1/ndeg weights of R_e are folded into the B operand
-    // (mode rotation) in both cases.
-    const bool gen = prec != Prec::F64 && s->nmax_e > 0 && ne <= 4096 && !(prec == Prec::F32 && L.nbp >= 16);
+    // from per-axis factors for the split-BF16 path (its short main loop
+    // would otherwise wait on the table; realistic workload 274 -> 225 ms per
+    // 4000-q launch), read from a table for FP64 and FP32, where the extra
+    // VALU work of generating them costs more than the table reads (FP32:
+    // 322 -> 291 ms per launch with the table; the mobility-shaped shard's
+    // fused stage 5.7 -> 5.2 s).  Generation needs the R_e offsets of a tile
+    // in LDS, hence the bound on ne.  The 1/ndeg weights of R_e are folded
+    // into the B operand (mode rotation) in both cases.
+    const bool gen = prec == Prec::BF16X2 && s->nmax_e > 0 && ne <= 4096;
     if (!gen && !L.kouter) launch_phase_table(prec, nk, p->kfrac, ne, s->Re, nullptr, bf ? L.kpad : ne, L.phi_k, st);
     const void* gsrc = s->gR;
     if (prec != Prec::F64) {
