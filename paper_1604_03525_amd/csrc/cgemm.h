@@ -64,20 +64,30 @@ struct Stage {
 // when it is fetched: k (row-major A, default) or m (A read transposed).
 // NS = 1: one LDS stage, two barriers per K step; NS = 2: the next K step is
 // stored into the other stage while this one is read, one barrier per step.
+// Waves: WN = BN / 64 across the columns, 4 / WN across the rows; each wave
+// owns RB row blocks of 16 x 64 (accumulator index rb * 4 + column block), so
+// a wave reads each B fragment once for RB row blocks.
+template <int BM, int BN> struct CWaves {
+    static constexpr int WN = BN / 64;
+    static constexpr int RB = BM * WN / 64;
+};
 template <typename T, int BM, int BN, int BK, class AF, class BF, bool A_KMAJOR = false, int NS = 1>
 __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF afetch, BF bfetch,
-                                      typename Cx<T>::acc (&cr)[4], typename Cx<T>::acc (&ci)[4])
+                                      typename Cx<T>::acc (&cr)[4 * CWaves<BM, BN>::RB],
+                                      typename Cx<T>::acc (&ci)[4 * CWaves<BM, BN>::RB])
 {
     static_assert(NS == 1 || NS == 2, "one or two LDS stages");
     typedef typename Cx<T>::type CT;
-    constexpr int WN = BN / 64;
+    constexpr int WN = CWaves<BM, BN>::WN;
+    constexpr int RB = CWaves<BM, BN>::RB;
+    static_assert(RB >= 1 && 16 * RB * (4 / WN) == BM, "wave layout");
     constexpr int AE = BM * BK / 256;
     constexpr int BE = BK * BN / 256;
     static_assert(AE >= 1 && BE >= 1, "tile too small for 256 threads");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
     CT ra[AE], rb[BE];
-    for (int c = 0; c < 4; ++c) {
+    for (int c = 0; c < 4 * RB; ++c) {
         for (int i = 0; i < 4; ++i) {
             cr[c][i] = T(0);
             ci[c][i] = T(0);
@@ -118,8 +128,8 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
     // P2 = sum ai bi, P3 = sum (ar + ai)(br + bi):  re = P1 - P2,
     // im = P3 - P1 - P2.  Three real MFMAs per complex block product instead
     // of four; the operand sums are formed in registers from the LDS planes.
-    typename Cx<T>::acc cm[4];
-    for (int c = 0; c < 4; ++c)
+    typename Cx<T>::acc cm[4 * RB];
+    for (int c = 0; c < 4 * RB; ++c)
         for (int i = 0; i < 4; ++i) cm[c][i] = T(0);
     gload(0);
     sstore(stages[0]);
@@ -131,9 +141,13 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             const int kr = kk + (lane >> 4);
-            const T ar = st.a_re[kr][wm * 16 + (lane & 15)];
-            const T ai = st.a_im[kr][wm * 16 + (lane & 15)];
-            const T as = ar + ai;
+            T ar[RB], ai[RB], as[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                ar[q] = st.a_re[kr][wm * 16 * RB + q * 16 + (lane & 15)];
+                ai[q] = st.a_im[kr][wm * 16 * RB + q * 16 + (lane & 15)];
+                as[q] = ar[q] + ai[q];
+            }
             T br[4], bi[4], bs[4];
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
@@ -141,12 +155,19 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
                 bi[c] = st.b_im[kr][wn * 64 + c * 16 + (lane & 15)];
                 bs[c] = br[c] + bi[c];
             }
+            // consecutive MFMAs cycle over the 4 RB accumulators of a product
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cr[c] = mfma4(ar, br[c], cr[c]);
+            for (int q = 0; q < RB; ++q)
 #pragma unroll
-            for (int c = 0; c < 4; ++c) cm[c] = mfma4(ai, bi[c], cm[c]);
+                for (int c = 0; c < 4; ++c) cr[q * 4 + c] = mfma4(ar[q], br[c], cr[q * 4 + c]);
 #pragma unroll
-            for (int c = 0; c < 4; ++c) ci[c] = mfma4(as, bs[c], ci[c]);
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cm[q * 4 + c] = mfma4(ai[q], bi[c], cm[q * 4 + c]);
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) ci[q * 4 + c] = mfma4(as[q], bs[c], ci[q * 4 + c]);
         }
         if constexpr (NS == 2) {
             // the other stage was last read in the previous step, before its barrier
@@ -160,7 +181,7 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
             }
         }
     }
-    for (int c = 0; c < 4; ++c)
+    for (int c = 0; c < 4 * RB; ++c)
         for (int i = 0; i < 4; ++i) {
             const T p1 = cr[c][i], p2 = cm[c][i];
             cr[c][i] = p1 - p2;

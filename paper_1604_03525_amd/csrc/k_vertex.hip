@@ -161,13 +161,14 @@ __global__ void mode_rotate_kernel(int ne, int nq, int nm, int nb, int nbp,
 // part[s][k][n]: the cross-block sum is a separate fixed-order reduction.
 
 // 64 x 64 (4096 complex entries) up to 8 padded bands; at 16 bands one band
-// block is 256 columns wide: 16 x 256 in float64 / float32, 32 x 256 in
+// block is 256 columns wide: 16 x 256 in float64, 32 x 256 in float32 and
 // split-bf16, where a 16-row tile uses each B column for too few k rows to
-// keep its faster main loop fed (the mobility-scale shard's split-bf16 fused
-// stage 5.3 -> 3.7 s)
+// keep the main loop fed (the mobility-scale shard's split-bf16 fused stage
+// 5.3 -> 3.7 s); the float64 C tile of 32 rows would not leave room in LDS
+// for a second resident block
 template <int MODE, int NBP> struct FusedShape {
     static constexpr int BN = NBP * NBP >= 64 ? NBP * NBP : 64;
-    static constexpr int BM = (MODE == 2 && BN >= 256 ? 8192 : 4096) / BN;
+    static constexpr int BM = (MODE != 0 && BN >= 256 ? 8192 : 4096) / BN;
 };
 
 // ---- split-bf16 tile: x = hi + lo (bf16 each), products hi.hi + hi.lo + lo.hi
@@ -449,7 +450,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     constexpr int JI = BN / (NBP * TPR);
     constexpr int RUN = JI < NBP ? JI : NBP;
     constexpr int NRUN = JI / RUN;
-    constexpr int RT = MODE == 2 ? 1 : RUN;        // bands of a run taken together in phase 2
+    constexpr int RT = (MODE == 2 || (MODE == 1 && NBP >= 16)) ? 1 : RUN;   // bands of a run taken together in phase 2
     static_assert(JI * NBP * TPR == BN && JI % RUN == 0 && NBP % RUN == 0, "epilogue split");
     constexpr int LDC = BN + 1;                    // C tile row stride: rows start on different LDS banks
     typedef Stage<T, BM, BN, BK> St;
@@ -596,7 +597,8 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 if (kk < a.ne && col < ncols) return Bm[(size_t)kk * ncols + col];
                 return cz<T>();
             };
-            typename Cx<T>::acc cr[4], ci[4];
+            constexpr int RB = CWaves<BM, BN>::RB;
+            typename Cx<T>::acc cr[4 * RB], ci[4 * RB];
             cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), false, NS>(
                 reinterpret_cast<St*>(smem), a.ne, afetch, bfetch, cr, ci);
             const int lane = tid & 63, wave = tid >> 6;
@@ -606,29 +608,31 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 // the Wannier-basis tile itself, straight to memory (the main
                 // loop's last barrier has released the LDS stage)
                 CT* G = reinterpret_cast<CT*>(a.gout);
-                for (int c = 0; c < 4; ++c) {
-                    const long col = n0 + wn * 64 + c * 16 + (lane & 15);
-                    for (int i = 0; i < 4; ++i) {
-                        const int row = m0 + wm * 16 + crow<T>(lane, i);
-                        if (row >= a.nk || col >= ncols) continue;
-                        CT v;
-                        v.x = cr[c][i];
-                        v.y = ci[c][i];
-                        G[(size_t)row * ncols + col] = v;
+                for (int q = 0; q < RB; ++q)
+                    for (int c = 0; c < 4; ++c) {
+                        const long col = n0 + wn * 64 + c * 16 + (lane & 15);
+                        for (int i = 0; i < 4; ++i) {
+                            const int row = m0 + wm * 16 * RB + q * 16 + crow<T>(lane, i);
+                            if (row >= a.nk || col >= ncols) continue;
+                            CT v;
+                            v.x = cr[q * 4 + c][i];
+                            v.y = ci[q * 4 + c][i];
+                            G[(size_t)row * ncols + col] = v;
+                        }
                     }
-                }
                 __builtin_amdgcn_s_setprio(0);
                 continue;
             }
-            for (int c = 0; c < 4; ++c)
-                for (int i = 0; i < 4; ++i) {
-                    const int row = wm * 16 + crow<T>(lane, i);
-                    const int col = wn * 64 + c * 16 + (lane & 15);
-                    CT v;
-                    v.x = cr[c][i];
-                    v.y = ci[c][i];
-                    Cs[row * LDC + col] = v;
-                }
+            for (int q = 0; q < RB; ++q)
+                for (int c = 0; c < 4; ++c)
+                    for (int i = 0; i < 4; ++i) {
+                        const int row = wm * 16 * RB + q * 16 + crow<T>(lane, i);
+                        const int col = wn * 64 + c * 16 + (lane & 15);
+                        CT v;
+                        v.x = cr[q * 4 + c][i];
+                        v.y = ci[q * 4 + c][i];
+                        Cs[row * LDC + col] = v;
+                    }
         }
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
@@ -1146,7 +1150,7 @@ inline unsigned blocks_for(size_t n, int bs) { return (unsigned)((n + bs - 1) / 
 template <int MODE, int NBP>
 void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     constexpr int BM = FusedShape<MODE, NBP>::BM, BN = FusedShape<MODE, NBP>::BN;
-    static_assert(BM == fused_tile_rows_c(NBP, MODE == 2), "tile rows known to the host code");
+    static_assert(BM == fused_tile_rows_c(NBP, MODE != 0), "tile rows known to the host code");
     const int tiles_m = (a.nk + BM - 1) / BM;
     const long ncols = (long)a.qc * a.nm * NBP * NBP;
     const int tiles_n = (int)((ncols + BN - 1) / BN);

@@ -156,13 +156,13 @@ void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t strea
 int fused_slices(int nk, int nbp, int ncols_tiles, int num_cu, Prec prec);
 // columns and k rows per tile of the fused kernel for a padded band count:
 // whole band blocks, at least 64 columns; 4096 complex entries, 8192 for
-// split-bf16 at 16 bands (32 x 256)
-constexpr int fused_tile_cols_c(int nbp, bool bf) { return nbp * nbp >= 64 ? nbp * nbp : 64; }
-constexpr int fused_tile_rows_c(int nbp, bool bf) {
-    return (bf && fused_tile_cols_c(nbp, bf) >= 256 ? 8192 : 4096) / fused_tile_cols_c(nbp, bf);
+// float32 and split-bf16 at 16 bands (32 x 256); `wide` = not float64
+constexpr int fused_tile_cols_c(int nbp, bool wide) { return nbp * nbp >= 64 ? nbp * nbp : 64; }
+constexpr int fused_tile_rows_c(int nbp, bool wide) {
+    return (wide && fused_tile_cols_c(nbp, wide) >= 256 ? 8192 : 4096) / fused_tile_cols_c(nbp, wide);
 }
-inline int fused_tile_cols(int nbp, Prec prec) { return fused_tile_cols_c(nbp, prec == Prec::BF16X2); }
-inline int fused_tile_rows(int nbp, Prec prec) { return fused_tile_rows_c(nbp, prec == Prec::BF16X2); }
+inline int fused_tile_cols(int nbp, Prec prec) { return fused_tile_cols_c(nbp, prec != Prec::F64); }
+inline int fused_tile_rows(int nbp, Prec prec) { return fused_tile_rows_c(nbp, prec != Prec::F64); }
 // raw[0] = sum_i exp(-((eps_i - mu)/sigma)^2) over n values (fixed order)
 void launch_dos_raw(size_t n, const double* eps, double mu, double sigma, double* raw, hipStream_t stream);
 // Pi''[q][nu] = 2 pi / (N_k sigma sqrt pi) sum_t part[0][t][q][nu];
