@@ -325,8 +325,8 @@ def main():
                     default="fp32,split_bf16,backward,backward_fp32,backward_split_bf16,mobility,phonon,resigma,"
                             "polar,transport,spectral",
                     help="comma list of fp32, split_bf16, backward, backward_fp32, backward_split_bf16, mobility "
-                         "(one 4096-q shard of the mobility-scale system), phonon, resigma, polar, transport, "
-                         "spectral")
+                         "(one 4096-q shard of the mobility-scale system), mobility_forward (its forward legs "
+                         "only), phonon, resigma, polar, transport, spectral")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--peak-gemm", action="store_true",
@@ -488,6 +488,8 @@ def main():
             elif var == "mobility":
                 variants[var] = mobility_shard(dev, ("fp64", "fp32", "split_bf16"), ("fp32", "split_bf16"), 1, 0,
                                                torch)
+            elif var == "mobility_forward":
+                variants[var] = mobility_shard(dev, ("fp64", "fp32", "split_bf16"), (), 1, 0, torch)
         except epw.EpwError as e:
             variants[var] = {"unavailable": str(e)}
     result["variants"] = variants
