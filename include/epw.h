@@ -399,12 +399,19 @@ int epw_phonon_selfenergy(const epw_system* sys, const epw_points* pts, const ep
  * modes.  The rotated vertex is recomputed, not stored.
  *  w       device [nk][nb] double
  *  dgR     device [nRe][nRp][nm][nb][nb] c128 out (NULL to skip)
- *  dHR     device [nRe][nb][nb] c128 out (NULL to skip; grid runs only)
+ *  dHR     device [nRe][nb][nb] c128 out (NULL to skip).  On grids it is
+ *          the k-set eigen-adjoint contracted back to R_e; off-grid (no kq
+ *          map) it adds, for every (k, q) pair, the eigen-adjoint of the
+ *          interpolated H(k+q) contracted back with the conjugate of the
+ *          phase that formed it.
  *  domega  device [nq][nm] double out (NULL to skip)
  * Outputs are overwritten (par->accumulate = 1 adds instead).
- * par->dtype: EPW_FP64 or EPW_FP32 (the contractions, rotations and the
- * per-pair adjoint in complex64; the eigen-adjoint, the dL/dH(R_e)
- * contraction and all outputs in float64); EPW_SPLIT_BF16 -> EPW_EDTYPE.
+ * par->dtype: EPW_FP64; EPW_FP32 (the contractions, rotations and the
+ * per-pair adjoint in complex64); EPW_SPLIT_BF16 (the R_e <-> k
+ * contractions on split-bf16 operands with float32 accumulation, the
+ * R_p <-> q sums and the per-pair adjoint as in EPW_FP32).  In every
+ * precision the eigen-adjoints, the dL/dH(R_e) contraction and all outputs
+ * are float64.
  * Errors: as epw_imsigma. */
 int epw_imsigma_backward(const epw_system* sys, const epw_points* pts, const epw_params* par,
                          const double* w, void* dgR, void* dHR, double* domega,
