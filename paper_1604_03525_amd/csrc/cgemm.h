@@ -81,9 +81,13 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
     constexpr int WN = CWaves<BM, BN>::WN;
     constexpr int RB = CWaves<BM, BN>::RB;
     static_assert(RB >= 1 && 16 * RB * (4 / WN) == BM, "wave layout");
-    constexpr int AE = BM * BK / 256;
+    // A tiles smaller than the block (16 rows at K step 8) load one element
+    // on the first BM * BK threads only
+    constexpr int AN = BM * BK;
+    constexpr int AE = AN >= 256 ? AN / 256 : 1;
     constexpr int BE = BK * BN / 256;
-    static_assert(AE >= 1 && BE >= 1, "tile too small for 256 threads");
+    static_assert((AN >= 256 ? AE * 256 == AN : 256 % AN == 0) && BE >= 1 && BE * 256 == BK * BN,
+                  "tile too small for 256 threads");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WN, wn = wave % WN;
     CT ra[AE], rb[BE];
@@ -97,6 +101,7 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
             const int idx = tid * AE + e;
+            if (AN < 256 && idx >= AN) break;
             if (A_KMAJOR)
                 ra[e] = afetch(idx % BM, k0 + idx / BM);
             else
@@ -112,6 +117,7 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
 #pragma unroll
         for (int e = 0; e < AE; ++e) {
             const int idx = tid * AE + e;
+            if (AN < 256 && idx >= AN) break;
             const int m = A_KMAJOR ? idx % BM : idx / BK;
             const int k = A_KMAJOR ? idx / BM : idx % BK;
             st.a_re[k][m] = ra[e].x;

@@ -281,6 +281,9 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
             //                col_q' = s col_p + c e^{-i phi} col_q (pair P2);
             // then rows:     row_p' = c row_p - s e^{i phi} row_q,
             //                row_q' = s row_p + c e^{i phi} row_q (pair P1).
+            // The same lane applies the column rotation of pair P2 to rows 2 P1 and
+            // 2 P1 + 1 of V (V <- V J), reusing the parameters it already holds;
+            // with 2 npair = n2 >= n those rows cover every row of V.
             {
                 const int P1 = lane >> (LOGN - 1), P2 = lane & (MAXN / 2 - 1);
                 if (P1 < npair && P2 < npair) {
@@ -290,6 +293,8 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                     const double c2 = rot[P2][0], s2 = rot[P2][1];
                     const double2 e2 = make_double2(rot[P2][2], -rot[P2][3]);
                     const double2 xpp = A[p1][p2], xpq = A[p1][q2], xqp = A[q1][p2], xqq = A[q1][q2];
+                    const int i1 = 2 * P1, i2 = 2 * P1 + 1;
+                    const double2 v1p = V[i1][p2], v1q = V[i1][q2], v2p = V[i2][p2], v2q = V[i2][q2];
                     // columns (pair P2) on rows p1 and q1
                     const double2 wp = cmul(xpq, e2), wq = cmul(xqq, e2);
                     const double2 ypp = make_double2(c2 * xpp.x - s2 * wp.x, c2 * xpp.y - s2 * wp.y);
@@ -313,20 +318,13 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                     A[p1][q2] = zpq;
                     A[q1][p2] = zqp;
                     A[q1][q2] = zqq;
+                    // V: columns (pair P2) on rows i1 and i2 (an inactive pair has J = 1)
+                    const double2 w1 = cmul(v1q, e2), w2 = cmul(v2q, e2);
+                    V[i1][p2] = make_double2(c2 * v1p.x - s2 * w1.x, c2 * v1p.y - s2 * w1.y);
+                    V[i1][q2] = make_double2(s2 * v1p.x + c2 * w1.x, s2 * v1p.y + c2 * w1.y);
+                    V[i2][p2] = make_double2(c2 * v2p.x - s2 * w2.x, c2 * v2p.y - s2 * w2.y);
+                    V[i2][q2] = make_double2(s2 * v2p.x + c2 * w2.x, s2 * v2p.y + c2 * w2.y);
                 }
-            }
-            // V <- V J: columns (p, q) of the active pairs, rows i < n
-            for (int item = lane; item < (MAXN / 2) * MAXN; item += 64) {
-                const int pr = item >> LOGN, i = item & (MAXN - 1);
-                if (pr >= npair || i >= n) continue;
-                const int pp = rpq[pr][0], qq = rpq[pr][1];
-                if (qq >= n) continue;
-                const double c = rot[pr][0], s = rot[pr][1];
-                const double2 emi = make_double2(rot[pr][2], -rot[pr][3]);
-                const double2 xp = V[i][pp];
-                const double2 w = cmul(V[i][qq], emi);
-                V[i][pp] = make_double2(c * xp.x - s * w.x, c * xp.y - s * w.y);
-                V[i][qq] = make_double2(s * xp.x + c * w.x, s * xp.y + c * w.y);
             }
             __syncthreads();
         }

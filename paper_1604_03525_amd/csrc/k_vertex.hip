@@ -441,7 +441,9 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     typedef typename ModeTypes<MODE>::TE TE;
     typedef typename ModeTypes<MODE>::CE CE;
     constexpr int BM = FusedShape<MODE, NBP>::BM, BN = FusedShape<MODE, NBP>::BN;
-    constexpr int BK = 16;
+    // K step: 8 for the float64 16 x 256 tile, whose B stage (16 complex
+    // doubles per thread at K step 16) would not fit beside its accumulators
+    constexpr int BK = (MODE == 0 && NBP >= 16) ? 8 : 16;
     constexpr int NB2 = NBP * NBP;
     constexpr int TPR = 256 / BM;                  // threads per k row
     // Epilogue work items of a row: (band block b, band x), x < NBP; thread
