@@ -472,15 +472,18 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     int* Roff = reinterpret_cast<int*>(dsm + (size_t)3 * BM * (2 * a.nmax + 1) * sizeof(CE));  // [ne]
 
     // XCD-aware remap: consecutive workgroup ids land on different XCDs
-    // (round-robin over 8); give each XCD a contiguous range of (s, mt)
-    // so blocks sharing a column slice run on the same L2.
+    // (round-robin over 8); each XCD gets a contiguous range of lin, i.e. a
+    // band of row tiles with all S column slices, so that its L2 serves the
+    // A strips of few row tiles and each B tile to several row tiles (with
+    // the slice index outermost, an XCD ran ~64 row tiles of one slice and
+    // fetched both operands of every tile from beyond its L2).
     const int G = gridDim.x;
     const int bid = blockIdx.x;
     const int per = G / 8;
     const int lin = (bid % 8) * per + bid / 8;
     if (lin >= tiles_m * a.S) return;
-    const int s = lin / tiles_m;
-    const int mt = lin % tiles_m;
+    const int s = lin % a.S;
+    const int mt = lin / a.S;
     const int m0 = mt * BM;
     const int NE = 2 * a.nmax + 1;
     if constexpr (GEN) {
