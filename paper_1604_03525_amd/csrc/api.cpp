@@ -458,15 +458,17 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
     const bool bf = prec == Prec::BF16X2;
     const Prec rprec = bf ? Prec::F32 : prec;      // precision of the R_p -> q step
     // Phases of the R_e -> k contraction: generated inside the fused kernel
-    // from per-axis factors for the split-BF16 path (its short main loop
-    // would otherwise wait on the table; realistic workload 274 -> 225 ms per
-    // 4000-q launch), read from a table for FP64 and FP32, where the extra
-    // VALU work of generating them costs more than the table reads (FP32:
-    // 322 -> 291 ms per launch with the table; the mobility-shaped shard's
-    // fused stage 5.7 -> 5.2 s).  Generation needs the R_e offsets of a tile
-    // in LDS, hence the bound on ne.  The 1/ndeg weights of R_e are folded
-    // into the B operand (mode rotation) in both cases.
-    const bool gen = prec == Prec::BF16X2 && s->nmax_e > 0 && ne <= 4096;
+    // from per-axis factors for the split-BF16 path up to 8 padded bands (its
+    // short main loop would otherwise wait on the table; realistic workload
+    // 248 -> 219 ms per 4000-q launch), read from a table for FP64 and FP32,
+    // where the extra VALU work of generating them costs more than the table
+    // reads (FP32: 322 -> 291 ms per launch with the table), and for
+    // split-BF16 at 16 padded bands, whose 32-row tiles amortise the
+    // generation over few rows (mobility-shaped shard: 129 -> 121 ms per
+    // launch with the table).  Generation needs the R_e offsets of a tile in
+    // LDS, hence the bound on ne.  The 1/ndeg weights of R_e are folded into
+    // the B operand (mode rotation) in both cases.
+    const bool gen = prec == Prec::BF16X2 && L.nbp < 16 && s->nmax_e > 0 && ne <= 4096;
     if (!gen && !L.kouter) launch_phase_table(prec, nk, p->kfrac, ne, s->Re, nullptr, bf ? L.kpad : ne, L.phi_k, st);
     const void* gsrc = s->gR;
     if (prec != Prec::F64) {
