@@ -146,6 +146,12 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
         const Stage<T, BM, BN, BK>& st = stages[NS == 2 ? (it & 1) : 0];
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
+            // the K tail in float32: sub-steps that start at or beyond K would
+            // only add zero rows (279 R vectors: 2 of the last step's 4 run;
+            // FP32 fused launch 287 -> 284 ms).  The float64 loop is left
+            // without the test, which stops the compiler from reading the next
+            // sub-step's operands under the current MFMAs there (255 -> 351 ms).
+            if (sizeof(T) == 4 && BK > 8 && k0 + kk >= K) break;
             const int kr = kk + (lane >> 4);
             T ar[RB], ai[RB], as[RB];
 #pragma unroll
