@@ -363,8 +363,9 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     }
     if (s->polar) L.polar_L = A.take(16 * (size_t)L.Q * nm);
     L.tiles_m = (nk + fused_tile_rows(L.nbp, L.prec) - 1) / fused_tile_rows(L.nbp, L.prec);
-    if (out == Out::IMSIGMA || out == Out::RESIGMA) L.part = (double*)A.take(8 * (size_t)L.S * nk * nb);
-    if (out == Out::RESIGMA) L.part2 = (double*)A.take(8 * (size_t)L.S * nk * nb);
+    // two slots per slice: the slice's own and its tail's (helper blocks)
+    if (out == Out::IMSIGMA || out == Out::RESIGMA) L.part = (double*)A.take(16 * (size_t)L.S * nk * nb);
+    if (out == Out::RESIGMA) L.part2 = (double*)A.take(16 * (size_t)L.S * nk * nb);
     if (omg) {
         L.nw = nw;
         // two records of padding: the frequency kernel reads two records ahead
@@ -625,6 +626,7 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.part = L.part;
         // (pole mode: the slices only spread the column tiles over blocks)
         a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp, prec), SLICE_CUS, prec);
+        fused_balance(a, prec, SLICE_CUS);
         a.gkq = gkq;
         a.part_ph = phon ? L.part_ph : nullptr;
         a.vel = trans ? L.vel : nullptr;
@@ -657,10 +659,12 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         } else if (re) {
             // Eq. (3) carries no pi: the BZ mean only
             const int acc = (c > 0 || par->accumulate) ? 1 : 0;
-            launch_reduce_partials(nk, nb, a.S, L.part, 1.0 / nqn, acc, imsig, st);
-            if (re_tilde) launch_reduce_partials_diff(nk, nb, a.S, L.part, L.part2, 1.0 / nqn, acc, re_tilde, st);
+            launch_reduce_partials(nk, nb, fused_part_slots(a), L.part, 1.0 / nqn, acc, imsig, st);
+            if (re_tilde)
+                launch_reduce_partials_diff(nk, nb, fused_part_slots(a), L.part, L.part2, 1.0 / nqn, acc, re_tilde, st);
         } else if (!gkq) {
-            launch_reduce_partials(nk, nb, a.S, L.part, scale, (c > 0 || par->accumulate) ? 1 : 0, imsig, st);
+            launch_reduce_partials(nk, nb, fused_part_slots(a), L.part, scale, (c > 0 || par->accumulate) ? 1 : 0,
+                                   imsig, st);
         }
     }
     if (omg) {
@@ -945,6 +949,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             a.mu = par->mu;
             a.part = nullptr;
             a.S = fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp, prec), SLICE_CUS, prec);
+            fused_balance(a, prec, SLICE_CUS);
             a.gkq = nullptr;
             a.part_ph = nullptr;
             a.part2 = nullptr;

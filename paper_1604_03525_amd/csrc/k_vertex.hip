@@ -481,491 +481,514 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     const int bid = blockIdx.x;
     const int per = G / 8;
     const int lin = (bid % 8) * per + bid / 8;
-    if (lin >= tiles_m * a.S) return;
-    const int s = lin % a.S;
-    const int mt = lin / a.S;
-    const int m0 = mt * BM;
+    const int R = tiles_m * a.S;                  // regular blocks: one per (row tile, slice)
+    if (lin >= R + a.helpers) return;
     const int NE = 2 * a.nmax + 1;
     if constexpr (GEN) {
-        for (int idx = threadIdx.x; idx < 3 * BM * NE; idx += 256) {
-            const int ax = idx / (BM * NE), rem = idx % (BM * NE);
-            const int row = rem / NE, j = rem % NE;
-            const int kr = m0 + row;
-            double x = kr < a.nk ? a.kfrac[3 * (size_t)kr + ax] * (double)(j - a.nmax) : 0.0;
-            x -= rint(x);
-            double sn, cs;
-            sincospi(2.0 * x, &sn, &cs);
-            Et[idx] = mk2((TE)cs, (TE)sn);
-        }
         // table offsets of each R_e, packed 8 bits per axis
         for (int r = threadIdx.x; r < a.ne; r += 256) {
             const int* rr = a.Re + 3 * r;
             Roff[r] = (rr[0] + a.nmax) | ((rr[1] + a.nmax) << 8) | ((rr[2] + a.nmax) << 16);
         }
-        __syncthreads();
     }
-    // phase of (local row m, R_e index kk), zero outside the valid range
-    auto phase = [&](int m, int kk) -> CE {
-        if (m0 + m >= a.nk || kk >= a.ne) return mk2(TE(0), TE(0));
-        const int off = Roff[kk];
-        const CE p0 = Et[(0 * BM + m) * NE + (off & 255)];
-        const CE p1 = Et[(1 * BM + m) * NE + ((off >> 8) & 255)];
-        const CE p2 = Et[(2 * BM + m) * NE + (off >> 16)];
-        return cmulx(cmulx(p0, p1), p2);
-    };
-
-    const int nb = a.nb, nm = a.nm;
-    const int tid = threadIdx.x;
-    const int r = tid / TPR, sub = tid % TPR;
-    const int k = m0 + r;
-    const long ncols = (long)a.qc * nm * NB2;
-    const double2* U = reinterpret_cast<const double2*>(a.U);
-    const bool active_row = k < a.nk;
-    // a Gaussian factor exp(-y^2) is exactly zero in TE beyond this y^2
-    const double ylim = sizeof(TE) == 8 ? 750.0 : 110.0;
-
-    // Items of one run are bands x0 .. x0 + RUN - 1 of one band block, with
-    // x0 = (sub*JI) % NBP the same for every run of the thread.
-    const int x0 = (sub * JI) % NBP;
-    // U_k columns x0 .. x0 + RUN - 1 (phase 1), in TE
-    auto load_uk = [&](CE (&uk)[RUN][NBP]) {
-#pragma unroll
-        for (int t = 0; t < RUN; ++t)
-#pragma unroll
-            for (int jj = 0; jj < NBP; ++jj) {
-                const int n = x0 + t;
-                const double2 u = (active_row && n < nb && jj < nb) ? U[((size_t)k * nb + jj) * nb + n]
-                                                                    : make_double2(0.0, 0.0);
-                uk[t][jj] = mk2((TE)u.x, (TE)u.y);
+    // Segments.  A regular block (lin < R) runs the first `keep` column tiles
+    // of slice s of row tile mt and writes its partial sums to slot s; helper
+    // h = lin - R runs the remaining tiles of the slices of regular blocks
+    // [h R / H, (h + 1) R / H) in turn and writes theirs to slot S + s.  When
+    // the regular blocks leave some of the two slots per CU empty, the helpers
+    // fill them and `keep` evens out the work of the two kinds of block.
+    // Only the instantiations in BAL take helpers (fused_balance): in the
+    // float64 and split-bf16 ones below 16 bands the segment state cost more
+    // registers than the balance saved (fcc 20^3: FP64 254 -> 269 ms per
+    // launch, split-BF16 219 -> 237), elsewhere it gained 3-9 %.
+    constexpr bool BAL = fused_balanced_c(NBP, MODE);
+    const bool helper = BAL && lin >= R;
+    const int rb0 = helper ? (int)((long)(lin - R) * R / a.helpers) : lin;
+    const int rb1 = helper ? (int)((long)(lin - R + 1) * R / a.helpers) : lin + 1;
+    for (int rb = rb0; rb < rb1; ++rb) {
+        if (rb > rb0) __syncthreads();                // the previous segment is done with LDS
+        const int s = rb % a.S;
+        const int mt = rb / a.S;
+        const int slot = helper ? a.S + s : s;
+        const int j0 = helper ? a.keep : 0;
+        const int j1 = BAL ? (helper ? 0x7fffffff : a.keep) : 0x7fffffff;
+        const int m0 = mt * BM;
+        if constexpr (GEN) {
+            for (int idx = threadIdx.x; idx < 3 * BM * NE; idx += 256) {
+                const int ax = idx / (BM * NE), rem = idx % (BM * NE);
+                const int row = rem / NE, j = rem % NE;
+                const int kr = m0 + row;
+                double x = kr < a.nk ? a.kfrac[3 * (size_t)kr + ax] * (double)(j - a.nmax) : 0.0;
+                x -= rint(x);
+                double sn, cs;
+                sincospi(2.0 * x, &sn, &cs);
+                Et[idx] = mk2((TE)cs, (TE)sn);
             }
-    };
-    // Per-row state kept over the block's tiles: the Im Sigma accumulators of
-    // the row's bands and, in the float32 modes, eps_nk and the U_k columns
-    // (the float64 mode reloads those per tile to stay within its registers).
-    constexpr bool HOIST = (MODE == 1 && NBP < 16) || (MODE == 2 && RUN * NBP <= 16);
-    double acc[NBP], acc2[RE ? NBP : 1];
-    double eps_h[HOIST ? NBP : 1];
-    CE uk_h[HOIST ? RUN : 1][NBP];
-#pragma unroll
-    for (int n = 0; n < NBP; ++n) acc[n] = 0.0;
-    if constexpr (RE) {
-#pragma unroll
-        for (int n = 0; n < NBP; ++n) acc2[n] = 0.0;
-    }
-    if constexpr (HOIST) {
-#pragma unroll
-        for (int n = 0; n < NBP; ++n) eps_h[n] = (active_row && n < nb) ? a.eps[(size_t)k * nb + n] : 0.0;
-        load_uk(uk_h);
-    }
-    const double inv_sig = 1.0 / a.sigma;
+            __syncthreads();
+        }
+        // phase of (local row m, R_e index kk), zero outside the valid range
+        auto phase = [&](int m, int kk) -> CE {
+            if (m0 + m >= a.nk || kk >= a.ne) return mk2(TE(0), TE(0));
+            const int off = Roff[kk];
+            const CE p0 = Et[(0 * BM + m) * NE + (off & 255)];
+            const CE p1 = Et[(1 * BM + m) * NE + ((off >> 8) & 255)];
+            const CE p2 = Et[(2 * BM + m) * NE + (off >> 16)];
+            return cmulx(cmulx(p0, p1), p2);
+        };
 
-    for (int nt = s; nt < tiles_n; nt += a.S) {
-        const long n0 = (long)nt * BN;
-        // The main loop runs at raised wave priority and the epilogue at the
-        // normal one: where one resident block is in its main loop and the
-        // other in its epilogue, the SIMD's arbiter then keeps the MFMA stream
-        // fed first and fills the gaps with the epilogue (FP64 170 -> 163 ms per
-        // 1260-q launch, FP32 -2 %, split-BF16 -2 %).
-        __builtin_amdgcn_s_setprio(1);
-        if constexpr (MODE == 2) {
-            constexpr int RB = BfWaves<BM, BN>::RB;
-            f4 cr[4 * RB], ci[4 * RB];
-            const uint16_t* Ap = reinterpret_cast<const uint16_t*>(a.phi_k);
-            const uint16_t* Bp = reinterpret_cast<const uint16_t*>(a.B);
-            auto agen = [&](int m, int kk) -> float2 { return phase(m, kk); };
-            bf16_mainloop<BM, BN, GEN>(*reinterpret_cast<Sb*>(smem), Ap, a.ldk, (long)a.nk * a.ldk, a.nk, m0, Bp,
-                                       a.ldk_b, ncols * a.ldk_b, ncols, n0, a.kpad, agen, cr, ci);
-            const int lane = tid & 63, wave = tid >> 6;
-            constexpr int WN = BN / 64;
-            const int wm = wave / WN, wn = wave % WN;
-            for (int q = 0; q < RB; ++q)
-                for (int c = 0; c < 4; ++c)
-                    for (int i = 0; i < 4; ++i) {
-                        const int row = wm * 16 * RB + q * 16 + 4 * (lane >> 4) + i;
-                        const int col = wn * 64 + c * 16 + (lane & 15);
-                        Cs[row * LDC + col] = make_float2(cr[q * 4 + c][i], ci[q * 4 + c][i]);
-                    }
-        } else {
-            const CT* phi = reinterpret_cast<const CT*>(a.phi_k);
-            const CT* Bm = reinterpret_cast<const CT*>(a.B);
-            auto afetch = [&](int m, int kk) -> CT {
-                if constexpr (GEN) {
-                    return phase(m, kk);
-                } else {
-                    const int row = m0 + m;
-                    if (row < a.nk && kk < a.ne) return phi[(size_t)row * a.ldk + kk];
-                    return cz<T>();
+        const int nb = a.nb, nm = a.nm;
+        const int tid = threadIdx.x;
+        const int r = tid / TPR, sub = tid % TPR;
+        const int k = m0 + r;
+        const long ncols = (long)a.qc * nm * NB2;
+        const double2* U = reinterpret_cast<const double2*>(a.U);
+        const bool active_row = k < a.nk;
+        // a Gaussian factor exp(-y^2) is exactly zero in TE beyond this y^2
+        const double ylim = sizeof(TE) == 8 ? 750.0 : 110.0;
+
+        // Items of one run are bands x0 .. x0 + RUN - 1 of one band block, with
+        // x0 = (sub*JI) % NBP the same for every run of the thread.
+        const int x0 = (sub * JI) % NBP;
+        // U_k columns x0 .. x0 + RUN - 1 (phase 1), in TE
+        auto load_uk = [&](CE (&uk)[RUN][NBP]) {
+#pragma unroll
+            for (int t = 0; t < RUN; ++t)
+#pragma unroll
+                for (int jj = 0; jj < NBP; ++jj) {
+                    const int n = x0 + t;
+                    const double2 u = (active_row && n < nb && jj < nb) ? U[((size_t)k * nb + jj) * nb + n]
+                                                                        : make_double2(0.0, 0.0);
+                    uk[t][jj] = mk2((TE)u.x, (TE)u.y);
                 }
-            };
-            auto bfetch = [&](int kk, int n) -> CT {
-                const long col = n0 + n;
-                if (kk < a.ne && col < ncols) return Bm[(size_t)kk * ncols + col];
-                return cz<T>();
-            };
-            constexpr int RB = CWaves<BM, BN>::RB;
-            typename Cx<T>::acc cr[4 * RB], ci[4 * RB];
-            cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), false, NS>(
-                reinterpret_cast<St*>(smem), a.ne, afetch, bfetch, cr, ci);
-            const int lane = tid & 63, wave = tid >> 6;
-            constexpr int WN = BN / 64;
-            const int wm = wave / WN, wn = wave % WN;
-            if constexpr (WSTORE) {
-                // the Wannier-basis tile itself, straight to memory (the main
-                // loop's last barrier has released the LDS stage)
-                CT* G = reinterpret_cast<CT*>(a.gout);
+        };
+        // Per-row state kept over the block's tiles: the Im Sigma accumulators of
+        // the row's bands and, in the float32 modes, eps_nk and the U_k columns
+        // (the float64 mode reloads those per tile to stay within its registers).
+        constexpr bool HOIST = (MODE == 1 && NBP < 16) || (MODE == 2 && RUN * NBP <= 16);
+        double acc[NBP], acc2[RE ? NBP : 1];
+        double eps_h[HOIST ? NBP : 1];
+        CE uk_h[HOIST ? RUN : 1][NBP];
+#pragma unroll
+        for (int n = 0; n < NBP; ++n) acc[n] = 0.0;
+        if constexpr (RE) {
+#pragma unroll
+            for (int n = 0; n < NBP; ++n) acc2[n] = 0.0;
+        }
+        if constexpr (HOIST) {
+#pragma unroll
+            for (int n = 0; n < NBP; ++n) eps_h[n] = (active_row && n < nb) ? a.eps[(size_t)k * nb + n] : 0.0;
+            load_uk(uk_h);
+        }
+        const double inv_sig = 1.0 / a.sigma;
+
+        for (int j = j0, nt = s + j0 * a.S; j < j1 && nt < tiles_n; ++j, nt += a.S) {
+            const long n0 = (long)nt * BN;
+            // The main loop runs at raised wave priority and the epilogue at the
+            // normal one: where one resident block is in its main loop and the
+            // other in its epilogue, the SIMD's arbiter then keeps the MFMA stream
+            // fed first and fills the gaps with the epilogue (FP64 170 -> 163 ms per
+            // 1260-q launch, FP32 -2 %, split-BF16 -2 %).
+            __builtin_amdgcn_s_setprio(1);
+            if constexpr (MODE == 2) {
+                constexpr int RB = BfWaves<BM, BN>::RB;
+                f4 cr[4 * RB], ci[4 * RB];
+                const uint16_t* Ap = reinterpret_cast<const uint16_t*>(a.phi_k);
+                const uint16_t* Bp = reinterpret_cast<const uint16_t*>(a.B);
+                auto agen = [&](int m, int kk) -> float2 { return phase(m, kk); };
+                bf16_mainloop<BM, BN, GEN>(*reinterpret_cast<Sb*>(smem), Ap, a.ldk, (long)a.nk * a.ldk, a.nk, m0, Bp,
+                                           a.ldk_b, ncols * a.ldk_b, ncols, n0, a.kpad, agen, cr, ci);
+                const int lane = tid & 63, wave = tid >> 6;
+                constexpr int WN = BN / 64;
+                const int wm = wave / WN, wn = wave % WN;
                 for (int q = 0; q < RB; ++q)
-                    for (int c = 0; c < 4; ++c) {
-                        const long col = n0 + wn * 64 + c * 16 + (lane & 15);
+                    for (int c = 0; c < 4; ++c)
                         for (int i = 0; i < 4; ++i) {
-                            const int row = m0 + wm * 16 * RB + q * 16 + crow<T>(lane, i);
-                            if (row >= a.nk || col >= ncols) continue;
+                            const int row = wm * 16 * RB + q * 16 + 4 * (lane >> 4) + i;
+                            const int col = wn * 64 + c * 16 + (lane & 15);
+                            Cs[row * LDC + col] = make_float2(cr[q * 4 + c][i], ci[q * 4 + c][i]);
+                        }
+            } else {
+                const CT* phi = reinterpret_cast<const CT*>(a.phi_k);
+                const CT* Bm = reinterpret_cast<const CT*>(a.B);
+                auto afetch = [&](int m, int kk) -> CT {
+                    if constexpr (GEN) {
+                        return phase(m, kk);
+                    } else {
+                        const int row = m0 + m;
+                        if (row < a.nk && kk < a.ne) return phi[(size_t)row * a.ldk + kk];
+                        return cz<T>();
+                    }
+                };
+                auto bfetch = [&](int kk, int n) -> CT {
+                    const long col = n0 + n;
+                    if (kk < a.ne && col < ncols) return Bm[(size_t)kk * ncols + col];
+                    return cz<T>();
+                };
+                constexpr int RB = CWaves<BM, BN>::RB;
+                typename Cx<T>::acc cr[4 * RB], ci[4 * RB];
+                cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), false, NS>(
+                    reinterpret_cast<St*>(smem), a.ne, afetch, bfetch, cr, ci);
+                const int lane = tid & 63, wave = tid >> 6;
+                constexpr int WN = BN / 64;
+                const int wm = wave / WN, wn = wave % WN;
+                if constexpr (WSTORE) {
+                    // the Wannier-basis tile itself, straight to memory (the main
+                    // loop's last barrier has released the LDS stage)
+                    CT* G = reinterpret_cast<CT*>(a.gout);
+                    for (int q = 0; q < RB; ++q)
+                        for (int c = 0; c < 4; ++c) {
+                            const long col = n0 + wn * 64 + c * 16 + (lane & 15);
+                            for (int i = 0; i < 4; ++i) {
+                                const int row = m0 + wm * 16 * RB + q * 16 + crow<T>(lane, i);
+                                if (row >= a.nk || col >= ncols) continue;
+                                CT v;
+                                v.x = cr[q * 4 + c][i];
+                                v.y = ci[q * 4 + c][i];
+                                G[(size_t)row * ncols + col] = v;
+                            }
+                        }
+                    __builtin_amdgcn_s_setprio(0);
+                    continue;
+                }
+                for (int q = 0; q < RB; ++q)
+                    for (int c = 0; c < 4; ++c)
+                        for (int i = 0; i < 4; ++i) {
+                            const int row = wm * 16 * RB + q * 16 + crow<T>(lane, i);
+                            const int col = wn * 64 + c * 16 + (lane & 15);
                             CT v;
                             v.x = cr[q * 4 + c][i];
                             v.y = ci[q * 4 + c][i];
-                            G[(size_t)row * ncols + col] = v;
+                            Cs[row * LDC + col] = v;
                         }
-                    }
-                __builtin_amdgcn_s_setprio(0);
-                continue;
             }
-            for (int q = 0; q < RB; ++q)
-                for (int c = 0; c < 4; ++c)
-                    for (int i = 0; i < 4; ++i) {
-                        const int row = wm * 16 * RB + q * 16 + crow<T>(lane, i);
-                        const int col = wn * 64 + c * 16 + (lane & 15);
-                        CT v;
-                        v.x = cr[q * 4 + c][i];
-                        v.y = ci[q * 4 + c][i];
-                        Cs[row * LDC + col] = v;
-                    }
-        }
-        __builtin_amdgcn_s_setprio(0);
-        __syncthreads();
-        // The band loops of both phases stop at nb for up to 8 padded bands; at
-        // 16 they run over the zero padding (G, U_k and the k+q columns are
-        // zero there), so they unroll completely and their arrays stay in
-        // registers instead of scratch.
-        // phase 1: V = G U_k for the thread's items (b, n), all rows i of V,
-        // written over G in LDS.  With JI >= NBP a thread owns whole band
-        // blocks; otherwise the TPR threads of a row share the single block
-        // and wait for each other between reading G and writing V.
-        {
-            CE uk[RUN][NBP];
-            if constexpr (HOIST) {
+            __builtin_amdgcn_s_setprio(0);
+            __syncthreads();
+            // The band loops of both phases stop at nb for up to 8 padded bands; at
+            // 16 they run over the zero padding (G, U_k and the k+q columns are
+            // zero there), so they unroll completely and their arrays stay in
+            // registers instead of scratch.
+            // phase 1: V = G U_k for the thread's items (b, n), all rows i of V,
+            // written over G in LDS.  With JI >= NBP a thread owns whole band
+            // blocks; otherwise the TPR threads of a row share the single block
+            // and wait for each other between reading G and writing V.
+            {
+                CE uk[RUN][NBP];
+                if constexpr (HOIST) {
 #pragma unroll
-                for (int t = 0; t < RUN; ++t)
+                    for (int t = 0; t < RUN; ++t)
 #pragma unroll
-                    for (int jj = 0; jj < NBP; ++jj) uk[t][jj] = uk_h[t][jj];
-            } else {
-                load_uk(uk);
-            }
-#pragma unroll
-            for (int rr = 0; rr < NRUN; ++rr) {
-                const int b = (sub * JI + rr * RUN) / NBP;
-                CT* Gt = Cs + r * LDC + b * NB2;
-                CE v[RUN][NBP];
-#pragma unroll
-                for (int t = 0; t < RUN; ++t)
-#pragma unroll
-                    for (int i = 0; i < NBP; ++i) v[t][i] = mk2(TE(0), TE(0));
-                if (active_row) {
-#pragma unroll
-                    for (int i = 0; i < NBP; ++i) {
-                        if (NBP < 16 && i >= nb) break;
-#pragma unroll
-                        for (int jj = 0; jj < NBP; ++jj) {
-                            if (NBP < 16 && jj >= nb) break;
-                            const CT g = Gt[i * NBP + jj];
-                            const TE gx = (TE)g.x, gy = (TE)g.y;
-#pragma unroll
-                            for (int t = 0; t < RUN; ++t) {
-                                const CE u = uk[t][jj];
-                                v[t][i].x += gx * u.x - gy * u.y;
-                                v[t][i].y += gx * u.y + gy * u.x;
-                            }
-                        }
-                    }
-                }
-                if constexpr (JI < NBP) __syncthreads();   // all of G has been read
-                if (active_row) {
-#pragma unroll
-                    for (int t = 0; t < RUN; ++t) {
-                        const int n = x0 + t;
-                        if (n >= nb) break;
-#pragma unroll
-                        for (int i = 0; i < NBP; ++i) {
-                            if (NBP < 16 && i >= nb) break;
-                            CT o;
-                            o.x = (T)v[t][i].x;
-                            o.y = (T)v[t][i].y;
-                            Gt[i * NBP + n] = o;
-                        }
-                    }
-                }
-            }
-            if constexpr (JI < NBP) __syncthreads();
-        }
-        // phase 2: g_mn = sum_i conj(U_k+q[i][m]) V[i][n] for the thread's
-        // items (b, m), all n; weights and |g|^2 accumulated per n (Im Sigma)
-        // or per run (phonon sums)
-        double pp[NRUN], pl[NRUN], pt[TR ? NRUN : 1];
-#pragma unroll
-        for (int rr = 0; rr < NRUN; ++rr) {
-            pp[rr] = 0.0;
-            pl[rr] = 0.0;
-            if constexpr (TR) pt[rr] = 0.0;
-        }
-        if (active_row) {
-#pragma unroll
-            for (int rr = 0; rr < NRUN; ++rr) {
-                const int b = (sub * JI + rr * RUN) / NBP;
-                if (x0 >= nb) continue;
-                const long gblk = n0 / NB2 + b;            // (q_local, nu)
-                const int ql = (int)(gblk / nm), nu = (int)(gblk % nm);
-                if (ql >= a.qc) continue;
-                const double scv = a.sc[(size_t)ql * nm + nu];
-                if (scv == 0.0 && !STORE && !POLE) continue;
-                const int q = a.q0 + ql;
-                // states at k+q: a member of the k set (grid runs) or per pair
-                const double2* Uq;
-                const double* eq;
-                const double* fq;
-                const double* vq = nullptr;   // velocities at k+q (transport mode, grid runs)
-                if (a.kq) {
-                    const int kq = a.kq[(size_t)k * a.nq_total + q];
-                    if ((unsigned)kq >= (unsigned)a.nk) {           // invalid map entry: no access
-                        if constexpr (POLE) {
-                            for (int t = 0; t < RUN; ++t) {
-                                if (x0 + t >= nb) break;
-                                double* rec = a.rec + ((((size_t)k * a.qc + ql) * nm + nu) * nb + x0 + t) * (4 + NBP);
-                                for (int j = 0; j < 4 + NBP; ++j) rec[j] = 0.0;
-                            }
-                        }
-                        continue;
-                    }
-                    Uq = U + (size_t)kq * nb * nb;
-                    eq = a.eps + (size_t)kq * nb;
-                    fq = a.ftab + (size_t)kq * nb;
-                    if constexpr (TR) vq = a.vel + (size_t)kq * nb * 3;
+                        for (int jj = 0; jj < NBP; ++jj) uk[t][jj] = uk_h[t][jj];
                 } else {
-                    const size_t pr = (size_t)k * a.qc + ql;
-                    Uq = reinterpret_cast<const double2*>(a.U_pair) + pr * nb * nb;
-                    eq = a.eps_pair + pr * nb;
-                    fq = a.f_pair + pr * nb;
-                    if constexpr (TR) vq = a.vel_pair + pr * nb * 3;
+                    load_uk(uk);
                 }
-                const double w = a.omega[(size_t)ql * nm + nu];
-                const double nB = a.nbose[(size_t)ql * nm + nu];
-                // the run's bands in groups of RT: split-bf16 takes one band at a time so
-                // its k+q eigenvector column and sums fit beside the wider main loop's state
-#pragma unroll 1
-                for (int tb = 0; tb < RUN; tb += RT) {
-                    CE uq[RT][NBP];
-                    double em[RT], fm[RT], dm[RT];
-                    double vm[TR ? RT : 1][3];
-                    bool mv[RT];
-#pragma unroll
-                    for (int t = 0; t < RT; ++t) {
-                        const int m = x0 + tb + t;
-                        mv[t] = m < nb;
-                        em[t] = mv[t] ? eq[m] : 0.0;
-                        fm[t] = mv[t] ? fq[m] : 0.0;
-                        if constexpr (PH) {
-                            const double ym = (em[t] - a.mu) * inv_sig;
-                            dm[t] = mv[t] ? exp(-ym * ym) : 0.0;
-                        }
-                        if constexpr (TR) {
-                            for (int c = 0; c < 3; ++c) vm[t][c] = mv[t] ? vq[3 * m + c] : 0.0;
-                        }
-#pragma unroll
-                        for (int i = 0; i < NBP; ++i) {
-                            const double2 u = (mv[t] && i < nb) ? Uq[i * nb + m] : make_double2(0.0, 0.0);
-                            uq[t][i] = mk2((TE)u.x, (TE)u.y);
-                        }
-                    }
-                    const CT* Vt = Cs + r * LDC + b * NB2;
-#pragma unroll
-                    for (int n = 0; n < NBP; ++n) {
-                        if (n >= nb) break;
-                        double epsn;
-                        if constexpr (HOIST) epsn = eps_h[n]; else epsn = a.eps[(size_t)k * nb + n];
-                        TE W[RT], WL[RT], WT[TR ? RT : 1];
-                        bool need = STORE || POLE;
-                        if constexpr (PH) {
-                            // Eq. (9): [f_nk - f_m,k+q] exp(-((eps_nk - eps_m,k+q - omega)/sigma)^2);
-                            // Eq. (11): exp(-((eps_nk - mu)/sigma)^2) exp(-((eps_m,k+q - mu)/sigma)^2)
-                            const double fn = a.ftab[(size_t)k * nb + n];
-                            const double yn = (epsn - a.mu) * inv_sig;
-                            const double dn = exp(-yn * yn);
-                            // Eq. (55): 1 - v_nk . v_m,k+q / |v_nk|^2, 1 at a zero velocity
-                            double vn[3] = {0.0, 0.0, 0.0}, inv_vv = 0.0;
-                            if constexpr (TR) {
-                                for (int c = 0; c < 3; ++c) vn[c] = a.vel[((size_t)k * nb + n) * 3 + c];
-                                const double vv = vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2];
-                                inv_vv = vv > 1e-18 ? 1.0 / vv : 0.0;
-                            }
-#pragma unroll
-                            for (int t = 0; t < RT; ++t) {
-                                W[t] = TE(0);
-                                WL[t] = TE(0);
-                                if constexpr (TR) WT[t] = TE(0);
-                                if (!mv[t]) continue;
-                                const double y = (epsn - em[t] - w) * inv_sig;
-                                const double s1 = y * y;
-                                if (s1 < ylim) W[t] = (TE)(fn - fm[t]) * fexp((TE)(-s1));
-                                WL[t] = (TE)(dn * dm[t]);
-                                if constexpr (TR) {
-                                    const double fac = inv_vv > 0.0
-                                        ? 1.0 - (vn[0] * vm[t][0] + vn[1] * vm[t][1] + vn[2] * vm[t][2]) * inv_vv
-                                        : 1.0;
-                                    WT[t] = (TE)(dn * dm[t] * fac);
-                                }
-                                need = need || (s1 < ylim) || (WL[t] != TE(0));
-                            }
-                        } else if constexpr (RE) {
-                            // Eq. (3), Re 1/(x + i delta) = x/(x^2 + delta^2), delta = sigma:
-                            // on shell x = eps_nk - eps_m,k+q +- omega; at eps_F x = mu - eps_m,k+q +- omega
-                            const double d2 = a.sigma * a.sigma;
-                            need = true;
-#pragma unroll
-                            for (int t = 0; t < RT; ++t) {
-                                W[t] = TE(0);
-                                WL[t] = TE(0);
-                                if (!mv[t]) continue;
-                                const double A1 = nB + fm[t], A2 = nB + 1.0 - fm[t];
-                                const double x1 = epsn - em[t] + w, x2 = epsn - em[t] - w;
-                                const double y1 = a.mu - em[t] + w, y2 = a.mu - em[t] - w;
-                                W[t] = (TE)(A1 * x1 / (x1 * x1 + d2) + A2 * x2 / (x2 * x2 + d2));
-                                WL[t] = (TE)(A1 * y1 / (y1 * y1 + d2) + A2 * y2 / (y2 * y2 + d2));
-                            }
-                        } else {
-#pragma unroll
-                            for (int t = 0; t < RT; ++t) {
-                                W[t] = TE(0);
-                                WL[t] = TE(0);
-                                if (STORE || POLE || !mv[t]) continue;
-                                const double x = epsn - em[t];
-                                const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
-                                const double s1 = y1 * y1, s2 = y2 * y2;
-                                if (s1 < ylim) W[t] += (TE)(nB + fm[t]) * fexp((TE)(-s1));
-                                if (s2 < ylim) W[t] += (TE)(nB + 1.0 - fm[t]) * fexp((TE)(-s2));
-                                need = need || (s1 < ylim) || (s2 < ylim);
-                            }
-                        }
-                        if (!need) continue;
-                        TE gr[RT], gi[RT];
-#pragma unroll
-                        for (int t = 0; t < RT; ++t) {
-                            gr[t] = TE(0);
-                            gi[t] = TE(0);
-                        }
-#pragma unroll
-                        for (int i = 0; i < NBP; ++i) {
-                            if (NBP < 16 && i >= nb) break;
-                            const CT vv = Vt[i * NBP + n];
-                            const TE vx = (TE)vv.x, vy = (TE)vv.y;
-#pragma unroll
-                            for (int t = 0; t < RT; ++t) {
-                                // conj(u) * v
-                                gr[t] += uq[t][i].x * vx + uq[t][i].y * vy;
-                                gi[t] += uq[t][i].x * vy - uq[t][i].y * vx;
-                            }
-                        }
-#pragma unroll
-                        for (int t = 0; t < RT; ++t) {
-                            if (!mv[t]) continue;
-                            if (STORE) {
-                                reinterpret_cast<double2*>(a.gkq)
-                                    [((((size_t)k * a.nq_total + q) * nm + nu) * nb + x0 + tb + t) * nb + n] =
-                                    make_double2((double)gr[t], (double)gi[t]);
-                            } else if (PH) {
-                                const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
-                                pp[rr] += (double)(g2 * W[t]);
-                                pl[rr] += (double)(g2 * WL[t]);
-                                if constexpr (TR) pt[rr] += (double)(g2 * WT[TR ? t : 0]);
-                            } else if (RE) {
-                                const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
-                                acc[n] += (double)(g2 * W[t]);
-                                acc2[n] += (double)(g2 * WL[t]);
-                            } else if (POLE) {
-                                double* rec = a.rec + ((((size_t)k * a.qc + ql) * nm + nu) * nb + x0 + tb + t) * (4 + NBP);
-                                rec[4 + n] = (double)(gr[t] * gr[t] + gi[t] * gi[t]);
-                                if (n == 0) {
-                                    const double xi = em[t] - a.mu;
-                                    const bool kept = scv != 0.0;
-                                    rec[0] = xi - w;
-                                    rec[1] = xi + w;
-                                    rec[2] = kept ? nB + fm[t] : 0.0;
-                                    rec[3] = kept ? nB + 1.0 - fm[t] : 0.0;
-                                    for (int j = nb; j < NBP; ++j) rec[4 + j] = 0.0;   // padded bands
-                                }
-                            } else {
-                                acc[n] += (double)((gr[t] * gr[t] + gi[t] * gi[t]) * W[t]);
-                            }
-                        }
-                        // keep the scheduler from overlapping band iterations (register pressure)
-                        __builtin_amdgcn_sched_barrier(0);
-                    }
-                }
-            }
-        }
-        if constexpr (PH) {
-            // fixed-order sums over the tile's k rows, per band block (q, nu):
-            // slot (b, r, j) holds run j of row r; rows are summed after the
-            // slots of each row, for Eq. (9) and then Eq. (11)
-            constexpr int NBLK = BN / NB2;
-            constexpr int SPB = NBP / RUN;                  // runs per band block and row
-            static_assert(SBYTES >= sizeof(double) * NBLK * BM * SPB, "phonon reduction buffer");
-            double* red = reinterpret_cast<double*>(smem);
-            const int jslot = x0 / RUN;
-            const size_t ncb = (size_t)a.qc * nm;
-#pragma unroll
-            for (int kind = 0; kind < (TR ? 3 : 2); ++kind) {
-                __syncthreads();                            // V, or the previous pass, no longer read
 #pragma unroll
                 for (int rr = 0; rr < NRUN; ++rr) {
                     const int b = (sub * JI + rr * RUN) / NBP;
-                    double val = kind == 0 ? pp[rr] : pl[rr];
-                    if constexpr (TR) val = kind == 2 ? pt[rr] : val;
-                    red[((size_t)b * BM + r) * SPB + jslot] = val;
+                    CT* Gt = Cs + r * LDC + b * NB2;
+                    CE v[RUN][NBP];
+#pragma unroll
+                    for (int t = 0; t < RUN; ++t)
+#pragma unroll
+                        for (int i = 0; i < NBP; ++i) v[t][i] = mk2(TE(0), TE(0));
+                    if (active_row) {
+#pragma unroll
+                        for (int i = 0; i < NBP; ++i) {
+                            if (NBP < 16 && i >= nb) break;
+#pragma unroll
+                            for (int jj = 0; jj < NBP; ++jj) {
+                                if (NBP < 16 && jj >= nb) break;
+                                const CT g = Gt[i * NBP + jj];
+                                const TE gx = (TE)g.x, gy = (TE)g.y;
+#pragma unroll
+                                for (int t = 0; t < RUN; ++t) {
+                                    const CE u = uk[t][jj];
+                                    v[t][i].x += gx * u.x - gy * u.y;
+                                    v[t][i].y += gx * u.y + gy * u.x;
+                                }
+                            }
+                        }
+                    }
+                    if constexpr (JI < NBP) __syncthreads();   // all of G has been read
+                    if (active_row) {
+#pragma unroll
+                        for (int t = 0; t < RUN; ++t) {
+                            const int n = x0 + t;
+                            if (n >= nb) break;
+#pragma unroll
+                            for (int i = 0; i < NBP; ++i) {
+                                if (NBP < 16 && i >= nb) break;
+                                CT o;
+                                o.x = (T)v[t][i].x;
+                                o.y = (T)v[t][i].y;
+                                Gt[i * NBP + n] = o;
+                            }
+                        }
+                    }
                 }
-                __syncthreads();
-                for (int t = tid; t < NBLK * BM; t += 256) {
-                    double v = 0.0;
-                    for (int j = 0; j < SPB; ++j) v += red[(size_t)t * SPB + j];
-                    red[(size_t)t * SPB] = v;
+                if constexpr (JI < NBP) __syncthreads();
+            }
+            // phase 2: g_mn = sum_i conj(U_k+q[i][m]) V[i][n] for the thread's
+            // items (b, m), all n; weights and |g|^2 accumulated per n (Im Sigma)
+            // or per run (phonon sums)
+            double pp[NRUN], pl[NRUN], pt[TR ? NRUN : 1];
+#pragma unroll
+            for (int rr = 0; rr < NRUN; ++rr) {
+                pp[rr] = 0.0;
+                pl[rr] = 0.0;
+                if constexpr (TR) pt[rr] = 0.0;
+            }
+            if (active_row) {
+#pragma unroll
+                for (int rr = 0; rr < NRUN; ++rr) {
+                    const int b = (sub * JI + rr * RUN) / NBP;
+                    if (x0 >= nb) continue;
+                    const long gblk = n0 / NB2 + b;            // (q_local, nu)
+                    const int ql = (int)(gblk / nm), nu = (int)(gblk % nm);
+                    if (ql >= a.qc) continue;
+                    const double scv = a.sc[(size_t)ql * nm + nu];
+                    if (scv == 0.0 && !STORE && !POLE) continue;
+                    const int q = a.q0 + ql;
+                    // states at k+q: a member of the k set (grid runs) or per pair
+                    const double2* Uq;
+                    const double* eq;
+                    const double* fq;
+                    const double* vq = nullptr;   // velocities at k+q (transport mode, grid runs)
+                    if (a.kq) {
+                        const int kq = a.kq[(size_t)k * a.nq_total + q];
+                        if ((unsigned)kq >= (unsigned)a.nk) {           // invalid map entry: no access
+                            if constexpr (POLE) {
+                                for (int t = 0; t < RUN; ++t) {
+                                    if (x0 + t >= nb) break;
+                                    double* rec = a.rec + ((((size_t)k * a.qc + ql) * nm + nu) * nb + x0 + t) * (4 + NBP);
+                                    for (int j = 0; j < 4 + NBP; ++j) rec[j] = 0.0;
+                                }
+                            }
+                            continue;
+                        }
+                        Uq = U + (size_t)kq * nb * nb;
+                        eq = a.eps + (size_t)kq * nb;
+                        fq = a.ftab + (size_t)kq * nb;
+                        if constexpr (TR) vq = a.vel + (size_t)kq * nb * 3;
+                    } else {
+                        const size_t pr = (size_t)k * a.qc + ql;
+                        Uq = reinterpret_cast<const double2*>(a.U_pair) + pr * nb * nb;
+                        eq = a.eps_pair + pr * nb;
+                        fq = a.f_pair + pr * nb;
+                        if constexpr (TR) vq = a.vel_pair + pr * nb * 3;
+                    }
+                    const double w = a.omega[(size_t)ql * nm + nu];
+                    const double nB = a.nbose[(size_t)ql * nm + nu];
+                    // the run's bands in groups of RT: split-bf16 takes one band at a time so
+                    // its k+q eigenvector column and sums fit beside the wider main loop's state
+#pragma unroll 1
+                    for (int tb = 0; tb < RUN; tb += RT) {
+                        CE uq[RT][NBP];
+                        double em[RT], fm[RT], dm[RT];
+                        double vm[TR ? RT : 1][3];
+                        bool mv[RT];
+#pragma unroll
+                        for (int t = 0; t < RT; ++t) {
+                            const int m = x0 + tb + t;
+                            mv[t] = m < nb;
+                            em[t] = mv[t] ? eq[m] : 0.0;
+                            fm[t] = mv[t] ? fq[m] : 0.0;
+                            if constexpr (PH) {
+                                const double ym = (em[t] - a.mu) * inv_sig;
+                                dm[t] = mv[t] ? exp(-ym * ym) : 0.0;
+                            }
+                            if constexpr (TR) {
+                                for (int c = 0; c < 3; ++c) vm[t][c] = mv[t] ? vq[3 * m + c] : 0.0;
+                            }
+#pragma unroll
+                            for (int i = 0; i < NBP; ++i) {
+                                const double2 u = (mv[t] && i < nb) ? Uq[i * nb + m] : make_double2(0.0, 0.0);
+                                uq[t][i] = mk2((TE)u.x, (TE)u.y);
+                            }
+                        }
+                        const CT* Vt = Cs + r * LDC + b * NB2;
+#pragma unroll
+                        for (int n = 0; n < NBP; ++n) {
+                            if (n >= nb) break;
+                            double epsn;
+                            if constexpr (HOIST) epsn = eps_h[n]; else epsn = a.eps[(size_t)k * nb + n];
+                            TE W[RT], WL[RT], WT[TR ? RT : 1];
+                            bool need = STORE || POLE;
+                            if constexpr (PH) {
+                                // Eq. (9): [f_nk - f_m,k+q] exp(-((eps_nk - eps_m,k+q - omega)/sigma)^2);
+                                // Eq. (11): exp(-((eps_nk - mu)/sigma)^2) exp(-((eps_m,k+q - mu)/sigma)^2)
+                                const double fn = a.ftab[(size_t)k * nb + n];
+                                const double yn = (epsn - a.mu) * inv_sig;
+                                const double dn = exp(-yn * yn);
+                                // Eq. (55): 1 - v_nk . v_m,k+q / |v_nk|^2, 1 at a zero velocity
+                                double vn[3] = {0.0, 0.0, 0.0}, inv_vv = 0.0;
+                                if constexpr (TR) {
+                                    for (int c = 0; c < 3; ++c) vn[c] = a.vel[((size_t)k * nb + n) * 3 + c];
+                                    const double vv = vn[0] * vn[0] + vn[1] * vn[1] + vn[2] * vn[2];
+                                    inv_vv = vv > 1e-18 ? 1.0 / vv : 0.0;
+                                }
+#pragma unroll
+                                for (int t = 0; t < RT; ++t) {
+                                    W[t] = TE(0);
+                                    WL[t] = TE(0);
+                                    if constexpr (TR) WT[t] = TE(0);
+                                    if (!mv[t]) continue;
+                                    const double y = (epsn - em[t] - w) * inv_sig;
+                                    const double s1 = y * y;
+                                    if (s1 < ylim) W[t] = (TE)(fn - fm[t]) * fexp((TE)(-s1));
+                                    WL[t] = (TE)(dn * dm[t]);
+                                    if constexpr (TR) {
+                                        const double fac = inv_vv > 0.0
+                                            ? 1.0 - (vn[0] * vm[t][0] + vn[1] * vm[t][1] + vn[2] * vm[t][2]) * inv_vv
+                                            : 1.0;
+                                        WT[t] = (TE)(dn * dm[t] * fac);
+                                    }
+                                    need = need || (s1 < ylim) || (WL[t] != TE(0));
+                                }
+                            } else if constexpr (RE) {
+                                // Eq. (3), Re 1/(x + i delta) = x/(x^2 + delta^2), delta = sigma:
+                                // on shell x = eps_nk - eps_m,k+q +- omega; at eps_F x = mu - eps_m,k+q +- omega
+                                const double d2 = a.sigma * a.sigma;
+                                need = true;
+#pragma unroll
+                                for (int t = 0; t < RT; ++t) {
+                                    W[t] = TE(0);
+                                    WL[t] = TE(0);
+                                    if (!mv[t]) continue;
+                                    const double A1 = nB + fm[t], A2 = nB + 1.0 - fm[t];
+                                    const double x1 = epsn - em[t] + w, x2 = epsn - em[t] - w;
+                                    const double y1 = a.mu - em[t] + w, y2 = a.mu - em[t] - w;
+                                    W[t] = (TE)(A1 * x1 / (x1 * x1 + d2) + A2 * x2 / (x2 * x2 + d2));
+                                    WL[t] = (TE)(A1 * y1 / (y1 * y1 + d2) + A2 * y2 / (y2 * y2 + d2));
+                                }
+                            } else {
+#pragma unroll
+                                for (int t = 0; t < RT; ++t) {
+                                    W[t] = TE(0);
+                                    WL[t] = TE(0);
+                                    if (STORE || POLE || !mv[t]) continue;
+                                    const double x = epsn - em[t];
+                                    const double y1 = (x + w) * inv_sig, y2 = (x - w) * inv_sig;
+                                    const double s1 = y1 * y1, s2 = y2 * y2;
+                                    if (s1 < ylim) W[t] += (TE)(nB + fm[t]) * fexp((TE)(-s1));
+                                    if (s2 < ylim) W[t] += (TE)(nB + 1.0 - fm[t]) * fexp((TE)(-s2));
+                                    need = need || (s1 < ylim) || (s2 < ylim);
+                                }
+                            }
+                            if (!need) continue;
+                            TE gr[RT], gi[RT];
+#pragma unroll
+                            for (int t = 0; t < RT; ++t) {
+                                gr[t] = TE(0);
+                                gi[t] = TE(0);
+                            }
+#pragma unroll
+                            for (int i = 0; i < NBP; ++i) {
+                                if (NBP < 16 && i >= nb) break;
+                                const CT vv = Vt[i * NBP + n];
+                                const TE vx = (TE)vv.x, vy = (TE)vv.y;
+#pragma unroll
+                                for (int t = 0; t < RT; ++t) {
+                                    // conj(u) * v
+                                    gr[t] += uq[t][i].x * vx + uq[t][i].y * vy;
+                                    gi[t] += uq[t][i].x * vy - uq[t][i].y * vx;
+                                }
+                            }
+#pragma unroll
+                            for (int t = 0; t < RT; ++t) {
+                                if (!mv[t]) continue;
+                                if (STORE) {
+                                    reinterpret_cast<double2*>(a.gkq)
+                                        [((((size_t)k * a.nq_total + q) * nm + nu) * nb + x0 + tb + t) * nb + n] =
+                                        make_double2((double)gr[t], (double)gi[t]);
+                                } else if (PH) {
+                                    const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
+                                    pp[rr] += (double)(g2 * W[t]);
+                                    pl[rr] += (double)(g2 * WL[t]);
+                                    if constexpr (TR) pt[rr] += (double)(g2 * WT[TR ? t : 0]);
+                                } else if (RE) {
+                                    const TE g2 = gr[t] * gr[t] + gi[t] * gi[t];
+                                    acc[n] += (double)(g2 * W[t]);
+                                    acc2[n] += (double)(g2 * WL[t]);
+                                } else if (POLE) {
+                                    double* rec = a.rec + ((((size_t)k * a.qc + ql) * nm + nu) * nb + x0 + tb + t) * (4 + NBP);
+                                    rec[4 + n] = (double)(gr[t] * gr[t] + gi[t] * gi[t]);
+                                    if (n == 0) {
+                                        const double xi = em[t] - a.mu;
+                                        const bool kept = scv != 0.0;
+                                        rec[0] = xi - w;
+                                        rec[1] = xi + w;
+                                        rec[2] = kept ? nB + fm[t] : 0.0;
+                                        rec[3] = kept ? nB + 1.0 - fm[t] : 0.0;
+                                        for (int j = nb; j < NBP; ++j) rec[4 + j] = 0.0;   // padded bands
+                                    }
+                                } else {
+                                    acc[n] += (double)((gr[t] * gr[t] + gi[t] * gi[t]) * W[t]);
+                                }
+                            }
+                            // keep the scheduler from overlapping band iterations (register pressure)
+                            __builtin_amdgcn_sched_barrier(0);
+                        }
+                    }
                 }
-                __syncthreads();
-                for (int b = tid; b < NBLK; b += 256) {
-                    const long gblk = n0 / NB2 + b;         // q_local * nm + nu
-                    if (gblk >= (long)ncb) continue;
-                    double v = 0.0;
-                    for (int rw = 0; rw < BM; ++rw) v += red[((size_t)b * BM + rw) * SPB];
-                    a.part_ph[((size_t)kind * tiles_m + mt) * ncb + gblk] = v;
+            }
+            if constexpr (PH) {
+                // fixed-order sums over the tile's k rows, per band block (q, nu):
+                // slot (b, r, j) holds run j of row r; rows are summed after the
+                // slots of each row, for Eq. (9) and then Eq. (11)
+                constexpr int NBLK = BN / NB2;
+                constexpr int SPB = NBP / RUN;                  // runs per band block and row
+                static_assert(SBYTES >= sizeof(double) * NBLK * BM * SPB, "phonon reduction buffer");
+                double* red = reinterpret_cast<double*>(smem);
+                const int jslot = x0 / RUN;
+                const size_t ncb = (size_t)a.qc * nm;
+#pragma unroll
+                for (int kind = 0; kind < (TR ? 3 : 2); ++kind) {
+                    __syncthreads();                            // V, or the previous pass, no longer read
+#pragma unroll
+                    for (int rr = 0; rr < NRUN; ++rr) {
+                        const int b = (sub * JI + rr * RUN) / NBP;
+                        double val = kind == 0 ? pp[rr] : pl[rr];
+                        if constexpr (TR) val = kind == 2 ? pt[rr] : val;
+                        red[((size_t)b * BM + r) * SPB + jslot] = val;
+                    }
+                    __syncthreads();
+                    for (int t = tid; t < NBLK * BM; t += 256) {
+                        double v = 0.0;
+                        for (int j = 0; j < SPB; ++j) v += red[(size_t)t * SPB + j];
+                        red[(size_t)t * SPB] = v;
+                    }
+                    __syncthreads();
+                    for (int b = tid; b < NBLK; b += 256) {
+                        const long gblk = n0 / NB2 + b;         // q_local * nm + nu
+                        if (gblk >= (long)ncb) continue;
+                        double v = 0.0;
+                        for (int rw = 0; rw < BM; ++rw) v += red[((size_t)b * BM + rw) * SPB];
+                        a.part_ph[((size_t)kind * tiles_m + mt) * ncb + gblk] = v;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+        if constexpr (KIND == 1 || KIND == 2 || KIND == 4 || KIND == 5 || KIND == 6) continue;
+        // fixed-order reduction over the TPR threads of each row (real-part
+        // mode: the on-shell sums, then the sums at eps_F)
+        double* red = reinterpret_cast<double*>(smem);   // [BM][TPR][NBP]
+#pragma unroll
+        for (int pass = 0; pass < (RE ? 2 : 1); ++pass) {
+            if (pass) __syncthreads();
+#pragma unroll
+            for (int n = 0; n < NBP; ++n) red[(size_t)tid * NBP + n] = pass ? acc2[RE ? n : 0] : acc[n];
+            __syncthreads();
+            double* dst = pass ? a.part2 : a.part;
+            if (active_row) {
+                for (int n = sub; n < nb; n += TPR) {
+                    double t = 0.0;
+                    for (int u = 0; u < TPR; ++u) t += red[((size_t)r * TPR + u) * NBP + n];
+                    dst[((size_t)slot * a.nk + k) * nb + n] = t;
                 }
             }
         }
-        __syncthreads();
-    }
-    if constexpr (KIND == 1 || KIND == 2 || KIND == 4 || KIND == 5 || KIND == 6) return;
-    // fixed-order reduction over the TPR threads of each row (real-part
-    // mode: the on-shell sums, then the sums at eps_F)
-    double* red = reinterpret_cast<double*>(smem);   // [BM][TPR][NBP]
-#pragma unroll
-    for (int pass = 0; pass < (RE ? 2 : 1); ++pass) {
-        if (pass) __syncthreads();
-#pragma unroll
-        for (int n = 0; n < NBP; ++n) red[(size_t)tid * NBP + n] = pass ? acc2[RE ? n : 0] : acc[n];
-        __syncthreads();
-        double* dst = pass ? a.part2 : a.part;
-        if (active_row) {
-            for (int n = sub; n < nb; n += TPR) {
-                double t = 0.0;
-                for (int u = 0; u < TPR; ++u) t += red[((size_t)r * TPR + u) * NBP + n];
-                dst[((size_t)s * a.nk + k) * nb + n] = t;
-            }
-        }
-    }
+    }   // segments
 }
 
 // a6 for the split-bf16 path: float32 g(R_e,q) [ne][qc][nm*nb*nb] ->
@@ -1159,7 +1182,7 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     const int tiles_m = (a.nk + BM - 1) / BM;
     const long ncols = (long)a.qc * a.nm * NBP * NBP;
     const int tiles_n = (int)((ncols + BN - 1) / BN);
-    const long total = (long)tiles_m * a.S;
+    const long total = (long)tiles_m * a.S + a.helpers;
     const long G = ((total + 7) / 8) * 8;
     (void)num_cu;
     (void)tiles_n;
@@ -1262,6 +1285,24 @@ int fused_slices(int nk, int nbp, int tiles_n, int num_cu, Prec prec) {
     if (S > tiles_n) S = tiles_n;
     if (S < 1) S = 1;
     return (int)S;
+}
+
+void fused_balance(FusedArgs& a, Prec prec, int num_cu) {
+    a.helpers = 0;
+    a.keep = 0x7fffffff;
+    const int BM = fused_tile_rows(a.nbp, prec), BN = fused_tile_cols(a.nbp, prec);
+    const long tiles_m = (a.nk + BM - 1) / BM;
+    const long tiles_n = ((long)a.qc * a.nm * a.nbp * a.nbp + BN - 1) / BN;
+    const long R = tiles_m * a.S;
+    const long H = 2L * (num_cu > 0 ? num_cu : 256) - R;   // empty slots of one round
+    const long J = (tiles_n + a.S - 1) / a.S;               // tiles of the longest slice
+    if (!fused_balanced_c(a.nbp, (int)prec) || H <= 0 || R <= 0 || J < 32) return;
+    // a helper runs at most c tails of J - keep tiles: keep = c (J - keep)
+    const long c = (R + H - 1) / H;
+    const long keep = (c * J + c) / (c + 1);
+    if (keep >= J) return;
+    a.helpers = (int)H;
+    a.keep = (int)keep;
 }
 
 void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t stream) {

@@ -137,11 +137,14 @@ struct FusedArgs {
     const double* sc;      // [qc][nm] (chunk-local)
     double sigma;
     double mu;         // chemical potential (phonon mode)
-    double* part;      // [S][nk][nb] partial sums (imsigma mode)
+    double* part;      // [S or 2 S][nk][nb] partial sums (imsigma mode): slot s of slice s,
+                       // slot S + s of its tail when helper blocks run (fused_part_slots)
     int S;             // number of slices
+    int helpers = 0;   // helper blocks beyond the tiles_m * S regular ones (fused_balance)
+    int keep = 0x7fffffff;   // column tiles of its slice a regular block runs when helpers > 0
     void* gkq;         // [nk][nq_total][nm][nb][nb] c128 (store mode)
     double* part_ph;   // [2][tiles_m][qc*nm] per-row-tile sums (phonon mode): Eq. (9), Eq. (11)
-    double* part2;     // [S][nk][nb] second partials (real-part mode: Sigma' at omega = 0; part
+    double* part2;     // [S or 2 S][nk][nb] second partials (real-part mode: Sigma' at omega = 0; part
                        // then holds Sigma' on shell)
     double* rec;       // [nk][qc][nm][nb] pole records of 4 + nbp doubles (pole mode)
     const double* vel; // [nk][nb][3] band velocities of the k set (transport mode, with part_ph)
@@ -154,6 +157,13 @@ struct FusedArgs {
 // a7 + a8 + the real-part sums of Eq. (3) (real-part mode, part2 != nullptr)
 void launch_fused_k(Prec prec, const FusedArgs& a, int num_cu, hipStream_t stream);
 int fused_slices(int nk, int nbp, int ncols_tiles, int num_cu, Prec prec);
+// helper blocks and the regular blocks' share of their slices (a.helpers,
+// a.keep) for a launch whose sizes and a.S are set; slots of a.part then
+void fused_balance(FusedArgs& a, Prec prec, int num_cu);
+inline int fused_part_slots(const FusedArgs& a) { return a.helpers > 0 ? 2 * a.S : a.S; }
+// fused-kernel instantiations that run helper blocks: float32, and every
+// precision at 16 padded bands (mode 0 float64, 1 float32, 2 split-bf16)
+constexpr bool fused_balanced_c(int nbp, int mode) { return mode == 1 || nbp >= 16; }
 // columns and k rows per tile of the fused kernel for a padded band count:
 // whole band blocks, at least 64 columns; 4096 complex entries, 8192 for
 // float32 and split-bf16 at 16 bands (32 x 256); `wide` = not float64
