@@ -202,6 +202,14 @@ struct Layout {
     int Sw = 1;
     void* polar_L = nullptr;     // [Q][nm] c128 long-range factors (polar systems)
     double* vel = nullptr;       // [nk][nb][3] band velocities (transport mode)
+    // folded R_e -> k contraction (float64 / float32): -R index, halved R
+    // list, partner rows, its R vectors and length
+    bool fold = false;
+    int32_t* fneg = nullptr;
+    int32_t* fhalf = nullptr;
+    int32_t* fpair = nullptr;
+    int32_t* fR = nullptr;
+    int32_t* fkh = nullptr;
     // k-outer order (frequency-grid mode): R_e -> k once, R_p -> q per chunk
     bool kouter = false;
     void* phi_e = nullptr;       // [nk][N_e] phases with 1/ndeg_e
@@ -345,6 +353,14 @@ void plan(const epw_system* s, const epw_points* p, const epw_params* par, Out o
     L.U = A.take(16 * (size_t)nk * nb * nb);
     L.ftab = (double*)A.take(8 * (size_t)nk * nb);
     if (!L.kouter) L.phi_k = A.take(bf ? 8 * (size_t)nk * L.kpad : cb * (size_t)nk * ne);
+    L.fold = !L.kouter && fused_fold_c(L.nbp, (int)L.prec);
+    if (L.fold) {
+        L.fneg = (int32_t*)A.take(4 * (size_t)ne);
+        L.fhalf = (int32_t*)A.take(4 * (size_t)ne);
+        L.fpair = (int32_t*)A.take(4 * (size_t)ne);
+        L.fR = (int32_t*)A.take(12 * (size_t)ne);
+        L.fkh = (int32_t*)A.take(4);
+    }
     if (L.prec != Prec::F64) L.gR_t = A.take(cb * (size_t)ne * np_ * nm * nb * nb);
     if (!given) {
         L.omega_c = (double*)A.take(8 * (size_t)L.Q * nm);
@@ -469,8 +485,15 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
     // launch with the table).  Generation needs the R_e offsets of a tile in
     // LDS, hence the bound on ne.  The 1/ndeg weights of R_e are folded into
     // the B operand (mode rotation) in both cases.
+    // FP32 up to 8 padded bands folds the sum over R_e by pairs (R, -R)
+    // (cfold_mainloop): its table holds the phases of the halved list.
     const bool gen = prec == Prec::BF16X2 && L.nbp < 16 && s->nmax_e > 0 && ne <= 4096;
-    if (!gen && !L.kouter) launch_phase_table(prec, nk, p->kfrac, ne, s->Re, nullptr, bf ? L.kpad : ne, L.phi_k, st);
+    if (L.fold) {
+        launch_half_list(ne, s->Re, L.fneg, L.fhalf, L.fpair, L.fR, L.fkh, st);
+        launch_phase_table(prec, nk, p->kfrac, ne, L.fR, nullptr, ne, L.phi_k, st);
+    } else if (!gen && !L.kouter) {
+        launch_phase_table(prec, nk, p->kfrac, ne, s->Re, nullptr, bf ? L.kpad : ne, L.phi_k, st);
+    }
     const void* gsrc = s->gR;
     if (prec != Prec::F64) {
         launch_c128_to_c64((size_t)ne * np_ * nm * nb * nb, s->gR, L.gR_t, st);
@@ -592,6 +615,8 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
             else
                 launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e, L.polar_L,
                                    s->Re);
+            if (L.fold)
+                launch_fold_pairs(prec, ne, L.fkh, L.fhalf, L.fpair, (long)qc * nm * L.nbp * L.nbp, L.Bnu, st);
         }
         FusedArgs a;
         a.nk = nk;
@@ -624,6 +649,9 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
         a.sigma = par->sigma;
         a.mu = par->mu;
         a.part = L.part;
+        a.half = L.fold ? L.fhalf : nullptr;
+        a.pair = L.fold ? L.fpair : nullptr;
+        a.kh = L.fold ? L.fkh : nullptr;
         // (pole mode: the slices only spread the column tiles over blocks)
         a.S = gkq ? 1 : fused_slices(nk, L.nbp, tiles_n_for(qc, nm, L.nbp, prec), SLICE_CUS, prec);
         fused_balance(a, prec, SLICE_CUS);

@@ -21,6 +21,9 @@ __device__ inline f4 mfma4(float a, float b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+template <bool B, class X, class Y> struct PickType { typedef X type; };
+template <class X, class Y> struct PickType<false, X, Y> { typedef Y type; };
+
 template <typename T> __device__ inline typename Cx<T>::type cz() {
     typename Cx<T>::type z;
     z.x = T(0);
@@ -201,6 +204,145 @@ __device__ inline void cgemm_mainloop(Stage<T, BM, BN, BK>* stages, int K, AF af
         }
 }
 
+
+// ------------------------------------------------ folded contraction main loop
+//
+// For a K set that pairs every vector R with -R, a sum of Phi(R) B(R) with
+// Phi(-R) = conj(Phi(R)) regroups over one member of each pair:
+//   sum_R Phi(R) B(R) = sum_h [c_h B+_h + i s_h B-_h],
+// c + i s = Phi(R_h), B+ = B(R_h) + B(-R_h), B- = B(R_h) - B(-R_h); a vector
+// without a partner (and R = 0) enters with B+ = B- = B(R_h).  Per K entry of
+// the halved sum the real and imaginary parts take two real MFMAs each:
+//   re += c B+re - s B-im,   im += c B+im + s B-re,
+// i.e. two real products per original vector instead of three (Gauss) or
+// four.  B- im is stored negated so that both updates are plain MFMAs.
+template <typename T, int BM, int BN, int BK>
+struct FoldStage {
+    static constexpr int PAD = 16;
+    T a_re[BK][BM + PAD];      // c
+    T a_im[BK][BM + PAD];      // s
+    T bp_re[BK][BN + PAD];     // B+ re
+    T bp_im[BK][BN + PAD];     // B+ im
+    T bm_re[BK][BN + PAD];     // B- re
+    T bm_ni[BK][BN + PAD];     // -B- im
+};
+template <typename CT> struct CPair {
+    CT p, m;   // B+ and B- entries
+};
+
+// Main loop over the halved K (Kh entries): afetch(m, h) gives c + i s of
+// row m, bfetch(h, n) the pair {B+, B-} of column n (zeros beyond Kh).  The
+// same block, wave and staging layout as cgemm_mainloop; the accumulators
+// are C re and C im.
+template <typename T, int BM, int BN, int BK, class AF, class BF, int NS = 1>
+__device__ inline void cfold_mainloop(FoldStage<T, BM, BN, BK>* stages, int Kh, AF afetch, BF bfetch,
+                                      typename Cx<T>::acc (&cr)[4 * CWaves<BM, BN>::RB],
+                                      typename Cx<T>::acc (&ci)[4 * CWaves<BM, BN>::RB])
+{
+    static_assert(NS == 1 || NS == 2, "one or two LDS stages");
+    typedef typename Cx<T>::type CT;
+    constexpr int WN = CWaves<BM, BN>::WN;
+    constexpr int RB = CWaves<BM, BN>::RB;
+    static_assert(RB >= 1 && 16 * RB * (4 / WN) == BM, "wave layout");
+    constexpr int AN = BM * BK;
+    constexpr int AE = AN >= 256 ? AN / 256 : 1;
+    constexpr int BE = BK * BN / 256;
+    static_assert((AN >= 256 ? AE * 256 == AN : 256 % AN == 0) && BE >= 1 && BE * 256 == BK * BN,
+                  "tile too small for 256 threads");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    CT ra[AE];
+    CPair<CT> rb[BE];
+    for (int c = 0; c < 4 * RB; ++c)
+        for (int i = 0; i < 4; ++i) {
+            cr[c][i] = T(0);
+            ci[c][i] = T(0);
+        }
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            const int idx = tid * AE + e;
+            if (AN < 256 && idx >= AN) break;
+            ra[e] = afetch(idx / BK, k0 + idx % BK);
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            const int idx = BN >= 256 ? e * 256 + tid : tid * BE + e;
+            rb[e] = bfetch(k0 + idx / BN, idx % BN);
+        }
+    };
+    auto sstore = [&](FoldStage<T, BM, BN, BK>& st) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            const int idx = tid * AE + e;
+            if (AN < 256 && idx >= AN) break;
+            st.a_re[idx % BK][idx / BK] = ra[e].x;
+            st.a_im[idx % BK][idx / BK] = ra[e].y;
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            const int idx = BN >= 256 ? e * 256 + tid : tid * BE + e;
+            st.bp_re[idx / BN][idx % BN] = rb[e].p.x;
+            st.bp_im[idx / BN][idx % BN] = rb[e].p.y;
+            st.bm_re[idx / BN][idx % BN] = rb[e].m.x;
+            st.bm_ni[idx / BN][idx % BN] = -rb[e].m.y;
+        }
+    };
+    gload(0);
+    sstore(stages[0]);
+    __syncthreads();
+    for (int k0 = 0, it = 0; k0 < Kh; k0 += BK, ++it) {
+        const bool more = k0 + BK < Kh;
+        if (more) gload(k0 + BK);
+        const FoldStage<T, BM, BN, BK>& st = stages[NS == 2 ? (it & 1) : 0];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            T ac[RB], as[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) {
+                ac[q] = st.a_re[kr][wm * 16 * RB + q * 16 + (lane & 15)];
+                as[q] = st.a_im[kr][wm * 16 * RB + q * 16 + (lane & 15)];
+            }
+            T pr[4], pi[4], mr[4], mn[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int col = wn * 64 + c * 16 + (lane & 15);
+                pr[c] = st.bp_re[kr][col];
+                pi[c] = st.bp_im[kr][col];
+                mr[c] = st.bm_re[kr][col];
+                mn[c] = st.bm_ni[kr][col];
+            }
+            // each accumulator's second update follows its first by 4 RB MFMAs
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cr[q * 4 + c] = mfma4(ac[q], pr[c], cr[q * 4 + c]);
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) ci[q * 4 + c] = mfma4(ac[q], pi[c], ci[q * 4 + c]);
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cr[q * 4 + c] = mfma4(as[q], mn[c], cr[q * 4 + c]);
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) ci[q * 4 + c] = mfma4(as[q], mr[c], ci[q * 4 + c]);
+        }
+        if constexpr (NS == 2) {
+            if (more) sstore(stages[(it + 1) & 1]);
+            __syncthreads();
+        } else {
+            __syncthreads();
+            if (more) {
+                sstore(stages[0]);
+                __syncthreads();
+            }
+        }
+    }
+}
 
 }  // namespace
 }  // namespace epw

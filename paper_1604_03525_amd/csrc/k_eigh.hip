@@ -374,6 +374,36 @@ __global__ void neg_index_kernel(int nR, const int32_t* __restrict__ R, int32_t*
     neg[r] = found;
 }
 
+// The halved R list of the folded contraction (cfold_mainloop): in order of
+// the set, every vector that is not the second member of a pair (R, -R),
+// with pair[h] its partner's row, or its own row when it has none (R = 0, a
+// vector whose negative is missing, a duplicate); kh[0] = the list's length.
+// Entries h >= kh repeat the last member's rows with a zero R (never read by
+// the contraction, kept finite for the phase table).  A pair needs neg to
+// map each member to the other, so any R list gives an exact fold.  One
+// thread: the list is a few thousand vectors at most.
+__global__ void half_list_kernel(int nR, const int32_t* __restrict__ R, const int32_t* __restrict__ neg,
+                                 int32_t* __restrict__ half, int32_t* __restrict__ pair,
+                                 int32_t* __restrict__ R_half, int32_t* __restrict__ kh) {
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    int h = 0;
+    for (int e = 0; e < nR; ++e) {
+        const int t = neg[e];
+        const bool mutual = t >= 0 && t < nR && neg[t] == e;
+        if (mutual && t < e) continue;               // second member of a pair
+        half[h] = e;
+        pair[h] = (mutual && t > e) ? t : e;
+        for (int a = 0; a < 3; ++a) R_half[3 * h + a] = R[3 * e + a];
+        ++h;
+    }
+    kh[0] = h;
+    for (int j = h; j < nR; ++j) {
+        half[j] = h > 0 ? half[h - 1] : 0;
+        pair[j] = h > 0 ? pair[h - 1] : 0;
+        for (int a = 0; a < 3; ++a) R_half[3 * j + a] = 0;
+    }
+}
+
 // Upper triangles (rows i with columns j >= i in turn) of the Hermitian part
 // of the interpolation: with Phi_R = exp(2 pi i p.R)/ndeg(R) and the set
 // closed under R -> -R,
@@ -401,6 +431,15 @@ __global__ void pack_upper_kernel(int n, int nR, const double2* __restrict__ X, 
         v = make_double2(__builtin_nan(""), __builtin_nan(""));
     }
     P[r * nt + i * n - i * (i - 1) / 2 + (j - i)] = v;
+}
+
+void launch_half_list(int nR, const int32_t* R, int32_t* neg, int32_t* half, int32_t* pair, int32_t* R_half,
+                      int32_t* kh, hipStream_t stream) {
+    if (nR <= 0) return;
+    neg_index_kernel<<<dim3((unsigned)((nR + 255) / 256)), dim3(256), 0, stream>>>(nR, R, neg);
+    launch_check("neg_index_kernel");
+    half_list_kernel<<<dim3(1), dim3(64), 0, stream>>>(nR, R, neg, half, pair, R_half, kh);
+    launch_check("half_list_kernel");
 }
 
 void launch_pack_upper(int n, int nR, const int32_t* R, const int32_t* ndeg, const void* X, int32_t* neg, void* P,

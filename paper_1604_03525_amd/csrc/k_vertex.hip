@@ -455,7 +455,15 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     constexpr int RT = (MODE == 2 || (MODE == 1 && NBP >= 16)) ? 1 : RUN;   // bands of a run taken together in phase 2
     static_assert(JI * NBP * TPR == BN && JI % RUN == 0 && NBP % RUN == 0, "epilogue split");
     constexpr int LDC = BN + 1;                    // C tile row stride: rows start on different LDS banks
-    typedef Stage<T, BM, BN, BK> St;
+    // folded R_e -> k contraction (cfold_mainloop): float32 up to 8 padded
+    // bands (fcc 20^3: 278 -> 226 ms per 4000-q launch with the row indices in
+    // LDS; with them read from memory, 296 ms).  In float64 the same fold ran
+    // slower (255 -> 288 ms per 2000-q launch: its main loop is bound by the
+    // staging and synchronisation of each K step, not by the MFMA count, and
+    // the fold doubles the B planes staged per step), and so it did at 16
+    // bands (FP32 131 -> 155 ms per mobility-shard launch).
+    constexpr bool FOLD = fused_fold_c(NBP, MODE) && !WSTORE && !GEN;
+    typedef typename PickType<FOLD, FoldStage<T, BM, BN, BK>, Stage<T, BM, BN, BK>>::type St;
     typedef BfStage<BM, BN> Sb;
     constexpr size_t CBYTES = sizeof(CT) * BM * LDC;
     // two LDS stages (one barrier per K step) for float32, where they fit
@@ -482,6 +490,17 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     const int per = G / 8;
     const int lin = (bid % 8) * per + bid / 8;
     const int R = tiles_m * a.S;                  // regular blocks: one per (row tile, slice)
+    int kh = 0;                                   // entries of the folded sum
+    int* Hs = reinterpret_cast<int*>(dsm);        // [ne] rows of B+ (FOLD)
+    int* Ps = Hs + a.ne;                          // [ne] rows of B-
+    if constexpr (fused_fold_c(NBP, MODE) && !WSTORE && !GEN) {
+        kh = a.kh[0];
+        for (int i = threadIdx.x; i < kh; i += 256) {
+            Hs[i] = a.half[i];
+            Ps[i] = a.pair[i];
+        }
+        __syncthreads();
+    }
     if (lin >= R + a.helpers) return;
     const int NE = 2 * a.nmax + 1;
     if constexpr (GEN) {
@@ -626,8 +645,31 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
                 };
                 constexpr int RB = CWaves<BM, BN>::RB;
                 typename Cx<T>::acc cr[4 * RB], ci[4 * RB];
-                cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), false, NS>(
-                    reinterpret_cast<St*>(smem), a.ne, afetch, bfetch, cr, ci);
+                if constexpr (FOLD) {
+                    // entry h of the halved sum: B+ in row half[h], B- in row pair[h]
+                    auto bfold = [&](int h, int n) -> CPair<CT> {
+                        const long col = n0 + n;
+                        CPair<CT> v;
+                        if (h < kh && col < ncols) {
+                            v.p = Bm[(size_t)Hs[h] * ncols + col];
+                            v.m = Bm[(size_t)Ps[h] * ncols + col];
+                        } else {
+                            v.p = cz<T>();
+                            v.m = cz<T>();
+                        }
+                        return v;
+                    };
+                    auto afold = [&](int m, int h) -> CT {
+                        const int row = m0 + m;
+                        if (row < a.nk && h < kh) return phi[(size_t)row * a.ldk + h];
+                        return cz<T>();
+                    };
+                    cfold_mainloop<T, BM, BN, BK, decltype(afold), decltype(bfold), NS>(
+                        reinterpret_cast<St*>(smem), kh, afold, bfold, cr, ci);
+                } else {
+                    cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), false, NS>(
+                        reinterpret_cast<St*>(smem), a.ne, afetch, bfetch, cr, ci);
+                }
                 const int lane = tid & 63, wave = tid >> 6;
                 constexpr int WN = BN / 64;
                 const int wm = wave / WN, wn = wave % WN;
@@ -1190,14 +1232,20 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     if (MODE == 0 && a.nmax > 0) throw HipFailure{(int)hipErrorInvalidValue, "fused_k_kernel (f64, nmax > 0)", __FILE__, __LINE__};
     constexpr bool CAN_GEN = MODE != 0;
     const bool gen = CAN_GEN && a.nmax > 0;
-    const size_t dyn = gen ? (size_t)3 * BM * (2 * a.nmax + 1) * 8 + 4 * (size_t)a.ne : 0;
+    // the folding instantiations read the halved R list (kh, half, pair)
+    if (fused_fold_c(NBP, MODE) && !a.gout && !(a.kh && a.half && a.pair))
+        throw HipFailure{(int)hipErrorInvalidValue, "fused_k_kernel (folded sum without its R list)", __FILE__,
+                         __LINE__};
+    const bool fold = fused_fold_c(NBP, MODE) && !a.gout;
+    const size_t dyn = gen ? (size_t)3 * BM * (2 * a.nmax + 1) * 8 + 4 * (size_t)a.ne
+                           : fold ? 8 * (size_t)a.ne : 0;
     const dim3 grid((unsigned)G), block(256);
     auto go = [&](auto kind) {
         constexpr int K = decltype(kind)::value;
         if (gen)
             fused_k_kernel<MODE, NBP, K, CAN_GEN><<<grid, block, dyn, stream>>>(a, tiles_m, tiles_n);
         else
-            fused_k_kernel<MODE, NBP, K, false><<<grid, block, 0, stream>>>(a, tiles_m, tiles_n);
+            fused_k_kernel<MODE, NBP, K, false><<<grid, block, dyn, stream>>>(a, tiles_m, tiles_n);
     };
     if constexpr (MODE != 2) {
         if (a.gout) {
@@ -1235,6 +1283,36 @@ void launch_phase_table(Prec prec, int np, const double* pts, int nR, const int3
     if (total == 0) return;
     phase_table_kernel<<<blocks_for(total, 256), 256, 0, stream>>>(np, pts, nR, R, ndeg, ld, (int)prec, out);
     launch_check("phase_table_kernel");
+}
+
+template <typename CT>
+__global__ void fold_pairs_kernel(const int32_t* __restrict__ kh, const int32_t* __restrict__ half,
+                                  const int32_t* __restrict__ pair, long cols, CT* __restrict__ B) {
+    const int h = blockIdx.y;
+    if (h >= kh[0]) return;
+    const long r1 = half[h], r2 = pair[h];
+    if (r1 == r2) return;
+    const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= cols) return;
+    const CT x = B[r1 * cols + col], y = B[r2 * cols + col];
+    CT p, m;
+    p.x = x.x + y.x;
+    p.y = x.y + y.y;
+    m.x = x.x - y.x;
+    m.y = x.y - y.y;
+    B[r1 * cols + col] = p;
+    B[r2 * cols + col] = m;
+}
+
+void launch_fold_pairs(Prec prec, int nR, const int32_t* kh, const int32_t* half, const int32_t* pair, long cols,
+                       void* B, hipStream_t stream) {
+    if (nR <= 0 || cols <= 0) return;
+    const dim3 grid((unsigned)((cols + 255) / 256), (unsigned)nR);
+    if (prec == Prec::F64)
+        fold_pairs_kernel<double2><<<grid, 256, 0, stream>>>(kh, half, pair, cols, (double2*)B);
+    else
+        fold_pairs_kernel<float2><<<grid, 256, 0, stream>>>(kh, half, pair, cols, (float2*)B);
+    launch_check("fold_pairs_kernel");
 }
 
 void launch_c128_to_c64(size_t n, const void* in, void* out, hipStream_t stream) {

@@ -30,11 +30,20 @@ void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs,
 // closed under R -> -R (a sum of these over R gives the Hermitised interpolated
 // matrix); neg [nR] int32 scratch receives the index of -R (entries of a vector
 // whose negative is missing become NaN)
+// halved R list of the folded R_e -> k contraction: neg[nR] (index of -R or
+// -1), half[nR], pair[nR], R_half[nR][3], kh[1] = the list's length
+void launch_half_list(int nR, const int32_t* R, int32_t* neg, int32_t* half, int32_t* pair, int32_t* R_half,
+                      int32_t* kh, hipStream_t stream);
 void launch_pack_upper(int n, int nR, const int32_t* R, const int32_t* ndeg, const void* X, int32_t* neg, void* P,
                        hipStream_t stream);
 
 // ---- k_vertex.hip ----
 enum class Prec { F64 = 0, F32 = 1, BF16X2 = 2 };
+// in place over rows of B [nR][cols] (complex in prec, float64 or float32):
+// for every h < kh with pair[h] != half[h], rows (half[h], pair[h]) become
+// (B+ , B-) = (x + y, x - y) of their entries (x, y)
+void launch_fold_pairs(Prec prec, int nR, const int32_t* kh, const int32_t* half, const int32_t* pair, long cols,
+                       void* B, hipStream_t stream);
 
 // exp(2 pi i p.R)/ndeg(R) -> [np][ld] complex in `prec` (columns >= nR zero;
 // ndeg == nullptr: weight 1).
@@ -149,6 +158,12 @@ struct FusedArgs {
     double* rec;       // [nk][qc][nm][nb] pole records of 4 + nbp doubles (pole mode)
     const double* vel; // [nk][nb][3] band velocities of the k set (transport mode, with part_ph)
     const double* vel_pair;  // [nk][qc][nb][3] velocities at k+q per pair (transport mode, off-grid)
+    // folded R_e -> k contraction (fused_fold_c, outside the store of the
+    // Wannier-basis vertex): B holds (B+, B-) in rows (half[h], pair[h]) and
+    // phi_k the phases of R_half; kh[0] = number of entries h
+    const int32_t* half = nullptr;
+    const int32_t* pair = nullptr;
+    const int32_t* kh = nullptr;
     void* gout = nullptr;    // [nk][qc*nm*nbp*nbp] complex in prec: the Wannier-basis g_nu(k,q)
                              // itself (no rotation or reduction; float64 / float32, phase table)
 };
@@ -164,6 +179,9 @@ inline int fused_part_slots(const FusedArgs& a) { return a.helpers > 0 ? 2 * a.S
 // fused-kernel instantiations that run helper blocks: float32, and every
 // precision at 16 padded bands (mode 0 float64, 1 float32, 2 split-bf16)
 constexpr bool fused_balanced_c(int nbp, int mode) { return mode == 1 || nbp >= 16; }
+// fused-kernel instantiations that fold the R_e -> k sum by pairs (R, -R):
+// float32 up to 8 padded bands
+constexpr bool fused_fold_c(int nbp, int mode) { return mode == 1 && nbp <= 8; }
 // columns and k rows per tile of the fused kernel for a padded band count:
 // whole band blocks, at least 64 columns; 4096 complex entries, 8192 for
 // float32 and split-bf16 at 16 bands (32 x 256); `wide` = not float64
