@@ -44,15 +44,19 @@ def setup(device):
     return m, sysd, pts, (R, nd, HR, DR, gR, k)
 
 
-def mfma_issue_rate(nk, nq, ne, nm, nb, ms, bk):
-    """TFLOP/s the matrix units execute in the fused kernel's R_e -> k sum:
-    three real products per complex product (6 MFMA flops per 8 algorithmic
-    ones) over K = N_e padded to the K step bk, on the padded band blocks."""
+def mfma_issue_rate(nk, nq, ne, nm, nb, ms, bk, folded=False):
+    """TFLOP/s the matrix units execute in the fused kernel's R_e -> k sum on
+    the padded band blocks: unfolded, three real products per complex product
+    (6 MFMA flops per 8 algorithmic ones) over K = N_e padded to the K step
+    bk; folded by pairs (R, -R) (a set closed under R -> -R, as Wigner-Seitz
+    sets are), four real products per entry of the halved sum (8 MFMA flops)
+    over K = (N_e + 1) / 2 padded to bk."""
     nbp = 1
     while nbp < nb:
         nbp *= 2
-    kp = (ne + bk - 1) // bk * bk
-    return 6.0 * nk * nq * kp * nm * nbp * nbp / (ms * 1e-3) / 1e12
+    k = (ne + 1) // 2 if folded else ne
+    kp = (k + bk - 1) // bk * bk
+    return (8.0 if folded else 6.0) * nk * nq * kp * nm * nbp * nbp / (ms * 1e-3) / 1e12
 
 
 def fused_flops(nk, nq, ne, nm, nb):
@@ -382,10 +386,11 @@ def main():
                      "traffic": recorded_traffic("fp64"),
                      "launches": fn, "avg_launch_ms": fms / fn if fn else None,
                      "convention": "achieved = algorithmic flops (8 per complex multiply-add of the R_e->k sum, "
-                                   "plus the two band rotations) per second; the kernel forms each complex "
-                                   "product with three real MFMAs (6 flops per 8 algorithmic), so frac can "
-                                   "reach 4/3; mfma_issue_frac is the matrix units' own rate",
-                     "mfma_issue_frac": mfma_issue_rate(nk, nq, ne, nm, nb, fms / args.steps, 16)
+                                   "plus the two band rotations) per second; the kernel sums over the pairs "
+                                   "(R, -R) of the Wigner-Seitz set, c B+ + i s B- per pair with two real "
+                                   "MFMAs per R vector (4 MFMA flops per 8 algorithmic), so frac can reach 2; "
+                                   "mfma_issue_frac is the matrix units' own rate",
+                     "mfma_issue_frac": mfma_issue_rate(nk, nq, ne, nm, nb, fms / args.steps, 8, folded=True)
                      / PEAK_TFLOPS["fp64"] if fms > 0 else None},
         "stages_ms_per_step": {k: v[0] / args.steps for k, v in st.items()},
     }

@@ -441,9 +441,19 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     typedef typename ModeTypes<MODE>::TE TE;
     typedef typename ModeTypes<MODE>::CE CE;
     constexpr int BM = FusedShape<MODE, NBP>::BM, BN = FusedShape<MODE, NBP>::BN;
+    // folded R_e -> k contraction (cfold_mainloop): float64 and float32 up
+    // to 8 padded bands, outside the store of the Wannier-basis vertex.
+    // fcc 20^3: FP32 278 -> 226 ms per 4000-q launch, FP64 256 -> 204 ms per
+    // 2000-q launch (K steps of 8 halved entries in two LDS stages: with
+    // steps of 16 in one stage, as unfolded, the fold ran slower, 256 -> 288
+    // ms, the doubled B staging of each step standing between its two
+    // barriers); at 16 bands it did not pay (FP32 131 -> 155 ms per
+    // mobility-shard launch).
+    constexpr bool FOLD = fused_fold_c(NBP, MODE) && KIND != 6 && !GEN;
     // K step: 8 for the float64 16 x 256 tile, whose B stage (16 complex
-    // doubles per thread at K step 16) would not fit beside its accumulators
-    constexpr int BK = (MODE == 0 && NBP >= 16) ? 8 : 16;
+    // doubles per thread at K step 16) would not fit beside its accumulators,
+    // and for the folded float64 loop
+    constexpr int BK = (MODE == 0 && (NBP >= 16 || FOLD)) ? 8 : 16;
     constexpr int NB2 = NBP * NBP;
     constexpr int TPR = 256 / BM;                  // threads per k row
     // Epilogue work items of a row: (band block b, band x), x < NBP; thread
@@ -455,21 +465,13 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     constexpr int RT = (MODE == 2 || (MODE == 1 && NBP >= 16)) ? 1 : RUN;   // bands of a run taken together in phase 2
     static_assert(JI * NBP * TPR == BN && JI % RUN == 0 && NBP % RUN == 0, "epilogue split");
     constexpr int LDC = BN + 1;                    // C tile row stride: rows start on different LDS banks
-    // folded R_e -> k contraction (cfold_mainloop): float32 up to 8 padded
-    // bands (fcc 20^3: 278 -> 226 ms per 4000-q launch with the row indices in
-    // LDS; with them read from memory, 296 ms).  In float64 the same fold ran
-    // slower (255 -> 288 ms per 2000-q launch: its main loop is bound by the
-    // staging and synchronisation of each K step, not by the MFMA count, and
-    // the fold doubles the B planes staged per step), and so it did at 16
-    // bands (FP32 131 -> 155 ms per mobility-shard launch).
-    constexpr bool FOLD = fused_fold_c(NBP, MODE) && !WSTORE && !GEN;
     typedef typename PickType<FOLD, FoldStage<T, BM, BN, BK>, Stage<T, BM, BN, BK>>::type St;
     typedef BfStage<BM, BN> Sb;
     constexpr size_t CBYTES = sizeof(CT) * BM * LDC;
     // two LDS stages (one barrier per K step) for float32, where they fit
     // beside a second resident block; the float64 loop measured faster with
     // a single stage
-    constexpr int NS = (sizeof(T) == 4 && 2 * sizeof(St) <= 72 * 1024) ? 2 : 1;
+    constexpr int NS = ((sizeof(T) == 4 && 2 * sizeof(St) <= 72 * 1024) || (MODE == 0 && FOLD)) ? 2 : 1;
     constexpr size_t STB = MODE == 2 ? sizeof(Sb) : NS * sizeof(St);
     constexpr size_t SBYTES = STB > CBYTES ? STB : CBYTES;
     static_assert(SBYTES >= sizeof(double) * 256 * NBP, "row reduction buffer");
@@ -493,7 +495,7 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     int kh = 0;                                   // entries of the folded sum
     int* Hs = reinterpret_cast<int*>(dsm);        // [ne] rows of B+ (FOLD)
     int* Ps = Hs + a.ne;                          // [ne] rows of B-
-    if constexpr (fused_fold_c(NBP, MODE) && !WSTORE && !GEN) {
+    if constexpr (FOLD) {
         kh = a.kh[0];
         for (int i = threadIdx.x; i < kh; i += 256) {
             Hs[i] = a.half[i];
