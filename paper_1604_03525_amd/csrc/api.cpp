@@ -730,6 +730,16 @@ struct BwdLayout {
     void* phi_q = nullptr;
     void* gq = nullptr;      // a5 output, reused for the mode-basis adjoint
     void* Bnu = nullptr;     // a6 output, reused for gbar_nu(R_e,q)
+    // folded recompute of G (float64 / float32 up to 8 padded bands): the
+    // halved R list (as in the forward) and its unweighted phases; B then
+    // carries the 1/ndeg weights
+    bool fold = false;
+    int32_t* fneg = nullptr;
+    int32_t* fhalf = nullptr;
+    int32_t* fpair = nullptr;
+    int32_t* fR = nullptr;
+    int32_t* fkh = nullptr;
+    void* phi_f = nullptr;
     void* G = nullptr;       // recomputed Wannier-basis g(k,q), overwritten by its adjoint
     double* ek_c = nullptr;
     double* ekq_c = nullptr;
@@ -790,6 +800,15 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     L.ftab = (double*)A.take(8 * (size_t)nk * nb);
     L.wbar = (double*)A.take(8 * (size_t)nk * nb);
     L.phi_k = A.take(bf ? 8 * (size_t)nk * L.kpad : cb * (size_t)nk * ne);
+    L.fold = !bf && fused_fold_c(L.nbp, (int)L.prec);
+    if (L.fold) {
+        L.fneg = (int32_t*)A.take(4 * (size_t)ne);
+        L.fhalf = (int32_t*)A.take(4 * (size_t)ne);
+        L.fpair = (int32_t*)A.take(4 * (size_t)ne);
+        L.fR = (int32_t*)A.take(12 * (size_t)ne);
+        L.fkh = (int32_t*)A.take(4);
+        L.phi_f = A.take(cb * (size_t)nk * ne);
+    }
     L.ebar = (double*)A.take(8 * (size_t)nk * nb);
     L.Ubar = A.take(16 * (size_t)nk * nb * nb);
     L.Xbar = A.take(16 * (size_t)nk * nb * nb);
@@ -859,6 +878,10 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
     } else {
         launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_k, st);
     }
+    if (L.fold) {
+        launch_half_list(ne, s->Re, L.fneg, L.fhalf, L.fpair, L.fR, L.fkh, st);
+        launch_phase_table(prec, nk, p->kfrac, ne, L.fR, nullptr, ne, L.phi_f, st);
+    }
     launch_fill((size_t)nk * nb, 0.0, L.ebar, st);
     launch_fill(2 * (size_t)nk * nb * nb, 0.0, (double*)L.Ubar, st);
     if (dgR && (L.nchunks == 0) && !acc0)
@@ -925,7 +948,11 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_bf16_gemm(d, st);
         } else {
-            launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, nullptr, L.polar_L, s->Re);
+            // the folded recompute takes the 1/ndeg weights in B (its phases are
+            // unweighted), the generic GEMM in the phase table
+            launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, L.fold ? s->ndeg_e : nullptr,
+                               L.polar_L, s->Re);
+            if (L.fold) launch_fold_pairs(prec, ne, L.fkh, L.fhalf, L.fpair, ncols, L.Bnu, st);
         }
         if (!bf && L.nbp >= 16) {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
             GemmDesc d;
@@ -954,7 +981,10 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             a.qc = qc;
             a.q0 = q0;
             a.nq_total = nq;
-            a.phi_k = L.phi_k;
+            a.phi_k = L.phi_f;
+            a.half = L.fhalf;
+            a.pair = L.fpair;
+            a.kh = L.fkh;
             a.ldk = ne;
             a.nmax = 0;
             a.Re = s->Re;

@@ -442,14 +442,14 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     typedef typename ModeTypes<MODE>::CE CE;
     constexpr int BM = FusedShape<MODE, NBP>::BM, BN = FusedShape<MODE, NBP>::BN;
     // folded R_e -> k contraction (cfold_mainloop): float64 and float32 up
-    // to 8 padded bands, outside the store of the Wannier-basis vertex.
+    // to 8 padded bands, every kind (the adjoint's recompute included).
     // fcc 20^3: FP32 278 -> 226 ms per 4000-q launch, FP64 256 -> 204 ms per
     // 2000-q launch (K steps of 8 halved entries in two LDS stages: with
     // steps of 16 in one stage, as unfolded, the fold ran slower, 256 -> 288
     // ms, the doubled B staging of each step standing between its two
     // barriers); at 16 bands it did not pay (FP32 131 -> 155 ms per
     // mobility-shard launch).
-    constexpr bool FOLD = fused_fold_c(NBP, MODE) && KIND != 6 && !GEN;
+    constexpr bool FOLD = fused_fold_c(NBP, MODE) && !GEN;
     // K step: 8 for the float64 16 x 256 tile, whose B stage (16 complex
     // doubles per thread at K step 16) would not fit beside its accumulators,
     // and for the folded float64 loop
@@ -1235,10 +1235,10 @@ void launch_fused_t(const FusedArgs& a, int num_cu, hipStream_t stream) {
     constexpr bool CAN_GEN = MODE != 0;
     const bool gen = CAN_GEN && a.nmax > 0;
     // the folding instantiations read the halved R list (kh, half, pair)
-    if (fused_fold_c(NBP, MODE) && !a.gout && !(a.kh && a.half && a.pair))
+    if (fused_fold_c(NBP, MODE) && !(a.kh && a.half && a.pair))
         throw HipFailure{(int)hipErrorInvalidValue, "fused_k_kernel (folded sum without its R list)", __FILE__,
                          __LINE__};
-    const bool fold = fused_fold_c(NBP, MODE) && !a.gout;
+    const bool fold = fused_fold_c(NBP, MODE);
     const size_t dyn = gen ? (size_t)3 * BM * (2 * a.nmax + 1) * 8 + 4 * (size_t)a.ne
                            : fold ? 8 * (size_t)a.ne : 0;
     const dim3 grid((unsigned)G), block(256);

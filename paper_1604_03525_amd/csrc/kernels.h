@@ -158,9 +158,9 @@ struct FusedArgs {
     double* rec;       // [nk][qc][nm][nb] pole records of 4 + nbp doubles (pole mode)
     const double* vel; // [nk][nb][3] band velocities of the k set (transport mode, with part_ph)
     const double* vel_pair;  // [nk][qc][nb][3] velocities at k+q per pair (transport mode, off-grid)
-    // folded R_e -> k contraction (fused_fold_c, outside the store of the
-    // Wannier-basis vertex): B holds (B+, B-) in rows (half[h], pair[h]) and
-    // phi_k the phases of R_half; kh[0] = number of entries h
+    // folded R_e -> k contraction (fused_fold_c): B holds (B+, B-) in rows
+    // (half[h], pair[h]) and phi_k the phases of R_half; kh[0] = number of
+    // entries h
     const int32_t* half = nullptr;
     const int32_t* pair = nullptr;
     const int32_t* kh = nullptr;
