@@ -433,8 +433,15 @@ def main():
                                  "steps": ksteps, "dtype": bdt,
                                  "outputs": "dL/dg(R_e,R_p), dL/dH(R_e), dL/domega",
                                  "ratio_to_forward": (1e3 * dtb / ksteps) / ms_step if bdt == "fp64" else None,
-                                 "roofline": {"bound": "mfma", "kernel": "adjoint contractions (cgemm_generic_kernel%s)"
-                                              % (", bf16_gemm_kernel" if bdt == "split_bf16" else ""),
+                                 "roofline": {"bound": "mfma",
+                                              "kernel": "adjoint contractions (%s)"
+                                              % ("cgemm_generic_kernel, bf16_gemm_kernel" if bdt == "split_bf16"
+                                                 else "fused_k_kernel recompute, ksum_fold_kernel, "
+                                                      "cgemm_generic_kernel"),
+                                              "convention": None if bdt == "split_bf16" else
+                                              "algorithmic flops (8 per complex multiply-add); the R_e <-> k "
+                                              "sums run folded by the pairs (R, -R) with two real MFMAs per "
+                                              "R vector, so frac can exceed 1",
                                               "achieved": bach, "peak": bpeak, "unit": "TFLOP/s",
                                               "frac": bach / bpeak if bach else None, "traffic": None,
                                               "launches": bn, "gemm_ms_per_step": bms / ksteps,

@@ -1100,6 +1100,22 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.ldc = ncols;
             StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_bf16_gemm(d, st);
+        } else if (dgR && L.fold) {
+            // gbar_nu(R_e, q) = sum_k conj(Phi_k[k][R_e]) Gbar[k][col] / ndeg(R_e) over the
+            // pairs (R, -R): a real-by-complex product of the halved list
+            KsumFoldDesc d;
+            d.nk = nk;
+            d.ne = ne;
+            d.ncols = ncols;
+            d.phi = L.phi_f;
+            d.ld = ne;
+            d.G = L.G;
+            d.half = L.fhalf;
+            d.pair = L.fpair;
+            d.kh = L.fkh;
+            d.ndeg = s->ndeg_e;
+            StageTimer tg(EPW_STAGE_BWD_GEMM, st);
+            launch_ksum_fold(prec, d, std::min(splitk_parts(ne, (int)ncols, nk), L.kparts), L.kpart, L.Bnu, st);
         } else if (dgR) {
             GemmDesc d;   // gbar_nu(R_e, q) = sum_k conj(Phi_k[k][R_e]) Gbar[k][col]
             d.M = ne;

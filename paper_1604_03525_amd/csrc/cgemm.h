@@ -344,5 +344,108 @@ __device__ inline void cfold_mainloop(FoldStage<T, BM, BN, BK>* stages, int Kh, 
     }
 }
 
+// ---------------------------------------- real A times complex B main loop
+//
+// C (complex) = A (real) B (complex): two real MFMAs per block product
+// (A B re, A B im).  afetch(m, k) gives the real A entry, bfetch(k, n) the
+// complex B entry; the same block, wave and staging layout as cgemm_mainloop
+// (64-column tiles).
+template <typename T, int BM, int BN, int BK>
+struct RStage {
+    static constexpr int PAD = 16;
+    T a[BK][BM + PAD];
+    T b_re[BK][BN + PAD];
+    T b_im[BK][BN + PAD];
+};
+template <typename T, int BM, int BN, int BK, class AF, class BF, int NS = 2>
+__device__ inline void rgemm_mainloop(RStage<T, BM, BN, BK>* stages, int K, AF afetch, BF bfetch,
+                                      typename Cx<T>::acc (&cr)[4 * CWaves<BM, BN>::RB],
+                                      typename Cx<T>::acc (&ci)[4 * CWaves<BM, BN>::RB])
+{
+    static_assert(NS == 1 || NS == 2, "one or two LDS stages");
+    typedef typename Cx<T>::type CT;
+    constexpr int WN = CWaves<BM, BN>::WN;
+    constexpr int RB = CWaves<BM, BN>::RB;
+    static_assert(RB >= 1 && 16 * RB * (4 / WN) == BM && BN < 256, "wave layout");
+    constexpr int AE = BM * BK / 256;
+    constexpr int BE = BK * BN / 256;
+    static_assert(AE >= 1 && AE * 256 == BM * BK && BE >= 1 && BE * 256 == BK * BN, "tile for 256 threads");
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave / WN, wn = wave % WN;
+    T ra[AE];
+    CT rb[BE];
+    for (int c = 0; c < 4 * RB; ++c)
+        for (int i = 0; i < 4; ++i) {
+            cr[c][i] = T(0);
+            ci[c][i] = T(0);
+        }
+    // A is fetched k-fastest across threads (its source is K-major: a phase
+    // table [k][h]), B as in cgemm_mainloop
+    auto gload = [&](int k0) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            const int idx = tid * AE + e;
+            ra[e] = afetch(idx % BM, k0 + idx / BM);
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            const int idx = tid * BE + e;
+            rb[e] = bfetch(k0 + idx / BN, idx % BN);
+        }
+    };
+    auto sstore = [&](RStage<T, BM, BN, BK>& st) {
+#pragma unroll
+        for (int e = 0; e < AE; ++e) {
+            const int idx = tid * AE + e;
+            st.a[idx / BM][idx % BM] = ra[e];
+        }
+#pragma unroll
+        for (int e = 0; e < BE; ++e) {
+            const int idx = tid * BE + e;
+            st.b_re[idx / BN][idx % BN] = rb[e].x;
+            st.b_im[idx / BN][idx % BN] = rb[e].y;
+        }
+    };
+    gload(0);
+    sstore(stages[0]);
+    __syncthreads();
+    for (int k0 = 0, it = 0; k0 < K; k0 += BK, ++it) {
+        const bool more = k0 + BK < K;
+        if (more) gload(k0 + BK);
+        const RStage<T, BM, BN, BK>& st = stages[NS == 2 ? (it & 1) : 0];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const int kr = kk + (lane >> 4);
+            T av[RB];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) av[q] = st.a[kr][wm * 16 * RB + q * 16 + (lane & 15)];
+            T br[4], bi[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                br[c] = st.b_re[kr][wn * 64 + c * 16 + (lane & 15)];
+                bi[c] = st.b_im[kr][wn * 64 + c * 16 + (lane & 15)];
+            }
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) cr[q * 4 + c] = mfma4(av[q], br[c], cr[q * 4 + c]);
+#pragma unroll
+            for (int q = 0; q < RB; ++q)
+#pragma unroll
+                for (int c = 0; c < 4; ++c) ci[q * 4 + c] = mfma4(av[q], bi[c], ci[q * 4 + c]);
+        }
+        if constexpr (NS == 2) {
+            if (more) sstore(stages[(it + 1) & 1]);
+            __syncthreads();
+        } else {
+            __syncthreads();
+            if (more) {
+                sstore(stages[0]);
+                __syncthreads();
+            }
+        }
+    }
+}
+
 }  // namespace
 }  // namespace epw

@@ -170,6 +170,85 @@ int splitk_parts(int M, int N, int K) {
     return parts < 1 ? 1 : (int)parts;
 }
 
+// The adjoint's sum over k, gbar(R_e, col) = sum_k conj(Phi_k(R_e)) Gbar[k][col]
+// / ndeg(R_e), folded by the pairs (R, -R) of the halved R list: with
+// c + i s = Phi_k(R_h) (unweighted), P = sum_k c Gbar_k and Q = sum_k s Gbar_k,
+//   gbar(R_h) = (P - i Q) / ndeg(R_h),   gbar(-R_h) = (P + i Q) / ndeg(-R_h),
+// a real-by-complex product of 2 kh rows: two real MFMAs per block where the
+// complex form takes three over N_e rows.  A 64-row tile holds P and Q of 32
+// entries h, placed so that both land in the same lane of the MFMA result
+// (each 16-row block: 8 entries, P and Q), where they are unfolded.
+template <typename T>
+__global__ __launch_bounds__(256, 2) void ksum_fold_kernel(KsumFoldDesc d)
+{
+    typedef typename Cx<T>::type CT;
+    constexpr int BM = 64, BN = 64, BK = 16;
+    __shared__ RStage<T, BM, BN, BK> st[2];
+    const int kh = d.kh[0];
+    const int tiles_m = (d.ne + 31) / 32;
+    const long bx = blockIdx.x;
+    const int mt = (int)(bx % tiles_m);
+    const long nt = bx / tiles_m;
+    const int h0 = mt * 32;
+    if (h0 >= kh) return;
+    const long n0 = nt * BN;
+    const int kb = d.kchunk > 0 ? (int)blockIdx.z * d.kchunk : 0;
+    const int Kz = d.kchunk > 0 ? min(d.kchunk, d.nk - kb) : d.nk;
+    const CT* phi = reinterpret_cast<const CT*>(d.phi);
+    const CT* G = reinterpret_cast<const CT*>(d.G);
+    // row m of the tile: entry h and part (0: P, from c; 1: Q, from s)
+    auto rowmap = [&](int m, int& h, int& part) {
+        const int b = m >> 4, l = m & 15;
+        if (sizeof(T) == 8) {        // f64 result rows l/16 + 4i: i and i + 1 hold P and Q
+            h = h0 + 8 * b + (l & 3) + 4 * (l >> 3);
+            part = (l >> 2) & 1;
+        } else {                     // f32 result rows 4 (l/16) + i
+            h = h0 + 8 * b + 2 * (l >> 2) + ((l & 3) >> 1);
+            part = l & 1;
+        }
+    };
+    auto afetch = [&](int m, int kl) -> T {
+        int h, part;
+        rowmap(m, h, part);
+        if (h < kh && kl < Kz) {
+            const CT v = phi[(size_t)(kb + kl) * d.ld + h];
+            return part ? v.y : v.x;
+        }
+        return T(0);
+    };
+    auto bfetch = [&](int kl, int n) -> CT {
+        const long col = n0 + n;
+        if (kl < Kz && col < d.ncols) return G[(size_t)(kb + kl) * d.ncols + col];
+        return cz<T>();
+    };
+    typename Cx<T>::acc cr[4], ci[4];
+    rgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), 2>(st, Kz, afetch, bfetch, cr, ci);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    CT* out = reinterpret_cast<CT*>(d.out) + (size_t)blockIdx.z * d.ne * d.ncols;
+    for (int c = 0; c < 4; ++c) {
+        const long col = n0 + c * 16 + (lane & 15);
+        if (col >= d.ncols) continue;
+        for (int i = 0; i < 4; i += 2) {
+            int h, part;
+            rowmap(wave * 16 + crow<T>(lane, i), h, part);   // part 0; element i + 1 holds Q
+            if (h >= kh) continue;
+            const T pr = cr[c][i], pim = ci[c][i], qr = cr[c][i + 1], qim = ci[c][i + 1];
+            const int e1 = d.half[h], e2 = d.pair[h];
+            const T w1 = T(1) / (T)d.ndeg[e1];
+            CT v;
+            v.x = (pr + qim) * w1;
+            v.y = (pim - qr) * w1;
+            out[(size_t)e1 * d.ncols + col] = v;
+            if (e2 != e1) {
+                const T w2 = T(1) / (T)d.ndeg[e2];
+                v.x = (pr - qim) * w2;
+                v.y = (pim + qr) * w2;
+                out[(size_t)e2 * d.ncols + col] = v;
+            }
+        }
+    }
+}
+
 void launch_cgemm_splitk(Prec prec, const GemmDesc& d, int parts, void* scratch, hipStream_t stream) {
     if (d.M <= 0 || d.N <= 0) return;
     if (parts <= 1 || d.ncb != d.N || d.kchunk != 0) {
@@ -194,6 +273,35 @@ void launch_cgemm_splitk(Prec prec, const GemmDesc& d, int parts, void* scratch,
         splitk_reduce_kernel<float2><<<nb, 256, 0, stream>>>(d.M, d.N, nz, (const float2*)scratch, d.sCm,
                                                              d.accumulate, (float2*)d.C);
     launch_check("splitk_reduce_kernel");
+}
+
+void launch_ksum_fold(Prec prec, const KsumFoldDesc& desc, int parts, void* scratch, void* C, hipStream_t stream) {
+    if (desc.ne <= 0 || desc.ncols <= 0) return;
+    KsumFoldDesc d = desc;
+    int nz = 1;
+    if (parts > 1 && d.nk > 16) {
+        d.kchunk = ((d.nk + parts - 1) / parts + 15) / 16 * 16;
+        nz = (d.nk + d.kchunk - 1) / d.kchunk;
+    } else {
+        d.kchunk = 0;
+    }
+    d.out = nz > 1 ? scratch : C;
+    const long tiles = (long)((d.ne + 31) / 32) * ((d.ncols + 63) / 64);
+    const dim3 grid((unsigned)tiles, 1, (unsigned)nz);
+    if (prec == Prec::F64) ksum_fold_kernel<double><<<grid, 256, 0, stream>>>(d);
+    else ksum_fold_kernel<float><<<grid, 256, 0, stream>>>(d);
+    launch_check("ksum_fold_kernel");
+    if (nz > 1) {
+        const size_t MN = (size_t)d.ne * d.ncols;
+        const unsigned nb = (unsigned)((MN + 255) / 256);
+        if (prec == Prec::F64)
+            splitk_reduce_kernel<double2><<<nb, 256, 0, stream>>>(d.ne, (int)d.ncols, nz, (const double2*)scratch,
+                                                                   d.ncols, 0, (double2*)C);
+        else
+            splitk_reduce_kernel<float2><<<nb, 256, 0, stream>>>(d.ne, (int)d.ncols, nz, (const float2*)scratch,
+                                                                 d.ncols, 0, (float2*)C);
+        launch_check("splitk_reduce_kernel");
+    }
 }
 
 void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream, int kparts) {

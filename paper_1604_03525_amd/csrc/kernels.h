@@ -233,6 +233,25 @@ int splitk_parts_wide(int M, int N, int K, int max_parts);
 // summed in fixed order into C; needs a single column slab (d.ncb == d.N)
 void launch_cgemm_splitk(Prec prec, const GemmDesc& d, int parts, void* scratch, hipStream_t stream);
 
+// the adjoint's sum over k folded by the pairs of the halved R list:
+// C[e][col] = sum_k conj(Phi_k(R_e)) G[k][col] / ndeg(R_e) for every row e of
+// C [ne][ncols], with phi the unweighted phases of R_half ([nk][ld]);
+// `parts` K slices in scratch ([parts][ne][ncols]) summed in fixed order
+struct KsumFoldDesc {
+    int nk = 0, ne = 0;
+    long ncols = 0;
+    const void* phi = nullptr;
+    int ld = 0;
+    const void* G = nullptr;
+    const int32_t* half = nullptr;
+    const int32_t* pair = nullptr;
+    const int32_t* kh = nullptr;
+    const int32_t* ndeg = nullptr;
+    void* out = nullptr;     // set by the launcher
+    int kchunk = 0;          // set by the launcher
+};
+void launch_ksum_fold(Prec prec, const KsumFoldDesc& d, int parts, void* scratch, void* C, hipStream_t stream);
+
 // ---- k_backward.hip (adjoint of L = sum_nk w_nk Im Sigma_nk) ----
 struct PairBwdArgs {
     int nk, nb, nbp, nm;
