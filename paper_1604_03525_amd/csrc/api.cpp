@@ -730,9 +730,12 @@ struct BwdLayout {
     void* phi_q = nullptr;
     void* gq = nullptr;      // a5 output, reused for the mode-basis adjoint
     void* Bnu = nullptr;     // a6 output, reused for gbar_nu(R_e,q)
-    // folded recompute of G (float64 / float32 up to 8 padded bands): the
-    // halved R list (as in the forward) and its unweighted phases; B then
+    // folded sums over R_e <-> k (float64 / float32): the halved R list (as
+    // in the forward) and its unweighted phases serve the sum over k
+    // (ksum_fold_kernel) at every band count (fold_tab) and the recompute of G
+    // on the fused kernel's tiling below 16 padded bands (fold), where B then
     // carries the 1/ndeg weights
+    bool fold_tab = false;
     bool fold = false;
     int32_t* fneg = nullptr;
     int32_t* fhalf = nullptr;
@@ -800,8 +803,9 @@ void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, A
     L.ftab = (double*)A.take(8 * (size_t)nk * nb);
     L.wbar = (double*)A.take(8 * (size_t)nk * nb);
     L.phi_k = A.take(bf ? 8 * (size_t)nk * L.kpad : cb * (size_t)nk * ne);
-    L.fold = !bf && fused_fold_c(L.nbp, (int)L.prec);
-    if (L.fold) {
+    L.fold_tab = !bf;
+    L.fold = L.fold_tab && L.nbp < 16 && fused_fold_c(L.nbp, (int)L.prec);
+    if (L.fold_tab) {
         L.fneg = (int32_t*)A.take(4 * (size_t)ne);
         L.fhalf = (int32_t*)A.take(4 * (size_t)ne);
         L.fpair = (int32_t*)A.take(4 * (size_t)ne);
@@ -878,7 +882,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
     } else {
         launch_phase_table(prec, nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, L.phi_k, st);
     }
-    if (L.fold) {
+    if (L.fold_tab) {
         launch_half_list(ne, s->Re, L.fneg, L.fhalf, L.fpair, L.fR, L.fkh, st);
         launch_phase_table(prec, nk, p->kfrac, ne, L.fR, nullptr, ne, L.phi_f, st);
     }
@@ -1100,7 +1104,7 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
             d.ldc = ncols;
             StageTimer tg(EPW_STAGE_BWD_GEMM, st);
             launch_bf16_gemm(d, st);
-        } else if (dgR && L.fold) {
+        } else if (dgR && L.fold_tab) {
             // gbar_nu(R_e, q) = sum_k conj(Phi_k[k][R_e]) Gbar[k][col] / ndeg(R_e) over the
             // pairs (R, -R): a real-by-complex product of the halved list
             KsumFoldDesc d;

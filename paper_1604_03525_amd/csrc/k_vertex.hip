@@ -441,19 +441,21 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     typedef typename ModeTypes<MODE>::TE TE;
     typedef typename ModeTypes<MODE>::CE CE;
     constexpr int BM = FusedShape<MODE, NBP>::BM, BN = FusedShape<MODE, NBP>::BN;
-    // folded R_e -> k contraction (cfold_mainloop): float64 and float32 up
+    // folded R_e -> k contraction (cfold_mainloop): float64, and float32 up
     // to 8 padded bands, every kind (the adjoint's recompute included).
     // fcc 20^3: FP32 278 -> 226 ms per 4000-q launch, FP64 256 -> 204 ms per
     // 2000-q launch (K steps of 8 halved entries in two LDS stages: with
     // steps of 16 in one stage, as unfolded, the fold ran slower, 256 -> 288
     // ms, the doubled B staging of each step standing between its two
-    // barriers); at 16 bands it did not pay (FP32 131 -> 155 ms per
-    // mobility-shard launch).
+    // barriers); mobility shard at 16 bands: FP64 205 -> 168 ms per launch
+    // (K steps of 4 in two stages), FP32 131 -> 155 ms with one stage, and
+    // two stages with the row indices exceed the LDS of two blocks.
     constexpr bool FOLD = fused_fold_c(NBP, MODE) && !GEN;
     // K step: 8 for the float64 16 x 256 tile, whose B stage (16 complex
     // doubles per thread at K step 16) would not fit beside its accumulators,
-    // and for the folded float64 loop
-    constexpr int BK = (MODE == 0 && (NBP >= 16 || FOLD)) ? 8 : 16;
+    // and for the folded float64 loop below 16 bands; 4 for the folded one
+    // at 16 bands
+    constexpr int BK = (MODE == 0 && NBP >= 16 && FOLD) ? 4 : (MODE == 0 && (NBP >= 16 || FOLD)) ? 8 : 16;
     constexpr int NB2 = NBP * NBP;
     constexpr int TPR = 256 / BM;                  // threads per k row
     // Epilogue work items of a row: (band block b, band x), x < NBP; thread

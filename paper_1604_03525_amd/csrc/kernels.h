@@ -180,8 +180,9 @@ inline int fused_part_slots(const FusedArgs& a) { return a.helpers > 0 ? 2 * a.S
 // precision at 16 padded bands (mode 0 float64, 1 float32, 2 split-bf16)
 constexpr bool fused_balanced_c(int nbp, int mode) { return mode == 1 || nbp >= 16; }
 // fused-kernel instantiations that fold the R_e -> k sum by pairs (R, -R):
-// float64 and float32 up to 8 padded bands
-constexpr bool fused_fold_c(int nbp, int mode) { return mode != 2 && nbp <= 8; }
+// float64, and float32 up to 8 padded bands (at 16 its stages and the row
+// indices would not fit two blocks per CU)
+constexpr bool fused_fold_c(int nbp, int mode) { return mode == 0 || (mode == 1 && nbp <= 8); }
 // columns and k rows per tile of the fused kernel for a padded band count:
 // whole band blocks, at least 64 columns; 4096 complex entries, 8192 for
 // float32 and split-bf16 at 16 bands (32 x 256); `wide` = not float64
