@@ -464,7 +464,12 @@ __global__ __launch_bounds__(256, 2) void fused_k_kernel(FusedArgs a, int tiles_
     constexpr int JI = BN / (NBP * TPR);
     constexpr int RUN = JI < NBP ? JI : NBP;
     constexpr int NRUN = JI / RUN;
-    constexpr int RT = (MODE == 2 || (MODE == 1 && NBP >= 16)) ? 1 : RUN;   // bands of a run taken together in phase 2
+    // bands of a run taken together in phase 2: one for split-bf16, float32 at
+    // 16 bands and the float64 Im Sigma reduction, whose k+q eigenvector
+    // columns then leave its accumulators in registers (fcc 20^3: 116 bytes
+    // per lane of spills, 29 GB of spill stores per launch -> none; 203 -> 191
+    // ms per 2000-q launch; the phonon kind ran 3.5 % slower so and keeps RUN)
+    constexpr int RT = (MODE == 2 || (MODE == 1 && NBP >= 16) || (MODE == 0 && KIND == 0)) ? 1 : RUN;
     static_assert(JI * NBP * TPR == BN && JI % RUN == 0 && NBP % RUN == 0, "epilogue split");
     constexpr int LDC = BN + 1;                    // C tile row stride: rows start on different LDS banks
     typedef typename PickType<FOLD, FoldStage<T, BM, BN, BK>, Stage<T, BM, BN, BK>>::type St;
