@@ -776,7 +776,10 @@ struct BwdLayout {
     double* dHR_pair = nullptr;  // [N_e][n_b][n_b] c128
 };
 
-constexpr size_t AUTO_BWD_CHUNK_BYTES = (size_t)16 << 30;
+// automatic q chunk of the adjoint: its per-q scratch holds the recomputed
+// vertex of every k (77 MB per q on the fcc 20^3 workload); 32 GB gives ~440 q
+// per chunk there (FP64 adjoint 2071 -> 2019 ms against a 16 GB budget)
+constexpr size_t AUTO_BWD_CHUNK_BYTES = (size_t)32 << 30;
 
 void plan_bwd(const epw_system* s, const epw_points* p, const epw_params* par, Arena& A, BwdLayout& L) {
     L.prec = (Prec)par->dtype;
