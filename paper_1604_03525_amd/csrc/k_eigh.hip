@@ -1,5 +1,5 @@
 // Interpolation of small Hermitian matrices (H(k), D(q)) from real space and
-// their float64 eigendecomposition, one wavefront per point.
+// their float64 eigendecomposition, four points per wavefront.
 //
 // X(p) = sum_R exp(2 pi i p.R) X(R)/ndeg(R): the phases of a block of R
 // vectors are staged in LDS; lanes split the (entry, R) work, partial sums
@@ -10,13 +10,19 @@
 // the 2 x 2 block of rows of one pair and columns of another depends only
 // on itself, so each lane updates one block in a single step (no barrier
 // between the column and the row rotations) and no two lanes touch the same
-// entry.  Jacobi is used because it reaches full float64 accuracy
-// for eigenvalues and eigenvectors at these sizes (n <= 16) and maps onto a
-// single wave without serial Householder steps.
+// entry; only the blocks above the diagonal are computed (A stays exactly
+// Hermitian).  The eigenvector matrix V <- V J stays in registers, one row per
+// lane: the pairs of each round are compile-time constants, so the rotation
+// of a row needs no indexing at run time and only A passes through LDS.
+// Jacobi is used because it reaches full float64 accuracy for eigenvalues and
+// eigenvectors at these sizes (n <= 16) and maps onto a wave without serial
+// Householder steps.
 #include <hip/hip_runtime.h>
 
 #include "epw_internal.h"
 #include "kernels.h"
+
+#include <utility>
 
 namespace epw {
 namespace {
@@ -34,11 +40,27 @@ __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// pair i of round r of the round-robin schedule on n2 (even) indices:
-// index n2 - 1 stays fixed, the others rotate (r < n2 - 1, i < n2 / 2, so
-// one conditional subtraction does the reduction mod n2 - 1)
-__device__ inline void rr_pair(int n2, int r, int i, int& p, int& q) {
-    const int m = n2 - 1;
+// pair i of round r of the round-robin schedule on MAXN indices: index
+// MAXN - 1 stays fixed, the others rotate (r < MAXN - 1, i < MAXN / 2).  Every
+// matrix runs on MAXN indices, those at or beyond its size n being zero rows
+// and columns whose pairs are not rotated; a sweep (MAXN - 1 rounds) still
+// meets every pair of indices below n once.  constexpr: with r and i known
+// at compile time the indices are constants, which keeps the rows of V in
+// registers.
+__host__ __device__ constexpr int rr_p(int r, int i) {
+    const int m = MAXN - 1;
+    const int a = (r + i) % m;
+    const int b = i == 0 ? m : (r - i + m) % m;
+    return a < b ? a : b;
+}
+__host__ __device__ constexpr int rr_q(int r, int i) {
+    const int m = MAXN - 1;
+    const int a = (r + i) % m;
+    const int b = i == 0 ? m : (r - i + m) % m;
+    return a < b ? b : a;
+}
+__device__ inline void rr_pair(int r, int i, int& p, int& q) {
+    const int m = MAXN - 1;
     int a = r + i;
     if (a >= m) a -= m;
     int b = r - i + m;
@@ -65,13 +87,54 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
     return y;
 }
 
-// sum over the 64 lanes of the wave; every lane receives the same value
-// (each butterfly step adds the same two operands in every lane)
-__device__ inline double wave_sum(double v) {
+// sum over the 16 lanes of one matrix (lanes 16 h .. 16 h + 15); every lane
+// of the group receives the same value
+__device__ inline double group_sum(double v) {
 #pragma unroll
-    for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     return v;
 }
+
+// V <- V J for round R on one row v of V (registers): the columns (p, q) of
+// each pair U, with the pair's parameters rt[U] = {c, s, cos phi, sin phi}.
+template <int R, int U>
+__device__ __forceinline__ void vrot_pair(double2 (&v)[MAXN], const double (*rt)[4]) {
+    constexpr int p = rr_p(R, U), q = rr_q(R, U);
+    const double c = rt[U][0], s = rt[U][1];
+    const double2 e = make_double2(rt[U][2], -rt[U][3]);
+    const double2 w = cmul(v[q], e);
+    const double2 x = v[p];
+    v[p] = make_double2(c * x.x - s * w.x, c * x.y - s * w.y);
+    v[q] = make_double2(s * x.x + c * w.x, s * x.y + c * w.y);
+}
+template <int R, int... U>
+__device__ __forceinline__ void vrot_round(double2 (&v)[MAXN], const double (*rt)[4],
+                                           std::integer_sequence<int, U...>) {
+    (vrot_pair<R, U>(v, rt), ...);
+}
+template <int... R>
+__device__ __forceinline__ void vrot(int r, double2 (&v)[MAXN], const double (*rt)[4],
+                                     std::integer_sequence<int, R...>) {
+    ((r == R ? vrot_round<R>(v, rt, std::make_integer_sequence<int, MAXN / 2>{}) : void()), ...);
+}
+
+// Four matrices per wave (matrix h of a block is point MPW blockIdx.x + h).
+// A (Hermitian, full) is in LDS; lane 16 h + i holds row i of V of matrix h
+// in registers.  A Jacobi round:
+//   - lane 8 h + u (u < 8, 32 lanes) computes the rotation of pair u of
+//     matrix h and writes the pair's own 2 x 2 diagonal block in closed form
+//     (a_pp - t |b|, a_qq + t |b|, exact zeros off the diagonal);
+//   - the 4 x 28 off-diagonal blocks (pairs P1 < P2) are rotated in two
+//     passes over the 64 lanes; each writes its block and the conjugate
+//     transpose, so A stays exactly Hermitian and no lane reads what
+//     another writes;
+//   - every lane rotates its row of V by all pairs of the round.
+// A matrix that has converged takes identity rotations, which change nothing
+// (exactly), so its result does not depend on the other matrices of its wave.
+constexpr int MPW = 4;
+constexpr int NPAIR = MAXN / 2;
+constexpr int NBLK = NPAIR * (NPAIR - 1) / 2;
+constexpr int APASS = (MPW * NBLK + 63) / 64;
 
 // REAL_IN: X(R) is real (dynamical matrix); else complex interleaved.
 // SQRT_OUT: write omega = sign(l) sqrt|l| instead of the eigenvalue l.
@@ -86,160 +149,193 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     const double* __restrict__ pts2, int npts2,
     double* __restrict__ evals, double2* __restrict__ evecs)
 {
-    __shared__ double2 A[MAXN + 1][LDA];
-    __shared__ double2 V[MAXN + 1][LDA];
-    __shared__ double2 ph[RBLK];
-    __shared__ double2 red[64];
-    __shared__ double rot[MAXN / 2][4];
-    __shared__ int rpq[MAXN / 2][2];
+    __shared__ double2 A[MPW][MAXN][LDA];
+    __shared__ double2 ph[GIVEN ? 1 : RBLK];
+    __shared__ double2 red[GIVEN ? 1 : 64];
+    __shared__ double rot[MPW][NPAIR][4];
+    __shared__ int rpq[MPW][NPAIR][2];
+    __shared__ int rk[MPW][MAXN];
 
     const int lane = threadIdx.x;
-    const int p = blockIdx.x;
-    if (p >= np) return;
-    if constexpr (GIVEN && PACKED) {
-        const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * (n * (n + 1) / 2);
-        for (int e = lane; e < n * n; e += 64) {
-            const int i = e / n, j = e % n;
-            if (i > j) continue;
-            const double2 x = X[i * n - i * (i - 1) / 2 + (j - i)];
-            V[i][j] = x;
-            if (i < j) V[j][i] = make_double2(x.x, -x.y);
-        }
-    } else if constexpr (GIVEN) {
-        const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * n * n;
-        for (int e = lane; e < n * n; e += 64) V[e / n][e % n] = X[e];
-    } else {
-        // point p, or the sum pts[p / npts2] + pts2[p % npts2] in pair mode
-        const size_t ia = pts2 ? (size_t)(p / npts2) : (size_t)p;
-        double k0 = pts[3 * ia + 0];
-        double k1 = pts[3 * ia + 1];
-        double k2 = pts[3 * ia + 2];
-        if (pts2) {
-            const size_t ib = (size_t)(p % npts2);
-            k0 += pts2[3 * ib + 0];
-            k1 += pts2[3 * ib + 1];
-            k2 += pts2[3 * ib + 2];
-        }
-        const int E = n * n;
-        const int P = (E >= 64) ? 1 : 64 / E;          // R partitions per entry
-        const int EPL = (E + 63) / 64;                   // entries per lane when P == 1
-
-        double2 acc[4];
-        for (int j = 0; j < 4; ++j) acc[j] = make_double2(0.0, 0.0);
-
-        for (int r0 = 0; r0 < nR; r0 += RBLK) {
-            const int cnt = min(RBLK, nR - r0);
-            __syncthreads();
-            for (int r = lane; r < cnt; r += 64) {
-                const int idx = r0 + r;
-                double x = k0 * (double)R[3 * idx] + k1 * (double)R[3 * idx + 1] +
-                           k2 * (double)R[3 * idx + 2];
-                x -= rint(x);
-                double s, c;
-                sincospi(2.0 * x, &s, &c);
-                const double w = 1.0 / (double)ndeg[idx];
-                ph[r] = make_double2(c * w, s * w);
+    const int p0 = blockIdx.x * MPW;
+    if (p0 >= np) return;
+    const int nmat = min(MPW, np - p0);
+    for (int e = lane; e < MPW * MAXN * MAXN; e += 64)
+        A[e >> (2 * LOGN)][(e >> LOGN) & (MAXN - 1)][e & (MAXN - 1)] = make_double2(0.0, 0.0);
+    __syncthreads();
+    // the raw matrices of the block's points -> A[h], one after the other
+    for (int h = 0; h < nmat; ++h) {
+        const int p = p0 + h;
+        if constexpr (GIVEN && PACKED) {
+            const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * (n * (n + 1) / 2);
+            for (int e = lane; e < n * n; e += 64) {
+                const int i = e / n, j = e % n;
+                if (i > j) continue;
+                const double2 x = X[i * n - i * (i - 1) / 2 + (j - i)];
+                A[h][i][j] = x;
+                if (i < j) A[h][j][i] = make_double2(x.x, -x.y);
             }
-            __syncthreads();
-            if (P > 1) {
-                const int e = lane % E, part = lane / E;
-                if (part < P) {
-                    for (int r = part; r < cnt; r += P) {
-                        const double2 f = ph[r];
-                        if (REAL_IN) {
-                            const double x = XR[(size_t)(r0 + r) * E + e];
-                            acc[0].x += f.x * x;
-                            acc[0].y += f.y * x;
-                        } else {
-                            const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
-                            const double2 t = cmul(f, x);
-                            acc[0].x += t.x;
-                            acc[0].y += t.y;
+        } else if constexpr (GIVEN) {
+            const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * n * n;
+            for (int e = lane; e < n * n; e += 64) A[h][e / n][e % n] = X[e];
+        } else {
+            // point p, or the sum pts[p / npts2] + pts2[p % npts2] in pair mode
+            const size_t ia = pts2 ? (size_t)(p / npts2) : (size_t)p;
+            double k0 = pts[3 * ia + 0];
+            double k1 = pts[3 * ia + 1];
+            double k2 = pts[3 * ia + 2];
+            if (pts2) {
+                const size_t ib = (size_t)(p % npts2);
+                k0 += pts2[3 * ib + 0];
+                k1 += pts2[3 * ib + 1];
+                k2 += pts2[3 * ib + 2];
+            }
+            const int E = n * n;
+            const int P = (E >= 64) ? 1 : 64 / E;          // R partitions per entry
+            const int EPL = (E + 63) / 64;                   // entries per lane when P == 1
+
+            double2 acc[4];
+            for (int j = 0; j < 4; ++j) acc[j] = make_double2(0.0, 0.0);
+
+            for (int r0 = 0; r0 < nR; r0 += RBLK) {
+                const int cnt = min(RBLK, nR - r0);
+                __syncthreads();
+                for (int r = lane; r < cnt; r += 64) {
+                    const int idx = r0 + r;
+                    double x = k0 * (double)R[3 * idx] + k1 * (double)R[3 * idx + 1] +
+                               k2 * (double)R[3 * idx + 2];
+                    x -= rint(x);
+                    double s, c;
+                    sincospi(2.0 * x, &s, &c);
+                    const double w = 1.0 / (double)ndeg[idx];
+                    ph[r] = make_double2(c * w, s * w);
+                }
+                __syncthreads();
+                if (P > 1) {
+                    const int e = lane % E, part = lane / E;
+                    if (part < P) {
+                        for (int r = part; r < cnt; r += P) {
+                            const double2 f = ph[r];
+                            if (REAL_IN) {
+                                const double x = XR[(size_t)(r0 + r) * E + e];
+                                acc[0].x += f.x * x;
+                                acc[0].y += f.y * x;
+                            } else {
+                                const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
+                                const double2 t = cmul(f, x);
+                                acc[0].x += t.x;
+                                acc[0].y += t.y;
+                            }
                         }
                     }
+                } else {
+                    for (int j = 0; j < EPL; ++j) {
+                        const int e = lane + 64 * j;
+                        if (e >= E) break;
+                        for (int r = 0; r < cnt; ++r) {
+                            const double2 f = ph[r];
+                            if (REAL_IN) {
+                                const double x = XR[(size_t)(r0 + r) * E + e];
+                                acc[j].x += f.x * x;
+                                acc[j].y += f.y * x;
+                            } else {
+                                const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
+                                const double2 t = cmul(f, x);
+                                acc[j].x += t.x;
+                                acc[j].y += t.y;
+                            }
+                        }
+                    }
+                }
+            }
+            if (P > 1) {
+                red[lane] = acc[0];
+                __syncthreads();
+                if (lane < E) {
+                    double2 s = make_double2(0.0, 0.0);
+                    for (int part = 0; part < P; ++part) {
+                        s.x += red[lane + E * part].x;
+                        s.y += red[lane + E * part].y;
+                    }
+                    A[h][lane / n][lane % n] = s;
                 }
             } else {
                 for (int j = 0; j < EPL; ++j) {
                     const int e = lane + 64 * j;
-                    if (e >= E) break;
-                    for (int r = 0; r < cnt; ++r) {
-                        const double2 f = ph[r];
-                        if (REAL_IN) {
-                            const double x = XR[(size_t)(r0 + r) * E + e];
-                            acc[j].x += f.x * x;
-                            acc[j].y += f.y * x;
-                        } else {
-                            const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
-                            const double2 t = cmul(f, x);
-                            acc[j].x += t.x;
-                            acc[j].y += t.y;
-                        }
-                    }
+                    if (e < E) A[h][e / n][e % n] = acc[j];
                 }
             }
-        }
-        // raw interpolated matrix -> V (scratch)
-        if (P > 1) {
-            red[lane] = acc[0];
-            __syncthreads();
-            if (lane < E) {
-                double2 s = make_double2(0.0, 0.0);
-                for (int part = 0; part < P; ++part) {
-                    s.x += red[lane + E * part].x;
-                    s.y += red[lane + E * part].y;
-                }
-                V[lane / n][lane % n] = s;
-            }
-        } else {
-            for (int j = 0; j < EPL; ++j) {
-                const int e = lane + 64 * j;
-                if (e < E) V[e / n][e % n] = acc[j];
-            }
-        }
-    }   // Fourier sum
-    __syncthreads();
-    // Hermitise into A; V <- identity; padding row/column of zeros
-    const int n2 = n + (n & 1);
-    for (int e = lane; e < n2 * n2; e += 64) {
-        const int i = e / n2, j = e % n2;
-        double2 a = make_double2(0.0, 0.0);
-        if (i < n && j < n) {
-            const double2 x = V[i][j], y = V[j][i];
-            a = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
-        }
-        A[i][j] = a;
+        }   // Fourier sum
+        __syncthreads();
     }
-    __syncthreads();
-    for (int e = lane; e < n2 * n2; e += 64) {
-        const int i = e / n2, j = e % n2;
-        V[i][j] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    // Hermitise in place: the lane of (i, j), i <= j, writes both entries
+    for (int e = lane; e < MPW * MAXN * MAXN; e += 64) {
+        const int h = e >> (2 * LOGN), i = (e >> LOGN) & (MAXN - 1), j = e & (MAXN - 1);
+        if (i > j || h >= nmat || j >= n) continue;
+        const double2 x = A[h][i][j], y = A[h][j][i];
+        const double2 a = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+        A[h][i][j] = a;
+        A[h][j][i] = make_double2(a.x, -a.y);
     }
     __syncthreads();
 
-    const int npair = n2 / 2;
-    for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
-        // convergence: off-diagonal mass against the whole matrix
-        double off = 0.0, dia = 0.0;
-        for (int e = lane; e < MAXN * MAXN; e += 64) {
-            const int i = e >> LOGN, j = e & (MAXN - 1);
-            if (i >= n || j >= n) continue;
-            const double2 a = A[i][j];
-            const double m2 = a.x * a.x + a.y * a.y;
-            if (i == j) dia += m2; else off += m2;
+    // row `vr` of V of matrix `vh` in registers
+    const int vh = lane >> LOGN, vr = lane & (MAXN - 1);
+    double2 v[MAXN];
+#pragma unroll
+    for (int j = 0; j < MAXN; ++j) v[j] = make_double2(j == vr ? 1.0 : 0.0, 0.0);
+    // rotation parameters: lane 8 ph_h + ph_u, for the 32 lanes below 32
+    const int ph_h = lane >> 3, ph_u = lane & (NPAIR - 1);
+    // off-diagonal blocks of the two passes: matrix, pairs (B1 < B2)
+    int bh[APASS], b1[APASS], b2[APASS];
+    bool bv[APASS];
+#pragma unroll
+    for (int k = 0; k < APASS; ++k) {
+        const int item = lane + 64 * k;
+        bv[k] = item < MPW * NBLK;
+        bh[k] = item / NBLK;
+        int w = item - bh[k] * NBLK;
+        b1[k] = 0;
+        b2[k] = 0;
+        for (int a = 0; a < NPAIR - 1; ++a) {
+            const int cnt = NPAIR - 1 - a;
+            if (w >= 0 && w < cnt) {
+                b1[k] = a;
+                b2[k] = a + 1 + w;
+            }
+            w -= cnt;
         }
-        const double so = wave_sum(off), sd = wave_sum(dia);
-        if (so <= 1e-30 * (so + sd)) break;   // the same decision in every lane
-        for (int r = 0; r < n2 - 1; ++r) {
-            // rotation of pair `lane`: J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on
-            // indices (p, q), which zeroes A[p][q] = |b| e^{i phi} of J^H A J.
-            // An inactive pair (q is the padding index of odd n) keeps J = 1.
-            if (lane < npair) {
+    }
+    for (int sweep = 0; sweep < MAX_SWEEPS; ++sweep) {
+        // convergence of matrix vh: off-diagonal mass against the whole matrix,
+        // lane vr summing row vr
+        double off = 0.0, dia = 0.0;
+        if (vr < n) {
+#pragma unroll
+            for (int j = 0; j < MAXN; ++j) {
+                if (j >= n) continue;
+                const double2 a = A[vh][vr][j];
+                const double m2 = a.x * a.x + a.y * a.y;
+                if (j == vr) dia += m2; else off += m2;
+            }
+        }
+        const double so = group_sum(off), sd = group_sum(dia);
+        const bool done = so <= 1e-30 * (so + sd);   // the same decision in the 16 lanes of a matrix
+        const unsigned long long dmask = __ballot(done);
+        if (dmask == ~0ull) break;
+        const bool ph_done = (dmask >> (16 * ph_h)) & 1ull;
+        for (int r = 0; r < MAXN - 1; ++r) {
+            // rotation of pair ph_u: J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on
+            // indices (p, q), which zeroes A[p][q] = |b| e^{i phi} of J^H A J.  A pair
+            // with q >= n (zero row and column) and a converged matrix keep J = 1.
+            if (lane < MPW * NPAIR) {
                 int pp, qq;
-                rr_pair(n2, r, lane, pp, qq);
+                rr_pair(r, ph_u, pp, qq);
                 double c = 1.0, s = 0.0, cph = 1.0, sph = 0.0;
-                if (qq < n) {
-                    const double app = A[pp][pp].x, aqq = A[qq][qq].x;
-                    const double2 b = A[pp][qq];
+                if (!ph_done && qq < n) {
+                    const double app = A[ph_h][pp][pp].x, aqq = A[ph_h][qq][qq].x;
+                    const double2 b = A[ph_h][pp][qq];
+                    double tb = 0.0;                          // t |b|
                     // b = |b| e^{i phi} with b scaled by max(|Re b|, |Im b|) first, so that the
                     // phase keeps unit modulus down to the smallest normal numbers; a coupling
                     // below 1e-300 is taken as zero (no rotation)
@@ -247,7 +343,8 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                     if (mb > 1e-300) {
                         const double im = rcp_pos(mb);
                         const double bx = b.x * im, by = b.y * im;
-                        const double ir = rsqrt_pos(fma(bx, bx, by * by));
+                        const double nb2 = fma(bx, bx, by * by);
+                        const double ir = rsqrt_pos(nb2);
                         cph = bx * ir;
                         sph = by * ir;
                         // tau = (a_qq - a_pp) / (2 |b|); the smaller root t of t^2 + 2 tau t = 1,
@@ -257,91 +354,91 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                         const double at = fabs(tau);
                         double t;
                         if (at < 1e150) {
-                            const double u = fma(at, at, 1.0);
-                            t = rcp_pos(at + u * rsqrt_pos(u));
+                            const double w = fma(at, at, 1.0);
+                            t = rcp_pos(at + w * rsqrt_pos(w));
                         } else {
                             t = 0.5 * rcp_pos(at);
                         }
                         if (tau < 0.0) t = -t;
                         c = rsqrt_pos(fma(t, t, 1.0));
                         s = t * c;
+                        tb = t * (mb * (nb2 * ir));               // |b| = mb sqrt(nb2)
                     }
+                    // the pair's own block after the rotation: a real diagonal, exact zeros
+                    // off it
+                    A[ph_h][pp][pp] = make_double2(app - tb, 0.0);
+                    A[ph_h][qq][qq] = make_double2(aqq + tb, 0.0);
+                    A[ph_h][pp][qq] = make_double2(0.0, 0.0);
+                    A[ph_h][qq][pp] = make_double2(0.0, 0.0);
                 }
-                rot[lane][0] = c;
-                rot[lane][1] = s;
-                rot[lane][2] = cph;
-                rot[lane][3] = sph;
-                rpq[lane][0] = pp;
-                rpq[lane][1] = qq;
+                rot[ph_h][ph_u][0] = c;
+                rot[ph_h][ph_u][1] = s;
+                rot[ph_h][ph_u][2] = cph;
+                rot[ph_h][ph_u][3] = sph;
+                rpq[ph_h][ph_u][0] = pp;
+                rpq[ph_h][ph_u][1] = qq;
             }
             __syncthreads();
-            // A <- J^H A J in one step: lane (P1, P2) owns the 2 x 2 block of rows
-            // (p1, q1) and columns (p2, q2), which depends on no other block.
+            // off-diagonal blocks: rows (p1, q1) of pair B1, columns (p2, q2) of pair B2.
             // Columns first: col_p' = c col_p - s e^{-i phi} col_q,
-            //                col_q' = s col_p + c e^{-i phi} col_q (pair P2);
+            //                col_q' = s col_p + c e^{-i phi} col_q (pair B2);
             // then rows:     row_p' = c row_p - s e^{i phi} row_q,
-            //                row_q' = s row_p + c e^{i phi} row_q (pair P1).
-            // The same lane applies the column rotation of pair P2 to rows 2 P1 and
-            // 2 P1 + 1 of V (V <- V J), reusing the parameters it already holds;
-            // with 2 npair = n2 >= n those rows cover every row of V.
-            {
-                const int P1 = lane >> (LOGN - 1), P2 = lane & (MAXN / 2 - 1);
-                if (P1 < npair && P2 < npair) {
-                    const int p1 = rpq[P1][0], q1 = rpq[P1][1], p2 = rpq[P2][0], q2 = rpq[P2][1];
-                    const double c1 = rot[P1][0], s1 = rot[P1][1];
-                    const double2 e1 = make_double2(rot[P1][2], rot[P1][3]);
-                    const double c2 = rot[P2][0], s2 = rot[P2][1];
-                    const double2 e2 = make_double2(rot[P2][2], -rot[P2][3]);
-                    const double2 xpp = A[p1][p2], xpq = A[p1][q2], xqp = A[q1][p2], xqq = A[q1][q2];
-                    const int i1 = 2 * P1, i2 = 2 * P1 + 1;
-                    const double2 v1p = V[i1][p2], v1q = V[i1][q2], v2p = V[i2][p2], v2q = V[i2][q2];
-                    // columns (pair P2) on rows p1 and q1
-                    const double2 wp = cmul(xpq, e2), wq = cmul(xqq, e2);
-                    const double2 ypp = make_double2(c2 * xpp.x - s2 * wp.x, c2 * xpp.y - s2 * wp.y);
-                    const double2 ypq = make_double2(s2 * xpp.x + c2 * wp.x, s2 * xpp.y + c2 * wp.y);
-                    const double2 yqp = make_double2(c2 * xqp.x - s2 * wq.x, c2 * xqp.y - s2 * wq.y);
-                    const double2 yqq = make_double2(s2 * xqp.x + c2 * wq.x, s2 * xqp.y + c2 * wq.y);
-                    // rows (pair P1) on columns p2 and q2
-                    const double2 up = cmul(yqp, e1), uq = cmul(yqq, e1);
-                    double2 zpp = make_double2(c1 * ypp.x - s1 * up.x, c1 * ypp.y - s1 * up.y);
-                    double2 zqp = make_double2(s1 * ypp.x + c1 * up.x, s1 * ypp.y + c1 * up.y);
-                    double2 zpq = make_double2(c1 * ypq.x - s1 * uq.x, c1 * ypq.y - s1 * uq.y);
-                    double2 zqq = make_double2(s1 * ypq.x + c1 * uq.x, s1 * ypq.y + c1 * uq.y);
-                    if (P1 == P2 && q1 < n) {
-                        // the rotated pair: exact zeros off the diagonal, a real diagonal
-                        zpq = make_double2(0.0, 0.0);
-                        zqp = make_double2(0.0, 0.0);
-                        zpp.y = 0.0;
-                        zqq.y = 0.0;
-                    }
-                    A[p1][p2] = zpp;
-                    A[p1][q2] = zpq;
-                    A[q1][p2] = zqp;
-                    A[q1][q2] = zqq;
-                    // V: columns (pair P2) on rows i1 and i2 (an inactive pair has J = 1)
-                    const double2 w1 = cmul(v1q, e2), w2 = cmul(v2q, e2);
-                    V[i1][p2] = make_double2(c2 * v1p.x - s2 * w1.x, c2 * v1p.y - s2 * w1.y);
-                    V[i1][q2] = make_double2(s2 * v1p.x + c2 * w1.x, s2 * v1p.y + c2 * w1.y);
-                    V[i2][p2] = make_double2(c2 * v2p.x - s2 * w2.x, c2 * v2p.y - s2 * w2.y);
-                    V[i2][q2] = make_double2(s2 * v2p.x + c2 * w2.x, s2 * v2p.y + c2 * w2.y);
-                }
+            //                row_q' = s row_p + c e^{i phi} row_q (pair B1).
+#pragma unroll
+            for (int k = 0; k < APASS; ++k) {
+                if (!bv[k]) continue;
+                const int h = bh[k], B1 = b1[k], B2 = b2[k];
+                const int p1 = rpq[h][B1][0], q1 = rpq[h][B1][1], p2 = rpq[h][B2][0], q2 = rpq[h][B2][1];
+                const double c1 = rot[h][B1][0], s1 = rot[h][B1][1];
+                const double2 e1 = make_double2(rot[h][B1][2], rot[h][B1][3]);
+                const double c2 = rot[h][B2][0], s2 = rot[h][B2][1];
+                const double2 e2 = make_double2(rot[h][B2][2], -rot[h][B2][3]);
+                const double2 xpp = A[h][p1][p2], xpq = A[h][p1][q2], xqp = A[h][q1][p2], xqq = A[h][q1][q2];
+                const double2 wp = cmul(xpq, e2), wq = cmul(xqq, e2);
+                const double2 ypp = make_double2(c2 * xpp.x - s2 * wp.x, c2 * xpp.y - s2 * wp.y);
+                const double2 ypq = make_double2(s2 * xpp.x + c2 * wp.x, s2 * xpp.y + c2 * wp.y);
+                const double2 yqp = make_double2(c2 * xqp.x - s2 * wq.x, c2 * xqp.y - s2 * wq.y);
+                const double2 yqq = make_double2(s2 * xqp.x + c2 * wq.x, s2 * xqp.y + c2 * wq.y);
+                const double2 up = cmul(yqp, e1), uq = cmul(yqq, e1);
+                const double2 zpp = make_double2(c1 * ypp.x - s1 * up.x, c1 * ypp.y - s1 * up.y);
+                const double2 zqp = make_double2(s1 * ypp.x + c1 * up.x, s1 * ypp.y + c1 * up.y);
+                const double2 zpq = make_double2(c1 * ypq.x - s1 * uq.x, c1 * ypq.y - s1 * uq.y);
+                const double2 zqq = make_double2(s1 * ypq.x + c1 * uq.x, s1 * ypq.y + c1 * uq.y);
+                A[h][p1][p2] = zpp;
+                A[h][p1][q2] = zpq;
+                A[h][q1][p2] = zqp;
+                A[h][q1][q2] = zqq;
+                A[h][p2][p1] = make_double2(zpp.x, -zpp.y);
+                A[h][q2][p1] = make_double2(zpq.x, -zpq.y);
+                A[h][p2][q1] = make_double2(zqp.x, -zqp.y);
+                A[h][q2][q1] = make_double2(zqq.x, -zqq.y);
             }
+            // V <- V J on the lane's row (the round's pair indices are constants)
+            vrot(r, v, rot[vh], std::make_integer_sequence<int, MAXN - 1>{});
             __syncthreads();
         }
     }
     // ascending order with a stable rank; eigenvector i is column i of V
-    if (lane < n) {
-        const double li = A[lane][lane].x;
+    if (vr < n) {
+        const double li = A[vh][vr][vr].x;
         int rank = 0;
         for (int j = 0; j < n; ++j) {
-            const double lj = A[j][j].x;
-            rank += (lj < li) || (lj == li && j < lane);
+            const double lj = A[vh][j][j].x;
+            rank += (lj < li) || (lj == li && j < vr);
         }
-        double out = li;
-        if (SQRT_OUT) out = (li < 0.0 ? -1.0 : 1.0) * sqrt(fabs(li));
-        evals[(size_t)p * n + rank] = out;
-        for (int row = 0; row < n; ++row)
-            evecs[((size_t)p * n + row) * n + rank] = V[row][lane];
+        rk[vh][vr] = rank;
+        if (vh < nmat) {
+            double out = li;
+            if (SQRT_OUT) out = (li < 0.0 ? -1.0 : 1.0) * sqrt(fabs(li));
+            evals[((size_t)p0 + vh) * n + rank] = out;
+        }
+    }
+    __syncthreads();
+    if (vr < n && vh < nmat) {
+        double2* row = evecs + (((size_t)p0 + vh) * n + vr) * n;
+#pragma unroll
+        for (int j = 0; j < MAXN; ++j)
+            if (j < n) row[rk[vh][j]] = v[j];
     }
 }
 
@@ -350,11 +447,11 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
 void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream, bool packed) {
     if (np <= 0) return;
     if (packed)
-        interp_eigh_kernel<false, false, true, true><<<dim3(np), dim3(64), 0, stream>>>(
+        interp_eigh_kernel<false, false, true, true><<<dim3((np + MPW - 1) / MPW), dim3(64), 0, stream>>>(
             n, 0, nullptr, nullptr, reinterpret_cast<const double*>(X), np, nullptr, nullptr, 1, evals,
             reinterpret_cast<double2*>(evecs));
     else
-        interp_eigh_kernel<false, false, true><<<dim3(np), dim3(64), 0, stream>>>(
+        interp_eigh_kernel<false, false, true><<<dim3((np + MPW - 1) / MPW), dim3(64), 0, stream>>>(
             n, 0, nullptr, nullptr, reinterpret_cast<const double*>(X), np, nullptr, nullptr, 1, evals,
             reinterpret_cast<double2*>(evecs));
     launch_check("interp_eigh_kernel (given)");
@@ -458,7 +555,7 @@ void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_
                         double* evals, void* evecs, hipStream_t stream, const double* pts2, int n2)
 {
     if (np <= 0) return;
-    dim3 grid(np), block(64);
+    dim3 grid((np + MPW - 1) / MPW), block(64);
     double2* ev = reinterpret_cast<double2*>(evecs);
     if (real_in && sqrt_out)
         interp_eigh_kernel<true, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
