@@ -27,40 +27,38 @@
 namespace epw {
 namespace {
 
-constexpr int MAXN = 16;
-constexpr int LDA = MAXN + 1;     // padded leading dimension in LDS
+constexpr int MAXN = 16;         // largest matrix
 constexpr int RBLK = 256;         // R vectors staged per pass
 constexpr int MAX_SWEEPS = 24;
-// work items of the rotation updates are decoded with shifts over the fixed
-// MAXN x MAXN layout (no division by the runtime size)
-constexpr int LOGN = 4;
-static_assert((1 << LOGN) == MAXN, "MAXN is a power of two");
 
 __device__ inline double2 cmul(double2 a, double2 b) {
     return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// pair i of round r of the round-robin schedule on MAXN indices: index
-// MAXN - 1 stays fixed, the others rotate (r < MAXN - 1, i < MAXN / 2).  Every
-// matrix runs on MAXN indices, those at or beyond its size n being zero rows
-// and columns whose pairs are not rotated; a sweep (MAXN - 1 rounds) still
-// meets every pair of indices below n once.  constexpr: with r and i known
-// at compile time the indices are constants, which keeps the rows of V in
+// pair i of round r of the round-robin schedule on N2 indices (8 or 16):
+// index N2 - 1 stays fixed, the others rotate (r < N2 - 1, i < N2 / 2).  A
+// matrix of size n <= N2 runs on N2 indices, those at or beyond n being zero
+// rows and columns whose pairs are not rotated; a sweep (N2 - 1 rounds) still
+// meets every pair of indices below n once.  constexpr: with r and i known at
+// compile time the indices are constants, which keeps the rows of V in
 // registers.
+template <int N2>
 __host__ __device__ constexpr int rr_p(int r, int i) {
-    const int m = MAXN - 1;
+    const int m = N2 - 1;
     const int a = (r + i) % m;
     const int b = i == 0 ? m : (r - i + m) % m;
     return a < b ? a : b;
 }
+template <int N2>
 __host__ __device__ constexpr int rr_q(int r, int i) {
-    const int m = MAXN - 1;
+    const int m = N2 - 1;
     const int a = (r + i) % m;
     const int b = i == 0 ? m : (r - i + m) % m;
     return a < b ? b : a;
 }
+template <int N2>
 __device__ inline void rr_pair(int r, int i, int& p, int& q) {
-    const int m = MAXN - 1;
+    const int m = N2 - 1;
     int a = r + i;
     if (a >= m) a -= m;
     int b = r - i + m;
@@ -87,19 +85,20 @@ __device__ __forceinline__ double rsqrt_pos(double x) {
     return y;
 }
 
-// sum over the 16 lanes of one matrix (lanes 16 h .. 16 h + 15); every lane
-// of the group receives the same value
+// sum over the N2 lanes of one matrix (lanes N2 h .. N2 h + N2 - 1); every
+// lane of the group receives the same value
+template <int N2>
 __device__ inline double group_sum(double v) {
 #pragma unroll
-    for (int m = 8; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+    for (int m = N2 / 2; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
     return v;
 }
 
 // V <- V J for round R on one row v of V (registers): the columns (p, q) of
 // each pair U, with the pair's parameters rt[U] = {c, s, cos phi, sin phi}.
-template <int R, int U>
-__device__ __forceinline__ void vrot_pair(double2 (&v)[MAXN], const double (*rt)[4]) {
-    constexpr int p = rr_p(R, U), q = rr_q(R, U);
+template <int N2, int R, int U>
+__device__ __forceinline__ void vrot_pair(double2 (&v)[N2], const double (*rt)[4]) {
+    constexpr int p = rr_p<N2>(R, U), q = rr_q<N2>(R, U);
     const double c = rt[U][0], s = rt[U][1];
     const double2 e = make_double2(rt[U][2], -rt[U][3]);
     const double2 w = cmul(v[q], e);
@@ -107,34 +106,40 @@ __device__ __forceinline__ void vrot_pair(double2 (&v)[MAXN], const double (*rt)
     v[p] = make_double2(c * x.x - s * w.x, c * x.y - s * w.y);
     v[q] = make_double2(s * x.x + c * w.x, s * x.y + c * w.y);
 }
-template <int R, int... U>
-__device__ __forceinline__ void vrot_round(double2 (&v)[MAXN], const double (*rt)[4],
+template <int N2, int R, int... U>
+__device__ __forceinline__ void vrot_round(double2 (&v)[N2], const double (*rt)[4],
                                            std::integer_sequence<int, U...>) {
-    (vrot_pair<R, U>(v, rt), ...);
+    (vrot_pair<N2, R, U>(v, rt), ...);
 }
-template <int... R>
-__device__ __forceinline__ void vrot(int r, double2 (&v)[MAXN], const double (*rt)[4],
+template <int N2, int... R>
+__device__ __forceinline__ void vrot(int r, double2 (&v)[N2], const double (*rt)[4],
                                      std::integer_sequence<int, R...>) {
-    ((r == R ? vrot_round<R>(v, rt, std::make_integer_sequence<int, MAXN / 2>{}) : void()), ...);
+    ((r == R ? vrot_round<N2, R>(v, rt, std::make_integer_sequence<int, N2 / 2>{}) : void()), ...);
 }
 
-// Four matrices per wave (matrix h of a block is point MPW blockIdx.x + h).
-// A (Hermitian, full) is in LDS; lane 16 h + i holds row i of V of matrix h
-// in registers.  A Jacobi round:
-//   - lane 8 h + u (u < 8, 32 lanes) computes the rotation of pair u of
-//     matrix h and writes the pair's own 2 x 2 diagonal block in closed form
+// 64 / N2 matrices per wave (matrix h of a block is point MPW blockIdx.x + h):
+// four on the 16-index schedule (n > 8), eight on the 8-index one.  A
+// (Hermitian, full) is in LDS; lane N2 h + i holds row i of V of matrix h in
+// registers.  A Jacobi round:
+//   - lane NPAIR h + u (32 lanes) computes the rotation of pair u of matrix h
+//     and writes the pair's own 2 x 2 diagonal block in closed form
 //     (a_pp - t |b|, a_qq + t |b|, exact zeros off the diagonal);
-//   - the 4 x 28 off-diagonal blocks (pairs P1 < P2) are rotated in two
-//     passes over the 64 lanes; each writes its block and the conjugate
-//     transpose, so A stays exactly Hermitian and no lane reads what
-//     another writes;
+//   - the off-diagonal blocks (pairs P1 < P2; 4 x 28 or 8 x 6) are rotated
+//     in APASS passes over the 64 lanes; each writes its block and the
+//     conjugate transpose, so A stays exactly Hermitian and no lane reads
+//     what another writes;
 //   - every lane rotates its row of V by all pairs of the round.
 // A matrix that has converged takes identity rotations, which change nothing
 // (exactly), so its result does not depend on the other matrices of its wave.
-constexpr int MPW = 4;
-constexpr int NPAIR = MAXN / 2;
-constexpr int NBLK = NPAIR * (NPAIR - 1) / 2;
-constexpr int APASS = (MPW * NBLK + 63) / 64;
+template <int N2> struct JacobiShape {
+    static constexpr int MPW = 64 / N2;
+    static constexpr int NPAIR = N2 / 2;
+    static constexpr int NBLK = NPAIR * (NPAIR - 1) / 2;
+    static constexpr int APASS = (MPW * NBLK + 63) / 64;
+    static constexpr int LDA = N2 + 1;          // padded leading dimension in LDS
+    static_assert(N2 == 8 || N2 == 16, "schedules on 8 or 16 indices");
+    static_assert(MPW * NPAIR == 32, "32 rotation-parameter lanes");
+};
 
 // REAL_IN: X(R) is real (dynamical matrix); else complex interleaved.
 // SQRT_OUT: write omega = sign(l) sqrt|l| instead of the eigenvalue l.
@@ -142,135 +147,158 @@ constexpr int APASS = (MPW * NBLK + 63) / 64;
 // GIVEN: the matrices are given ([np][n][n] complex at XR), no Fourier sum;
 // with PACKED only their upper triangles ([np][n(n+1)/2], rows i with columns
 // j >= i in turn), the lower triangle being the conjugate.
-template <bool REAL_IN, bool SQRT_OUT, bool GIVEN = false, bool PACKED = false>
+template <int N2, bool REAL_IN, bool SQRT_OUT, bool GIVEN = false, bool PACKED = false>
 __global__ __launch_bounds__(64) void interp_eigh_kernel(
     int n, int nR, const int32_t* __restrict__ R, const int32_t* __restrict__ ndeg,
     const double* __restrict__ XR, int np, const double* __restrict__ pts,
     const double* __restrict__ pts2, int npts2,
     double* __restrict__ evals, double2* __restrict__ evecs)
 {
-    __shared__ double2 A[MPW][MAXN][LDA];
+    typedef JacobiShape<N2> S;
+    constexpr int MPW = S::MPW, NPAIR = S::NPAIR, NBLK = S::NBLK, APASS = S::APASS;
+    __shared__ double2 A[MPW][N2][S::LDA];
     __shared__ double2 ph[GIVEN ? 1 : RBLK];
     __shared__ double2 red[GIVEN ? 1 : 64];
     __shared__ double rot[MPW][NPAIR][4];
     __shared__ int rpq[MPW][NPAIR][2];
-    __shared__ int rk[MPW][MAXN];
+    __shared__ int rk[MPW][N2];
 
     const int lane = threadIdx.x;
     const int p0 = blockIdx.x * MPW;
     if (p0 >= np) return;
     const int nmat = min(MPW, np - p0);
-    for (int e = lane; e < MPW * MAXN * MAXN; e += 64)
-        A[e >> (2 * LOGN)][(e >> LOGN) & (MAXN - 1)][e & (MAXN - 1)] = make_double2(0.0, 0.0);
+    for (int e = lane; e < MPW * N2 * N2; e += 64)
+        A[e / (N2 * N2)][(e / N2) % N2][e % N2] = make_double2(0.0, 0.0);
     __syncthreads();
-    // the raw matrices of the block's points -> A[h], one after the other
-    for (int h = 0; h < nmat; ++h) {
-        const int p = p0 + h;
-        if constexpr (GIVEN && PACKED) {
-            const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * (n * (n + 1) / 2);
-            for (int e = lane; e < n * n; e += 64) {
-                const int i = e / n, j = e % n;
-                if (i > j) continue;
-                const double2 x = X[i * n - i * (i - 1) / 2 + (j - i)];
-                A[h][i][j] = x;
-                if (i < j) A[h][j][i] = make_double2(x.x, -x.y);
+    if constexpr (GIVEN) {
+        // the given matrices of the block's points -> A[h], one after the other
+        for (int h = 0; h < nmat; ++h) {
+            const int p = p0 + h;
+            if constexpr (PACKED) {
+                const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * (n * (n + 1) / 2);
+                for (int e = lane; e < n * n; e += 64) {
+                    const int i = e / n, j = e % n;
+                    if (i > j) continue;
+                    const double2 x = X[i * n - i * (i - 1) / 2 + (j - i)];
+                    A[h][i][j] = x;
+                    if (i < j) A[h][j][i] = make_double2(x.x, -x.y);
+                }
+            } else {
+                const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * n * n;
+                for (int e = lane; e < n * n; e += 64) A[h][e / n][e % n] = X[e];
             }
-        } else if constexpr (GIVEN) {
-            const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * n * n;
-            for (int e = lane; e < n * n; e += 64) A[h][e / n][e % n] = X[e];
-        } else {
-            // point p, or the sum pts[p / npts2] + pts2[p % npts2] in pair mode
-            const size_t ia = pts2 ? (size_t)(p / npts2) : (size_t)p;
-            double k0 = pts[3 * ia + 0];
-            double k1 = pts[3 * ia + 1];
-            double k2 = pts[3 * ia + 2];
-            if (pts2) {
-                const size_t ib = (size_t)(p % npts2);
-                k0 += pts2[3 * ib + 0];
-                k1 += pts2[3 * ib + 1];
-                k2 += pts2[3 * ib + 2];
-            }
-            const int E = n * n;
-            const int P = (E >= 64) ? 1 : 64 / E;          // R partitions per entry
-            const int EPL = (E + 63) / 64;                   // entries per lane when P == 1
+        }
+    } else {
+        // the Fourier sums of the block's points together: every entry of X(R)
+        // read from memory feeds all of them.  Point p is pts[p], or the sum
+        // pts[p / npts2] + pts2[p % npts2] in pair mode; an absent point (past np)
+        // gets zero phases.
+        constexpr int EPLMAX = (N2 * N2 + 63) / 64;     // entries per lane, at most
+        constexpr int RB = RBLK / MPW;                  // R vectors per staging pass
+        const int E = n * n;
+        const int P = (E >= 64) ? 1 : 64 / E;           // R partitions per entry
+        const int EPL = (E + 63) / 64;                  // entries per lane when P == 1
+        double2 acc[EPLMAX][MPW];
+#pragma unroll
+        for (int j = 0; j < EPLMAX; ++j)
+#pragma unroll
+            for (int h = 0; h < MPW; ++h) acc[j][h] = make_double2(0.0, 0.0);
 
-            double2 acc[4];
-            for (int j = 0; j < 4; ++j) acc[j] = make_double2(0.0, 0.0);
-
-            for (int r0 = 0; r0 < nR; r0 += RBLK) {
-                const int cnt = min(RBLK, nR - r0);
-                __syncthreads();
-                for (int r = lane; r < cnt; r += 64) {
+        for (int r0 = 0; r0 < nR; r0 += RB) {
+            const int cnt = min(RB, nR - r0);
+            __syncthreads();
+            for (int t = lane; t < MPW * cnt; t += 64) {
+                const int h = t / cnt, r = t - h * cnt;
+                double2 f = make_double2(0.0, 0.0);
+                if (h < nmat) {
+                    const size_t pp = (size_t)p0 + h;
+                    const size_t ia = pts2 ? pp / npts2 : pp;
+                    double k0 = pts[3 * ia + 0];
+                    double k1 = pts[3 * ia + 1];
+                    double k2 = pts[3 * ia + 2];
+                    if (pts2) {
+                        const size_t ib = pp % npts2;
+                        k0 += pts2[3 * ib + 0];
+                        k1 += pts2[3 * ib + 1];
+                        k2 += pts2[3 * ib + 2];
+                    }
                     const int idx = r0 + r;
                     double x = k0 * (double)R[3 * idx] + k1 * (double)R[3 * idx + 1] +
                                k2 * (double)R[3 * idx + 2];
                     x -= rint(x);
-                    double s, c;
-                    sincospi(2.0 * x, &s, &c);
+                    double sn, cs;
+                    sincospi(2.0 * x, &sn, &cs);
                     const double w = 1.0 / (double)ndeg[idx];
-                    ph[r] = make_double2(c * w, s * w);
+                    f = make_double2(cs * w, sn * w);
                 }
-                __syncthreads();
-                if (P > 1) {
-                    const int e = lane % E, part = lane / E;
-                    if (part < P) {
-                        for (int r = part; r < cnt; r += P) {
-                            const double2 f = ph[r];
-                            if (REAL_IN) {
-                                const double x = XR[(size_t)(r0 + r) * E + e];
-                                acc[0].x += f.x * x;
-                                acc[0].y += f.y * x;
-                            } else {
-                                const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
-                                const double2 t = cmul(f, x);
-                                acc[0].x += t.x;
-                                acc[0].y += t.y;
-                            }
-                        }
+                ph[h * RB + r] = f;
+            }
+            __syncthreads();
+            // acc[j][h] += phase(h, R) X_e(R) for the lane's entries e
+            auto accumulate = [&](int j, int e, int r) {
+                if (REAL_IN) {
+                    const double x = XR[(size_t)(r0 + r) * E + e];
+#pragma unroll
+                    for (int h = 0; h < MPW; ++h) {
+                        const double2 f = ph[h * RB + r];
+                        acc[j][h].x += f.x * x;
+                        acc[j][h].y += f.y * x;
                     }
                 } else {
-                    for (int j = 0; j < EPL; ++j) {
-                        const int e = lane + 64 * j;
-                        if (e >= E) break;
-                        for (int r = 0; r < cnt; ++r) {
-                            const double2 f = ph[r];
-                            if (REAL_IN) {
-                                const double x = XR[(size_t)(r0 + r) * E + e];
-                                acc[j].x += f.x * x;
-                                acc[j].y += f.y * x;
-                            } else {
-                                const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
-                                const double2 t = cmul(f, x);
-                                acc[j].x += t.x;
-                                acc[j].y += t.y;
-                            }
-                        }
+                    const double2 x = reinterpret_cast<const double2*>(XR)[(size_t)(r0 + r) * E + e];
+#pragma unroll
+                    for (int h = 0; h < MPW; ++h) {
+                        const double2 t = cmul(ph[h * RB + r], x);
+                        acc[j][h].x += t.x;
+                        acc[j][h].y += t.y;
                     }
                 }
-            }
+            };
             if (P > 1) {
-                red[lane] = acc[0];
+                const int e = lane % E, part = lane / E;
+                if (part < P)
+                    for (int r = part; r < cnt; r += P) accumulate(0, e, r);
+            } else {
+#pragma unroll
+                for (int j = 0; j < EPLMAX; ++j) {
+                    const int e = lane + 64 * j;
+                    if (j < EPL && e < E)
+                        for (int r = 0; r < cnt; ++r) accumulate(j, e, r);
+                }
+            }
+        }
+        if (P > 1) {
+            // the partitions' partial sums, one point at a time, in a fixed order
+#pragma unroll
+            for (int h = 0; h < MPW; ++h) {
+                if (h >= nmat) break;
+                __syncthreads();
+                red[lane] = acc[0][h];
                 __syncthreads();
                 if (lane < E) {
-                    double2 s = make_double2(0.0, 0.0);
+                    double2 sum = make_double2(0.0, 0.0);
                     for (int part = 0; part < P; ++part) {
-                        s.x += red[lane + E * part].x;
-                        s.y += red[lane + E * part].y;
+                        sum.x += red[lane + E * part].x;
+                        sum.y += red[lane + E * part].y;
                     }
-                    A[h][lane / n][lane % n] = s;
-                }
-            } else {
-                for (int j = 0; j < EPL; ++j) {
-                    const int e = lane + 64 * j;
-                    if (e < E) A[h][e / n][e % n] = acc[j];
+                    A[h][lane / n][lane % n] = sum;
                 }
             }
-        }   // Fourier sum
-        __syncthreads();
+        } else {
+#pragma unroll
+            for (int j = 0; j < EPLMAX; ++j) {
+                const int e = lane + 64 * j;
+                if (j >= EPL || e >= E) continue;
+#pragma unroll
+                for (int h = 0; h < MPW; ++h)
+                    if (h < nmat) A[h][e / n][e % n] = acc[j][h];
+            }
+        }
     }
+    __syncthreads();
     // Hermitise in place: the lane of (i, j), i <= j, writes both entries
-    for (int e = lane; e < MPW * MAXN * MAXN; e += 64) {
-        const int h = e >> (2 * LOGN), i = (e >> LOGN) & (MAXN - 1), j = e & (MAXN - 1);
+    for (int e = lane; e < MPW * N2 * N2; e += 64) {
+        const int h = e / (N2 * N2), i = (e / N2) % N2, j = e % N2;
         if (i > j || h >= nmat || j >= n) continue;
         const double2 x = A[h][i][j], y = A[h][j][i];
         const double2 a = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
@@ -280,12 +308,12 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     __syncthreads();
 
     // row `vr` of V of matrix `vh` in registers
-    const int vh = lane >> LOGN, vr = lane & (MAXN - 1);
-    double2 v[MAXN];
+    const int vh = lane / N2, vr = lane % N2;
+    double2 v[N2];
 #pragma unroll
-    for (int j = 0; j < MAXN; ++j) v[j] = make_double2(j == vr ? 1.0 : 0.0, 0.0);
-    // rotation parameters: lane 8 ph_h + ph_u, for the 32 lanes below 32
-    const int ph_h = lane >> 3, ph_u = lane & (NPAIR - 1);
+    for (int j = 0; j < N2; ++j) v[j] = make_double2(j == vr ? 1.0 : 0.0, 0.0);
+    // rotation parameters: lane NPAIR ph_h + ph_u, for the 32 lanes below 32
+    const int ph_h = lane / NPAIR, ph_u = lane % NPAIR;
     // off-diagonal blocks of the two passes: matrix, pairs (B1 < B2)
     int bh[APASS], b1[APASS], b2[APASS];
     bool bv[APASS];
@@ -312,25 +340,28 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
         double off = 0.0, dia = 0.0;
         if (vr < n) {
 #pragma unroll
-            for (int j = 0; j < MAXN; ++j) {
+            for (int j = 0; j < N2; ++j) {
                 if (j >= n) continue;
                 const double2 a = A[vh][vr][j];
                 const double m2 = a.x * a.x + a.y * a.y;
                 if (j == vr) dia += m2; else off += m2;
             }
         }
-        const double so = group_sum(off), sd = group_sum(dia);
-        const bool done = so <= 1e-30 * (so + sd);   // the same decision in the 16 lanes of a matrix
+        const double so = group_sum<N2>(off), sd = group_sum<N2>(dia);
+        const bool done = so <= 1e-30 * (so + sd);   // the same decision in the N2 lanes of a matrix
         const unsigned long long dmask = __ballot(done);
         if (dmask == ~0ull) break;
-        const bool ph_done = (dmask >> (16 * ph_h)) & 1ull;
-        for (int r = 0; r < MAXN - 1; ++r) {
+        const bool ph_done = (dmask >> (N2 * ph_h)) & 1ull;
+        // rounds kept rolled: unrolled, their schedules overlap and the registers
+        // double (one wave per SIMD); each round picks its V rotation by a branch
+#pragma unroll 1
+        for (int r = 0; r < N2 - 1; ++r) {
             // rotation of pair ph_u: J = [[c, s], [-s e^{-i phi}, c e^{-i phi}]] on
             // indices (p, q), which zeroes A[p][q] = |b| e^{i phi} of J^H A J.  A pair
             // with q >= n (zero row and column) and a converged matrix keep J = 1.
             if (lane < MPW * NPAIR) {
                 int pp, qq;
-                rr_pair(r, ph_u, pp, qq);
+                rr_pair<N2>(r, ph_u, pp, qq);
                 double c = 1.0, s = 0.0, cph = 1.0, sph = 0.0;
                 if (!ph_done && qq < n) {
                     const double app = A[ph_h][pp][pp].x, aqq = A[ph_h][qq][qq].x;
@@ -414,7 +445,7 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                 A[h][q2][q1] = make_double2(zqq.x, -zqq.y);
             }
             // V <- V J on the lane's row (the round's pair indices are constants)
-            vrot(r, v, rot[vh], std::make_integer_sequence<int, MAXN - 1>{});
+            vrot<N2>(r, v, rot[vh], std::make_integer_sequence<int, N2 - 1>{});
             __syncthreads();
         }
     }
@@ -437,23 +468,35 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     if (vr < n && vh < nmat) {
         double2* row = evecs + (((size_t)p0 + vh) * n + vr) * n;
 #pragma unroll
-        for (int j = 0; j < MAXN; ++j)
+        for (int j = 0; j < N2; ++j)
             if (j < n) row[rk[vh][j]] = v[j];
     }
 }
 
 }  // namespace
 
+// matrices of size n <= 8 run on the 8-index schedule (eight per wave), the
+// others on the 16-index one (four per wave); sizes are 1..16 (checked by the
+// entry points)
+template <int N2>
+static void launch_given_t(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream, bool packed) {
+    const dim3 grid((np + JacobiShape<N2>::MPW - 1) / JacobiShape<N2>::MPW), block(64);
+    const double* x = reinterpret_cast<const double*>(X);
+    double2* ev = reinterpret_cast<double2*>(evecs);
+    if (packed)
+        interp_eigh_kernel<N2, false, false, true, true><<<grid, block, 0, stream>>>(n, 0, nullptr, nullptr, x, np,
+                                                                                    nullptr, nullptr, 1, evals, ev);
+    else
+        interp_eigh_kernel<N2, false, false, true><<<grid, block, 0, stream>>>(n, 0, nullptr, nullptr, x, np,
+                                                                              nullptr, nullptr, 1, evals, ev);
+}
+
 void launch_eigh_given(int n, int np, const void* X, double* evals, void* evecs, hipStream_t stream, bool packed) {
     if (np <= 0) return;
-    if (packed)
-        interp_eigh_kernel<false, false, true, true><<<dim3((np + MPW - 1) / MPW), dim3(64), 0, stream>>>(
-            n, 0, nullptr, nullptr, reinterpret_cast<const double*>(X), np, nullptr, nullptr, 1, evals,
-            reinterpret_cast<double2*>(evecs));
+    if (n <= 8)
+        launch_given_t<8>(n, np, X, evals, evecs, stream, packed);
     else
-        interp_eigh_kernel<false, false, true><<<dim3((np + MPW - 1) / MPW), dim3(64), 0, stream>>>(
-            n, 0, nullptr, nullptr, reinterpret_cast<const double*>(X), np, nullptr, nullptr, 1, evals,
-            reinterpret_cast<double2*>(evecs));
+        launch_given_t<16>(n, np, X, evals, evecs, stream, packed);
     launch_check("interp_eigh_kernel (given)");
 }
 
@@ -550,21 +593,32 @@ void launch_pack_upper(int n, int nR, const int32_t* R, const int32_t* ndeg, con
     launch_check("pack_upper_kernel");
 }
 
+template <int N2>
+static void launch_interp_t(bool real_in, bool sqrt_out, int n, int nR, const int32_t* R, const int32_t* ndeg,
+                     const double* XR, int np, const double* pts, double* evals, void* evecs, hipStream_t stream,
+                     const double* pts2, int n2) {
+    const dim3 grid((np + JacobiShape<N2>::MPW - 1) / JacobiShape<N2>::MPW), block(64);
+    double2* ev = reinterpret_cast<double2*>(evecs);
+    if (real_in && sqrt_out)
+        interp_eigh_kernel<N2, true, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
+    else if (real_in)
+        interp_eigh_kernel<N2, true, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
+    else if (sqrt_out)
+        interp_eigh_kernel<N2, false, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
+    else
+        interp_eigh_kernel<N2, false, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals,
+                                                                         ev);
+}
+
 void launch_interp_eigh(bool real_in, bool sqrt_out, int n, int nR, const int32_t* R,
                         const int32_t* ndeg, const double* XR, int np, const double* pts,
                         double* evals, void* evecs, hipStream_t stream, const double* pts2, int n2)
 {
     if (np <= 0) return;
-    dim3 grid((np + MPW - 1) / MPW), block(64);
-    double2* ev = reinterpret_cast<double2*>(evecs);
-    if (real_in && sqrt_out)
-        interp_eigh_kernel<true, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
-    else if (real_in)
-        interp_eigh_kernel<true, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
-    else if (sqrt_out)
-        interp_eigh_kernel<false, true><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
+    if (n <= 8)
+        launch_interp_t<8>(real_in, sqrt_out, n, nR, R, ndeg, XR, np, pts, evals, evecs, stream, pts2, n2);
     else
-        interp_eigh_kernel<false, false><<<grid, block, 0, stream>>>(n, nR, R, ndeg, XR, np, pts, pts2, n2, evals, ev);
+        launch_interp_t<16>(real_in, sqrt_out, n, nR, R, ndeg, XR, np, pts, evals, evecs, stream, pts2, n2);
     launch_check("interp_eigh_kernel");
 }
 
