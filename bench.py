@@ -168,12 +168,13 @@ def backward_gemm_flops(nk, nq, ne, np_, nm, nb):
 
 
 def pair_eigh_flops(n):
-    """Arithmetic of one n x n complex Jacobi sweep as the eigensolver runs it
-    (one-sided count, flops = real additions and multiplications): each of the
-    n(n-1)/2 rotations of a sweep rewrites two rows and two columns of A
-    (4n complex entries, each 2 complex-by-real products, one complex phase
-    product and one complex addition: 14 flops) and two columns of V (2n
-    entries, 14 flops each)."""
+    """Arithmetic of one n x n complex Jacobi sweep of the two-sided method
+    (flops = real additions and multiplications): each of the n(n-1)/2
+    rotations of a sweep rewrites two rows and two columns of A (4n complex
+    entries, each 2 complex-by-real products, one complex phase product and
+    one complex addition: 14 flops) and two columns of V (2n entries, 14 flops
+    each).  The eigensolver computes only the half of A above the diagonal and
+    mirrors it, so it executes about two thirds of this count."""
     return n * (n - 1) / 2 * (4 * n + 2 * n) * 14.0
 
 

@@ -7,12 +7,16 @@
 //   a8  g_mn,nu(k,q)  = [U_{k+q}^dag g_nu(k,q) U_k]_mn              fused epilogue
 //   a9  Im Sigma_nk  += |g_mn,nu|^2 {(n+f) d(x+w) + (n+1-f) d(x-w)}  fused epilogue
 //
-// The 1/ndeg weights of R_e are folded into the B operand by a6.  Complex
-// products in float64 / float32 use Gauss's three-multiplication form (three
-// real MFMAs per complex block product, cgemm.h); the split-bf16 path uses
-// four real products of three split terms each.  The MFMAs of one K step are
-// interleaved over the wave's C blocks so consecutive ones never depend on
-// each other.
+// The 1/ndeg weights of R_e are folded into the B operand by a6.  Float64 (at
+// every band count) and float32 (up to 8 padded bands) run the a7 sum folded
+// by the pairs (R, -R) of the R_e list: with c and s the cosine and sine of a
+// pair's phase, the pair contributes c (B(R) + B(-R)) + i s (B(R) - B(-R)),
+// two real MFMAs per original R vector (cfold_mainloop, cgemm.h; a vector
+// without its negative enters alone).  Float32 at 16 padded bands uses Gauss's
+// three-multiplication form (three real MFMAs per complex block product), the
+// split-bf16 path four real products of three split terms each.  The MFMAs of
+// one K step are interleaved over the wave's C blocks so consecutive ones
+// never depend on each other.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
