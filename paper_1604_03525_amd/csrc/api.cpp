@@ -162,6 +162,17 @@ struct PairScratch {
     void* H = nullptr;       // [batch][n_b (n_b + 1) / 2] c128: upper triangles of H(k+q)
     void* HRu = nullptr;     // [N_e][n_b (n_b + 1) / 2] c128: upper triangles of the Hermitian part of H(R_e)
     int32_t* negR = nullptr; // [N_e] index of -R_e
+    // the H(k+q) product folded by the pairs (R, -R): halved R list, its phase
+    // tables without weights, and the B+ / B- rows of HRu (1/ndeg_e included)
+    int32_t* fneg = nullptr;
+    int32_t* fhalf = nullptr;
+    int32_t* fpair = nullptr;
+    int32_t* fR = nullptr;
+    int32_t* fkh = nullptr;
+    void* fphi_k = nullptr;  // [N_k][N_e] c128 (rows of the halved list)
+    void* fphi_q = nullptr;  // [Q][N_e] c128
+    void* HRp = nullptr;     // [N_e][n_b (n_b + 1) / 2] c128
+    void* HRm = nullptr;
     long batch = 0;
     // band velocities at k+q (transport mode): i R_a H(R) for a = x, y, z,
     // their Fourier sums for one batch, and the velocities of every pair
@@ -225,7 +236,7 @@ struct Layout {
 // bytes per q point of the per-pair k+q states (off-grid runs)
 size_t pair_bytes_per_q(const epw_system* s, const epw_points* p) {
     if (p->kq) return 0;
-    return (size_t)p->nk * (16 * (size_t)s->nb + 16 * (size_t)s->nb * s->nb) + 16 * (size_t)s->nRe;
+    return (size_t)p->nk * (16 * (size_t)s->nb + 16 * (size_t)s->nb * s->nb) + 32 * (size_t)s->nRe;
 }
 
 // extra bytes per q point of the k+q velocities (off-grid transport runs)
@@ -247,6 +258,15 @@ void take_pair_states(const epw_system* s, const epw_points* p, int Q, Arena& A,
     ps.H = A.take(16 * (size_t)ps.batch * nbb);
     ps.HRu = A.take(16 * (size_t)s->nRe * (s->nb * (s->nb + 1) / 2));
     ps.negR = (int32_t*)A.take(4 * (size_t)s->nRe);
+    ps.fneg = (int32_t*)A.take(4 * (size_t)s->nRe);
+    ps.fhalf = (int32_t*)A.take(4 * (size_t)s->nRe);
+    ps.fpair = (int32_t*)A.take(4 * (size_t)s->nRe);
+    ps.fR = (int32_t*)A.take(12 * (size_t)s->nRe);
+    ps.fkh = (int32_t*)A.take(4);
+    ps.fphi_k = A.take(16 * (size_t)p->nk * s->nRe);
+    ps.fphi_q = A.take(16 * (size_t)Q * s->nRe);
+    ps.HRp = A.take(16 * (size_t)s->nRe * (s->nb * (s->nb + 1) / 2));
+    ps.HRm = A.take(16 * (size_t)s->nRe * (s->nb * (s->nb + 1) / 2));
     if (velocities) {
         ps.dHR3 = A.take(16 * 3 * (size_t)s->nRe * nbb);
         ps.dH3 = A.take(16 * 3 * (size_t)ps.batch * nbb);
@@ -261,14 +281,22 @@ void pair_states(const epw_system* s, const epw_points* p, const epw_params* par
     if (p->kq) return;
     const int nb = s->nb, ne = s->nRe, nbb = nb * nb;
     // H(k+q) is Hermitian: only its upper triangle is formed, from the upper
-    // triangles of the Hermitian part of H(R_e) (exact for any H(R_e))
+    // triangles of the Hermitian part of H(R_e) (exact for any H(R_e)), summed
+    // over the pairs (R, -R) of R_e: sum_h c (B(R) + B(-R)) + i s (B(R) - B(-R))
+    // with c + i s = exp(2 pi i (k+q).R) and B(R) = HRu(R) / ndeg(R)
     const int ntri = nb * (nb + 1) / 2;
     {
         StageTimer t(EPW_STAGE_EIGH, st);
-        if (q0 == 0) launch_phase_table(Prec::F64, p->nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, ps.phi_k, st);
-        if (q0 == 0) launch_pack_upper(nb, ne, s->Re, s->ndeg_e, s->HR, ps.negR, ps.HRu, st);
+        if (q0 == 0) {
+            launch_phase_table(Prec::F64, p->nk, p->kfrac, ne, s->Re, s->ndeg_e, ne, ps.phi_k, st);
+            launch_pack_upper(nb, ne, s->Re, s->ndeg_e, s->HR, ps.negR, ps.HRu, st);
+            launch_half_list(ne, s->Re, ps.fneg, ps.fhalf, ps.fpair, ps.fR, ps.fkh, st);
+            launch_phase_table(Prec::F64, p->nk, p->kfrac, ne, ps.fR, nullptr, ne, ps.fphi_k, st);
+            launch_fold_gather(ne, ps.fkh, ps.fhalf, ps.fpair, s->ndeg_e, ntri, ps.HRu, ps.HRp, ps.HRm, st);
+        }
         if (q0 == 0 && ps.dHR3) launch_velocity_operands(nb, ne, s->Re, s->HR, ps.vectors9, ps.dHR3, st);
         launch_phase_table(Prec::F64, qc, p->qfrac + 3 * (size_t)q0, ne, s->Re, nullptr, ne, ps.phi_q, st);
+        launch_phase_table(Prec::F64, qc, p->qfrac + 3 * (size_t)q0, ne, ps.fR, nullptr, ne, ps.fphi_q, st);
     }
     const long npair = (long)p->nk * qc;
     for (long b0 = 0; b0 < npair; b0 += ps.batch) {
@@ -289,7 +317,13 @@ void pair_states(const epw_system* s, const epw_points* p, const epw_params* par
         d.sCm = ntri;
         {
             StageTimer t(EPW_STAGE_PAIR_GEMM, st);
-            launch_cgemm(Prec::F64, d, st);
+            GemmDesc df = d;   // the same sum folded by the pairs (R, -R)
+            df.A = ps.fphi_k;
+            df.A2 = ps.fphi_q;
+            df.B = ps.HRp;
+            df.B2 = ps.HRm;
+            df.kh = ps.fkh;
+            launch_cgemm(Prec::F64, df, st);
         }
         {
             StageTimer t(EPW_STAGE_PAIR_EIGH, st);

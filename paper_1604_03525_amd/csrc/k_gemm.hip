@@ -4,7 +4,10 @@
 // as n = e * ncb + c so that batched slabs (one per Wannier vector R_e) are
 // addressed without copies.  Used for the R_p -> q contraction, the
 // recomputation of the vertex in the adjoint, and the transposed
-// contractions of the adjoint.
+// contractions of the adjoint.  The float64 pair-operand product (H(k+q)
+// from H(R_e)) also runs folded by the pairs (R, -R): A = c + i s over a
+// halved R list, C = sum_h c B+ + i s B- (cfold_mainloop), two real MFMAs
+// per original R vector instead of three.
 #include <hip/hip_runtime.h>
 
 #include "cgemm.h"
@@ -14,12 +17,14 @@
 namespace epw {
 namespace {
 
-template <typename T, bool CONJ_TRANS_A>
+template <typename T, bool CONJ_TRANS_A, bool FOLD = false>
 __global__ __launch_bounds__(256, 2) void cgemm_generic_kernel(GemmDesc d)
 {
+    static_assert(!FOLD || (!CONJ_TRANS_A && sizeof(T) == 8), "folded sums: float64, row-major pair operand");
     typedef typename Cx<T>::type CT;
-    constexpr int BM = 64, BN = 64, BK = 16;
-    __shared__ Stage<T, BM, BN, BK> st[2];
+    // the folded stage holds six planes: K steps of 8 keep two stages per block
+    // within the LDS of two resident blocks
+    constexpr int BM = 64, BN = 64, BK = FOLD ? 8 : 16;
     // 1-D grid: with few row tiles the row tile varies fastest, so the blocks
     // sharing a column tile of B run together and share it in L2
     const int tiles_m = (d.M + BM - 1) / BM;
@@ -31,7 +36,7 @@ __global__ __launch_bounds__(256, 2) void cgemm_generic_kernel(GemmDesc d)
     const long n0 = nt * BN;
     // split K: block z covers k in [kb, kb + Kz) and writes its own partial C
     const int kb = d.kchunk > 0 ? (int)blockIdx.z * d.kchunk : 0;
-    const int Kz = d.kchunk > 0 ? min(d.kchunk, d.K - kb) : d.K;
+    const int Kz = FOLD ? d.kh[0] : d.kchunk > 0 ? min(d.kchunk, d.K - kb) : d.K;
     const CT* A = reinterpret_cast<const CT*>(d.A);
     const CT* B = reinterpret_cast<const CT*>(d.B);
     CT* C = reinterpret_cast<CT*>(d.C) + (size_t)blockIdx.z * d.sCz;
@@ -100,7 +105,34 @@ __global__ __launch_bounds__(256, 2) void cgemm_generic_kernel(GemmDesc d)
         return cz<T>();
     };
     typename Cx<T>::acc cr[4], ci[4];
-    cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), CONJ_TRANS_A, 2>(st, Kz, afetch, bfetch, cr, ci);
+    if constexpr (FOLD) {
+        // B+ and B- of entry h of the halved list, same column decoding as bfetch
+        const CT* B2 = reinterpret_cast<const CT*>(d.B2);
+        auto bfold = [&](int kl, int n) -> CPair<CT> {
+            CPair<CT> v;
+            v.p = cz<T>();
+            v.m = cz<T>();
+            const long col = n0 + n;
+            if (kl < Kz && col < d.N) {
+                long e = e_base;
+                int c = c_base + (n - nbase);
+                while (c >= d.ncb) {
+                    c -= d.ncb;
+                    ++e;
+                }
+                const size_t off = (size_t)e * d.sBe + (size_t)kl * d.sBk + c;
+                v.p = B[off];
+                v.m = B2[off];
+            }
+            return v;
+        };
+        __shared__ FoldStage<T, BM, BN, BK> fst[2];
+        cfold_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfold), 2>(fst, Kz, afetch, bfold, cr, ci);
+    } else {
+        __shared__ Stage<T, BM, BN, BK> st[2];
+        cgemm_mainloop<T, BM, BN, BK, decltype(afetch), decltype(bfetch), CONJ_TRANS_A, 2>(st, Kz, afetch, bfetch, cr,
+                                                                                          ci);
+    }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int c = 0; c < 4; ++c) {
         const long col = n0 + c * 16 + (lane & 15);
@@ -249,6 +281,43 @@ __global__ __launch_bounds__(256, 2) void ksum_fold_kernel(KsumFoldDesc d)
     }
 }
 
+namespace {
+// B+ / B- rows of a halved R list (launch_fold_gather); rows h >= kh[0] are zero
+__global__ void fold_gather_kernel(const int32_t* __restrict__ kh, const int32_t* __restrict__ half,
+                                   const int32_t* __restrict__ pair, const int32_t* __restrict__ ndeg, long cols,
+                                   const double2* __restrict__ B, double2* __restrict__ Bp, double2* __restrict__ Bm) {
+    const long h = blockIdx.y;
+    const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (col >= cols) return;
+    double2 p = make_double2(0.0, 0.0), m = p;
+    if (h < kh[0]) {
+        const long r1 = half[h], r2 = pair[h];
+        const double w1 = 1.0 / (double)ndeg[r1];
+        const double2 x = B[r1 * cols + col];
+        p = make_double2(x.x * w1, x.y * w1);
+        m = p;
+        if (r2 != r1) {
+            const double w2 = 1.0 / (double)ndeg[r2];
+            const double2 y = B[r2 * cols + col];
+            const double2 yw = make_double2(y.x * w2, y.y * w2);
+            p = make_double2(x.x * w1 + yw.x, x.y * w1 + yw.y);
+            m = make_double2(x.x * w1 - yw.x, x.y * w1 - yw.y);
+        }
+    }
+    Bp[h * cols + col] = p;
+    Bm[h * cols + col] = m;
+}
+}  // namespace
+
+void launch_fold_gather(int nR, const int32_t* kh, const int32_t* half, const int32_t* pair, const int32_t* ndeg,
+                        long cols, const void* B, void* Bp, void* Bm, hipStream_t stream) {
+    if (nR <= 0 || cols <= 0) return;
+    const dim3 grid((unsigned)((cols + 255) / 256), (unsigned)nR);
+    fold_gather_kernel<<<grid, 256, 0, stream>>>(kh, half, pair, ndeg, cols, (const double2*)B, (double2*)Bp,
+                                                 (double2*)Bm);
+    launch_check("fold_gather_kernel");
+}
+
 void launch_cgemm_splitk(Prec prec, const GemmDesc& d, int parts, void* scratch, hipStream_t stream) {
     if (d.M <= 0 || d.N <= 0) return;
     if (parts <= 1 || d.ncb != d.N || d.kchunk != 0) {
@@ -310,7 +379,11 @@ void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream, int kparts) 
     if (d.ncb < 1 || d.n2 < 1) throw HipFailure{(int)hipErrorInvalidValue, "cgemm descriptor (ncb, n2)", __FILE__, __LINE__};
     const long tiles = (long)((d.N + 63) / 64) * ((d.M + 63) / 64);
     dim3 grid((unsigned)tiles, 1, (unsigned)(kparts > 1 ? kparts : 1));
-    if (prec == Prec::F64) {
+    if (d.kh) {
+        if (prec != Prec::F64 || d.conj_trans_a || !d.A2 || !d.B2 || d.kchunk != 0 || kparts > 1)
+            throw HipFailure{(int)hipErrorInvalidValue, "folded cgemm descriptor", __FILE__, __LINE__};
+        cgemm_generic_kernel<double, false, true><<<grid, 256, 0, stream>>>(d);
+    } else if (prec == Prec::F64) {
         if (d.conj_trans_a) cgemm_generic_kernel<double, true><<<grid, 256, 0, stream>>>(d);
         else cgemm_generic_kernel<double, false><<<grid, 256, 0, stream>>>(d);
     } else {

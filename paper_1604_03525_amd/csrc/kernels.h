@@ -223,9 +223,21 @@ struct GemmDesc {
     long row0 = 0;
     int kchunk = 0;    // split K: blockIdx.z covers [z*kchunk, (z+1)*kchunk) (0: all of K)
     long sCz = 0;      // C offset between the split-K partial outputs
+    // folded sum (float64, pair operand, no conj_trans_a, no split K): K runs over
+    // the kh[0] entries h of a halved R list (read on the device), A(m, h) = c + i s
+    // is the pair operand over that list, B holds B+ rows and B2 the B- rows
+    // (launch_fold_gather); C = sum_h c B+ + i s B-
+    const int32_t* kh = nullptr;
+    const void* B2 = nullptr;
 };
 // kparts > 1 launches that many K slices (d.kchunk must cover K)
 void launch_cgemm(Prec prec, const GemmDesc& d, hipStream_t stream, int kparts = 1);
+// B+ and B- rows of the halved R list for a folded float64 GEMM: for h < kh[0],
+// x = B[half[h]] / ndeg[half[h]] and y = B[pair[h]] / ndeg[pair[h]] (rows of
+// `cols` complex entries), Bp[h] = x + y and Bm[h] = x - y, or both x for an
+// entry without a partner (pair[h] == half[h])
+void launch_fold_gather(int nR, const int32_t* kh, const int32_t* half, const int32_t* pair, const int32_t* ndeg,
+                        long cols, const void* B, void* Bp, void* Bm, hipStream_t stream);
 // number of K slices launch_cgemm_splitk uses for an M x N x K product
 int splitk_parts(int M, int N, int K);
 // the same for products with very few output tiles (up to max_parts slices)
