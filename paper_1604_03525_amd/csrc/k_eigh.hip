@@ -118,25 +118,31 @@ __device__ __forceinline__ void vrot(int r, double2 (&v)[N2], const double (*rt)
 }
 
 // 64 / N2 matrices per wave (matrix h of a block is point MPW blockIdx.x + h):
-// four on the 16-index schedule (n > 8), eight on the 8-index one.  A
-// (Hermitian, full) is in LDS; lane N2 h + i holds row i of V of matrix h in
-// registers.  A Jacobi round:
+// four on the 16-index schedule (n > 8), eight on the 8-index one.  A is in
+// LDS as its upper triangle (entry (i, j), i <= j, at tri(i, j); an entry
+// below the diagonal is read and written as the conjugate of its mirror);
+// lane N2 h + i holds row i of V of matrix h in registers.  A Jacobi round:
 //   - lane NPAIR h + u (32 lanes) computes the rotation of pair u of matrix h
 //     and writes the pair's own 2 x 2 diagonal block in closed form
 //     (a_pp - t |b|, a_qq + t |b|, exact zeros off the diagonal);
 //   - the off-diagonal blocks (pairs P1 < P2; 4 x 28 or 8 x 6) are rotated
-//     in APASS passes over the 64 lanes; each writes its block and the
-//     conjugate transpose, so A stays exactly Hermitian and no lane reads
-//     what another writes;
+//     in APASS passes over the 64 lanes; each block's four entries lie in
+//     four distinct places of the triangle that no other block touches;
 //   - every lane rotates its row of V by all pairs of the round.
 // A matrix that has converged takes identity rotations, which change nothing
 // (exactly), so its result does not depend on the other matrices of its wave.
+// offset of entry (lo, hi), lo <= hi, in the row-major upper triangle of N2 x N2
+template <int N2>
+__device__ __forceinline__ int tri(int lo, int hi) {
+    return (lo * (2 * N2 - 1 - lo) >> 1) + hi;
+}
+
 template <int N2> struct JacobiShape {
     static constexpr int MPW = 64 / N2;
     static constexpr int NPAIR = N2 / 2;
     static constexpr int NBLK = NPAIR * (NPAIR - 1) / 2;
     static constexpr int APASS = (MPW * NBLK + 63) / 64;
-    static constexpr int LDA = N2 + 1;          // padded leading dimension in LDS
+    static constexpr int NT = N2 * (N2 + 1) / 2;  // entries of the upper triangle
     static_assert(N2 == 8 || N2 == 16, "schedules on 8 or 16 indices");
     static_assert(MPW * NPAIR == 32, "32 rotation-parameter lanes");
 };
@@ -148,7 +154,7 @@ template <int N2> struct JacobiShape {
 // with PACKED only their upper triangles ([np][n(n+1)/2], rows i with columns
 // j >= i in turn), the lower triangle being the conjugate.
 template <int N2, bool REAL_IN, bool SQRT_OUT, bool GIVEN = false, bool PACKED = false>
-__global__ __launch_bounds__(64) void interp_eigh_kernel(
+__global__ __launch_bounds__(64, N2 == 16 ? (GIVEN ? 3 : 2) : 4) void interp_eigh_kernel(
     int n, int nR, const int32_t* __restrict__ R, const int32_t* __restrict__ ndeg,
     const double* __restrict__ XR, int np, const double* __restrict__ pts,
     const double* __restrict__ pts2, int npts2,
@@ -156,7 +162,8 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
 {
     typedef JacobiShape<N2> S;
     constexpr int MPW = S::MPW, NPAIR = S::NPAIR, NBLK = S::NBLK, APASS = S::APASS;
-    __shared__ double2 A[MPW][N2][S::LDA];
+    constexpr int NT = S::NT;
+    __shared__ double2 A[MPW][NT];
     __shared__ double2 ph[GIVEN ? 1 : RBLK];
     __shared__ double2 red[GIVEN ? 1 : 64];
     __shared__ double rot[MPW][NPAIR][4];
@@ -167,8 +174,7 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     const int p0 = blockIdx.x * MPW;
     if (p0 >= np) return;
     const int nmat = min(MPW, np - p0);
-    for (int e = lane; e < MPW * N2 * N2; e += 64)
-        A[e / (N2 * N2)][(e / N2) % N2][e % N2] = make_double2(0.0, 0.0);
+    for (int e = lane; e < MPW * NT; e += 64) A[e / NT][e % NT] = make_double2(0.0, 0.0);
     __syncthreads();
     if constexpr (GIVEN) {
         // the given matrices of the block's points -> A[h], one after the other
@@ -179,13 +185,17 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                 for (int e = lane; e < n * n; e += 64) {
                     const int i = e / n, j = e % n;
                     if (i > j) continue;
-                    const double2 x = X[i * n - i * (i - 1) / 2 + (j - i)];
-                    A[h][i][j] = x;
-                    if (i < j) A[h][j][i] = make_double2(x.x, -x.y);
+                    A[h][tri<N2>(i, j)] = X[i * n - i * (i - 1) / 2 + (j - i)];
                 }
             } else {
+                // the Hermitian part (X + X^dag) / 2
                 const double2* X = reinterpret_cast<const double2*>(XR) + (size_t)p * n * n;
-                for (int e = lane; e < n * n; e += 64) A[h][e / n][e % n] = X[e];
+                for (int e = lane; e < n * n; e += 64) {
+                    const int i = e / n, j = e % n;
+                    if (i > j) continue;
+                    const double2 x = X[e], y = X[j * n + i];
+                    A[h][tri<N2>(i, j)] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
+                }
             }
         }
     } else {
@@ -267,12 +277,13 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                 }
             }
         }
-        if (P > 1) {
-            // the partitions' partial sums, one point at a time, in a fixed order
+        // point h's raw matrix (the partitions' partial sums added in a fixed
+        // order) -> ph as [n][n], then its Hermitian part -> the triangle of A[h]
 #pragma unroll
-            for (int h = 0; h < MPW; ++h) {
-                if (h >= nmat) break;
-                __syncthreads();
+        for (int h = 0; h < MPW; ++h) {
+            if (h >= nmat) break;
+            __syncthreads();
+            if (P > 1) {
                 red[lane] = acc[0][h];
                 __syncthreads();
                 if (lane < E) {
@@ -281,29 +292,23 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                         sum.x += red[lane + E * part].x;
                         sum.y += red[lane + E * part].y;
                     }
-                    A[h][lane / n][lane % n] = sum;
+                    ph[lane] = sum;
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < EPLMAX; ++j) {
+                    const int e = lane + 64 * j;
+                    if (j < EPL && e < E) ph[e] = acc[j][h];
                 }
             }
-        } else {
-#pragma unroll
-            for (int j = 0; j < EPLMAX; ++j) {
-                const int e = lane + 64 * j;
-                if (j >= EPL || e >= E) continue;
-#pragma unroll
-                for (int h = 0; h < MPW; ++h)
-                    if (h < nmat) A[h][e / n][e % n] = acc[j][h];
+            __syncthreads();
+            for (int e = lane; e < E; e += 64) {
+                const int i = e / n, j = e % n;
+                if (i > j) continue;
+                const double2 x = ph[e], y = ph[j * n + i];
+                A[h][tri<N2>(i, j)] = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
             }
         }
-    }
-    __syncthreads();
-    // Hermitise in place: the lane of (i, j), i <= j, writes both entries
-    for (int e = lane; e < MPW * N2 * N2; e += 64) {
-        const int h = e / (N2 * N2), i = (e / N2) % N2, j = e % N2;
-        if (i > j || h >= nmat || j >= n) continue;
-        const double2 x = A[h][i][j], y = A[h][j][i];
-        const double2 a = make_double2(0.5 * (x.x + y.x), 0.5 * (x.y - y.y));
-        A[h][i][j] = a;
-        A[h][j][i] = make_double2(a.x, -a.y);
     }
     __syncthreads();
 
@@ -342,7 +347,7 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
 #pragma unroll
             for (int j = 0; j < N2; ++j) {
                 if (j >= n) continue;
-                const double2 a = A[vh][vr][j];
+                const double2 a = A[vh][vr <= j ? tri<N2>(vr, j) : tri<N2>(j, vr)];
                 const double m2 = a.x * a.x + a.y * a.y;
                 if (j == vr) dia += m2; else off += m2;
             }
@@ -364,8 +369,8 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                 rr_pair<N2>(r, ph_u, pp, qq);
                 double c = 1.0, s = 0.0, cph = 1.0, sph = 0.0;
                 if (!ph_done && qq < n) {
-                    const double app = A[ph_h][pp][pp].x, aqq = A[ph_h][qq][qq].x;
-                    const double2 b = A[ph_h][pp][qq];
+                    const double app = A[ph_h][tri<N2>(pp, pp)].x, aqq = A[ph_h][tri<N2>(qq, qq)].x;
+                    const double2 b = A[ph_h][tri<N2>(pp, qq)];
                     double tb = 0.0;                          // t |b|
                     // b = |b| e^{i phi} with b scaled by max(|Re b|, |Im b|) first, so that the
                     // phase keeps unit modulus down to the smallest normal numbers; a coupling
@@ -397,10 +402,9 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                     }
                     // the pair's own block after the rotation: a real diagonal, exact zeros
                     // off it
-                    A[ph_h][pp][pp] = make_double2(app - tb, 0.0);
-                    A[ph_h][qq][qq] = make_double2(aqq + tb, 0.0);
-                    A[ph_h][pp][qq] = make_double2(0.0, 0.0);
-                    A[ph_h][qq][pp] = make_double2(0.0, 0.0);
+                    A[ph_h][tri<N2>(pp, pp)] = make_double2(app - tb, 0.0);
+                    A[ph_h][tri<N2>(qq, qq)] = make_double2(aqq + tb, 0.0);
+                    A[ph_h][tri<N2>(pp, qq)] = make_double2(0.0, 0.0);
                 }
                 rot[ph_h][ph_u][0] = c;
                 rot[ph_h][ph_u][1] = s;
@@ -424,7 +428,21 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                 const double2 e1 = make_double2(rot[h][B1][2], rot[h][B1][3]);
                 const double c2 = rot[h][B2][0], s2 = rot[h][B2][1];
                 const double2 e2 = make_double2(rot[h][B2][2], -rot[h][B2][3]);
-                const double2 xpp = A[h][p1][p2], xpq = A[h][p1][q2], xqp = A[h][q1][p2], xqq = A[h][q1][q2];
+                // the block's entries (row, column): offset in the triangle and whether
+                // the entry lies below the diagonal (stored as its mirror's conjugate)
+                auto at = [&](int i, int j, int& off) -> bool {
+                    const bool low = i > j;
+                    off = low ? tri<N2>(j, i) : tri<N2>(i, j);
+                    return low;
+                };
+                auto rd = [&](int off, bool low) -> double2 {
+                    const double2 v = A[h][off];
+                    return make_double2(v.x, low ? -v.y : v.y);
+                };
+                auto wr = [&](int off, bool low, double2 v) { A[h][off] = make_double2(v.x, low ? -v.y : v.y); };
+                int opp, opq, oqp, oqq;
+                const bool lpp = at(p1, p2, opp), lpq = at(p1, q2, opq), lqp = at(q1, p2, oqp), lqq = at(q1, q2, oqq);
+                const double2 xpp = rd(opp, lpp), xpq = rd(opq, lpq), xqp = rd(oqp, lqp), xqq = rd(oqq, lqq);
                 const double2 wp = cmul(xpq, e2), wq = cmul(xqq, e2);
                 const double2 ypp = make_double2(c2 * xpp.x - s2 * wp.x, c2 * xpp.y - s2 * wp.y);
                 const double2 ypq = make_double2(s2 * xpp.x + c2 * wp.x, s2 * xpp.y + c2 * wp.y);
@@ -435,14 +453,10 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
                 const double2 zqp = make_double2(s1 * ypp.x + c1 * up.x, s1 * ypp.y + c1 * up.y);
                 const double2 zpq = make_double2(c1 * ypq.x - s1 * uq.x, c1 * ypq.y - s1 * uq.y);
                 const double2 zqq = make_double2(s1 * ypq.x + c1 * uq.x, s1 * ypq.y + c1 * uq.y);
-                A[h][p1][p2] = zpp;
-                A[h][p1][q2] = zpq;
-                A[h][q1][p2] = zqp;
-                A[h][q1][q2] = zqq;
-                A[h][p2][p1] = make_double2(zpp.x, -zpp.y);
-                A[h][q2][p1] = make_double2(zpq.x, -zpq.y);
-                A[h][p2][q1] = make_double2(zqp.x, -zqp.y);
-                A[h][q2][q1] = make_double2(zqq.x, -zqq.y);
+                wr(opp, lpp, zpp);
+                wr(opq, lpq, zpq);
+                wr(oqp, lqp, zqp);
+                wr(oqq, lqq, zqq);
             }
             // V <- V J on the lane's row (the round's pair indices are constants)
             vrot<N2>(r, v, rot[vh], std::make_integer_sequence<int, N2 - 1>{});
@@ -451,10 +465,10 @@ __global__ __launch_bounds__(64) void interp_eigh_kernel(
     }
     // ascending order with a stable rank; eigenvector i is column i of V
     if (vr < n) {
-        const double li = A[vh][vr][vr].x;
+        const double li = A[vh][tri<N2>(vr, vr)].x;
         int rank = 0;
         for (int j = 0; j < n; ++j) {
-            const double lj = A[vh][j][j].x;
+            const double lj = A[vh][tri<N2>(j, j)].x;
             rank += (lj < li) || (lj == li && j < vr);
         }
         rk[vh][vr] = rank;
