@@ -646,11 +646,12 @@ void run_forward(const epw_system* s, const epw_points* p, const epw_params* par
             if (bf)
                 launch_mode_rotate_bf16(ne, qc, nm, nb, L.nbp, L.kpad, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e,
                                         L.polar_L, s->Re);
+            else if (L.fold)
+                launch_mode_rotate_fold(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, s->ndeg_e, L.fkh, L.fhalf,
+                                        L.fpair, L.polar_L, s->Re, L.Bnu, st);
             else
                 launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, s->ndeg_e, L.polar_L,
                                    s->Re);
-            if (L.fold)
-                launch_fold_pairs(prec, ne, L.fkh, L.fhalf, L.fpair, (long)qc * nm * L.nbp * L.nbp, L.Bnu, st);
         }
         FusedArgs a;
         a.nk = nk;
@@ -991,9 +992,11 @@ void run_backward(const epw_system* s, const epw_points* p, const epw_params* pa
         } else {
             // the folded recompute takes the 1/ndeg weights in B (its phases are
             // unweighted), the generic GEMM in the phase table
-            launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, L.fold ? s->ndeg_e : nullptr,
-                               L.polar_L, s->Re);
-            if (L.fold) launch_fold_pairs(prec, ne, L.fkh, L.fhalf, L.fpair, ncols, L.Bnu, st);
+            if (L.fold)
+                launch_mode_rotate_fold(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, s->ndeg_e, L.fkh, L.fhalf,
+                                        L.fpair, L.polar_L, s->Re, L.Bnu, st);
+            else
+                launch_mode_rotate(prec, ne, qc, nm, nb, L.nbp, L.gq, ev, L.sc, L.Bnu, st, nullptr, L.polar_L, s->Re);
         }
         if (!bf && L.nbp >= 16) {   // recompute G = Phi_k B (Wannier basis, all k of the chunk)
             GemmDesc d;

@@ -155,6 +155,95 @@ __global__ void mode_rotate_kernel(int ne, int nq, int nm, int nb, int nbp,
     }
 }
 
+// a6 and the fold of the R_e rows by the pairs (R, -R) in one pass: thread
+// (h, q, i, j) rotates rows half[h] and pair[h] of g(R_e, q), each with its
+// 1/ndeg, and writes B+ = B(R) + B(-R) to row half[h] and B- = B(R) - B(-R)
+// to row pair[h], or B(R) alone for an entry without a partner; the same
+// values as mode_rotate_kernel (with the ndeg weights) followed by the fold.
+template <typename T>
+__global__ void mode_rotate_fold_kernel(int ne, int nq, int nm, int nb, int nbp,
+                                        const typename Cx<T>::type* __restrict__ in,
+                                        const double2* __restrict__ evec, const double* __restrict__ sc,
+                                        const int32_t* __restrict__ ndeg, const int32_t* __restrict__ kh,
+                                        const int32_t* __restrict__ half, const int32_t* __restrict__ pair,
+                                        const double2* __restrict__ Lq, const int32_t* __restrict__ Re,
+                                        typename Cx<T>::type* __restrict__ out)
+{
+    typedef typename Cx<T>::type CT;
+    const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int nbp2 = nbp * nbp;
+    const size_t total = (size_t)ne * nq * nbp2;
+    if (idx >= total) return;
+    const int ij = (int)(idx % nbp2);
+    const size_t hq = idx / nbp2;
+    const int q = (int)(hq % nq);
+    const int h = (int)(hq / nq);
+    if (h >= kh[0]) return;
+    const int e1 = half[h], e2 = pair[h];
+    const bool two = e2 != e1;
+    CT* o1 = out + ((size_t)e1 * nq + q) * nm * nbp2 + ij;
+    CT* o2 = out + ((size_t)e2 * nq + q) * nm * nbp2 + ij;
+    const int i = ij / nbp, j = ij % nbp;
+    if (i >= nb || j >= nb) {
+        for (int v = 0; v < nm; ++v) {
+            o1[(size_t)v * nbp2] = cz<T>();
+            if (two) o2[(size_t)v * nbp2] = cz<T>();
+        }
+        return;
+    }
+    const CT* x1 = in + ((size_t)e1 * nq + q) * nm * nb * nb + i * nb + j;
+    const CT* x2 = in + ((size_t)e2 * nq + q) * nm * nb * nb + i * nb + j;
+    const double w1 = 1.0 / (double)ndeg[e1], w2 = 1.0 / (double)ndeg[e2];
+    // the polar long-range term sits on the row with R_e = 0 (its own partner)
+    const bool z1 = Lq && i == j && (Re[3 * e1] | Re[3 * e1 + 1] | Re[3 * e1 + 2]) == 0;
+    const bool z2 = Lq && i == j && (Re[3 * e2] | Re[3 * e2 + 1] | Re[3 * e2 + 2]) == 0;
+    for (int v = 0; v < nm; ++v) {
+        const double s = sc[(size_t)q * nm + v];
+        T ar = T(0), ai = T(0), br = T(0), bi = T(0);
+        if (s != 0.0) {
+            for (int a = 0; a < nm; ++a) {
+                const double2 ev = evec[((size_t)q * nm + a) * nm + v];
+                const CT g = x1[(size_t)a * nb * nb];
+                ar += g.x * (T)ev.x - g.y * (T)ev.y;
+                ai += g.x * (T)ev.y + g.y * (T)ev.x;
+                if (two) {
+                    const CT f = x2[(size_t)a * nb * nb];
+                    br += f.x * (T)ev.x - f.y * (T)ev.y;
+                    bi += f.x * (T)ev.y + f.y * (T)ev.x;
+                }
+            }
+            ar *= (T)(s * w1);
+            ai *= (T)(s * w1);
+            br *= (T)(s * w2);
+            bi *= (T)(s * w2);
+        }
+        if (z1 || z2) {
+            const double2 l = Lq[(size_t)q * nm + v];
+            if (z1) {
+                ar += (T)l.x;
+                ai += (T)l.y;
+            }
+            if (z2) {
+                br += (T)l.x;
+                bi += (T)l.y;
+            }
+        }
+        CT r;
+        r.x = ar + br;
+        r.y = ai + bi;
+        if (two) {
+            CT m;
+            m.x = ar - br;
+            m.y = ai - bi;
+            o2[(size_t)v * nbp2] = m;
+        } else {
+            r.x = ar;
+            r.y = ai;
+        }
+        o1[(size_t)v * nbp2] = r;
+    }
+}
+
 // ------------------------------------------------------------ a7+a8+a9
 //
 // Block (mt, s): k rows [mt*BM, mt*BM+BM), column tiles nt = s, s+S, ...
@@ -1298,36 +1387,6 @@ void launch_phase_table(Prec prec, int np, const double* pts, int nR, const int3
     launch_check("phase_table_kernel");
 }
 
-template <typename CT>
-__global__ void fold_pairs_kernel(const int32_t* __restrict__ kh, const int32_t* __restrict__ half,
-                                  const int32_t* __restrict__ pair, long cols, CT* __restrict__ B) {
-    const int h = blockIdx.y;
-    if (h >= kh[0]) return;
-    const long r1 = half[h], r2 = pair[h];
-    if (r1 == r2) return;
-    const long col = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (col >= cols) return;
-    const CT x = B[r1 * cols + col], y = B[r2 * cols + col];
-    CT p, m;
-    p.x = x.x + y.x;
-    p.y = x.y + y.y;
-    m.x = x.x - y.x;
-    m.y = x.y - y.y;
-    B[r1 * cols + col] = p;
-    B[r2 * cols + col] = m;
-}
-
-void launch_fold_pairs(Prec prec, int nR, const int32_t* kh, const int32_t* half, const int32_t* pair, long cols,
-                       void* B, hipStream_t stream) {
-    if (nR <= 0 || cols <= 0) return;
-    const dim3 grid((unsigned)((cols + 255) / 256), (unsigned)nR);
-    if (prec == Prec::F64)
-        fold_pairs_kernel<double2><<<grid, 256, 0, stream>>>(kh, half, pair, cols, (double2*)B);
-    else
-        fold_pairs_kernel<float2><<<grid, 256, 0, stream>>>(kh, half, pair, cols, (float2*)B);
-    launch_check("fold_pairs_kernel");
-}
-
 void launch_c128_to_c64(size_t n, const void* in, void* out, hipStream_t stream) {
     if (n == 0) return;
     c128_to_c64_kernel<<<blocks_for(n, 256), 256, 0, stream>>>(n, (const double2*)in, (float2*)out);
@@ -1363,6 +1422,22 @@ void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, cons
             ne, nq, nm, nb, nbp, (const float2*)in, (const double2*)evec, sc, ndeg_fold, (const double2*)Lq, Re,
             (float2*)out);
     launch_check("mode_rotate_kernel");
+}
+
+void launch_mode_rotate_fold(Prec prec, int ne, int nq, int nm, int nb, int nbp, const void* in, const void* evec,
+                             const double* sc, const int32_t* ndeg, const int32_t* kh, const int32_t* half,
+                             const int32_t* pair, const void* Lq, const int32_t* Re, void* out, hipStream_t stream) {
+    const size_t total = (size_t)ne * nq * nbp * nbp;
+    if (total == 0) return;
+    if (prec == Prec::F64)
+        mode_rotate_fold_kernel<double><<<blocks_for(total, 256), 256, 0, stream>>>(
+            ne, nq, nm, nb, nbp, (const double2*)in, (const double2*)evec, sc, ndeg, kh, half, pair,
+            (const double2*)Lq, Re, (double2*)out);
+    else
+        mode_rotate_fold_kernel<float><<<blocks_for(total, 256), 256, 0, stream>>>(
+            ne, nq, nm, nb, nbp, (const float2*)in, (const double2*)evec, sc, ndeg, kh, half, pair,
+            (const double2*)Lq, Re, (float2*)out);
+    launch_check("mode_rotate_fold_kernel");
 }
 
 int fused_slices(int nk, int nbp, int tiles_n, int num_cu, Prec prec) {

@@ -39,11 +39,6 @@ void launch_pack_upper(int n, int nR, const int32_t* R, const int32_t* ndeg, con
 
 // ---- k_vertex.hip ----
 enum class Prec { F64 = 0, F32 = 1, BF16X2 = 2 };
-// in place over rows of B [nR][cols] (complex in prec, float64 or float32):
-// for every h < kh with pair[h] != half[h], rows (half[h], pair[h]) become
-// (B+ , B-) = (x + y, x - y) of their entries (x, y)
-void launch_fold_pairs(Prec prec, int nR, const int32_t* kh, const int32_t* half, const int32_t* pair, long cols,
-                       void* B, hipStream_t stream);
 
 // exp(2 pi i p.R)/ndeg(R) -> [np][ld] complex in `prec` (columns >= nR zero;
 // ndeg == nullptr: weight 1).
@@ -73,6 +68,15 @@ void launch_mode_rotate(Prec prec, int ne, int nq, int nm, int nb, int nbp, cons
                         const void* evec, const double* sc, void* out, hipStream_t stream,
                         const int32_t* ndeg_fold = nullptr, const void* Lq = nullptr,
                         const int32_t* Re = nullptr);
+
+// a6 with the R_e rows folded by the pairs (R, -R) of the halved list (half,
+// pair, kh as from launch_half_list): out holds B+ in row half[h] and B- in
+// row pair[h] (B alone for an entry without a partner), each B(R) with its
+// 1/ndeg[R]; the result of launch_mode_rotate with ndeg_fold = ndeg followed by
+// the fold B+ = B(R) + B(-R), B- = B(R) - B(-R), in one pass
+void launch_mode_rotate_fold(Prec prec, int ne, int nq, int nm, int nb, int nbp, const void* in, const void* evec,
+                             const double* sc, const int32_t* ndeg, const int32_t* kh, const int32_t* half,
+                             const int32_t* pair, const void* Lq, const int32_t* Re, void* out, hipStream_t stream);
 
 // a6 for split-bf16: float32 g(R_e,q) [ne][qc][nm*nb*nb] -> four bf16 planes
 // [4][qc*nm*nbp*nbp][kpad] (R_e contiguous), scaled by sc and rotated by e_q.
