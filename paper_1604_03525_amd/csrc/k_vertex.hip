@@ -160,7 +160,7 @@ __global__ void mode_rotate_kernel(int ne, int nq, int nm, int nb, int nbp,
 // 1/ndeg, and writes B+ = B(R) + B(-R) to row half[h] and B- = B(R) - B(-R)
 // to row pair[h], or B(R) alone for an entry without a partner; the same
 // values as mode_rotate_kernel (with the ndeg weights) followed by the fold.
-template <typename T>
+template <typename T, int NMX>
 __global__ void mode_rotate_fold_kernel(int ne, int nq, int nm, int nb, int nbp,
                                         const typename Cx<T>::type* __restrict__ in,
                                         const double2* __restrict__ evec, const double* __restrict__ sc,
@@ -191,8 +191,21 @@ __global__ void mode_rotate_fold_kernel(int ne, int nq, int nm, int nb, int nbp,
         }
         return;
     }
+    // NMX > 0: the row's nm entries loaded once into registers (NMX >= nm, indices
+    // known at compile time); NMX == 0 (more than 8 modes): read in the mode loop
     const CT* x1 = in + ((size_t)e1 * nq + q) * nm * nb * nb + i * nb + j;
     const CT* x2 = in + ((size_t)e2 * nq + q) * nm * nb * nb + i * nb + j;
+    constexpr int NG = NMX > 0 ? NMX : 1;
+    CT g1[NG], g2[NG];
+#pragma unroll
+    for (int a = 0; a < NG; ++a) {
+        g1[a] = cz<T>();
+        g2[a] = cz<T>();
+        if (NMX > 0 && a < nm) {
+            g1[a] = x1[(size_t)a * nb * nb];
+            if (two) g2[a] = x2[(size_t)a * nb * nb];
+        }
+    }
     const double w1 = 1.0 / (double)ndeg[e1], w2 = 1.0 / (double)ndeg[e2];
     // the polar long-range term sits on the row with R_e = 0 (its own partner)
     const bool z1 = Lq && i == j && (Re[3 * e1] | Re[3 * e1 + 1] | Re[3 * e1 + 2]) == 0;
@@ -201,15 +214,27 @@ __global__ void mode_rotate_fold_kernel(int ne, int nq, int nm, int nb, int nbp,
         const double s = sc[(size_t)q * nm + v];
         T ar = T(0), ai = T(0), br = T(0), bi = T(0);
         if (s != 0.0) {
-            for (int a = 0; a < nm; ++a) {
-                const double2 ev = evec[((size_t)q * nm + a) * nm + v];
-                const CT g = x1[(size_t)a * nb * nb];
-                ar += g.x * (T)ev.x - g.y * (T)ev.y;
-                ai += g.x * (T)ev.y + g.y * (T)ev.x;
-                if (two) {
-                    const CT f = x2[(size_t)a * nb * nb];
-                    br += f.x * (T)ev.x - f.y * (T)ev.y;
-                    bi += f.x * (T)ev.y + f.y * (T)ev.x;
+            if constexpr (NMX > 0) {
+#pragma unroll
+                for (int a = 0; a < NMX; ++a) {
+                    if (a >= nm) break;
+                    const double2 ev = evec[((size_t)q * nm + a) * nm + v];
+                    ar += g1[a].x * (T)ev.x - g1[a].y * (T)ev.y;
+                    ai += g1[a].x * (T)ev.y + g1[a].y * (T)ev.x;
+                    br += g2[a].x * (T)ev.x - g2[a].y * (T)ev.y;
+                    bi += g2[a].x * (T)ev.y + g2[a].y * (T)ev.x;
+                }
+            } else {
+                for (int a = 0; a < nm; ++a) {
+                    const double2 ev = evec[((size_t)q * nm + a) * nm + v];
+                    const CT g = x1[(size_t)a * nb * nb];
+                    ar += g.x * (T)ev.x - g.y * (T)ev.y;
+                    ai += g.x * (T)ev.y + g.y * (T)ev.x;
+                    if (two) {
+                        const CT f = x2[(size_t)a * nb * nb];
+                        br += f.x * (T)ev.x - f.y * (T)ev.y;
+                        bi += f.x * (T)ev.y + f.y * (T)ev.x;
+                    }
                 }
             }
             ar *= (T)(s * w1);
@@ -1429,14 +1454,21 @@ void launch_mode_rotate_fold(Prec prec, int ne, int nq, int nm, int nb, int nbp,
                              const int32_t* pair, const void* Lq, const int32_t* Re, void* out, hipStream_t stream) {
     const size_t total = (size_t)ne * nq * nbp * nbp;
     if (total == 0) return;
-    if (prec == Prec::F64)
-        mode_rotate_fold_kernel<double><<<blocks_for(total, 256), 256, 0, stream>>>(
-            ne, nq, nm, nb, nbp, (const double2*)in, (const double2*)evec, sc, ndeg, kh, half, pair,
-            (const double2*)Lq, Re, (double2*)out);
-    else
-        mode_rotate_fold_kernel<float><<<blocks_for(total, 256), 256, 0, stream>>>(
-            ne, nq, nm, nb, nbp, (const float2*)in, (const double2*)evec, sc, ndeg, kh, half, pair,
-            (const double2*)Lq, Re, (float2*)out);
+    // up to 8 modes: the mode count rounded up to 4 or 8, entries in registers
+    auto go = [&](auto nmx) {
+        constexpr int NMX = decltype(nmx)::value;
+        if (prec == Prec::F64)
+            mode_rotate_fold_kernel<double, NMX><<<blocks_for(total, 256), 256, 0, stream>>>(
+                ne, nq, nm, nb, nbp, (const double2*)in, (const double2*)evec, sc, ndeg, kh, half, pair,
+                (const double2*)Lq, Re, (double2*)out);
+        else
+            mode_rotate_fold_kernel<float, NMX><<<blocks_for(total, 256), 256, 0, stream>>>(
+                ne, nq, nm, nb, nbp, (const float2*)in, (const double2*)evec, sc, ndeg, kh, half, pair,
+                (const double2*)Lq, Re, (float2*)out);
+    };
+    if (nm <= 4) go(std::integral_constant<int, 4>{});
+    else if (nm <= 8) go(std::integral_constant<int, 8>{});
+    else go(std::integral_constant<int, 0>{});
     launch_check("mode_rotate_fold_kernel");
 }
 
